@@ -1,0 +1,213 @@
+"""Benchmark: Laplace FMM on one MI355X.
+
+One step = build the octree + evaluate potentials and fields (every step of
+the forward path: keys, level selection, sort, P2M, M2M, M2L, L2L, L2P, P2P,
+combine) for N = 1e6 particles uniform in the unit cube, charges U[0,1),
+p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
+
+  value        particles/s of the mixed form (N / step time)
+  p2p_gint_s   P2P Ginteractions/s (mixed), pairs from the tree / P2P time
+  fp64         the plain FP64 form measured the same way
+  rel_l2       errors vs the FP64 direct sum on 1000 sampled targets
+  roofline     dominant kernel, from HIP events recorded by the library on
+               the stream its kernels run on
+  cpu_baseline the CPU oracle FMM on a bounded sample, host cores
+  adjoint      forward + backward throughput of the differentiable form
+               (N = 1e6, p = 8, leaf <= 64)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+P2P_FLOP_PER_PAIR = 19
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    return ap.parse_args()
+
+
+def timed_steps(step, steps, warmup, sync):
+    for _ in range(warmup):
+        step()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1106_2176_amd as fmm
+    from paper_1106_2176_amd import inputs
+
+    wl = inputs.WORKLOADS[args.workload]
+    pos_np, q_np = inputs.workload(args.workload)
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos_np).to(dev)
+    q = torch.from_numpy(q_np).to(dev)
+    sync = torch.cuda.synchronize
+    out = {}
+
+    def run_form(precision, steps, warmup):
+        tree = fmm.Tree(pos, p=wl.p, leaf_max=wl.leaf_max, precision=precision, profile=True)
+        phi = torch.empty_like(q)
+        E = torch.empty_like(pos)
+        stage_sum = {}
+        nrec = [0]
+
+        def step():
+            tree.rebuild(pos)
+            tree.evaluate(q, vec="field", phi=phi, out_vec=E)
+
+        def step_rec():
+            step()
+            st = tree.stage_times()
+            for k, v in st.items():
+                stage_sum[k] = stage_sum.get(k, 0.0) + v
+            nrec[0] += 1
+
+        sec = timed_steps(step, steps, warmup, sync)
+        # stage times over the same number of steps (events are recorded by
+        # the library around each stage on the evaluation stream)
+        for _ in range(steps):
+            step_rec()
+        info = tree.info()
+        stages = {k: v / nrec[0] for k, v in stage_sum.items()}
+        res = {"sec": sec, "stages_ms": stages, "info": info, "phi": phi.clone(), "E": E.clone()}
+        tree.close()
+        return res
+
+    mixed = run_form("mixed", args.steps, args.warmup)
+    info = mixed["info"]
+    n = wl.n
+    value = n / mixed["sec"]
+    p2p_ms = mixed["stages_ms"]["P2P"]
+    m2l_ms = mixed["stages_ms"]["M2L"]
+    pairs = info["p2p_pairs"]
+    m2l_pairs = info["m2l_pairs"]
+    p2p_tflops = P2P_FLOP_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
+    m2l_tflops = 2.0 * wl.p ** 4 * m2l_pairs / (m2l_ms * 1e-3) / 1e12
+    if p2p_ms >= m2l_ms:
+        roof = {"kernel": "k_p2p<float>", "bound": "alu", "achieved": p2p_tflops,
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": p2p_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": None}
+    else:
+        roof = {"kernel": "k_m2l_bf16", "bound": "mfma", "achieved": m2l_tflops,
+                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": m2l_tflops / PEAK_BF16_MFMA_TFLOPS, "traffic": None}
+
+    # accuracy on sampled targets vs the FP64 direct sum
+    t_idx = inputs.targets(n, wl.seed)
+    import oracle
+    phi_d, E_d = oracle.direct(pos_np, q_np, t_idx)
+
+    def errs(res):
+        ph = res["phi"].cpu().numpy()[t_idx]
+        Ef = res["E"].cpu().numpy()[t_idx]
+        qq = q_np[t_idx][:, None]
+        return {"phi": float(np.linalg.norm(ph - phi_d) / np.linalg.norm(phi_d)),
+                "F": float(np.linalg.norm(qq * (Ef - E_d)) / np.linalg.norm(qq * E_d))}
+
+    rel = {"mixed_vs_direct": errs(mixed)}
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_form("fp64", max(3, args.steps // 4), 1)
+        rel["fp64_vs_direct"] = errs(fp64)
+        a, b = mixed["phi"].cpu().numpy(), fp64["phi"].cpu().numpy()
+        Ea, Eb = mixed["E"].cpu().numpy(), fp64["E"].cpu().numpy()
+        qq = q_np[:, None]
+        rel["mixed_vs_fp64_all"] = {
+            "phi": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "F": float(np.linalg.norm(qq * (Ea - Eb)) / np.linalg.norm(qq * Eb))}
+
+    adj = None
+    if not args.no_adjoint:
+        w5 = inputs.WORKLOADS["C5"]
+        p5, q5 = inputs.workload("C5")
+        wv = torch.from_numpy(inputs.weights(w5.n, w5.seed)).to(dev)
+        P5 = torch.from_numpy(p5).to(dev)
+        Q5 = torch.from_numpy(q5).to(dev)
+        tree5 = fmm.Tree(P5, p=w5.p, leaf_max=w5.leaf_max, precision="mixed")
+
+        def fb():
+            tree5.rebuild(P5)
+            _, E5 = tree5.evaluate(Q5)
+            tree5.rebuild(P5)  # the tree is recomputed for the backward pass
+            tree5.backward(Q5, wv, E5)
+
+        s5 = timed_steps(fb, max(3, args.steps // 2), 2, sync)
+        tree5.close()
+        adj = {"workload": w5.describe() + ", loss sum w_i phi_i, w ~ N(0,1)",
+               "fwd_bwd_particles_per_s": w5.n / s5, "ms_per_step": s5 * 1e3}
+
+    cpu = None
+    if not args.no_cpu:
+        ns = args.cpu_sample
+        ps, qs = inputs.particles(ns, wl.seed, wl.charges, wl.dtype)
+        t0 = time.perf_counter()
+        oracle.fmm(ps.astype(np.float64), qs.astype(np.float64), wl.p, wl.leaf_max)
+        tc = time.perf_counter() - t0
+        cpu = {"value": ns / tc, "unit": "particles/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "FP64 Cartesian-Taylor oracle FMM on N=%d particles of the same "
+                         "distribution, p=%d, leaf<=%d (%.1f s)" % (ns, wl.p, wl.leaf_max, tc)}
+
+    line = {
+        "metric": "particles/s + P2P Ginteractions/s at 1e-6 rel-L2, mixed vs FP64 on 1 GPU",
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16(split)+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.describe(), "form": "mixed", "levels": info["levels"],
+                   "p2p_pairs": pairs, "m2l_pairs": m2l_pairs},
+        "p2p_gint_s": pairs / (p2p_ms * 1e-3) / 1e9,
+        "stages_ms": mixed["stages_ms"],
+        "roofline": roof,
+        "rel_l2": rel,
+        "cpu_baseline": cpu,
+        "adjoint": adj,
+    }
+    if fp64 is not None:
+        line["fp64"] = {"particles_per_s": n / fp64["sec"], "ms_per_step": fp64["sec"] * 1e3,
+                        "p2p_gint_s": pairs / (fp64["stages_ms"]["P2P"] * 1e-3) / 1e9,
+                        "stages_ms": fp64["stages_ms"]}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

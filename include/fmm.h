@@ -1,0 +1,220 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) Laplace fast multipole library.
+ *
+ * The library evaluates, for N charged particles in a cube, the 1/r potential
+ *     phi_i = sum_{j != i, x_j != x_i} q_j / |x_i - x_j|
+ * and the field E_i = -grad phi_i (or the force F_i = q_i E_i) with the fast
+ * multipole method of Yokota & Barba, arXiv:1106.2176: the problem statement
+ * of Sec. 2.1 (N sources of a 1/r potential, O(N) instead of O(N^2)), the
+ * operator sequence of Fig. 1 and Fig. 3 (P2M, M2M, M2L, L2L, L2P, and the
+ * near-field P2P of Sec. 3.1), expansions "truncated after p terms" (Sec. 2.1,
+ * read here as spherical-harmonic degrees 0..p-1, i.e. p^2 real coefficients
+ * per box), and a uniform octree whose leaves are Morton-indexed boxes at one
+ * prescribed level (Sec. 2.2 and the future-directions paragraph of Sec. 5).
+ *
+ * Conventions shared by every entry point:
+ *  - extern "C", plain pointers and sizes; no C++ types cross the ABI and no
+ *    exception escapes it.
+ *  - "device" pointers are HIP device memory on the current HIP device, owned
+ *    by the caller, which must keep them alive until the stream work that
+ *    uses them has completed.  "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    fmm_build_tree performs exactly one blocking stream synchronisation (it
+ *    reads the level-selection and validation counters); fmm_evaluate and
+ *    fmm_backward are asynchronous on `stream`.  A tree is used by one stream
+ *    at a time.
+ *  - Every call returns an fmm_status; after a non-OK status the outputs are
+ *    unspecified.  fmm_last_error_message() gives a thread-local description
+ *    of the most recent failure on the calling thread.
+ *  - Results are deterministic: no floating-point atomics are used, so two
+ *    calls with the same inputs and configuration give bitwise equal outputs.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_ABI_VERSION 1u
+#define FMM_P_MAX 16
+#define FMM_MAX_LEVEL 10
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_EINVAL = 1,       /* bad argument: n < 1, p outside [1, FMM_P_MAX], leaf_max < 1,
+                             box_size <= 0, max_level outside [0, FMM_MAX_LEVEL], NULL required
+                             pointer, unknown dtype/precision, ABI version mismatch */
+    FMM_EDOMAIN = 2,      /* a coordinate is not finite or lies outside [lo, lo + size] */
+    FMM_ENOMEM = 3,       /* the allocator returned NULL */
+    FMM_EDEVICE = 4,      /* a HIP launch, copy or synchronisation failed */
+    FMM_EUNSUPPORTED = 5  /* valid request this build does not implement */
+} fmm_status;
+
+typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
+
+typedef enum {
+    /* plain form: every step in FP64 (P2P, P2M/L2P, M2M/L2L, M2L on FP64 MFMA) */
+    FMM_PREC_FP64 = 0,
+    /* mixed form: P2P in FP32 on leaf-relative coordinates with FP64 merges,
+     * M2L as split-BF16 products on MFMA with FP32 accumulation merged into
+     * FP64, P2M/L2P and fine-level M2M/L2L in FP32, coarse-level (<= 4096
+     * boxes) M2M/L2L and the final far+near sum in FP64 */
+    FMM_PREC_MIXED = 1
+} fmm_precision;
+
+/* Allocator callbacks: return device memory of `bytes` usable in stream order
+ * on `stream`, or NULL on failure (reported as FMM_ENOMEM).  When `alloc` is
+ * NULL the library uses hipMallocAsync/hipFreeAsync on the call's stream. */
+typedef void *(*fmm_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*fmm_free_fn)(void *ptr, void *stream, void *ctx);
+
+typedef struct {
+    uint32_t abi_version;      /* must equal FMM_ABI_VERSION */
+    int32_t p;                 /* expansion order: harmonic degrees 0..p-1, 1 <= p <= 16 */
+    int32_t leaf_max;          /* leaf cap: the leaf level is the smallest level l <= max_level
+                                  whose fullest box holds <= leaf_max particles (max_level if
+                                  none does) */
+    int32_t max_level;         /* 0..10; keys are 3*level <= 30 bits */
+    int32_t precision;         /* fmm_precision */
+    int32_t bf16_splits;       /* mixed form only: 2 (hi+lo, 3 MFMA products) or
+                                  3 (hi+mid+lo, 6 products); 0 selects 2 */
+    double box_lo[3];          /* root cube corner */
+    double box_size;           /* root cube edge, > 0 */
+    fmm_alloc_fn alloc;        /* optional, see above */
+    fmm_free_fn free;
+    void *alloc_ctx;
+    int32_t profile;           /* nonzero: record HIP events around each stage of
+                                  fmm_evaluate (read with fmm_stage_times) */
+    int32_t reserved[7];       /* zero */
+} fmm_config;
+
+/* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
+ * precision, 2 splits, root cube [0,1)^3, library allocator, no profiling. */
+void fmm_config_default(fmm_config *cfg);
+
+typedef struct fmm_tree fmm_tree; /* opaque, library-owned */
+
+typedef struct {
+    int32_t levels;            /* leaf level L (the tree has levels 0..L) */
+    int32_t p;
+    int64_t n;
+    int64_t n_leaves;          /* 8^L */
+    int64_t max_leaf_count;    /* fullest leaf */
+    int64_t p2p_pairs;         /* ordered pairs (i, j), i != j, in each other's near field
+                                  (27-leaf neighbourhood), i.e. P2P interactions evaluated */
+    int64_t m2l_pairs;         /* (target box, source box) M2L translations over all levels */
+    size_t workspace_bytes;    /* device memory held by the tree */
+} fmm_tree_info_t;
+
+/*
+ * Build the octree for `n` particles (Sec. 2.1 hierarchical subdivision;
+ * Morton keys and the sorted start/offset particle layout of Sec. 5).
+ *   pos    device [n][3] row-major, in `dtype`; read during the call only
+ *          (everything the tree needs is copied into library memory).
+ *   out    receives the tree.  If *out is a tree previously built by this
+ *          library with the same p, precision and dtype, it is rebuilt in
+ *          place and its memory reused when large enough; otherwise *out
+ *          must be NULL and a new tree is created.
+ * Steps: Morton key per particle, leaf-occupancy histogram, level selection
+ * (one host synchronisation), exclusive scan of leaf counts, stable counting
+ * sort (ties keep input order) and a gather of leaf-relative coordinates.
+ * Errors: FMM_EINVAL, FMM_EDOMAIN (detected at the synchronisation; a
+ * coordinate equal to lo + size is clamped into the last box), FMM_ENOMEM,
+ * FMM_EDEVICE.  On error a newly created tree is destroyed and *out is left
+ * NULL; a tree passed in for reuse stays valid for fmm_tree_destroy only.
+ */
+fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const void *pos,
+                          void *stream, fmm_tree **out);
+
+#define FMM_VEC_NONE 0  /* no vector output */
+#define FMM_VEC_FIELD 1 /* vec = E_i = -grad phi at x_i */
+#define FMM_VEC_FORCE 2 /* vec = F_i = q_i E_i */
+/* optional part selection, OR-ed into flags (default: both parts) */
+#define FMM_PART_NEAR_ONLY 4 /* only the P2P (near-field) part */
+#define FMM_PART_FAR_ONLY 8  /* only the P2M..L2P (far-field) part */
+
+/*
+ * Evaluate potentials (and optionally fields or forces) for charges `q`
+ * (device [n] in the tree's dtype) at the tree's particles, in the caller's
+ * particle order: P2M, M2M (upward sweep), M2L at every level >= 2 (no
+ * barrier between levels, Sec. 5 "hierarchical synchronization"), L2L
+ * (downward sweep), L2P, P2P and the far + near sum (Fig. 1, Fig. 3).
+ *   phi  device [n] output (tree dtype), required.
+ *   vec  device [n][3] output (tree dtype), required unless the vector
+ *        kind (flags & 3) is FMM_VEC_NONE.
+ *   flags  vector kind (FMM_VEC_*) OR-ed with at most one FMM_PART_* bit,
+ *        which restricts the output to the near or far part (for per-part
+ *        verification; the work of the other part is skipped).
+ * Errors: FMM_EINVAL (NULL tree/q/phi, bad flags), FMM_ENOMEM, FMM_EDEVICE.
+ */
+fmm_status fmm_evaluate(fmm_tree *tree, const void *q, void *phi, void *vec, int32_t flags,
+                        void *stream);
+
+/*
+ * Gradient of the weighted-potential loss  Loss = sum_i w_i phi_i  of the
+ * FMM as computed by fmm_evaluate on the same tree and charges, with respect
+ * to the charges and positions.  Hand-written adjoint: the transposed
+ * operator chain L2P^T, L2L^T (upward), M2L^T, M2M^T (downward), P2M^T with
+ * its position derivative, plus P2P with charges w; leaf assignments are
+ * held fixed (they are piecewise constant in the positions).
+ *   q          device [n] charges used in the forward evaluation.
+ *   w          device [n] dLoss/dphi.
+ *   field_fwd  device [n][3] the field E (FMM_VEC_FIELD) of the forward
+ *              evaluation with charges q on this tree.
+ *   grad_q     device [n] output dLoss/dq, or NULL.
+ *   grad_pos   device [n][3] output dLoss/dx, or NULL.
+ *   grad_q_i   = psi_i + phi_w,i   (adjoint far potential + P2P potential of w)
+ *   grad_pos_i = -(w_i E_i + q_i E_w,i)
+ * All arrays are in the tree's dtype and the caller's particle order.
+ * Errors: FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE.
+ */
+fmm_status fmm_backward(fmm_tree *tree, const void *q, const void *w, const void *field_fwd,
+                        void *grad_q, void *grad_pos, void *stream);
+
+/* Sizes and work counts of a built tree (host struct, filled synchronously;
+ * pair counts are computed on the host from the leaf counts, which the
+ * library copies back at the end of fmm_build_tree). */
+fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
+
+/* Stage timings (milliseconds) of the most recent fmm_evaluate or
+ * fmm_backward on a tree built with cfg.profile != 0.  Synchronises the
+ * stream of that call.  Stages, in order:
+ *   0 gather   1 P2M   2 M2M   3 pack (M2L operand)   4 M2L   5 L2L
+ *   6 L2P      7 P2P   8 combine
+ * `ms` receives min(n_stages, 9) values.  FMM_EINVAL if profiling is off. */
+fmm_status fmm_stage_times(const fmm_tree *tree, double *ms, int32_t n_stages);
+
+/* Copy the tree's sorting results to host memory (any pointer may be NULL):
+ * perm[n] (sorted position -> input index, uint32), leaf_start[8^L + 1]
+ * (uint32, Morton leaf order).  Synchronous. */
+fmm_status fmm_tree_export(const fmm_tree *tree, uint32_t *perm, uint32_t *leaf_start);
+
+/* Release all device memory of the tree (stream ordered on the build stream).
+ * NULL is ignored. */
+void fmm_tree_destroy(fmm_tree *tree);
+
+/* Host-side translation operators in the library's real basis, FP64,
+ * row-major [rows][cols] with rows = cols = p^2 (host, synchronous, no GPU):
+ *   kind 0: M2M child -> parent, child octant `index` in 0..7 (bit 0 x, bit 1 y, bit 2 z)
+ *   kind 1: L2L parent -> child, child octant `index`
+ *   kind 2: M2L, offset index `index` = (ox+3) + 7 (oy+3) + 49 (oz+3), target minus source
+ *           in box widths, |o|_inf in 2..3
+ * Basis: multipole vector mu = sum_j q_j rho(u_j) and potential
+ * phi(x) = (1/w) ell . rho(u) with u = (x - c)/w, rho the real and imaginary
+ * parts of the regular solid harmonics R_n^m (m >= 0) defined by
+ * sum_{n,m} R_n^m(x) s^n t^m = exp(s (z + (x+iy)/(2t) - t (x-iy)/2)).
+ * `out` receives p^4 doubles.  For inspection and host tests. */
+fmm_status fmm_operator_host(int32_t p, int32_t kind, int32_t index, double *out);
+
+const char *fmm_status_string(fmm_status s);
+const char *fmm_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H */

@@ -1,0 +1,625 @@
+// api.cpp -- the C ABI (include/fmm.h): validation, memory, level selection,
+// operator tables and the order of kernel launches.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "opgen.hpp"
+
+using namespace fmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+fmm_status fail(fmm_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(FMM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+// ------------------------------------------------------------- allocation
+struct Alloc {
+    fmm_alloc_fn fa = nullptr;
+    fmm_free_fn ff = nullptr;
+    void *ctx = nullptr;
+};
+
+void ensure_pool(int dev) {
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> g(mu);
+    for (int d : done)
+        if (d == dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done.push_back(dev);
+}
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+// ------------------------------------------------------------ operators
+struct Ops {
+    int p = 0;
+    // [8][P2][P2] input-major transfer tables
+    double *up64 = nullptr, *down64 = nullptr, *aup64 = nullptr, *adown64 = nullptr;
+    float *up32 = nullptr, *down32 = nullptr, *aup32 = nullptr, *adown32 = nullptr;
+    // M2L tables [316][R][S]: FP64 and 3 bf16 parts, forward and adjoint
+    double *m2l64 = nullptr, *am2l64 = nullptr;
+    uint16_t *m2lbf = nullptr, *am2lbf = nullptr;
+    size_t bf_part = 0;  // elements per bf16 part
+    int2 *cls = nullptr; // [8][189] (packed source offset, table id)
+};
+
+std::mutex g_ops_mu;
+std::map<std::pair<int, int>, Ops *> g_ops;
+
+int id316_of(int dx, int dy, int dz) {
+    static int tab[343];
+    static bool init = false;
+    if (!init) {
+        int c = 0;
+        for (int i = 0; i < 343; ++i) {
+            const int ox = i % 7 - 3, oy = (i / 7) % 7 - 3, oz = i / 49 - 3;
+            const int m = std::max(std::abs(ox), std::max(std::abs(oy), std::abs(oz)));
+            tab[i] = m >= 2 ? c++ : -1;
+        }
+        init = true;
+    }
+    return tab[offset_id343(dx, dy, dz)];
+}
+
+fmm_status build_ops(int p, Ops **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_ops_mu);
+    auto it = g_ops.find({dev, p});
+    if (it != g_ops.end()) {
+        *out = it->second;
+        return FMM_OK;
+    }
+    const int P2 = p * p, R = m2l_rows(p), S = coef_stride(p);
+    Ops *o = new Ops();
+    o->p = p;
+    std::vector<double> mat((size_t)P2 * P2);
+    std::vector<double> up((size_t)8 * P2 * P2), down(up.size()), aup(up.size()), adown(up.size());
+    for (int c = 0; c < 8; ++c) {
+        op_m2m(p, c, mat.data());  // A_c [out][in]
+        for (int i = 0; i < P2; ++i)
+            for (int j = 0; j < P2; ++j) {
+                up[((size_t)c * P2 + j) * P2 + i] = mat[(size_t)i * P2 + j];     // [c][in][out]
+                adown[((size_t)c * P2 + i) * P2 + j] = mat[(size_t)i * P2 + j];  // A_c^T
+            }
+        op_l2l(p, c, mat.data());  // B_c [out][in]
+        for (int i = 0; i < P2; ++i)
+            for (int j = 0; j < P2; ++j) {
+                down[((size_t)c * P2 + j) * P2 + i] = mat[(size_t)i * P2 + j];
+                aup[((size_t)c * P2 + i) * P2 + j] = mat[(size_t)i * P2 + j];  // B_c^T
+            }
+    }
+    const size_t nT = (size_t)kNumOffsets * R * S;
+    std::vector<double> f64(nT, 0.0), af64(nT, 0.0);
+    std::vector<uint16_t> fbf(3 * nT, 0), afbf(3 * nT, 0);
+    for (int i = 0; i < 343; ++i) {
+        const int dx = i % 7 - 3, dy = (i / 7) % 7 - 3, dz = i / 49 - 3;
+        const int id = id316_of(dx, dy, dz);
+        if (id < 0) continue;
+        // forward: source at t + d, operator for offset (target - source) = -d
+        op_m2l(p, -dx, -dy, -dz, mat.data());
+        for (int r = 0; r < P2; ++r)
+            for (int c = 0; c < P2; ++c) f64[((size_t)id * R + r) * S + c] = mat[(size_t)r * P2 + c];
+        // adjoint: transpose of the operator for offset d
+        op_m2l(p, dx, dy, dz, mat.data());
+        for (int r = 0; r < P2; ++r)
+            for (int c = 0; c < P2; ++c) af64[((size_t)id * R + r) * S + c] = mat[(size_t)c * P2 + r];
+    }
+    for (size_t e = 0; e < nT; ++e) {
+        uint16_t pt[3];
+        split_bf16(f64[e], 3, pt);
+        for (int k = 0; k < 3; ++k) fbf[k * nT + e] = pt[k];
+        split_bf16(af64[e], 3, pt);
+        for (int k = 0; k < 3; ++k) afbf[k * nT + e] = pt[k];
+    }
+    std::vector<int2> cls((size_t)8 * kOffsetsPerClass);
+    for (int k = 0; k < 8; ++k) {
+        const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
+        int s = 0;
+        for (int dz = -2 - kz; dz <= 3 - kz; ++dz)
+            for (int dy = -2 - ky; dy <= 3 - ky; ++dy)
+                for (int dx = -2 - kx; dx <= 3 - kx; ++dx) {
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                    int2 e;
+                    e.x = (dx + 4) | ((dy + 4) << 4) | ((dz + 4) << 8);
+                    e.y = id316_of(dx, dy, dz);
+                    cls[(size_t)k * kOffsetsPerClass + s++] = e;
+                }
+    }
+    auto up32f = [](const std::vector<double> &v) {
+        std::vector<float> f(v.size());
+        for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+        return f;
+    };
+    auto upload = [](void **dst, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    const size_t tb = up.size();
+    hipError_t e = hipSuccess;
+    std::vector<float> t32;
+#define UP64(field, vec) \
+    if (e == hipSuccess) e = upload((void **)&o->field, vec.data(), vec.size() * sizeof(vec[0]));
+    UP64(up64, up) UP64(down64, down) UP64(aup64, aup) UP64(adown64, adown)
+    t32 = up32f(up); UP64(up32, t32)
+    t32 = up32f(down); UP64(down32, t32)
+    t32 = up32f(aup); UP64(aup32, t32)
+    t32 = up32f(adown); UP64(adown32, t32)
+    UP64(m2l64, f64) UP64(am2l64, af64) UP64(m2lbf, fbf) UP64(am2lbf, afbf) UP64(cls, cls)
+#undef UP64
+    (void)tb;
+    if (e != hipSuccess) return fail(FMM_EDEVICE, std::string("operator upload: ") + hipGetErrorString(e));
+    o->bf_part = nT;
+    g_ops[{dev, p}] = o;
+    *out = o;
+    return FMM_OK;
+}
+
+constexpr int kStages = 9;
+
+}  // namespace
+
+struct fmm_tree {
+    fmm_config cfg;
+    int dtype = FMM_F64;
+    int64_t n = 0;
+    int L = 0;
+    int64_t nleaf = 1;
+    int64_t max_count = 0;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    Alloc al;
+    Buf key10, cnt, start, fill, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs;
+    Buf M[FMM_MAX_LEVEL + 1], Lc[FMM_MAX_LEVEL + 1], pack[FMM_MAX_LEVEL + 1];
+    unsigned int *host_counters = nullptr;  // pinned [4]
+    Ops *ops = nullptr;
+    hipEvent_t ev[kStages + 1] = {};
+    bool ev_ready = false;
+    bool have_times = false;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+bool is_f64_form(const fmm_tree *t) { return t->cfg.precision == FMM_PREC_FP64; }
+
+// Storage precision of the coefficients of level l: FP64 in the plain form;
+// in the mixed form FP64 for coarse levels (<= 4096 boxes) except the leaf
+// level, whose multipoles and locals are produced and consumed by the FP32
+// P2M and L2P kernels together with the FP32 particle layout.
+int level_f64(const fmm_tree *t, int l) {
+    if (is_f64_form(t)) return 1;
+    return (l <= 4 && l != t->L) ? 1 : 0;
+}
+
+fmm_status ensure(fmm_tree *t, Buf &b, size_t bytes, hipStream_t st) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return FMM_OK;
+    if (b.p) {
+        if (t->al.fa)
+            t->al.ff(b.p, st, t->al.ctx);
+        else
+            (void)hipFreeAsync(b.p, st);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    void *p = nullptr;
+    if (t->al.fa) {
+        p = t->al.fa(bytes, st, t->al.ctx);
+        if (!p) return fail(FMM_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMallocAsync(&p, bytes, st);
+        if (e != hipSuccess || !p)
+            return fail(FMM_ENOMEM, "hipMallocAsync(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    b.p = p;
+    b.cap = bytes;
+    return FMM_OK;
+}
+
+void release(fmm_tree *t, Buf &b, hipStream_t st) {
+    if (!b.p) return;
+    if (t->al.fa)
+        t->al.ff(b.p, st, t->al.ctx);
+    else
+        (void)hipFreeAsync(b.p, st);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+fmm_status validate_cfg(const fmm_config *c) {
+    if (!c) return fail(FMM_EINVAL, "config is NULL");
+    if (c->abi_version != FMM_ABI_VERSION) return fail(FMM_EINVAL, "ABI version mismatch");
+    if (c->p < 1 || c->p > FMM_P_MAX) return fail(FMM_EINVAL, "p must be in [1, 16]");
+    if (c->leaf_max < 1) return fail(FMM_EINVAL, "leaf_max must be >= 1");
+    if (c->max_level < 0 || c->max_level > FMM_MAX_LEVEL) return fail(FMM_EINVAL, "max_level must be in [0, 10]");
+    if (c->precision != FMM_PREC_FP64 && c->precision != FMM_PREC_MIXED)
+        return fail(FMM_EINVAL, "unknown precision");
+    if (c->bf16_splits != 0 && c->bf16_splits != 2 && c->bf16_splits != 3)
+        return fail(FMM_EINVAL, "bf16_splits must be 0, 2 or 3");
+    if (!(c->box_size > 0.0) || !std::isfinite(c->box_size)) return fail(FMM_EINVAL, "box_size must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c->box_lo[a])) return fail(FMM_EINVAL, "box_lo must be finite");
+    if ((c->alloc == nullptr) != (c->free == nullptr))
+        return fail(FMM_EINVAL, "alloc and free callbacks must be given together");
+    return FMM_OK;
+}
+
+fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
+    if (!t->cfg.profile) return FMM_OK;
+    if (!t->ev_ready) {
+        for (int i = 0; i <= kStages; ++i) HIPCHK(hipEventCreate(&t->ev[i]));
+        t->ev_ready = true;
+    }
+    HIPCHK(hipEventRecord(t->ev[stage], st));
+    return FMM_OK;
+}
+
+#define CHK(x)                           \
+    do {                                 \
+        fmm_status s_ = (x);             \
+        if (s_ != FMM_OK) return s_;     \
+    } while (0)
+
+// The far + near chain shared by the forward evaluation and the adjoint.
+fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far, bool do_near,
+                     hipStream_t st) {
+    const int P = t->cfg.p, S = coef_stride(P), L = t->L;
+    const bool f64 = is_f64_form(t);
+    void *src = f64 ? t->xyz64.p : t->xyz32.p;
+    const uint32_t *start = (const uint32_t *)t->start.p;
+    const int nsplit = t->cfg.bf16_splits == 3 ? 3 : 2;
+    t->have_times = false;
+    t->last_stream = st;
+
+    // guards: every buffer a kernel will touch holds what that kernel assumes
+    const size_t src_bytes = (f64 ? sizeof(double4) : sizeof(float4)) * (size_t)t->n;
+    if ((f64 ? t->xyz64.cap : t->xyz32.cap) < src_bytes || !src)
+        return fail(FMM_EDEVICE, "internal: particle buffer does not match the form");
+    if (t->start.cap < sizeof(uint32_t) * (size_t)(t->nleaf + 1) || t->perm.cap < sizeof(uint32_t) * (size_t)t->n)
+        return fail(FMM_EDEVICE, "internal: tree buffers too small");
+    if (L >= 2 && level_f64(t, L) != (int)f64)
+        return fail(FMM_EDEVICE, "internal: leaf-level precision differs from the particle precision");
+    CHK(rec(t, 0, st));
+    HIPCHK(launch_gather_q(t->n, t->dtype, f64, (const uint32_t *)t->perm.p, charges, src, st));
+    CHK(ensure(t, t->nearf, sizeof(double4) * (size_t)t->n, st));
+    if (L >= 2 && do_far) {
+        if (!t->ops) CHK(build_ops(P, &t->ops));
+        const Ops *o = t->ops;
+        CHK(ensure(t, t->farf, sizeof(double4) * (size_t)t->n, st));
+        for (int l = 2; l <= L; ++l) {
+            const size_t nb = (size_t)1 << (3 * l);
+            const size_t es = level_f64(t, l) ? 8 : 4;
+            CHK(ensure(t, t->M[l], nb * S * es, st));
+            CHK(ensure(t, t->Lc[l], nb * S * es, st));
+            const size_t g = ((size_t)1 << l) + 6;
+            const size_t pk = f64 ? g * g * g * S * 8 : g * g * g * S * 2 * nsplit;
+            CHK(ensure(t, t->pack[l], pk, st));
+        }
+        CHK(rec(t, 1, st));
+        // P2M at the leaves (for the adjoint: L2P^T, the same sum with w)
+        HIPCHK(launch_p2m(P, L, f64, src, start, t->M[L].p, 1.0, st));
+        CHK(rec(t, 2, st));
+        // upward sweep (adjoint: L2L^T)
+        for (int l = L - 1; l >= 2; --l)
+            HIPCHK(launch_transfer(true, P, l, level_f64(t, l + 1), level_f64(t, l), t->M[l + 1].p,
+                                   t->M[l].p, adjoint ? o->aup32 : o->up32,
+                                   adjoint ? o->aup64 : o->up64, st));
+        CHK(rec(t, 3, st));
+        for (int l = 2; l <= L; ++l) {
+            const size_t g = ((size_t)1 << l) + 6;
+            HIPCHK(launch_pack(P, l, level_f64(t, l), f64 ? 0 : nsplit, t->M[l].p, t->pack[l].p,
+                               g * g * g * S, st));
+        }
+        CHK(rec(t, 4, st));
+        // M2L at every level >= 2 (levels are independent)
+        for (int l = 2; l <= L; ++l) {
+            const size_t g = ((size_t)1 << l) + 6;
+            if (f64)
+                HIPCHK(launch_m2l_f64(P, l, (const double *)t->pack[l].p,
+                                      adjoint ? o->am2l64 : o->m2l64, o->cls, (double *)t->Lc[l].p,
+                                      st));
+            else
+                HIPCHK(launch_m2l_bf16(P, l, nsplit, (const uint16_t *)t->pack[l].p, g * g * g * S,
+                                       adjoint ? o->am2lbf : o->m2lbf, o->bf_part, o->cls,
+                                       t->Lc[l].p, level_f64(t, l), st));
+        }
+        CHK(rec(t, 5, st));
+        // downward sweep (adjoint: M2M^T)
+        for (int l = 2; l < L; ++l)
+            HIPCHK(launch_transfer(false, P, l, level_f64(t, l), level_f64(t, l + 1), t->Lc[l].p,
+                                   t->Lc[l + 1].p, adjoint ? o->adown32 : o->down32,
+                                   adjoint ? o->adown64 : o->down64, st));
+        CHK(rec(t, 6, st));
+        // L2P (adjoint: P2M^T with its position derivative)
+        // leaf-level coefficients share the particle precision (level_f64)
+        HIPCHK(launch_l2p(P, L, f64, src, start, t->Lc[L].p, (double4 *)t->farf.p, st));
+    } else {
+        for (int s = 1; s <= 6; ++s) CHK(rec(t, s, st));
+    }
+    CHK(rec(t, 7, st));
+    if (do_near) HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, st));
+    else HIPCHK(hipMemsetAsync(t->nearf.p, 0, sizeof(double4) * (size_t)t->n, st));
+    CHK(rec(t, 8, st));
+    return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fmm_config_default(fmm_config *c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->abi_version = FMM_ABI_VERSION;
+    c->p = 8;
+    c->leaf_max = 64;
+    c->max_level = FMM_MAX_LEVEL;
+    c->precision = FMM_PREC_MIXED;
+    c->bf16_splits = 2;
+    c->box_size = 1.0;
+}
+
+const char *fmm_status_string(fmm_status s) {
+    switch (s) {
+        case FMM_OK: return "ok";
+        case FMM_EINVAL: return "invalid argument";
+        case FMM_EDOMAIN: return "position outside the domain or not finite";
+        case FMM_ENOMEM: return "out of device memory";
+        case FMM_EDEVICE: return "HIP device error";
+        case FMM_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *fmm_last_error_message(void) { return g_err.c_str(); }
+
+fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const void *pos,
+                          void *stream, fmm_tree **out) {
+    CHK(validate_cfg(cfg));
+    if (n < 1) return fail(FMM_EINVAL, "n must be >= 1");
+    if (n >= ((int64_t)1 << 31)) return fail(FMM_EINVAL, "n must be < 2^31");
+    if (dtype != FMM_F32 && dtype != FMM_F64) return fail(FMM_EINVAL, "unknown dtype");
+    if (!pos) return fail(FMM_EINVAL, "pos is NULL");
+    if (!out) return fail(FMM_EINVAL, "out is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    fmm_tree *t = *out;
+    const bool fresh = (t == nullptr);
+    if (fresh) {
+        t = new (std::nothrow) fmm_tree();
+        if (!t) return fail(FMM_ENOMEM, "host allocation failed");
+    }
+    auto bail = [&](fmm_status s) {
+        if (fresh) {
+            fmm_tree_destroy(t);
+            *out = nullptr;
+        }
+        return s;
+    };
+    t->cfg = *cfg;
+    t->dtype = dtype;
+    t->n = n;
+    t->stream = st;
+    t->al.fa = cfg->alloc;
+    t->al.ff = cfg->free;
+    t->al.ctx = cfg->alloc_ctx;
+    t->have_times = false;
+    if (hipGetDevice(&t->dev) != hipSuccess) return bail(fail(FMM_EDEVICE, "hipGetDevice failed"));
+    if (!t->al.fa) ensure_pool(t->dev);
+    if (!t->host_counters) {
+        if (hipHostMalloc((void **)&t->host_counters, 4 * sizeof(unsigned int)) != hipSuccess)
+            return bail(fail(FMM_EDEVICE, "hipHostMalloc failed"));
+    }
+    fmm_status s;
+    if ((s = ensure(t, t->key10, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->counters, 4 * sizeof(unsigned int), st)) != FMM_OK) return bail(s);
+    unsigned int *dc = (unsigned int *)t->counters.p;
+    hipError_t e = hipMemsetAsync(dc, 0, 4 * sizeof(unsigned int), st);
+    if (e == hipSuccess) e = launch_keys(n, dtype, pos, cfg->box_lo, cfg->box_size, (uint32_t *)t->key10.p, dc, st);
+    if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("key kernel: ") + hipGetErrorString(e)));
+    // S1: smallest level whose fullest leaf holds <= leaf_max; the coarsest
+    // candidate is the first level with 8^l * leaf_max >= n (fewer boxes
+    // cannot hold n particles under the cap)
+    int lev = 0;
+    while (lev < cfg->max_level && ((int64_t)1 << (3 * lev)) * (int64_t)cfg->leaf_max < n) ++lev;
+    for (;;) {
+        const size_t nb = (size_t)1 << (3 * lev);
+        if ((s = ensure(t, t->cnt, sizeof(uint32_t) * nb, st)) != FMM_OK) return bail(s);
+        e = launch_hist(n, (const uint32_t *)t->key10.p, lev, (uint32_t *)t->cnt.p, dc + 1, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(t->host_counters, dc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("level selection: ") + hipGetErrorString(e)));
+        if (t->host_counters[0] != 0)
+            return bail(fail(FMM_EDOMAIN, std::to_string(t->host_counters[0]) +
+                                              " positions outside the root cube or not finite"));
+        t->max_count = t->host_counters[1];
+        if (t->max_count <= cfg->leaf_max || lev >= cfg->max_level) break;
+        ++lev;
+    }
+    t->L = lev;
+    t->nleaf = (int64_t)1 << (3 * lev);
+    const size_t nb = (size_t)t->nleaf;
+    const bool f64 = is_f64_form(t);
+    if ((s = ensure(t, t->start, sizeof(uint32_t) * (nb + 1), st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->scan, sizeof(uint32_t) * scan_scratch_words(nb), st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->fill, sizeof(uint32_t) * nb, st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->tmp, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->perm, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
+    if (f64) {
+        if ((s = ensure(t, t->xyz64, sizeof(double4) * n, st)) != FMM_OK) return bail(s);
+    } else {
+        if ((s = ensure(t, t->xyz32, sizeof(float4) * n, st)) != FMM_OK) return bail(s);
+    }
+    e = launch_scan((int64_t)nb, (const uint32_t *)t->cnt.p, (uint32_t *)t->start.p, (uint32_t *)t->scan.p, st);
+    if (e == hipSuccess)
+        e = launch_sort(n, lev, (const uint32_t *)t->key10.p, (const uint32_t *)t->start.p,
+                        (uint32_t *)t->fill.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
+                        cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (float4 *)t->xyz32.p,
+                        f64 ? (double4 *)t->xyz64.p : nullptr, st);
+    if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("sort: ") + hipGetErrorString(e)));
+    *out = t;
+    return FMM_OK;
+}
+
+fmm_status fmm_evaluate(fmm_tree *t, const void *q, void *phi, void *vec, int32_t flags,
+                        void *stream) {
+    if (!t || !q || !phi) return fail(FMM_EINVAL, "tree, q and phi are required");
+    const int kind = flags & 3, part = flags & ~3;
+    if (kind == 3 || (part != 0 && part != FMM_PART_NEAR_ONLY && part != FMM_PART_FAR_ONLY))
+        return fail(FMM_EINVAL, "unknown flags");
+    if (kind != FMM_VEC_NONE && !vec) return fail(FMM_EINVAL, "vec is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
+    CHK(run_chain(t, q, false, do_far, do_near, st));
+    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
+    HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, (const double4 *)t->nearf.p,
+                          (t->L >= 2 && do_far) ? (const double4 *)t->farf.p : nullptr, inv_w, q, phi,
+                          vec, kind, st));
+    CHK(rec(t, kStages, st));
+    t->have_times = t->cfg.profile != 0;
+    return FMM_OK;
+}
+
+fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *field_fwd,
+                        void *grad_q, void *grad_pos, void *stream) {
+    if (!t || !q || !w) return fail(FMM_EINVAL, "tree, q and w are required");
+    if (grad_pos && !field_fwd) return fail(FMM_EINVAL, "field_fwd is required for grad_pos");
+    if (!grad_q && !grad_pos) return FMM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    CHK(run_chain(t, w, true, true, true, st));
+    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
+    HIPCHK(launch_combine_grad(t->n, t->dtype, (const uint32_t *)t->perm.p,
+                               (const double4 *)t->nearf.p,
+                               t->L >= 2 ? (const double4 *)t->farf.p : nullptr, inv_w, q, w,
+                               field_fwd, grad_q, grad_pos, st));
+    CHK(rec(t, kStages, st));
+    t->have_times = t->cfg.profile != 0;
+    return FMM_OK;
+}
+
+fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
+    if (!tc || !info) return fail(FMM_EINVAL, "tree and info are required");
+    fmm_tree *t = const_cast<fmm_tree *>(tc);
+    std::memset(info, 0, sizeof(*info));
+    info->levels = t->L;
+    info->p = t->cfg.p;
+    info->n = t->n;
+    info->n_leaves = t->nleaf;
+    info->max_leaf_count = t->max_count;
+    CHK(ensure(t, t->pairs, sizeof(unsigned long long), t->stream));
+    HIPCHK(launch_pair_count(t->L, (const uint32_t *)t->start.p, (unsigned long long *)t->pairs.p, t->stream));
+    unsigned long long pairs = 0;
+    HIPCHK(hipMemcpyAsync(&pairs, t->pairs.p, sizeof(pairs), hipMemcpyDeviceToHost, t->stream));
+    HIPCHK(hipStreamSynchronize(t->stream));
+    info->p2p_pairs = (int64_t)pairs - t->n;
+    // M2L pairs: per axis the count factorises; sum over targets of
+    // (children of in-domain parent neighbours) - (in-domain near boxes)
+    int64_t m2l = 0;
+    for (int l = 2; l <= t->L; ++l) {
+        const int64_t n = (int64_t)1 << l, h = n / 2;
+        int64_t sc = 0, sm = 0;
+        for (int64_t x = 0; x < n; ++x) {
+            const int64_t pp = x / 2;
+            sc += 2 * ((pp - 1 >= 0) + 1 + (pp + 1 < h));
+            sm += (x - 1 >= 0) + 1 + (x + 1 < n);
+        }
+        m2l += sc * sc * sc - sm * sm * sm;
+    }
+    info->m2l_pairs = m2l;
+    size_t ws = 0;
+    const Buf *bufs[] = {&t->key10, &t->cnt, &t->start, &t->fill, &t->tmp, &t->perm, &t->scan,
+                         &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs};
+    for (const Buf *b : bufs) ws += b->cap;
+    for (int l = 0; l <= FMM_MAX_LEVEL; ++l) ws += t->M[l].cap + t->Lc[l].cap + t->pack[l].cap;
+    info->workspace_bytes = ws;
+    return FMM_OK;
+}
+
+fmm_status fmm_stage_times(const fmm_tree *t, double *ms, int32_t n_stages) {
+    if (!t || !ms) return fail(FMM_EINVAL, "tree and ms are required");
+    if (!t->cfg.profile || !t->have_times) return fail(FMM_EINVAL, "profiling is off or nothing was recorded");
+    HIPCHK(hipEventSynchronize(t->ev[kStages]));
+    for (int i = 0; i < std::min<int>(n_stages, kStages); ++i) {
+        float f = 0.f;
+        HIPCHK(hipEventElapsedTime(&f, t->ev[i], t->ev[i + 1]));
+        ms[i] = f;
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_tree_export(const fmm_tree *t, uint32_t *perm, uint32_t *leaf_start) {
+    if (!t) return fail(FMM_EINVAL, "tree is NULL");
+    if (perm) HIPCHK(hipMemcpyAsync(perm, t->perm.p, sizeof(uint32_t) * t->n, hipMemcpyDeviceToHost, t->stream));
+    if (leaf_start)
+        HIPCHK(hipMemcpyAsync(leaf_start, t->start.p, sizeof(uint32_t) * (t->nleaf + 1),
+                              hipMemcpyDeviceToHost, t->stream));
+    HIPCHK(hipStreamSynchronize(t->stream));
+    return FMM_OK;
+}
+
+void fmm_tree_destroy(fmm_tree *t) {
+    if (!t) return;
+    hipStream_t st = t->stream;
+    Buf *bufs[] = {&t->key10, &t->cnt, &t->start, &t->fill, &t->tmp, &t->perm, &t->scan,
+                   &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs};
+    for (Buf *b : bufs) release(t, *b, st);
+    for (int l = 0; l <= FMM_MAX_LEVEL; ++l) {
+        release(t, t->M[l], st);
+        release(t, t->Lc[l], st);
+        release(t, t->pack[l], st);
+    }
+    if (t->ev_ready)
+        for (int i = 0; i <= kStages; ++i) (void)hipEventDestroy(t->ev[i]);
+    if (t->host_counters) (void)hipHostFree(t->host_counters);
+    delete t;
+}
+
+fmm_status fmm_operator_host(int32_t p, int32_t kind, int32_t index, double *out) {
+    if (p < 1 || p > FMM_P_MAX || !out) return fail(FMM_EINVAL, "bad p or NULL output");
+    if (kind == 0 || kind == 1) {
+        if (index < 0 || index > 7) return fail(FMM_EINVAL, "octant must be in 0..7");
+        if (kind == 0)
+            op_m2m(p, index, out);
+        else
+            op_l2l(p, index, out);
+        return FMM_OK;
+    }
+    if (kind == 2) {
+        if (index < 0 || index >= 343) return fail(FMM_EINVAL, "offset index out of range");
+        const int ox = index % 7 - 3, oy = (index / 7) % 7 - 3, oz = index / 49 - 3;
+        if (std::max(std::abs(ox), std::max(std::abs(oy), std::abs(oz))) < 2)
+            return fail(FMM_EINVAL, "M2L offsets need |o|_inf >= 2");
+        op_m2l(p, ox, oy, oz, out);
+        return FMM_OK;
+    }
+    return fail(FMM_EINVAL, "unknown operator kind");
+}
+
+}  // extern "C"

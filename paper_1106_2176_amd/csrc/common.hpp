@@ -1,0 +1,108 @@
+// common.hpp -- shared definitions of the gfx950 FMM library (device and host).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+// ---------------------------------------------------------------- layout
+// Real coefficient vectors of length p^2 per box.  Degree n occupies slots
+// n^2 .. n^2+2n: slot n^2 holds the m = 0 term, slots n^2+2m-1 and n^2+2m the
+// cosine-like (real) and sine-like (imaginary) parts of order m = 1..n.
+__host__ __device__ constexpr int cidx(int n, int m) { return n * n + (m == 0 ? 0 : 2 * m - 1); }
+
+// Coefficient stride of a box in device arrays: p^2 rounded up to 8, so that
+// an 8-wide bf16 MFMA operand piece never straddles two boxes.
+__host__ __device__ constexpr int coef_stride(int p) { return (p * p + 7) & ~7; }
+// Rows of an M2L operator: p^2 rounded up to the 16-row MFMA tile.
+__host__ __device__ constexpr int m2l_rows(int p) { return (p * p + 15) & ~15; }
+
+// Number of M2L offsets o in {-3..3}^3 with |o|_inf >= 2, and the ones a
+// target of child class k (bit 0 x, 1 y, 2 z) interacts with: per axis the
+// components -2-k_a .. 3-k_a, minus the 27 near offsets: 6^3 - 27 = 189.
+constexpr int kNumOffsets = 316;
+constexpr int kOffsetsPerClass = 189;
+
+__host__ __device__ inline int offset_id343(int ox, int oy, int oz) {
+    return (ox + 3) + 7 * ((oy + 3) + 7 * (oz + 3));
+}
+
+// ---------------------------------------------------------------- Morton
+// Key bit 3b is bit b of the x box coordinate, 3b+1 of y, 3b+2 of z.
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v) {
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x3ffu;
+    return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// ------------------------------------------------------- solid harmonics
+// Regular solid harmonics R_n^m, the coefficients of the generating function
+//   sum_{n,m} R_n^m(x) s^n t^m = exp(s (z + (x+iy)/(2t) - t (x-iy)/2)),
+// so that R_n^m(a+b) = sum R_k^l(a) R_{n-k}^{m-l}(b) and
+// 1/|x-y| = sum_{n,m} R_n^m(y) I_n^m(x) with I_n^m the irregular harmonics
+// below.  For m >= 0:
+//   R_0^0 = 1,  R_m^m = -(x - iy)/(2m) R_{m-1}^{m-1},  R_{m+1}^m = z R_m^m,
+//   (n-m)(n+m) R_n^m = (2n-1) z R_{n-1}^m - r^2 R_{n-2}^m,
+// and R_n^{-m} = (-1)^m conj(R_n^m).
+// Writes the real vector rho (slots as cidx) for degrees 0..P-1.
+template <typename T>
+__host__ __device__ inline void regular_rho(int P, T x, T y, T z, T *rho) {
+    const T r2 = x * x + y * y + z * z;
+    T dr = T(1), di = T(0);
+    for (int m = 0; m < P; ++m) {
+        if (m > 0) {
+            const T inv = T(-1) / T(2 * m);
+            const T nr = (dr * x + di * y) * inv;
+            const T ni = (di * x - dr * y) * inv;
+            dr = nr;
+            di = ni;
+        }
+        T ar = dr, ai = di;       // R_{m}^m
+        T br = T(0), bi = T(0);   // R_{m-1}^m (= 0)
+        for (int n = m; n < P; ++n) {
+            T cr, ci;
+            if (n == m) {
+                cr = ar;
+                ci = ai;
+            } else if (n == m + 1) {
+                cr = z * ar;
+                ci = z * ai;
+            } else {
+                const T inv = T(1) / T((n - m) * (n + m));
+                cr = (T(2 * n - 1) * z * ar - r2 * br) * inv;
+                ci = (T(2 * n - 1) * z * ai - r2 * bi) * inv;
+            }
+            if (n > m) {
+                br = ar;
+                bi = ai;
+                ar = cr;
+                ai = ci;
+            }
+            if (m == 0) {
+                rho[n * n] = cr;
+            } else {
+                rho[n * n + 2 * m - 1] = cr;
+                rho[n * n + 2 * m] = ci;
+            }
+        }
+    }
+}
+
+}  // namespace fmm

@@ -1,0 +1,53 @@
+// kernels.hpp -- launchers of the device kernels (all asynchronous on `st`).
+#pragma once
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace fmm {
+
+// tree.hip
+hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3], double size,
+                       uint32_t *key10, unsigned int *nbad, hipStream_t st);
+hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt,
+                       unsigned int *mx, hipStream_t st);
+int64_t scan_scratch_words(int64_t nb);
+hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
+                       hipStream_t st);
+hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *start,
+                       uint32_t *fill, uint32_t *tmp, int dtype, const void *pos,
+                       const double lo[3], double size, uint32_t *perm, float4 *xyz32,
+                       double4 *xyz64, hipStream_t st);
+hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long long *out,
+                             hipStream_t st);
+
+// p2p.hip
+hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, double4 *out,
+                      hipStream_t st);
+
+// far.hip
+hipError_t launch_p2m(int P, int L, bool f64, const void *src, const uint32_t *start, void *M,
+                      double scale, hipStream_t st);
+hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *start,
+                      const void *Lc, double4 *out, hipStream_t st);
+hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
+                           void *out, const void *tab32, const void *tab64, hipStream_t st);
+hipError_t launch_pack(int P, int l, bool in_f64, int parts, const void *in, void *out,
+                       size_t part_stride, hipStream_t st);
+hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm, const void *q,
+                           void *xyzq, hipStream_t st);
+hipError_t launch_combine(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
+                          const double4 *farf, double inv_w, const void *q, void *phi, void *vec,
+                          int flags, hipStream_t st);
+hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
+                               const double4 *farf, double inv_w, const void *q, const void *w,
+                               const void *Eq, void *gq, void *gx, hipStream_t st);
+
+// m2l.hip
+hipError_t launch_m2l_bf16(int P, int l, int nsplit, const uint16_t *B, size_t bstride,
+                           const uint16_t *A, size_t astride, const int2 *cls, void *Lout,
+                           int out_f64, hipStream_t st);
+hipError_t launch_m2l_f64(int P, int l, const double *B, const double *A, const int2 *cls,
+                          double *Lout, hipStream_t st);
+
+}  // namespace fmm

