@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--splits", type=int, default=3, help="bf16 parts of the mixed M2L (2 or 3)")
     return ap.parse_args()
 
 
@@ -77,7 +78,8 @@ def main():
     out = {}
 
     def run_form(precision, steps, warmup):
-        tree = fmm.Tree(pos, p=wl.p, leaf_max=wl.leaf_max, precision=precision, profile=True)
+        tree = fmm.Tree(pos, p=wl.p, leaf_max=wl.leaf_max, precision=precision, profile=True,
+                        bf16_splits=args.splits)
         phi = torch.empty_like(q)
         E = torch.empty_like(pos)
         stage_sum = {}
@@ -193,7 +195,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+bf16(split)+f64",
         "data": "synthetic",
-        "config": {"workload": wl.describe(), "form": "mixed", "levels": info["levels"],
+        "config": {"workload": wl.describe(), "form": "mixed", "bf16_splits": args.splits,
+                   "levels": info["levels"],
                    "p2p_pairs": pairs, "m2l_pairs": m2l_pairs},
         "p2p_gint_s": pairs / (p2p_ms * 1e-3) / 1e9,
         "stages_ms": mixed["stages_ms"],

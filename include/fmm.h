@@ -81,7 +81,7 @@ typedef struct {
     int32_t max_level;         /* 0..10; keys are 3*level <= 30 bits */
     int32_t precision;         /* fmm_precision */
     int32_t bf16_splits;       /* mixed form only: 2 (hi+lo, 3 MFMA products) or
-                                  3 (hi+mid+lo, 6 products); 0 selects 2 */
+                                  3 (hi+mid+lo, 6 products); 0 selects 3 */
     double box_lo[3];          /* root cube corner */
     double box_size;           /* root cube edge, > 0 */
     fmm_alloc_fn alloc;        /* optional, see above */
@@ -93,7 +93,8 @@ typedef struct {
 } fmm_config;
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
- * precision, 2 splits, root cube [0,1)^3, library allocator, no profiling. */
+ * precision, 3 bf16 splits, root cube [0,1)^3, library allocator, no
+ * profiling. */
 void fmm_config_default(fmm_config *cfg);
 
 typedef struct fmm_tree fmm_tree; /* opaque, library-owned */

@@ -112,7 +112,7 @@ def _check(rc):
         raise FMMError(rc, msg.decode() if msg else "")
 
 
-def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=2,
+def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False):
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
@@ -173,7 +173,7 @@ def _check_tensor(t, name, shape, dtype):
 class Tree:
     """An octree built on the GPU; owns library memory until close()."""
 
-    def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=2,
+    def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                  box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,

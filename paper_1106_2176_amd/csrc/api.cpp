@@ -62,10 +62,10 @@ struct Ops {
     // [8][P2][P2] input-major transfer tables
     double *up64 = nullptr, *down64 = nullptr, *aup64 = nullptr, *adown64 = nullptr;
     float *up32 = nullptr, *down32 = nullptr, *aup32 = nullptr, *adown32 = nullptr;
-    // M2L tables [316][R][S]: FP64 and 3 bf16 parts, forward and adjoint
+    // M2L tables [316][R][S]: FP64 and FP32 (split into bf16 parts on the fly
+    // by the mixed kernel), forward and adjoint
     double *m2l64 = nullptr, *am2l64 = nullptr;
-    uint16_t *m2lbf = nullptr, *am2lbf = nullptr;
-    size_t bf_part = 0;  // elements per bf16 part
+    float *m2l32 = nullptr, *am2l32 = nullptr;
     int2 *cls = nullptr; // [8][189] (packed source offset, table id)
 };
 
@@ -115,9 +115,10 @@ fmm_status build_ops(int p, Ops **out) {
                 aup[((size_t)c * P2 + i) * P2 + j] = mat[(size_t)i * P2 + j];  // B_c^T
             }
     }
-    const size_t nT = (size_t)kNumOffsets * R * S;
+    // 316 operators plus one all-zero operator (id 316) that kernels read
+    // for K pieces past the end of a class's list
+    const size_t nT = (size_t)(kNumOffsets + 1) * R * S;
     std::vector<double> f64(nT, 0.0), af64(nT, 0.0);
-    std::vector<uint16_t> fbf(3 * nT, 0), afbf(3 * nT, 0);
     for (int i = 0; i < 343; ++i) {
         const int dx = i % 7 - 3, dy = (i / 7) % 7 - 3, dz = i / 49 - 3;
         const int id = id316_of(dx, dy, dz);
@@ -130,13 +131,6 @@ fmm_status build_ops(int p, Ops **out) {
         op_m2l(p, dx, dy, dz, mat.data());
         for (int r = 0; r < P2; ++r)
             for (int c = 0; c < P2; ++c) af64[((size_t)id * R + r) * S + c] = mat[(size_t)c * P2 + r];
-    }
-    for (size_t e = 0; e < nT; ++e) {
-        uint16_t pt[3];
-        split_bf16(f64[e], 3, pt);
-        for (int k = 0; k < 3; ++k) fbf[k * nT + e] = pt[k];
-        split_bf16(af64[e], 3, pt);
-        for (int k = 0; k < 3; ++k) afbf[k * nT + e] = pt[k];
     }
     std::vector<int2> cls((size_t)8 * kOffsetsPerClass);
     for (int k = 0; k < 8; ++k) {
@@ -172,11 +166,13 @@ fmm_status build_ops(int p, Ops **out) {
     t32 = up32f(down); UP64(down32, t32)
     t32 = up32f(aup); UP64(aup32, t32)
     t32 = up32f(adown); UP64(adown32, t32)
-    UP64(m2l64, f64) UP64(am2l64, af64) UP64(m2lbf, fbf) UP64(am2lbf, afbf) UP64(cls, cls)
+    UP64(m2l64, f64) UP64(am2l64, af64)
+    t32 = up32f(f64); UP64(m2l32, t32)
+    t32 = up32f(af64); UP64(am2l32, t32)
+    UP64(cls, cls)
 #undef UP64
     (void)tb;
     if (e != hipSuccess) return fail(FMM_EDEVICE, std::string("operator upload: ") + hipGetErrorString(e));
-    o->bf_part = nT;
     g_ops[{dev, p}] = o;
     *out = o;
     return FMM_OK;
@@ -295,12 +291,12 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     const bool f64 = is_f64_form(t);
     void *src = f64 ? t->xyz64.p : t->xyz32.p;
     const uint32_t *start = (const uint32_t *)t->start.p;
-    const int nsplit = t->cfg.bf16_splits == 3 ? 3 : 2;
+    const int nsplit = t->cfg.bf16_splits == 2 ? 2 : 3;
     t->have_times = false;
     t->last_stream = st;
 
     // guards: every buffer a kernel will touch holds what that kernel assumes
-    const size_t src_bytes = (f64 ? sizeof(double4) : sizeof(float4)) * (size_t)t->n;
+    const size_t src_bytes = (f64 ? sizeof(double4) : sizeof(int4)) * (size_t)t->n;
     if ((f64 ? t->xyz64.cap : t->xyz32.cap) < src_bytes || !src)
         return fail(FMM_EDEVICE, "internal: particle buffer does not match the form");
     if (t->start.cap < sizeof(uint32_t) * (size_t)(t->nleaf + 1) || t->perm.cap < sizeof(uint32_t) * (size_t)t->n)
@@ -320,7 +316,7 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
             CHK(ensure(t, t->M[l], nb * S * es, st));
             CHK(ensure(t, t->Lc[l], nb * S * es, st));
             const size_t g = ((size_t)1 << l) + 6;
-            const size_t pk = f64 ? g * g * g * S * 8 : g * g * g * S * 2 * nsplit;
+            const size_t pk = g * g * g * S * (f64 ? 8 : 4);
             CHK(ensure(t, t->pack[l], pk, st));
         }
         CHK(rec(t, 1, st));
@@ -335,21 +331,22 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
         CHK(rec(t, 3, st));
         for (int l = 2; l <= L; ++l) {
             const size_t g = ((size_t)1 << l) + 6;
-            HIPCHK(launch_pack(P, l, level_f64(t, l), f64 ? 0 : nsplit, t->M[l].p, t->pack[l].p,
+            HIPCHK(launch_pack(P, l, level_f64(t, l), f64 ? 0 : 1, t->M[l].p, t->pack[l].p,
                                g * g * g * S, st));
         }
         CHK(rec(t, 4, st));
-        // M2L at every level >= 2 (levels are independent)
-        for (int l = 2; l <= L; ++l) {
-            const size_t g = ((size_t)1 << l) + 6;
-            if (f64)
-                HIPCHK(launch_m2l_f64(P, l, (const double *)t->pack[l].p,
-                                      adjoint ? o->am2l64 : o->m2l64, o->cls, (double *)t->Lc[l].p,
-                                      st));
-            else
-                HIPCHK(launch_m2l_bf16(P, l, nsplit, (const uint16_t *)t->pack[l].p, g * g * g * S,
-                                       adjoint ? o->am2lbf : o->m2lbf, o->bf_part, o->cls,
-                                       t->Lc[l].p, level_f64(t, l), st));
+        // M2L at every level >= 2 in one launch (the levels are independent)
+        {
+            void *Bp[FMM_MAX_LEVEL + 1] = {}, *Lp[FMM_MAX_LEVEL + 1] = {};
+            int of64[FMM_MAX_LEVEL + 1] = {};
+            for (int l = 2; l <= L; ++l) {
+                Bp[l] = t->pack[l].p;
+                Lp[l] = t->Lc[l].p;
+                of64[l] = level_f64(t, l);
+            }
+            const void *A = f64 ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
+                                : (const void *)(adjoint ? o->am2l32 : o->m2l32);
+            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, 0, o->cls, st));
         }
         CHK(rec(t, 5, st));
         // downward sweep (adjoint: M2M^T)
@@ -383,7 +380,7 @@ void fmm_config_default(fmm_config *c) {
     c->leaf_max = 64;
     c->max_level = FMM_MAX_LEVEL;
     c->precision = FMM_PREC_MIXED;
-    c->bf16_splits = 2;
+    c->bf16_splits = 3;
     c->box_size = 1.0;
 }
 
@@ -475,13 +472,13 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     if (f64) {
         if ((s = ensure(t, t->xyz64, sizeof(double4) * n, st)) != FMM_OK) return bail(s);
     } else {
-        if ((s = ensure(t, t->xyz32, sizeof(float4) * n, st)) != FMM_OK) return bail(s);
+        if ((s = ensure(t, t->xyz32, sizeof(int4) * n, st)) != FMM_OK) return bail(s);
     }
     e = launch_scan((int64_t)nb, (const uint32_t *)t->cnt.p, (uint32_t *)t->start.p, (uint32_t *)t->scan.p, st);
     if (e == hipSuccess)
         e = launch_sort(n, lev, (const uint32_t *)t->key10.p, (const uint32_t *)t->start.p,
                         (uint32_t *)t->fill.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
-                        cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (float4 *)t->xyz32.p,
+                        cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (int4 *)t->xyz32.p,
                         f64 ? (double4 *)t->xyz64.p : nullptr, st);
     if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("sort: ") + hipGetErrorString(e)));
     *out = t;

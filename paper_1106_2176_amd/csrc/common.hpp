@@ -105,4 +105,28 @@ __host__ __device__ inline void regular_rho(int P, T x, T y, T z, T *rho) {
     }
 }
 
+// ----------------------------------------------------- particle records
+// Sorted particles are stored relative to their leaf centre in units of the
+// leaf width, u in [-1/2, 1/2]^3, with the charge:
+//   mixed form: int4 (x, y, z) as 32-bit fixed point in units of 2^-30 leaf
+//               widths, w = the FP32 charge's bits.  A neighbour shift is an
+//               exact integer add (|u + d| <= 3/2 < 2), a pair difference an
+//               exact integer subtraction rounded once to FP32.
+//   FP64 form:  double4 (x, y, z, q).
+constexpr double kFixScale = 1073741824.0;                 // 2^30
+constexpr float kFixInv = 9.313225746154785156e-10f;       // 2^-30
+
+__device__ inline void unpack_rec(const int4 r, float &x, float &y, float &z, float &q) {
+    x = (float)r.x * kFixInv;
+    y = (float)r.y * kFixInv;
+    z = (float)r.z * kFixInv;
+    q = __int_as_float(r.w);
+}
+__device__ inline void unpack_rec(const double4 r, double &x, double &y, double &z, double &q) {
+    x = r.x;
+    y = r.y;
+    z = r.z;
+    q = r.w;
+}
+
 }  // namespace fmm

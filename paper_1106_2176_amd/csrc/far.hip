@@ -5,6 +5,8 @@
 // S = coef_stride(p): a uniform tree needs no hash tables.  Box (i,j,k) of
 // level l is row i + 2^l (j + 2^l k).  Leaves are visited in Morton order
 // (the sorted particle order) and mapped to their row.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace fmm {
@@ -51,8 +53,9 @@ __device__ __forceinline__ void rho_strided(T x, T y, T z, T *out, int stride) {
     }
 }
 
+// particle record type of each form (see common.hpp)
 template <typename T> struct V4T;
-template <> struct V4T<float> { using type = float4; };
+template <> struct V4T<float> { using type = int4; };
 template <> struct V4T<double> { using type = double4; };
 
 // ---------------------------------------------------------------- P2M
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(64) void k_p2m(int L, const typename V4T<T>::type *
                                             double scale) {
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
-    constexpr int RSraw = 32768 / (P2 * (int)sizeof(T));
+    constexpr int RSraw = 16384 / (P2 * (int)sizeof(T));
     constexpr int RS = RSraw >= 64 ? 64 : RSraw >= 32 ? 32 : RSraw >= 16 ? 16 : 8;
     constexpr int NA = (P2 + 63) / 64;
     __shared__ T buf[P2 * (RS + 1)];
@@ -82,9 +85,9 @@ __global__ __launch_bounds__(64) void k_p2m(int L, const typename V4T<T>::type *
         const int nr = (int)min((uint32_t)RS, cnt - c0);
         __syncthreads();
         if (lane < nr) {
-            const auto v = src[s0 + c0 + lane];
-            rho_strided<P, T>(v.x, v.y, v.z, buf + lane, RS + 1);
-            const T q = v.w;
+            T x, y, z, q;
+            unpack_rec(src[s0 + c0 + lane], x, y, z, q);
+            rho_strided<P, T>(x, y, z, buf + lane, RS + 1);
 #pragma unroll
             for (int c = 0; c < P2; ++c) buf[c * (RS + 1) + lane] *= q;
         }
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
                                             const T *__restrict__ Lc, double4 *__restrict__ out) {
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
-    using V = typename V4T<T>::type;
+    using V = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
     __shared__ T ell[P2];
     __shared__ V coef[P2];  // (ell, Gx, Gy, Gz) per slot
     const int lane = threadIdx.x;
@@ -188,12 +191,12 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
     }
     __syncthreads();
     for (uint32_t j0 = lane; j0 < cnt; j0 += 64) {
-        const V pt = src[s0 + j0];
-        const T x = pt.x, y = pt.y, z = pt.z;
+        T x, y, z, qq;
+        unpack_rec(src[s0 + j0], x, y, z, qq);
         const T r2 = x * x + y * y + z * z;
         T phi = T(0), gx = T(0), gy = T(0), gz = T(0);
         T dr = T(1), di = T(0);
-#pragma unroll
+#pragma unroll 1
         for (int m = 0; m < P; ++m) {
             if (m > 0) {
                 const T inv = T(-1) / T(2 * m);
@@ -242,107 +245,109 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
 // ------------------------------------------------------- M2M / L2L transfers
 // UP:   out[parent][o]  = sum_c sum_k tab[c][k][o] in[child c][k]
 // DOWN: out[child c][o] += sum_k tab[c][k][o] in[parent][k]
-// tab is [8][p^2][p^2] (input-major, so threads = output rows read
-// contiguously).  Tile of NP consecutive parents per block.
-constexpr int kNP = 16;
+// tab is [8][p^2][p^2] input-major.  Both are small GEMMs (rows = output
+// coefficients, columns = parents) run on the FP64 matrix cores whatever the
+// storage precision of the levels: one wave per tile of 16 output rows x 16
+// consecutive parents, K in steps of 4 (v_mfma_f64_16x16x4_f64; A lane l
+// holds row l%16, K l/16; B lane l holds K l/16, column l%16; result lane l,
+// item i holds row l/16 + 4i of column l%16).
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-template <typename Tin, typename Tout, typename Tc>
+template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void k_up(int P, int lp, const Tin *__restrict__ in,
-                                            Tout *__restrict__ out, const Tc *__restrict__ tab) {
-    extern __shared__ unsigned char smem_raw[];
-    Tc *sm = (Tc *)smem_raw;  // [kNP][P2]
-    const int P2 = P * P, S = coef_stride(P);
-    const int np = 1 << lp;  // parents per axis
-    const int64_t npar = (int64_t)np * np * np;
-    const int64_t p0 = (int64_t)blockIdx.x * kNP;
-    const int o = threadIdx.x;
-    Tc acc[kNP];
+                                            Tout *__restrict__ out, const double *__restrict__ tab) {
+    const int P2 = P * P, S = coef_stride(P), K = 8 * P2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int rt = blockIdx.y * 4 + wave;  // row tile
+    if (rt * 16 >= P2) return;
+    const int64_t np = (int64_t)1 << lp, nc = 2 * np, npar = np * np * np;
+    const int64_t par = (int64_t)blockIdx.x * 16 + col;
+    const bool valid = par < npar;
+    const int64_t pc = valid ? par : 0;
+    const int64_t pi = pc % np, pj = (pc / np) % np, pk = pc / (np * np);
+    int64_t child[8];
 #pragma unroll
-    for (int a = 0; a < kNP; ++a) acc[a] = Tc(0);
-    for (int c = 0; c < 8; ++c) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kNP * P2; e += blockDim.x) {
-            const int a = e / P2, k = e - a * P2;
-            const int64_t pid = p0 + a;
-            Tc v = Tc(0);
-            if (pid < npar) {
-                const int64_t pi = pid % np, pj = (pid / np) % np, pk = pid / ((int64_t)np * np);
-                const int64_t nc = 2 * (int64_t)np;
-                const int64_t ci = 2 * pi + (c & 1), cj = 2 * pj + ((c >> 1) & 1),
-                              ck = 2 * pk + ((c >> 2) & 1);
-                v = (Tc)in[(ci + nc * (cj + nc * ck)) * S + k];
-            }
-            sm[a * P2 + k] = v;
-        }
-        __syncthreads();
-        if (o < P2) {
-            const Tc *t = tab + (size_t)c * P2 * P2 + o;
-            for (int k = 0; k < P2; ++k) {
-                const Tc w = t[(size_t)k * P2];
+    for (int c = 0; c < 8; ++c)
+        child[c] = ((2 * pi + (c & 1)) + nc * ((2 * pj + ((c >> 1) & 1)) + nc * (2 * pk + ((c >> 2) & 1)))) * S;
+    const int orow = rt * 16 + col;  // A row held by this lane
+    const bool rowok = orow < P2;
+    f64x4_t acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        double a[4], b[4];
 #pragma unroll
-                for (int a = 0; a < kNP; ++a) acc[a] += w * sm[a * P2 + k];
+        for (int j = 0; j < 4; ++j) {
+            const int kk = k0 + 4 * j + q;
+            a[j] = 0.0;
+            b[j] = 0.0;
+            if (kk < K) {
+                const int c = kk / P2, k = kk - c * P2;
+                if (rowok) a[j] = tab[((size_t)c * P2 + k) * P2 + orow];
+                b[j] = (double)in[child[c] + k];
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
     }
-    if (o < P2)
+    if (!valid) return;
 #pragma unroll
-        for (int a = 0; a < kNP; ++a)
-            if (p0 + a < npar) out[(p0 + a) * S + o] = (Tout)acc[a];
+    for (int i = 0; i < 4; ++i) {
+        const int o = rt * 16 + q + 4 * i;
+        if (o < P2) out[par * S + o] = (Tout)acc[i];
+    }
 }
 
-template <typename Tin, typename Tout, typename Tc>
+// rows of the stacked [8 p^2] output (child-major); K = p^2
+template <typename Tin, typename Tout>
 __global__ __launch_bounds__(256) void k_down(int P, int lp, const Tin *__restrict__ in,
-                                              Tout *__restrict__ out, const Tc *__restrict__ tab) {
-    extern __shared__ unsigned char smem_raw[];
-    Tc *sm = (Tc *)smem_raw;  // [kNP][P2]
-    const int P2 = P * P, S = coef_stride(P);
-    const int np = 1 << lp;
-    const int64_t npar = (int64_t)np * np * np;
-    const int64_t p0 = (int64_t)blockIdx.x * kNP;
-    const int o = threadIdx.x;
-    for (int e = threadIdx.x; e < kNP * P2; e += blockDim.x) {
-        const int a = e / P2, k = e - a * P2;
-        sm[e] = (p0 + a < npar) ? (Tc)in[(p0 + a) * S + k] : Tc(0);
+                                              Tout *__restrict__ out, const double *__restrict__ tab) {
+    const int P2 = P * P, S = coef_stride(P), M = 8 * P2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int rt = blockIdx.y * 4 + wave;
+    if (rt * 16 >= M) return;
+    const int64_t np = (int64_t)1 << lp, nc = 2 * np, npar = np * np * np;
+    const int64_t par = (int64_t)blockIdx.x * 16 + col;
+    const bool valid = par < npar;
+    const int64_t pc = valid ? par : 0;
+    const int arow = rt * 16 + col;  // stacked row held by this lane as A row
+    const bool rowok = arow < M;
+    const int ac = rowok ? arow / P2 : 0, ao = rowok ? arow - ac * P2 : 0;
+    f64x4_t acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < P2; k0 += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + 4 * j + q;
+            a[j] = 0.0;
+            b[j] = 0.0;
+            if (k < P2) {
+                if (rowok) a[j] = tab[((size_t)ac * P2 + k) * P2 + ao];
+                b[j] = (double)in[pc * S + k];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
     }
-    __syncthreads();
-    if (o >= P2) return;
-    const int64_t nc = 2 * (int64_t)np;
-    for (int c = 0; c < 8; ++c) {
-        Tc acc[kNP];
+    if (!valid) return;
+    const int64_t pi = pc % np, pj = (pc / np) % np, pk = pc / (np * np);
 #pragma unroll
-        for (int a = 0; a < kNP; ++a) acc[a] = Tc(0);
-        const Tc *t = tab + (size_t)c * P2 * P2 + o;
-        for (int k = 0; k < P2; ++k) {
-            const Tc w = t[(size_t)k * P2];
-#pragma unroll
-            for (int a = 0; a < kNP; ++a) acc[a] += w * sm[a * P2 + k];
-        }
-#pragma unroll
-        for (int a = 0; a < kNP; ++a) {
-            const int64_t pid = p0 + a;
-            if (pid >= npar) continue;
-            const int64_t pi = pid % np, pj = (pid / np) % np, pk = pid / ((int64_t)np * np);
-            const int64_t ci = 2 * pi + (c & 1), cj = 2 * pj + ((c >> 1) & 1),
-                          ck = 2 * pk + ((c >> 2) & 1);
-            Tout *dst = out + (ci + nc * (cj + nc * ck)) * S + o;
-            *dst = (Tout)((Tc)*dst + acc[a]);
-        }
+    for (int i = 0; i < 4; ++i) {
+        const int row = rt * 16 + q + 4 * i;
+        if (row >= M) continue;
+        const int c = row / P2, o = row - c * P2;
+        const int64_t ch = (2 * pi + (c & 1)) + nc * ((2 * pj + ((c >> 1) & 1)) + nc * (2 * pk + ((c >> 2) & 1)));
+        Tout *dst = out + ch * S + o;
+        *dst = (Tout)((double)*dst + acc[i]);
     }
 }
 
 // -------------------------------------------------------------- M2L operand
 // Pack level-l multipoles into a zero-padded grid with a 3-box halo
-// [(n+6)^3][S], split into bf16 parts (mixed) or copied in FP64.
-__device__ inline uint16_t bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-template <typename Tin>
-__global__ void k_pack_bf16(int P, int l, int parts, const Tin *__restrict__ in,
-                            uint16_t *__restrict__ out, size_t part_stride) {
+// [(n+6)^3][S]: FP32 for the mixed form (split into bf16 parts inside the
+// M2L kernel), FP64 for the plain form.
+template <typename Tin, typename Tout>
+__global__ void k_pack(int P, int l, const Tin *__restrict__ in, Tout *__restrict__ out) {
     const int S = coef_stride(P), P2 = P * P;
     const int64_t n = 1 << l, g = n + 6;
     const int64_t total = g * g * g * S;
@@ -351,38 +356,26 @@ __global__ void k_pack_bf16(int P, int l, int parts, const Tin *__restrict__ in,
     const int c = (int)(e % S);
     const int64_t b = e / S;
     const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
-    double v = 0.0;
+    Tout v = Tout(0);
     if (c < P2 && x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n)
-        v = (double)in[(x + n * (y + n * z)) * S + c];
-    for (int k = 0; k < parts; ++k) {
-        const uint16_t h = bf16_rne((float)v);
-        out[k * part_stride + e] = h;
-        v -= (double)bf16_to_f(h);
-    }
-}
-
-__global__ void k_pack_f64(int P, int l, const double *__restrict__ in, double *__restrict__ out) {
-    const int S = coef_stride(P), P2 = P * P;
-    const int64_t n = 1 << l, g = n + 6;
-    const int64_t total = g * g * g * S;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    const int c = (int)(e % S);
-    const int64_t b = e / S;
-    const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
-    double v = 0.0;
-    if (c < P2 && x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n)
-        v = in[(x + n * (y + n * z)) * S + c];
+        v = (Tout)in[(x + n * (y + n * z)) * S + c];
     out[e] = v;
 }
 
 // ------------------------------------------------------------ gather/combine
-template <typename Tq, typename V>
-__global__ void k_gather_q(int64_t n, const uint32_t *__restrict__ perm, const Tq *__restrict__ q,
-                           V *__restrict__ xyzq) {
+template <typename Tq>
+__global__ void k_gather_q64(int64_t n, const uint32_t *__restrict__ perm, const Tq *__restrict__ q,
+                             double4 *__restrict__ xyzq) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    xyzq[i].w = (decltype(xyzq[i].w))q[perm[i]];
+    xyzq[i].w = (double)q[perm[i]];
+}
+template <typename Tq>
+__global__ void k_gather_q32(int64_t n, const uint32_t *__restrict__ perm, const Tq *__restrict__ q,
+                             int4 *__restrict__ xyzq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    xyzq[i].w = __float_as_int((float)q[perm[i]]);
 }
 
 // phi = (near + far) / w,  E = (near + far) / w^2 in FP64, scattered to the
@@ -477,48 +470,46 @@ hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *s
                : l2p_dispatch<float>(P, L, src, start, (const float *)Lc, out, st);
 }
 
-// in/out precisions: 0 = f32, 1 = f64; compute in FP64 when either is FP64
+// in/out storage precisions: 0 = f32, 1 = f64 (the arithmetic is FP64)
 hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
                            void *out, const void *tab32, const void *tab64, hipStream_t st) {
+    (void)tab32;
     const int64_t np = (int64_t)1 << (3 * lp);
-    const unsigned grid = nblk(np, kNP);
-    const int threads = P * P <= 64 ? 64 : P * P <= 128 ? 128 : 256;
-    const bool c64 = in_f64 || out_f64;
-    const size_t sh = (size_t)kNP * P * P * (c64 ? 8 : 4);
-#define LAUNCH(TI, TO, TC, TAB)                                                                    \
-    do {                                                                                           \
-        if (up)                                                                                    \
-            k_up<TI, TO, TC><<<grid, threads, sh, st>>>(P, lp, (const TI *)in, (TO *)out,           \
-                                                        (const TC *)TAB);                         \
-        else                                                                                       \
-            k_down<TI, TO, TC><<<grid, threads, sh, st>>>(P, lp, (const TI *)in, (TO *)out,         \
-                                                          (const TC *)TAB);                       \
+    const int rows = up ? P * P : 8 * P * P;
+    const dim3 grid((unsigned)((np + 15) / 16), (unsigned)((rows + 63) / 64));
+    const double *tab = (const double *)tab64;
+#define LAUNCH(TI, TO)                                                                           \
+    do {                                                                                         \
+        if (up)                                                                                  \
+            k_up<TI, TO><<<grid, 256, 0, st>>>(P, lp, (const TI *)in, (TO *)out, tab);          \
+        else                                                                                     \
+            k_down<TI, TO><<<grid, 256, 0, st>>>(P, lp, (const TI *)in, (TO *)out, tab);        \
     } while (0)
-    if (!c64)
-        LAUNCH(float, float, float, tab32);
-    else if (in_f64 && out_f64)
-        LAUNCH(double, double, double, tab64);
+    if (in_f64 && out_f64)
+        LAUNCH(double, double);
     else if (in_f64)
-        LAUNCH(double, float, double, tab64);
+        LAUNCH(double, float);
+    else if (out_f64)
+        LAUNCH(float, double);
     else
-        LAUNCH(float, double, double, tab64);
+        LAUNCH(float, float);
 #undef LAUNCH
     return hipGetLastError();
 }
 
+// parts == 0: FP64 output (plain form); otherwise FP32 output (mixed form)
 hipError_t launch_pack(int P, int l, bool in_f64, int parts, const void *in, void *out,
                        size_t part_stride, hipStream_t st) {
+    (void)part_stride;
     const int64_t g = ((int64_t)1 << l) + 6;
     const int64_t total = g * g * g * coef_stride(P);
-    if (parts == 0) {
-        k_pack_f64<<<nblk(total, 256), 256, 0, st>>>(P, l, (const double *)in, (double *)out);
-    } else if (in_f64) {
-        k_pack_bf16<double><<<nblk(total, 256), 256, 0, st>>>(P, l, parts, (const double *)in,
-                                                               (uint16_t *)out, part_stride);
-    } else {
-        k_pack_bf16<float><<<nblk(total, 256), 256, 0, st>>>(P, l, parts, (const float *)in,
-                                                              (uint16_t *)out, part_stride);
-    }
+    const unsigned gr = nblk(total, 256);
+    if (parts == 0)
+        k_pack<double, double><<<gr, 256, 0, st>>>(P, l, (const double *)in, (double *)out);
+    else if (in_f64)
+        k_pack<double, float><<<gr, 256, 0, st>>>(P, l, (const double *)in, (float *)out);
+    else
+        k_pack<float, float><<<gr, 256, 0, st>>>(P, l, (const float *)in, (float *)out);
     return hipGetLastError();
 }
 
@@ -526,18 +517,14 @@ hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm,
                            void *xyzq, hipStream_t st) {
     if (dtype == FMM_F64) {
         if (f64)
-            k_gather_q<double, double4><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const double *)q,
-                                                                       (double4 *)xyzq);
+            k_gather_q64<double><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const double *)q, (double4 *)xyzq);
         else
-            k_gather_q<double, float4><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const double *)q,
-                                                                      (float4 *)xyzq);
+            k_gather_q32<double><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const double *)q, (int4 *)xyzq);
     } else {
         if (f64)
-            k_gather_q<float, double4><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const float *)q,
-                                                                      (double4 *)xyzq);
+            k_gather_q64<float><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const float *)q, (double4 *)xyzq);
         else
-            k_gather_q<float, float4><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const float *)q,
-                                                                     (float4 *)xyzq);
+            k_gather_q32<float><<<nblk(n, 256), 256, 0, st>>>(n, perm, (const float *)q, (int4 *)xyzq);
     }
     return hipGetLastError();
 }

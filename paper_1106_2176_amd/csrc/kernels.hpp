@@ -16,7 +16,7 @@ hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *
                        hipStream_t st);
 hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *start,
                        uint32_t *fill, uint32_t *tmp, int dtype, const void *pos,
-                       const double lo[3], double size, uint32_t *perm, float4 *xyz32,
+                       const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st);
 hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long long *out,
                              hipStream_t st);
@@ -43,11 +43,9 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
                                const double4 *farf, double inv_w, const void *q, const void *w,
                                const void *Eq, void *gq, void *gx, hipStream_t st);
 
-// m2l.hip
-hipError_t launch_m2l_bf16(int P, int l, int nsplit, const uint16_t *B, size_t bstride,
-                           const uint16_t *A, size_t astride, const int2 *cls, void *Lout,
-                           int out_f64, hipStream_t st);
-hipError_t launch_m2l_f64(int P, int l, const double *B, const double *A, const int2 *cls,
-                          double *Lout, hipStream_t st);
+// m2l.hip: every level 2..L in one launch; B[l], Lc[l] indexed by level
+hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
+                      const int *out_f64, const void *A, size_t astride, const int2 *cls,
+                      hipStream_t st);
 
 }  // namespace fmm

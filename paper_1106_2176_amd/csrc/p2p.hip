@@ -11,29 +11,33 @@
 // lanes holding two targets each, replicated into K = 64/G groups that take
 // every K-th source of a tile (source split); group partials are summed at
 // the end.  Each source read from LDS feeds two pair interactions.
-// Mixed form: FP32 pair arithmetic with the hardware reciprocal square root;
-// per-tile FP32 partial sums are merged into FP64 accumulators.
+// Mixed form: positions are 32-bit fixed point (units of 2^-30 leaf widths),
+// so a pair difference is an exact integer subtraction rounded once to FP32;
+// the pair arithmetic is FP32 with the hardware reciprocal square root in
+// these raw units, per-tile FP32 partial sums are merged into FP64, and the
+// sums are rescaled at the end (phi by 2^30, E by 2^60, both exact).
 // Plain form: FP64 throughout; 1/sqrt from the hardware estimate refined by
 // two Newton-Raphson steps y <- y + y (1 - r^2 y^2) / 2.
 // Pairs in the target's own leaf are masked when r^2 == 0 (the particle
 // itself and exact duplicates contribute nothing); pairs with other leaves
-// add a tiny constant (1e-20 leaf widths^2 in FP32, 1e-200 in FP64) to r^2,
-// which keeps a rounding-induced r^2 == 0 finite and changes no pair farther
-// apart than 1e-6 leaf widths by more than 1e-8 relative.
+// add a tiny constant to r^2 (one raw unit^2 = 2^-60 leaf widths^2 in the
+// mixed form, 1e-200 in FP64), which keeps a quantisation-induced r^2 == 0
+// finite and changes no pair farther apart than 1e-6 leaf widths by more
+// than 1e-6 relative.
 #include "kernels.hpp"
 
 namespace fmm {
 
 template <bool SELF>
-__device__ __forceinline__ void pair_f32(float xi, float yi, float zi, const float4 s, float &phi,
-                                         float &ex, float &ey, float &ez) {
-    const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-    float r2 = SELF ? dx * dx : __builtin_fmaf(dx, dx, 1e-20f);
+__device__ __forceinline__ void pair_fix(int xi, int yi, int zi, const int4 s, float &phi, float &ex,
+                                         float &ey, float &ez) {
+    const float dx = (float)(xi - s.x), dy = (float)(yi - s.y), dz = (float)(zi - s.z);
+    float r2 = SELF ? dx * dx : __builtin_fmaf(dx, dx, 1.0f);
     r2 = __builtin_fmaf(dy, dy, r2);
     r2 = __builtin_fmaf(dz, dz, r2);
     float rinv = __builtin_amdgcn_rsqf(r2);
     if (SELF) rinv = r2 > 0.0f ? rinv : 0.0f;
-    const float qr = s.w * rinv;
+    const float qr = __int_as_float(s.w) * rinv;
     phi += qr;
     const float qr3 = qr * (rinv * rinv);
     ex = __builtin_fmaf(qr3, dx, ex);
@@ -63,16 +67,37 @@ __device__ __forceinline__ void pair_f64(double xi, double yi, double zi, const 
 }
 
 template <typename T> struct V4;
-template <> struct V4<float> { using type = float4; };
+template <> struct V4<float> { using type = int4; };
 template <> struct V4<double> { using type = double4; };
 
-template <typename T, bool SELF>
-__device__ __forceinline__ void pair(T xi, T yi, T zi, const typename V4<T>::type s, T &phi, T &ex,
-                                     T &ey, T &ez) {
-    if constexpr (sizeof(T) == 4)
-        pair_f32<SELF>(xi, yi, zi, s, phi, ex, ey, ez);
-    else
-        pair_f64<SELF>(xi, yi, zi, s, phi, ex, ey, ez);
+template <typename T> struct Acc;
+template <> struct Acc<float> { using type = float; };
+template <> struct Acc<double> { using type = double; };
+
+template <bool SELF>
+__device__ __forceinline__ void pair(const int4 t, const int4 s, float &phi, float &ex, float &ey,
+                                     float &ez) {
+    pair_fix<SELF>(t.x, t.y, t.z, s, phi, ex, ey, ez);
+}
+template <bool SELF>
+__device__ __forceinline__ void pair(const double4 t, const double4 s, double &phi, double &ex,
+                                     double &ey, double &ez) {
+    pair_f64<SELF>(t.x, t.y, t.z, s, phi, ex, ey, ez);
+}
+
+// |u| <= 1/2 - 2^-30 after quantisation, so shifted sources lie within
+// +-(3/2) 2^30 and every target - source difference within +-(2^31 - 1).
+__device__ __forceinline__ int4 shifted(int4 v, int dx, int dy, int dz) {
+    v.x += dx * (1 << 30);
+    v.y += dy * (1 << 30);
+    v.z += dz * (1 << 30);
+    return v;
+}
+__device__ __forceinline__ double4 shifted(double4 v, int dx, int dy, int dz) {
+    v.x += (double)dx;
+    v.y += (double)dy;
+    v.z += (double)dz;
+    return v;
 }
 
 // src: sorted particles (u_x, u_y, u_z, q) in leaf units; start: Morton leaf
@@ -118,27 +143,21 @@ __global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
                     for (uint32_t sc = 0; sc < ns; sc += 64) {
                         const int nsc = (int)min(64u, ns - sc);
                         __syncthreads();
-                        if (lane < nsc) {
-                            V v = src[s0 + sc + lane];
-                            v.x += (T)dx;
-                            v.y += (T)dy;
-                            v.z += (T)dz;
-                            tile[lane] = v;
-                        }
+                        if (lane < nsc) tile[lane] = shifted(src[s0 + sc + lane], dx, dy, dz);
                         __syncthreads();
                         T pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
                         if (act) {
                             if (self) {
                                 for (int j = grp; j < nsc; j += K) {
                                     const V sj = tile[j];
-                                    pair<T, true>(ta.x, ta.y, ta.z, sj, pa0, pa1, pa2, pa3);
-                                    pair<T, true>(tb.x, tb.y, tb.z, sj, pb0, pb1, pb2, pb3);
+                                    pair<true>(ta, sj, pa0, pa1, pa2, pa3);
+                                    pair<true>(tb, sj, pb0, pb1, pb2, pb3);
                                 }
                             } else {
                                 for (int j = grp; j < nsc; j += K) {
                                     const V sj = tile[j];
-                                    pair<T, false>(ta.x, ta.y, ta.z, sj, pa0, pa1, pa2, pa3);
-                                    pair<T, false>(tb.x, tb.y, tb.z, sj, pb0, pb1, pb2, pb3);
+                                    pair<false>(ta, sj, pa0, pa1, pa2, pa3);
+                                    pair<false>(tb, sj, pb0, pb1, pb2, pb3);
                                 }
                             }
                         }
@@ -161,6 +180,19 @@ __global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
         __syncthreads();
         if (grp == 0) {
             double4 sa = red[0][r], sb = red[1][r];
+            if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
+                const double s1 = kFixScale, s3 = kFixScale * kFixScale;
+                for (int g = 1; g < K; ++g) {
+                    const double4 xa = red[0][g * G + r], xb = red[1][g * G + r];
+                    sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
+                    sb.x += xb.x; sb.y += xb.y; sb.z += xb.z; sb.w += xb.w;
+                }
+                sa = make_double4(sa.x * s1, sa.y * s3, sa.z * s3, sa.w * s3);
+                sb = make_double4(sb.x * s1, sb.y * s3, sb.z * s3, sb.w * s3);
+                out[t0 + tc + r] = sa;
+                if (hasb) out[t0 + tc + r + G] = sb;
+                continue;
+            }
             for (int g = 1; g < K; ++g) {
                 const double4 xa = red[0][g * G + r], xb = red[1][g * G + r];
                 sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
@@ -180,7 +212,7 @@ hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, d
     if (f64)
         k_p2p<double><<<grid, 64, 0, st>>>(L, per, (const double4 *)src, start, out);
     else
-        k_p2p<float><<<grid, 64, 0, st>>>(L, per, (const float4 *)src, start, out);
+        k_p2p<float><<<grid, 64, 0, st>>>(L, per, (const int4 *)src, start, out);
     return hipGetLastError();
 }
 

@@ -110,8 +110,8 @@ __global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key10, int shi
 // One 256-thread block per leaf: orders the leaf's particles by input index
 // (making the counting sort stable and the whole build deterministic), writes
 // perm and the particles' coordinates relative to the leaf centre in units of
-// the leaf width, u = s 2^L - (i + 1/2) in [-1/2, 1/2] (FP64, rounded to FP32
-// for the mixed form).
+// the leaf width, u = s 2^L - (i + 1/2) in [-1/2, 1/2], computed in FP64 and
+// stored as FP64 (plain form) or rounded to 32-bit fixed point (mixed form).
 constexpr int kFixupCache = 4096;
 
 template <typename T>
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict
                                                const uint32_t *__restrict__ tmp,
                                                const T *__restrict__ pos, double lo0, double lo1,
                                                double lo2, double size, uint32_t *__restrict__ perm,
-                                               float4 *__restrict__ xyz32, double4 *__restrict__ xyz64) {
+                                               int4 *__restrict__ xyz32, double4 *__restrict__ xyz64) {
     __shared__ uint32_t idx[kFixupCache];
     const uint32_t leaf = blockIdx.x;
     const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
@@ -144,7 +144,14 @@ __global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict
         const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
         const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
         const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
-        if (xyz32) xyz32[d] = make_float4((float)ux, (float)uy, (float)uz, 0.0f);
+        if (xyz32) {
+            // fixed point in [-2^29, 2^29 - 1]: u = +1/2 (a point on the upper
+            // face of the root cube) moves by 2^-30 leaf widths
+            const int top = (1 << 29) - 1;
+            xyz32[d] = make_int4(min(__double2int_rn(ux * kFixScale), top),
+                                 min(__double2int_rn(uy * kFixScale), top),
+                                 min(__double2int_rn(uz * kFixScale), top), 0);
+        }
         if (xyz64) xyz64[d] = make_double4(ux, uy, uz, 0.0);
     }
 }
@@ -229,7 +236,7 @@ hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *
 
 hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *start,
                        uint32_t *fill, uint32_t *tmp, int dtype, const void *pos,
-                       const double lo[3], double size, uint32_t *perm, float4 *xyz32,
+                       const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st) {
     const int64_t nb = (int64_t)1 << (3 * level);
     hipError_t e = hipMemsetAsync(fill, 0, sizeof(uint32_t) * nb, st);
