@@ -81,7 +81,9 @@ typedef struct {
     int32_t max_level;         /* 0..10; keys are 3*level <= 30 bits */
     int32_t precision;         /* fmm_precision */
     int32_t bf16_splits;       /* mixed form only: 2 (hi+lo, 3 MFMA products) or
-                                  3 (hi+mid+lo, 6 products); 0 selects 3 */
+                                  3 (hi+mid+lo, 6 products); 0 selects 3.  The
+                                  mixed form with 3 parts supports p <= 13
+                                  (FMM_EUNSUPPORTED above: use 2 parts or FP64) */
     double box_lo[3];          /* root cube corner */
     double box_size;           /* root cube edge, > 0 */
     fmm_alloc_fn alloc;        /* optional, see above */

@@ -62,10 +62,11 @@ struct Ops {
     // [8][P2][P2] input-major transfer tables
     double *up64 = nullptr, *down64 = nullptr, *aup64 = nullptr, *adown64 = nullptr;
     float *up32 = nullptr, *down32 = nullptr, *aup32 = nullptr, *adown32 = nullptr;
-    // M2L tables [316][R][S]: FP64 and FP32 (split into bf16 parts on the fly
-    // by the mixed kernel), forward and adjoint
+    // M2L tables [317][R][S] (316 operators + a zero one): FP64, and three
+    // bf16 parts [3][317][R][S] for the mixed form; forward and adjoint
     double *m2l64 = nullptr, *am2l64 = nullptr;
-    float *m2l32 = nullptr, *am2l32 = nullptr;
+    uint16_t *m2lbf = nullptr, *am2lbf = nullptr;
+    size_t bf_part = 0;  // elements per bf16 part
     int2 *cls = nullptr; // [8][189] (packed source offset, table id)
 };
 
@@ -166,13 +167,20 @@ fmm_status build_ops(int p, Ops **out) {
     t32 = up32f(down); UP64(down32, t32)
     t32 = up32f(aup); UP64(aup32, t32)
     t32 = up32f(adown); UP64(adown32, t32)
-    UP64(m2l64, f64) UP64(am2l64, af64)
-    t32 = up32f(f64); UP64(m2l32, t32)
-    t32 = up32f(af64); UP64(am2l32, t32)
+    std::vector<uint16_t> fbf(3 * nT), afbf(3 * nT);
+    for (size_t i = 0; i < nT; ++i) {
+        uint16_t pt[3];
+        split_bf16(f64[i], 3, pt);
+        for (int k = 0; k < 3; ++k) fbf[k * nT + i] = pt[k];
+        split_bf16(af64[i], 3, pt);
+        for (int k = 0; k < 3; ++k) afbf[k * nT + i] = pt[k];
+    }
+    UP64(m2l64, f64) UP64(am2l64, af64) UP64(m2lbf, fbf) UP64(am2lbf, afbf)
     UP64(cls, cls)
 #undef UP64
     (void)tb;
     if (e != hipSuccess) return fail(FMM_EDEVICE, std::string("operator upload: ") + hipGetErrorString(e));
+    o->bf_part = nT;
     g_ops[{dev, p}] = o;
     *out = o;
     return FMM_OK;
@@ -190,9 +198,10 @@ struct fmm_tree {
     int64_t nleaf = 1;
     int64_t max_count = 0;
     int dev = 0;
+    int ncu = 0;  // compute units of the device
     hipStream_t stream = nullptr;
     Alloc al;
-    Buf key10, cnt, start, fill, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs;
+    Buf key10, cnt, start, fill, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs, m2lpart;
     Buf M[FMM_MAX_LEVEL + 1], Lc[FMM_MAX_LEVEL + 1], pack[FMM_MAX_LEVEL + 1];
     unsigned int *host_counters = nullptr;  // pinned [4]
     Ops *ops = nullptr;
@@ -260,6 +269,8 @@ fmm_status validate_cfg(const fmm_config *c) {
         return fail(FMM_EINVAL, "unknown precision");
     if (c->bf16_splits != 0 && c->bf16_splits != 2 && c->bf16_splits != 3)
         return fail(FMM_EINVAL, "bf16_splits must be 0, 2 or 3");
+    if (c->precision == FMM_PREC_MIXED && c->bf16_splits != 2 && c->p > kMixedSplit3PMax)
+        return fail(FMM_EUNSUPPORTED, "the mixed form with a 3-part split supports p <= 13");
     if (!(c->box_size > 0.0) || !std::isfinite(c->box_size)) return fail(FMM_EINVAL, "box_size must be > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->box_lo[a])) return fail(FMM_EINVAL, "box_lo must be finite");
@@ -316,9 +327,11 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
             CHK(ensure(t, t->M[l], nb * S * es, st));
             CHK(ensure(t, t->Lc[l], nb * S * es, st));
             const size_t g = ((size_t)1 << l) + 6;
-            const size_t pk = g * g * g * S * (f64 ? 8 : 4);
+            const size_t pk = g * g * g * S * (f64 ? 8 : 2 * nsplit);
             CHK(ensure(t, t->pack[l], pk, st));
         }
+        const size_t pbytes = m2l_partial_bytes(P, L, f64, t->ncu);
+        if (pbytes) CHK(ensure(t, t->m2lpart, pbytes, st));
         CHK(rec(t, 1, st));
         // P2M at the leaves (for the adjoint: L2P^T, the same sum with w)
         HIPCHK(launch_p2m(P, L, f64, src, start, t->M[L].p, 1.0, st));
@@ -331,22 +344,26 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
         CHK(rec(t, 3, st));
         for (int l = 2; l <= L; ++l) {
             const size_t g = ((size_t)1 << l) + 6;
-            HIPCHK(launch_pack(P, l, level_f64(t, l), f64 ? 0 : 1, t->M[l].p, t->pack[l].p,
+            HIPCHK(launch_pack(P, l, level_f64(t, l), f64 ? 0 : nsplit, t->M[l].p, t->pack[l].p,
                                g * g * g * S, st));
         }
         CHK(rec(t, 4, st));
         // M2L at every level >= 2 in one launch (the levels are independent)
         {
             void *Bp[FMM_MAX_LEVEL + 1] = {}, *Lp[FMM_MAX_LEVEL + 1] = {};
+            size_t bst[FMM_MAX_LEVEL + 1] = {};
             int of64[FMM_MAX_LEVEL + 1] = {};
             for (int l = 2; l <= L; ++l) {
+                const size_t g = ((size_t)1 << l) + 6;
                 Bp[l] = t->pack[l].p;
+                bst[l] = g * g * g * S;
                 Lp[l] = t->Lc[l].p;
                 of64[l] = level_f64(t, l);
             }
             const void *A = f64 ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
-                                : (const void *)(adjoint ? o->am2l32 : o->m2l32);
-            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, 0, o->cls, st));
+                                : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
+            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, bst, Lp, of64, A, o->bf_part, o->cls,
+                              (double *)t->m2lpart.p, t->m2lpart.cap, t->ncu, st));
         }
         CHK(rec(t, 5, st));
         // downward sweep (adjoint: M2M^T)
@@ -429,6 +446,9 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     t->al.ctx = cfg->alloc_ctx;
     t->have_times = false;
     if (hipGetDevice(&t->dev) != hipSuccess) return bail(fail(FMM_EDEVICE, "hipGetDevice failed"));
+    if (hipDeviceGetAttribute(&t->ncu, hipDeviceAttributeMultiprocessorCount, t->dev) != hipSuccess ||
+        t->ncu < 1)
+        return bail(fail(FMM_EDEVICE, "cannot read the compute unit count"));
     if (!t->al.fa) ensure_pool(t->dev);
     if (!t->host_counters) {
         if (hipHostMalloc((void **)&t->host_counters, 4 * sizeof(unsigned int)) != hipSuccess)
@@ -552,7 +572,7 @@ fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
     info->m2l_pairs = m2l;
     size_t ws = 0;
     const Buf *bufs[] = {&t->key10, &t->cnt, &t->start, &t->fill, &t->tmp, &t->perm, &t->scan,
-                         &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs};
+                         &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};
     for (const Buf *b : bufs) ws += b->cap;
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) ws += t->M[l].cap + t->Lc[l].cap + t->pack[l].cap;
     info->workspace_bytes = ws;
@@ -585,7 +605,7 @@ void fmm_tree_destroy(fmm_tree *t) {
     if (!t) return;
     hipStream_t st = t->stream;
     Buf *bufs[] = {&t->key10, &t->cnt, &t->start, &t->fill, &t->tmp, &t->perm, &t->scan,
-                   &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs};
+                   &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};
     for (Buf *b : bufs) release(t, *b, st);
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) {
         release(t, t->M[l], st);

@@ -344,22 +344,58 @@ __global__ __launch_bounds__(256) void k_down(int P, int lp, const Tin *__restri
 
 // -------------------------------------------------------------- M2L operand
 // Pack level-l multipoles into a zero-padded grid with a 3-box halo
-// [(n+6)^3][S]: FP32 for the mixed form (split into bf16 parts inside the
-// M2L kernel), FP64 for the plain form.
-template <typename Tin, typename Tout>
-__global__ void k_pack(int P, int l, const Tin *__restrict__ in, Tout *__restrict__ out) {
+// [(n+6)^3][S]: FP64 for the plain form; for the mixed form NSPLIT bf16
+// parts [part][(n+6)^3][S] with x = x0 + x1 (+ x2), each part the
+// round-to-nearest-even bf16 of what the previous parts leave (hardware
+// v_cvt_pk_bf16_f32), computed from the value rounded to FP32.
+__device__ inline void pad_index(int64_t e, int S, int64_t n, int64_t g, int &c, int64_t &src,
+                                 bool &inside) {
+    c = (int)(e % S);
+    const int64_t b = e / S;
+    const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
+    inside = x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n;
+    src = inside ? (x + n * (y + n * z)) * S + c : 0;
+}
+
+__global__ void k_pack_f64(int P, int l, const double *__restrict__ in, double *__restrict__ out) {
     const int S = coef_stride(P), P2 = P * P;
     const int64_t n = 1 << l, g = n + 6;
     const int64_t total = g * g * g * S;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
-    const int c = (int)(e % S);
-    const int64_t b = e / S;
-    const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
-    Tout v = Tout(0);
-    if (c < P2 && x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n)
-        v = (Tout)in[(x + n * (y + n * z)) * S + c];
-    out[e] = v;
+    int c;
+    int64_t src;
+    bool inside;
+    pad_index(e, S, n, g, c, src, inside);
+    out[e] = (inside && c < P2) ? in[src] : 0.0;
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// two coefficients per thread (S is even)
+template <typename Tin>
+__global__ void k_pack_bf16(int P, int l, int parts, const Tin *__restrict__ in,
+                            uint16_t *__restrict__ out, size_t part_stride) {
+    const int S = coef_stride(P), P2 = P * P;
+    const int64_t n = 1 << l, g = n + 6;
+    const int64_t total = g * g * g * S;
+    const int64_t e = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= total) return;
+    int c;
+    int64_t src;
+    bool inside;
+    pad_index(e, S, n, g, c, src, inside);
+    f32x2_t v = {0.0f, 0.0f};
+    if (inside && c < P2) v.x = (float)in[src];
+    if (inside && c + 1 < P2) v.y = (float)in[src + 1];
+    for (int s = 0; s < parts; ++s) {
+        const bf16x2_t hb = __builtin_convertvector(v, bf16x2_t);
+        const uint32_t w = __builtin_bit_cast(uint32_t, hb);
+        *(uint32_t *)(out + s * part_stride + e) = w;
+        v.x -= __uint_as_float(w << 16);
+        v.y -= __uint_as_float(w & 0xffff0000u);
+    }
 }
 
 // ------------------------------------------------------------ gather/combine
@@ -497,19 +533,22 @@ hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, cons
     return hipGetLastError();
 }
 
-// parts == 0: FP64 output (plain form); otherwise FP32 output (mixed form)
+// parts == 0: FP64 grid (plain form); otherwise `parts` bf16 grids spaced
+// part_stride elements apart (mixed form)
 hipError_t launch_pack(int P, int l, bool in_f64, int parts, const void *in, void *out,
                        size_t part_stride, hipStream_t st) {
-    (void)part_stride;
     const int64_t g = ((int64_t)1 << l) + 6;
     const int64_t total = g * g * g * coef_stride(P);
-    const unsigned gr = nblk(total, 256);
-    if (parts == 0)
-        k_pack<double, double><<<gr, 256, 0, st>>>(P, l, (const double *)in, (double *)out);
-    else if (in_f64)
-        k_pack<double, float><<<gr, 256, 0, st>>>(P, l, (const double *)in, (float *)out);
-    else
-        k_pack<float, float><<<gr, 256, 0, st>>>(P, l, (const float *)in, (float *)out);
+    if (parts == 0) {
+        k_pack_f64<<<nblk(total, 256), 256, 0, st>>>(P, l, (const double *)in, (double *)out);
+    } else {
+        if (part_stride < (size_t)total) return hipErrorInvalidValue;
+        const unsigned gr = nblk(total / 2, 256);
+        if (in_f64)
+            k_pack_bf16<double><<<gr, 256, 0, st>>>(P, l, parts, (const double *)in, (uint16_t *)out, part_stride);
+        else
+            k_pack_bf16<float><<<gr, 256, 0, st>>>(P, l, parts, (const float *)in, (uint16_t *)out, part_stride);
+    }
     return hipGetLastError();
 }
 

@@ -43,9 +43,15 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
                                const double4 *farf, double inv_w, const void *q, const void *w,
                                const void *Eq, void *gq, void *gx, hipStream_t st);
 
-// m2l.hip: every level 2..L in one launch; B[l], Lc[l] indexed by level
-hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
-                      const int *out_f64, const void *A, size_t astride, const int2 *cls,
+// m2l.hip: every level 2..L in one launch; B[l], Lc[l] indexed by level.
+// Mixed form: A = bf16 operator parts spaced astride elements apart, B[l] =
+// bf16 multipole parts spaced bstride[l] elements apart (>= the level's padded
+// grid), `partial` >= m2l_partial_bytes() of FP64 scratch.
+size_t m2l_partial_bytes(int P, int L, bool f64, int ncu);
+constexpr int kMixedSplit3PMax = 13;  // LDS holds the 3-part operator ring up to p = 13
+hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, const size_t *bstride,
+                      void *const *Lc, const int *out_f64, const void *A, size_t astride,
+                      const int2 *cls, double *partial, size_t partial_bytes, int ncu,
                       hipStream_t st);
 
 }  // namespace fmm

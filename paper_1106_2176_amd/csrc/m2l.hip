@@ -15,16 +15,20 @@
 // grid with a 3-box halo, so t + d is always a valid address and the shift
 // of every column is the same constant for a given offset.
 //
-// Mixed form: operands stored in FP32 and split on the fly into bf16 parts
-// x = x0 + x1 (+ x2); the products x_i y_j with i + j < parts are
-// accumulated by v_mfma_f32_16x16x32_bf16 in FP32 and merged into FP64
-// accumulators every 256 K terms.
-// Plain form: v_mfma_f64_16x16x4_f64.
+// Mixed form: both operands are stored pre-split into bf16 parts
+// x = x0 + x1 (+ x2) (operators once at set-up, multipoles by the packing
+// kernel); the products x_i y_j with i + j < parts are accumulated by
+// v_mfma_f32_16x16x32_bf16 in FP32 and merged into FP64 accumulators every
+// 256 K terms.  Plain form: v_mfma_f64_16x16x4_f64.
 // MFMA operand layout (16 x 16 tiles, 64 lanes): A lane l holds row l%16,
 // K-group l/16; B lane l holds column l%16, K-group l/16.  Results: for the
 // bf16 instruction lane l holds rows 4(l/16) .. 4(l/16)+3 of column l%16; for
 // the FP64 instruction lane l, item i holds row l/16 + 4i of column l%16
 // (both layouts measured on gfx950).
+#include <algorithm>
+#include <queue>
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace fmm {
@@ -38,237 +42,370 @@ __device__ inline int64_t unpack_delta(int e, int64_t G) {
     return (int64_t)dx + G * ((int64_t)dy + G * (int64_t)dz);
 }
 
-// Work decomposition (both kernels): a block of four waves owns a tile of 128
-// targets of one class (128 consecutive parents in Morton order) and all p^2
-// output rows; each wave owns 32 targets (two 16-column MFMA blocks).  Every
-// level runs in the same launch (the levels are independent): a block finds
-// its level from the per-level block offsets.  Per block, the operator id and
-// the source shift of each of the 189 offsets of its class are first cached
-// in LDS; the operator rows of the current K-chunk are staged in LDS (double
-// buffered, loaded by all waves) and the shifted source multipoles of the next
-// chunk are prefetched into registers while the current chunk runs on the
-// matrix cores.  Blocks are dealt round-robin to the 8 XCDs; when the level is
-// large enough each XCD gets the tiles of one Morton octant of the parent
-// grid, so its L2 holds that octant's sources.
+// ------------------------------------------------------------ work plan
+// A tile is 128 targets of one class at one level (128 consecutive parents
+// in Morton order) and all p^2 output rows; a block of four waves owns one
+// tile, each wave 32 targets (two 16-column MFMA blocks).  Every level runs
+// in the same launch.  A tile's K range (the 189 offsets) may be cut into
+// `nsplit` parts, each a block of its own, so that the small levels fill the
+// chip after the largest level's tiles: the parts write FP64 partial sums
+// and a fix-up kernel adds them in part order (deterministic, no atomics).
+// Blocks are dealt round-robin to the 8 XCDs; when a level is large enough
+// each XCD gets the tiles of one Morton octant of the parent grid (its L2
+// holds that octant's sources), and consecutive blocks of an XCD cycle
+// through the 8 classes, so the blocks running at one time on an XCD read
+// the same operator stream roughly in step.
 constexpr int kTile = 128;
 constexpr int kMaxLev = FMM_MAX_LEVEL + 1;
 
-struct M2LLevels {
+struct M2LPlan {
     int nlev;
     int level[kMaxLev];
-    int64_t block0[kMaxLev + 1];  // first block of each level
-    const void *B[kMaxLev];       // padded operand grid of the level
-    void *L[kMaxLev];             // local expansions of the level
+    int64_t unit0[kMaxLev + 1];  // first block of each level
+    int64_t ntile[kMaxLev];      // tiles of the level (8 classes)
+    int nsplit[kMaxLev];         // K parts per tile
+    int64_t part0[kMaxLev];      // first partial slot of the level
+    const void *B[kMaxLev];      // padded operand grid of the level
+    int64_t bstride[kMaxLev];    // elements between its bf16 parts (mixed form)
+    void *L[kMaxLev];            // local expansions of the level
     int out_f64[kMaxLev];
+    int64_t fix0[kMaxLev + 1];   // first fix-up block of each level
 };
 
-struct M2LBlock {
-    int li;         // index into M2LLevels
+struct M2LUnit {
+    int li;         // index into M2LPlan
     int l;          // level
     int k;          // child class
+    int part;       // K part
+    int64_t tile;   // tile within the level
     int64_t pbase;  // first parent (Morton) of the tile
 };
 
-__device__ inline M2LBlock m2l_block(const M2LLevels &ls) {
-    M2LBlock t;
-    const int64_t b = blockIdx.x;
+// Uniform selection from the per-level kernel-argument arrays (an unrolled
+// select chain: indexing them with a runtime value would copy the whole
+// argument struct to scratch memory).
+template <typename T, int N>
+__device__ inline T pick(const T (&a)[N], int i) {
+    T v = a[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j)
+        if (i == j) v = a[j];
+    return v;
+}
+
+__device__ inline int find_level(const int64_t (&first)[kMaxLev + 1], int nlev, int64_t b) {
     int li = 0;
-    while (li + 1 < ls.nlev && b >= ls.block0[li + 1]) ++li;
-    t.li = li;
-    t.l = ls.level[li];
-    const int64_t h = (int64_t)1 << (t.l - 1), npar = h * h * h;
-    const int64_t lb = b - ls.block0[li];
+#pragma unroll
+    for (int j = 1; j < kMaxLev; ++j)
+        if (j < nlev && b >= first[j]) li = j;
+    return li;
+}
+
+__device__ inline void tile_place(int l, int64_t lt, int &k, int64_t &pbase) {
+    const int64_t h = (int64_t)1 << (l - 1), npar = h * h * h;
     if (npar >= 8 * kTile) {
-        const int64_t xcd = lb & 7, j = lb >> 3;
-        t.k = (int)(j & 7);
-        t.pbase = xcd * (npar >> 3) + (j >> 3) * kTile;
+        const int64_t xcd = lt & 7, j = lt >> 3;
+        k = (int)(j & 7);
+        pbase = xcd * (npar >> 3) + (j >> 3) * kTile;
     } else {
-        t.k = (int)(lb & 7);
-        t.pbase = (lb >> 3) * kTile;
-    }
-    return t;
-}
-
-// bf16 parts of FP32 values: part 0 = RNE(x), part i = RNE of the remainder
-__device__ inline uint32_t bf16_pack2(float a, float b, float &ra, float &rb) {
-    uint32_t ua = __float_as_uint(a), ub = __float_as_uint(b);
-    ua += 0x7fffu + ((ua >> 16) & 1u);
-    ub += 0x7fffu + ((ub >> 16) & 1u);
-    ua &= 0xffff0000u;
-    ub &= 0xffff0000u;
-    ra = a - __uint_as_float(ua);
-    rb = b - __uint_as_float(ub);
-    return (ua >> 16) | ub;
-}
-
-template <int NSPLIT>
-__device__ inline void split8(const float4 lo4, const float4 hi4, bf16x8 (&out)[NSPLIT]) {
-    float v[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
-#pragma unroll
-    for (int s = 0; s < NSPLIT; ++s) {
-        uint32_t w[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = bf16_pack2(v[2 * i], v[2 * i + 1], v[2 * i], v[2 * i + 1]);
-        out[s] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+        k = (int)(lt & 7);
+        pbase = (lt >> 3) * kTile;
     }
 }
 
-// Mixed form.  Operators and source multipoles are stored in FP32 and split
-// into NSPLIT bf16 parts on the fly (operators while being staged into LDS,
-// multipoles in registers).  Block = 8 waves = 128 targets; each wave owns
-// one 16-target column block and all row tiles.
-template <int NSPLIT, int RT>
-__global__ __launch_bounds__(512) void k_m2l_bf16(int P, M2LLevels ls, const float *__restrict__ A,
-                                                  const int2 *__restrict__ cls) {
-    constexpr int R = RT * 16;
-    constexpr int KP = 4;                      // pieces of 8 K per chunk (one MFMA K-step)
-    constexpr int ROWP = 8 * KP + 8;           // LDS row pitch in bf16
-    constexpr int NEL = R * 8 * KP;            // FP32 operator values per chunk
-    constexpr int EPT = (NEL / 4 + 511) / 512; // float4 per thread
-    __shared__ __align__(16) uint16_t As[2][NSPLIT][R][ROWP];
+__device__ inline M2LUnit m2l_unit(const M2LPlan &pl) {
+    M2LUnit u;
+    const int64_t b = blockIdx.x;
+    u.li = find_level(pl.unit0, pl.nlev, b);
+    u.l = pick(pl.level, u.li);
+    const int64_t nt = pick(pl.ntile, u.li);
+    const int64_t ul = b - pick(pl.unit0, u.li);
+    u.part = (int)(ul / nt);
+    u.tile = ul - (int64_t)u.part * nt;
+    tile_place(u.l, u.tile, u.k, u.pbase);
+    return u;
+}
+
+// target box of parent `pid` in class k: padded-grid offset and output row
+__device__ inline void target_of(int64_t pid, int k, int n, int64_t G, int S, int64_t &tpad,
+                                 int64_t &trow) {
+    const uint32_t pc = (uint32_t)pid;
+    const int64_t tx = 2 * (int64_t)compact3(pc) + (k & 1), ty = 2 * (int64_t)compact3(pc >> 1) + ((k >> 1) & 1),
+                  tz = 2 * (int64_t)compact3(pc >> 2) + (k >> 2);
+    tpad = ((tx + 3) + G * ((ty + 3) + G * (tz + 3))) * S;
+    trow = tx + (int64_t)n * (ty + (int64_t)n * tz);
+}
+
+// ------------------------------------------------------------ mixed form
+// gfx950 copies global memory straight into LDS: each lane's 16 bytes land
+// at (LDS base + 16 * lane); the base must be uniform over the wave.
+__device__ __forceinline__ void dma16(const void *g, void *lds) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                     (void __attribute__((address_space(3))) *)lds, 16, 0, 0);
+}
+
+// s_waitcnt with vmcnt = N (expcnt, lgkmcnt left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit counter");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Workgroup barrier with this wave's LDS reads complete.  Written as one asm
+// statement with a memory clobber so that the compiler moves no memory
+// access across it and adds no wait of its own for the global loads still
+// in flight (the operator ring is synchronised by the explicit vmcnt waits).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int NSPLIT, int P>
+struct MixCfg {
+    static constexpr int P2 = P * P, S = coef_stride(P), PPO = S / 8;
+    static constexpr int RT = m2l_rows(P) / 16, R = RT * 16;
+    static constexpr int NB = 2;                     // 16-column blocks per wave
+    static constexpr int NCHK = NSPLIT * RT;         // 1 KB operator chunks per K-step
+    static constexpr int CPW = (NCHK + 3) / 4;       // chunks loaded per wave
+    static constexpr int STAGE = 4 * CPW;            // chunk slots per ring stage
+    static constexpr int NA = 4;                     // operator ring stages in LDS
+    static constexpr int D = 4;                      // multipole register ring stages
+    static constexpr int NBL = NB * NSPLIT;          // multipole loads per K-step
+    // loads this wave issues after the operator chunks of step kc, counted at
+    // the top of step kc: the multipole loads of the step that issued them and
+    // everything of the NA - 2 steps between
+    static constexpr int VMW = NBL + (NA - 2) * (CPW + NBL);
+    static constexpr int NPC = kOffsetsPerClass * PPO;  // K pieces of a class
+    static constexpr int NCH = ((NPC + 3) / 4 + 7) / 8 * 8;  // K-steps, padded to 8
+    static_assert(VMW < 64, "vmcnt range");
+    static_assert(NA * STAGE <= 150, "LDS");
+};
+
+// Operators: pre-split bf16 parts [part][317][R][S] (operator 316 is zero);
+// multipoles: pre-split bf16 parts [part][G^3][S] of the padded grid (box 0
+// is a halo box, all zero).  K-step kc covers the 4 pieces (8 K each)
+// 4 kc .. 4 kc + 3 of the class's concatenated K range; a lane's piece is
+// g = 4 kc + q.  The operator chunk (part s, row tile r) of a K-step is
+// copied to LDS in MFMA fragment order (lane L = (g4, c): row 16 r + c,
+// piece 4 kc + g4), so a wave's A fragment read is one contiguous kilobyte.
+// All loads are unconditional: pieces past the end read the zero operator
+// and the zero box.
+template <int NSPLIT, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_m2l_bf16(
+    M2LPlan pl, const uint16_t *__restrict__ A, size_t astride, const int2 *__restrict__ cls,
+    double *__restrict__ partial) {
+    using C = MixCfg<NSPLIT, P>;
+    constexpr int P2 = C::P2, S = C::S, PPO = C::PPO, RT = C::RT, R = C::R, NB = C::NB;
+    constexpr int NCHK = C::NCHK, CPW = C::CPW, STAGE = C::STAGE, NA = C::NA, D = C::D;
+    constexpr int NPC = C::NPC, NCH = C::NCH;
+    __shared__ __align__(16) uint4 ring0[STAGE * 64];
+    __shared__ __align__(16) uint4 ring1[STAGE * 64];
+    __shared__ __align__(16) uint4 ring2[STAGE * 64];
+    __shared__ __align__(16) uint4 ring3[STAGE * 64];
     __shared__ int sA[kOffsetsPerClass], sB[kOffsetsPerClass];
+    static_assert(NA == 4 && D == 4, "the ring below is written out for four stages");
 
-    const M2LBlock tb = m2l_block(ls);
-    const int l = tb.l, k = tb.k;
-    const float *__restrict__ B = (const float *)ls.B[tb.li];
-    const int S = coef_stride(P), PPO = S / 8, P2 = P * P;
+    const M2LUnit u = m2l_unit(pl);
+    const int l = u.l, k = u.k;
+    const uint16_t *__restrict__ B = (const uint16_t *)pick(pl.B, u.li);
+    const int nsplit = pick(pl.nsplit, u.li);
+    const int64_t bstride = pick(pl.bstride, u.li);
     const int n = 1 << l, h = n >> 1;
     const int64_t G = n + 6;
     const int64_t npar = (int64_t)h * h * h;
-    const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = lane >> 4, col = lane & 15;
+    // K range of this part, in whole groups of 8 K-steps
+    const int kbeg = (int)((int64_t)u.part * (NCH / 8) / nsplit) * 8;
+    const int kend = (int)((int64_t)(u.part + 1) * (NCH / 8) / nsplit) * 8;
+    const int zeroA = kNumOffsets * R * S;
 
-    for (int i = tid; i < kOffsetsPerClass; i += 512) {
+    for (int i = tid; i < kOffsetsPerClass; i += 256) {
         const int2 e = cls[k * kOffsetsPerClass + i];
         sA[i] = e.y * R * S;
         sB[i] = (int)unpack_delta(e.x, G) * S;
     }
-    const int64_t pid = tb.pbase + wave * 16 + col;
-    const bool cvalid = pid < npar;
-    int64_t tpad, trow;
-    {
-        const uint32_t pc = cvalid ? (uint32_t)pid : 0u;
-        const int64_t tx = 2 * (int64_t)compact3(pc) + kx, ty = 2 * (int64_t)compact3(pc >> 1) + ky,
-                      tz = 2 * (int64_t)compact3(pc >> 2) + kz;
-        tpad = ((tx + 3) + G * ((ty + 3) + G * (tz + 3))) * S;
-        trow = tx + (int64_t)n * (ty + (int64_t)n * tz);
+    int64_t tpad[NB], trow[NB];
+    bool cvalid[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int64_t pid = u.pbase + wave * 16 * NB + b * 16 + col;
+        cvalid[b] = pid < npar;
+        target_of(cvalid[b] ? pid : 0, k, n, G, S, tpad[b], trow[b]);
     }
     __syncthreads();
-    const int NPC = kOffsetsPerClass * PPO;
-    const int NCH = (NPC + KP - 1) / KP;
 
-    // Operator chunk kc: R rows x 32 K as float4 quads (quad e -> row e/8,
-    // quad e%8); multipole chunk kc: 8 FP32 values of piece 4 kc + q.  Loads
-    // run D chunks ahead of the MFMAs through a ring of register stages.
-    // Every load is issued unconditionally (so the compiler can keep the ring
-    // in flight): pieces past the end read the zero operator appended to the
-    // tables (id 316) and the all-zero halo box at the start of the grid.
-    constexpr int D = 6;
-    const int zeroA = kNumOffsets * R * S;
-    const int NCHP = (NCH + D - 1) / D * D;
-    float4 ar[D][EPT];
-    float4 bl[D], bh[D];
-    auto load_stage = [&](int kc, float4 (&a)[EPT], float4 &b0, float4 &b1) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = min(tid + 512 * i, NEL / 4 - 1);
-            const int row = e >> 3, qd = e & 7;
-            const int g = KP * kc + (qd >> 1);
-            const int slot = min(g / PPO, kOffsetsPerClass - 1), cp = g - (g / PPO) * PPO;
-            const int base = g < NPC ? sA[slot] : zeroA;
-            a[i] = *(const float4 *)(A + base + row * S + 8 * cp + 4 * (qd & 1));
-        }
-        const int g = KP * kc + q;
-        const int slot = min(g / PPO, kOffsetsPerClass - 1), cp = g - (g / PPO) * PPO;
-        const float *src = g < NPC ? B + tpad + sB[slot] + 8 * cp : B;
-        b0 = *(const float4 *)src;
-        b1 = *(const float4 *)(src + 4);
+    // per lane and K-step: operator base + piece offset, multipole offset
+    auto piece = [&](int kc, int &aoff, int &boff, bool &inb) __attribute__((always_inline)) {
+        const int g = 4 * kc + q;
+        inb = g < NPC;
+        const int gs = inb ? g : 0;
+        const int slot = gs / PPO, cp = gs - slot * PPO;
+        aoff = (inb ? sA[slot] : zeroA) + col * S + 8 * cp;
+        boff = sB[slot] + 8 * cp;
     };
-    auto store_a = [&](int buf, const float4 (&a)[EPT]) {
+    auto issue_a = [&](int kc, uint4 *stage) __attribute__((always_inline)) {
+        int aoff, boff;
+        bool inb;
+        piece(kc, aoff, boff, inb);
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + 512 * i;
-            if (e < NEL / 4) {
-                const int row = e >> 3, qd = e & 7;
-                float v[4] = {a[i].x, a[i].y, a[i].z, a[i].w};
+        for (int i = 0; i < CPW; ++i) {
+            const int ch = 4 * i + wave;  // wave-uniform
+            const int c0 = ch < NCHK ? ch : 0;
+            const int sp = c0 / RT, r = c0 - sp * RT;
+            dma16(A + sp * astride + aoff + 16 * r * S, stage + ch * 64);
+        }
+    };
+    auto issue_b = [&](int kc, uint4 (&bv)[NB][NSPLIT]) __attribute__((always_inline)) {
+        int aoff, boff;
+        bool inb;
+        piece(kc, aoff, boff, inb);
 #pragma unroll
-                for (int s = 0; s < NSPLIT; ++s) {
-                    const uint32_t w0 = bf16_pack2(v[0], v[1], v[0], v[1]);
-                    const uint32_t w1 = bf16_pack2(v[2], v[3], v[2], v[3]);
-                    *(uint2 *)&As[buf][s][row][4 * qd] = make_uint2(w0, w1);
-                }
-            }
+        for (int b = 0; b < NB; ++b) {
+            const int64_t off = inb ? tpad[b] + boff : 0;
+#pragma unroll
+            for (int sp = 0; sp < NSPLIT; ++sp)
+                bv[b][sp] = *(const uint4 *)(B + sp * bstride + off);
         }
     };
 
-    f32x4 acc[RT];
-    f64x4 acc64[RT];
+    f32x4 acc[RT][NB];
+    f64x4 acc64[RT][NB];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        acc[r] = f32x4{0, 0, 0, 0};
-        acc64[r] = f64x4{0, 0, 0, 0};
-    }
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
-    for (int d = 0; d < D; ++d) load_stage(d, ar[d], bl[d], bh[d]);
-    store_a(0, ar[0]);
-    __syncthreads();
-    for (int kc0 = 0; kc0 < NCHP; kc0 += D) {
+        for (int b = 0; b < NB; ++b) {
+            acc[r][b] = f32x4{0, 0, 0, 0};
+            acc64[r][b] = f64x4{0, 0, 0, 0};
+        }
+
+    // prologue: operators of the first NA - 1 steps, multipoles of the first D
+    uint4 bv[D][NB][NSPLIT];
+    issue_a(kbeg + 0, ring0);
+    issue_a(kbeg + 1, ring1);
+    issue_a(kbeg + 2, ring2);
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int kc = kc0 + d;
-            store_a((kc + 1) & 1, ar[(d + 1) % D]);
-            bf16x8 bf[NSPLIT];
-            split8<NSPLIT>(bl[d], bh[d], bf);
-            const int cur = kc & 1;
+    for (int d = 0; d < D; ++d) issue_b(kbeg + d, bv[d]);
+
+    // one K-step; d (ring stage of both rings) is a compile-time constant
+    auto step = [&](int kc, auto dc) __attribute__((always_inline)) {
+        constexpr int d = decltype(dc)::value;
+        uint4 *const cur = d == 0 ? ring0 : d == 1 ? ring1 : d == 2 ? ring2 : ring3;
+        uint4 *const nxt = d == 0 ? ring3 : d == 1 ? ring0 : d == 2 ? ring1 : ring2;
+        wait_vm<C::VMW>();  // this wave's operator chunks of step kc are in LDS
+        lds_barrier();      // ... and everyone's; step kc - 1 is done with its stage
+        issue_a(kc + NA - 1, nxt);
+        bf16x8 bf[NB][NSPLIT];
 #pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                bf16x8 af[NSPLIT];
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int s = 0; s < NSPLIT; ++s) af[s] = *(const bf16x8 *)&As[cur][s][16 * r + col][8 * q];
+            for (int sp = 0; sp < NSPLIT; ++sp) bf[b][sp] = __builtin_bit_cast(bf16x8, bv[d][b][sp]);
 #pragma unroll
-                for (int i = 0; i < NSPLIT; ++i)
+        for (int r = 0; r < RT; ++r) {
+            bf16x8 af[NSPLIT];
 #pragma unroll
-                    for (int j = 0; i + j < NSPLIT; ++j)
-                        acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[r], 0, 0, 0);
+            for (int sp = 0; sp < NSPLIT; ++sp)
+                af[sp] = __builtin_bit_cast(bf16x8, cur[(sp * RT + r) * 64 + lane]);
+            // the small cross products first
+#pragma unroll
+            for (int t = NSPLIT - 1; t >= 0; --t)
+#pragma unroll
+                for (int a = 0; a <= t; ++a)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b][t - a], acc[r][b], 0, 0, 0);
+        }
+        issue_b(kc + D, bv[d]);
+    };
+    for (int kc = kbeg; kc < kend; kc += 8) {
+        step(kc + 0, std::integral_constant<int, 0>{});
+        step(kc + 1, std::integral_constant<int, 1>{});
+        step(kc + 2, std::integral_constant<int, 2>{});
+        step(kc + 3, std::integral_constant<int, 3>{});
+        step(kc + 4, std::integral_constant<int, 0>{});
+        step(kc + 5, std::integral_constant<int, 1>{});
+        step(kc + 6, std::integral_constant<int, 2>{});
+        step(kc + 7, std::integral_constant<int, 3>{});
+        // merge every 256 K terms
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc64[r][b][i] += (double)acc[r][b][i];
+                acc[r][b] = f32x4{0, 0, 0, 0};
             }
-            load_stage(kc + D, ar[d], bl[d], bh[d]);
-            if ((kc & 7) == 7) {  // merge every 256 K terms
+    }
+    wait_vm<0>();  // no copy into LDS outlives the block
+
+    if (nsplit == 1) {
+        void *Lout = pick(pl.L, u.li);
+        const int out_f64 = pick(pl.out_f64, u.li);
 #pragma unroll
-                for (int r = 0; r < RT; ++r) {
+        for (int b = 0; b < NB; ++b) {
+            if (!cvalid[b]) continue;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) acc64[r][i] += (double)acc[r][i];
-                    acc[r] = f32x4{0, 0, 0, 0};
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + 4 * q + i;
+                    if (row < P2) {
+                        if (out_f64)
+                            ((double *)Lout)[trow[b] * S + row] = acc64[r][b][i];
+                        else
+                            ((float *)Lout)[trow[b] * S + row] = (float)acc64[r][b][i];
+                    }
                 }
-            }
-            __syncthreads();
         }
+    } else {
+        const int64_t slot = pick(pl.part0, u.li) + (int64_t)u.part * pick(pl.ntile, u.li) + u.tile;
+        double *dst = partial + slot * kTile * P2;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + 4 * q + i;
+                    if (row < P2) dst[(wave * 16 * NB + b * 16 + col) * P2 + row] = acc64[r][b][i];
+                }
     }
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc64[r][i] += (double)acc[r][i];
-    if (!cvalid) return;
-    void *Lout = ls.L[tb.li];
-    const int out_f64 = ls.out_f64[tb.li];
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 16 * r + 4 * q + i;
-            if (row < P2) {
-                if (out_f64)
-                    ((double *)Lout)[trow * S + row] = acc64[r][i];
-                else
-                    ((float *)Lout)[trow * S + row] = (float)acc64[r][i];
-            }
-        }
 }
 
-// FP64: K-chunks of 16 (four MFMA K-steps); lane group q takes K index
-// 16 kc + 4 j + q in step j.
+// Sum of the K parts of a split tile, in part order.  One block per tile.
+__global__ __launch_bounds__(256) void k_m2l_fixup(int P, M2LPlan pl, const double *__restrict__ partial) {
+    const int64_t b = blockIdx.x;
+    const int li = find_level(pl.fix0, pl.nlev, b);
+    const int l = pick(pl.level, li), ns = pick(pl.nsplit, li);
+    const int64_t nt = pick(pl.ntile, li), lt = b - pick(pl.fix0, li);
+    int k;
+    int64_t pbase;
+    tile_place(l, lt, k, pbase);
+    const int n = 1 << l, h = n >> 1, S = coef_stride(P), P2 = P * P;
+    const int64_t npar = (int64_t)h * h * h;
+    void *Lout = pick(pl.L, li);
+    const int out_f64 = pick(pl.out_f64, li);
+    const double *src = partial + (pick(pl.part0, li) + lt) * kTile * P2;
+    for (int e = threadIdx.x; e < kTile * P2; e += 256) {
+        const int c = e / P2, row = e - c * P2;
+        const int64_t pid = pbase + c;
+        if (pid >= npar) continue;
+        double v = 0.0;
+        for (int j = 0; j < ns; ++j) v += src[(int64_t)j * nt * kTile * P2 + e];
+        int64_t tpad, trow;
+        target_of(pid, k, n, n + 6, S, tpad, trow);
+        if (out_f64)
+            ((double *)Lout)[trow * S + row] = v;
+        else
+            ((float *)Lout)[trow * S + row] = (float)v;
+    }
+}
+
+// ------------------------------------------------------------ plain form
+// K-chunks of 16 (four MFMA K-steps); lane group q takes K index
+// 16 kc + 4 j + q in step j.  Tiles as above, never split.
 template <int RT>
-__global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LLevels ls, const double *__restrict__ A,
+__global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double *__restrict__ A,
                                                  const int2 *__restrict__ cls) {
     constexpr int NB = 2, R = RT * 16, KC = 16, ROWP = KC + 1;
     constexpr int NEL = R * KC;
@@ -276,14 +413,13 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LLevels ls, const doub
     __shared__ double As[2][R][ROWP];
     __shared__ int sA[kOffsetsPerClass], sB[kOffsetsPerClass];
 
-    const M2LBlock tb = m2l_block(ls);
-    const int l = tb.l, k = tb.k;
-    const double *__restrict__ B = (const double *)ls.B[tb.li];
+    const M2LUnit u = m2l_unit(pl);
+    const int l = u.l, k = u.k;
+    const double *__restrict__ B = (const double *)pick(pl.B, u.li);
     const int S = coef_stride(P), P2 = P * P;
     const int n = 1 << l, h = n >> 1;
     const int64_t G = n + 6;
     const int64_t npar = (int64_t)h * h * h;
-    const int kx = k & 1, ky = (k >> 1) & 1, kz = k >> 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, col = lane & 15;
 
@@ -296,13 +432,9 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LLevels ls, const doub
     bool cvalid[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const int64_t pid = tb.pbase + wave * NB * 16 + b * 16 + col;
+        const int64_t pid = u.pbase + wave * NB * 16 + b * 16 + col;
         cvalid[b] = pid < npar;
-        const uint32_t pc = cvalid[b] ? (uint32_t)pid : 0u;
-        const int64_t tx = 2 * (int64_t)compact3(pc) + kx, ty = 2 * (int64_t)compact3(pc >> 1) + ky,
-                      tz = 2 * (int64_t)compact3(pc >> 2) + kz;
-        tpad[b] = ((tx + 3) + G * ((ty + 3) + G * (tz + 3))) * S;
-        trow[b] = tx + (int64_t)n * (ty + (int64_t)n * tz);
+        target_of(cvalid[b] ? pid : 0, k, n, G, S, tpad[b], trow[b]);
     }
     __syncthreads();
     const int NK = kOffsetsPerClass * P2;
@@ -387,7 +519,7 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LLevels ls, const doub
                 for (int b = 0; b < NB; ++b) bcur[j][b] = bnext[j][b];
         }
     }
-    double *Lout = (double *)ls.L[tb.li];
+    double *Lout = (double *)pick(pl.L, u.li);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (!cvalid[b]) continue;
@@ -402,54 +534,135 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LLevels ls, const doub
     }
 }
 
-static int64_t m2l_blocks(int l) {
+// ------------------------------------------------------------ host side
+static int64_t level_tiles(int l) {
     const int64_t h = (int64_t)1 << (l - 1);
-    const int64_t npar = h * h * h;
-    return 8 * ((npar + kTile - 1) / kTile);
+    return 8 * ((h * h * h + kTile - 1) / kTile);
 }
 
-hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
-                      const int *out_f64, const void *A, size_t astride, const int2 *cls,
+// Plan: levels largest first.  Levels with at least one tile per CU run
+// unsplit; the others share one split factor s, chosen by simulating the
+// in-order dispatch of blocks onto ncu one-block-per-CU slots (a whole tile
+// takes time 1, a part 1/s plus a small fixed overhead).
+static M2LPlan make_plan(int P, int L, bool allow_split, int ncu) {
+    M2LPlan pl{};
+    pl.nlev = L - 1;
+    const int S = coef_stride(P);
+    const int nch = (kOffsetsPerClass * (S / 8) + 3) / 4;  // K-steps of a tile
+    int64_t big = 0, small = 0;
+    for (int i = 0; i < pl.nlev; ++i) {
+        const int l = L - i;
+        pl.level[i] = l;
+        pl.ntile[i] = level_tiles(l);
+        if (pl.ntile[i] >= ncu) big += pl.ntile[i];
+        else small += pl.ntile[i];
+    }
+    int best_s = 1;
+    if (allow_split && small > 0 && ncu > 0) {
+        const double ovh = 8.0 / nch;
+        double best_t = 1e300;
+        const int smax = std::max(1, std::min(8, nch / 32));
+        for (int s = 1; s <= smax; ++s) {
+            std::priority_queue<double, std::vector<double>, std::greater<double>> slots;
+            for (int c = 0; c < ncu; ++c) slots.push(0.0);
+            auto run = [&](int64_t cnt, double dur) {
+                for (int64_t j = 0; j < cnt; ++j) {
+                    const double t0 = slots.top();
+                    slots.pop();
+                    slots.push(t0 + dur);
+                }
+            };
+            run(big, 1.0 + ovh);
+            run(small * s, 1.0 / s + ovh);
+            double t = 0;
+            while (!slots.empty()) {
+                t = slots.top();
+                slots.pop();
+            }
+            if (t < best_t - 1e-9) {
+                best_t = t;
+                best_s = s;
+            }
+        }
+    }
+    int64_t nu = 0, np = 0, nf = 0;
+    for (int i = 0; i < pl.nlev; ++i) {
+        pl.nsplit[i] = pl.ntile[i] >= ncu ? 1 : best_s;
+        pl.unit0[i] = nu;
+        nu += pl.ntile[i] * pl.nsplit[i];
+        pl.part0[i] = np;
+        pl.fix0[i] = nf;
+        if (pl.nsplit[i] > 1) {
+            np += pl.ntile[i] * pl.nsplit[i];
+            nf += pl.ntile[i];
+        }
+    }
+    pl.unit0[pl.nlev] = nu;
+    pl.fix0[pl.nlev] = nf;
+    return pl;
+}
+
+size_t m2l_partial_bytes(int P, int L, bool f64, int ncu) {
+    if (L < 2 || f64) return 0;
+    const M2LPlan pl = make_plan(P, L, true, ncu);
+    int64_t np = 0;
+    for (int i = 0; i < pl.nlev; ++i)
+        if (pl.nsplit[i] > 1) np += pl.ntile[i] * pl.nsplit[i];
+    return (size_t)np * kTile * P * P * sizeof(double);
+}
+
+hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, const size_t *bstride,
+                      void *const *Lc, const int *out_f64, const void *A, size_t astride,
+                      const int2 *cls, double *partial, size_t partial_bytes, int ncu,
                       hipStream_t st) {
     if (L < 2) return hipSuccess;
-    M2LLevels ls{};
-    ls.nlev = L - 1;
-    int64_t nb = 0;
-    for (int i = 0; i < ls.nlev; ++i) {
-        const int l = L - i;  // the largest level first: its blocks start earliest
-        ls.level[i] = l;
-        ls.block0[i] = nb;
-        ls.B[i] = B[l];
-        ls.L[i] = Lc[l];
-        ls.out_f64[i] = out_f64[l];
-        nb += m2l_blocks(l);
+    M2LPlan pl = make_plan(P, L, !f64, ncu);
+    for (int i = 0; i < pl.nlev; ++i) {
+        const int l = pl.level[i];
+        pl.B[i] = B[l];
+        pl.bstride[i] = f64 ? 0 : (int64_t)bstride[l];
+        pl.L[i] = Lc[l];
+        pl.out_f64[i] = out_f64[l];
     }
-    ls.block0[ls.nlev] = nb;
+    const unsigned nb = (unsigned)pl.unit0[pl.nlev];
+    const unsigned nfix = (unsigned)pl.fix0[pl.nlev];
+    if (!f64 && nfix > 0 && (!partial || partial_bytes < m2l_partial_bytes(P, L, f64, ncu)))
+        return hipErrorInvalidValue;
     const int RT = m2l_rows(P) / 16;
     if (f64) {
         switch (RT) {
 #define CASE(RR) \
-    case RR: k_m2l_f64<RR><<<(unsigned)nb, 256, 0, st>>>(P, ls, (const double *)A, cls); break;
+    case RR: k_m2l_f64<RR><<<nb, 256, 0, st>>>(P, pl, (const double *)A, cls); break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
             CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (nsplit == 3 && P > kMixedSplit3PMax) return hipErrorInvalidValue;
+#define CASE3(PP) \
+    case PP: k_m2l_bf16<3, PP><<<nb, 256, 0, st>>>(pl, (const uint16_t *)A, astride, cls, partial); break;
+#define CASE2(PP) \
+    case PP: k_m2l_bf16<2, PP><<<nb, 256, 0, st>>>(pl, (const uint16_t *)A, astride, cls, partial); break;
+    if (nsplit == 3) {
+        switch (P) {
+            CASE3(1) CASE3(2) CASE3(3) CASE3(4) CASE3(5) CASE3(6) CASE3(7) CASE3(8)
+            CASE3(9) CASE3(10) CASE3(11) CASE3(12) CASE3(13)
             default: return hipErrorInvalidValue;
         }
     } else {
-        switch (RT) {
-#define CASE(RR)                                                                                        \
-    case RR:                                                                                            \
-        if (nsplit == 3)                                                                                \
-            k_m2l_bf16<3, RR><<<(unsigned)nb, 512, 0, st>>>(P, ls, (const float *)A, cls);        \
-        else                                                                                            \
-            k_m2l_bf16<2, RR><<<(unsigned)nb, 512, 0, st>>>(P, ls, (const float *)A, cls);        \
-        break;
-            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-            CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
-#undef CASE
+        switch (P) {
+            CASE2(1) CASE2(2) CASE2(3) CASE2(4) CASE2(5) CASE2(6) CASE2(7) CASE2(8)
+            CASE2(9) CASE2(10) CASE2(11) CASE2(12) CASE2(13) CASE2(14) CASE2(15) CASE2(16)
             default: return hipErrorInvalidValue;
         }
     }
+#undef CASE3
+#undef CASE2
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nfix == 0) return e;
+    k_m2l_fixup<<<nfix, 256, 0, st>>>(P, pl, partial);
     return hipGetLastError();
 }
 
