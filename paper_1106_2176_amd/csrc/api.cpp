@@ -62,8 +62,10 @@ struct Ops {
     // [8][P2][P2] input-major transfer tables
     double *up64 = nullptr, *down64 = nullptr, *aup64 = nullptr, *adown64 = nullptr;
     float *up32 = nullptr, *down32 = nullptr, *aup32 = nullptr, *adown32 = nullptr;
-    // M2L tables [317][R][S] (316 operators + a zero one): FP64, and three
-    // bf16 parts [3][317][R][S] for the mixed form; forward and adjoint
+    // M2L tables (316 operators + a zero one): FP64 [317][R][S], and three
+    // bf16 parts [3][317][R/16][S/8][16][8] for the mixed form (a 16-row tile
+    // stored piece by piece, so that the mixed kernel's copy of four pieces
+    // of a row tile reads one contiguous kilobyte); forward and adjoint
     double *m2l64 = nullptr, *am2l64 = nullptr;
     uint16_t *m2lbf = nullptr, *am2lbf = nullptr;
     size_t bf_part = 0;  // elements per bf16 part
@@ -168,12 +170,16 @@ fmm_status build_ops(int p, Ops **out) {
     t32 = up32f(aup); UP64(aup32, t32)
     t32 = up32f(adown); UP64(adown32, t32)
     std::vector<uint16_t> fbf(3 * nT), afbf(3 * nT);
+    const int PPO = S / 8;
     for (size_t i = 0; i < nT; ++i) {
+        const size_t id = i / ((size_t)R * S), rem = i % ((size_t)R * S);
+        const int row = (int)(rem / S), col = (int)(rem % S);
+        const size_t j = id * R * S + (((size_t)(row / 16) * PPO + col / 8) * 16 + row % 16) * 8 + col % 8;
         uint16_t pt[3];
         split_bf16(f64[i], 3, pt);
-        for (int k = 0; k < 3; ++k) fbf[k * nT + i] = pt[k];
+        for (int k = 0; k < 3; ++k) fbf[k * nT + j] = pt[k];
         split_bf16(af64[i], 3, pt);
-        for (int k = 0; k < 3; ++k) afbf[k * nT + i] = pt[k];
+        for (int k = 0; k < 3; ++k) afbf[k * nT + j] = pt[k];
     }
     UP64(m2l64, f64) UP64(am2l64, af64) UP64(m2lbf, fbf) UP64(am2lbf, afbf)
     UP64(cls, cls)
@@ -327,7 +333,7 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
             CHK(ensure(t, t->M[l], nb * S * es, st));
             CHK(ensure(t, t->Lc[l], nb * S * es, st));
             const size_t g = ((size_t)1 << l) + 6;
-            const size_t pk = g * g * g * S * (f64 ? 8 : 2 * nsplit);
+            const size_t pk = g * g * g * S * (f64 ? 8 : 4);
             CHK(ensure(t, t->pack[l], pk, st));
         }
         const size_t pbytes = m2l_partial_bytes(P, L, f64, t->ncu);
@@ -344,25 +350,21 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
         CHK(rec(t, 3, st));
         for (int l = 2; l <= L; ++l) {
             const size_t g = ((size_t)1 << l) + 6;
-            HIPCHK(launch_pack(P, l, level_f64(t, l), f64 ? 0 : nsplit, t->M[l].p, t->pack[l].p,
-                               g * g * g * S, st));
+            HIPCHK(launch_pack(P, l, level_f64(t, l), f64, t->M[l].p, t->pack[l].p, st));
         }
         CHK(rec(t, 4, st));
         // M2L at every level >= 2 in one launch (the levels are independent)
         {
             void *Bp[FMM_MAX_LEVEL + 1] = {}, *Lp[FMM_MAX_LEVEL + 1] = {};
-            size_t bst[FMM_MAX_LEVEL + 1] = {};
             int of64[FMM_MAX_LEVEL + 1] = {};
             for (int l = 2; l <= L; ++l) {
-                const size_t g = ((size_t)1 << l) + 6;
                 Bp[l] = t->pack[l].p;
-                bst[l] = g * g * g * S;
                 Lp[l] = t->Lc[l].p;
                 of64[l] = level_f64(t, l);
             }
             const void *A = f64 ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
                                 : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
-            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, bst, Lp, of64, A, o->bf_part, o->cls,
+            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, o->bf_part, o->cls,
                               (double *)t->m2lpart.p, t->m2lpart.cap, t->ncu, st));
         }
         CHK(rec(t, 5, st));

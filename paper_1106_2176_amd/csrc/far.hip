@@ -247,61 +247,72 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
 // DOWN: out[child c][o] += sum_k tab[c][k][o] in[parent][k]
 // tab is [8][p^2][p^2] input-major.  Both are small GEMMs (rows = output
 // coefficients, columns = parents) run on the FP64 matrix cores whatever the
-// storage precision of the levels: one wave per tile of 16 output rows x 16
+// storage precision of the levels, in tiles of 16 output rows x 16
 // consecutive parents, K in steps of 4 (v_mfma_f64_16x16x4_f64; A lane l
 // holds row l%16, K l/16; B lane l holds K l/16, column l%16; result lane l,
 // item i holds row l/16 + 4i of column l%16).
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_up(int P, int lp, const Tin *__restrict__ in,
-                                            Tout *__restrict__ out, const double *__restrict__ tab) {
-    const int P2 = P * P, S = coef_stride(P), K = 8 * P2;
+// UP: a block = one tile of 16 output rows x 16 parents; its 4 waves take a
+// quarter of K = 8 p^2 each and their partial tiles are summed in wave order
+// through LDS.
+template <int P, typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_up(int lp, const Tin *__restrict__ in, Tout *__restrict__ out,
+                                            const double *__restrict__ tab) {
+    constexpr int P2 = P * P, S = coef_stride(P), K = 8 * P2, NIT = (K + 15) / 16;
+    constexpr int NITW = (NIT + 3) / 4;  // K-chunks per wave
+    __shared__ f64x4_t red[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, col = lane & 15;
-    const int rt = blockIdx.y * 4 + wave;  // row tile
-    if (rt * 16 >= P2) return;
+    const int rt = blockIdx.y;  // row tile
     const int64_t np = (int64_t)1 << lp, nc = 2 * np, npar = np * np * np;
     const int64_t par = (int64_t)blockIdx.x * 16 + col;
     const bool valid = par < npar;
     const int64_t pc = valid ? par : 0;
     const int64_t pi = pc % np, pj = (pc / np) % np, pk = pc / (np * np);
-    int64_t child[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-        child[c] = ((2 * pi + (c & 1)) + nc * ((2 * pj + ((c >> 1) & 1)) + nc * (2 * pk + ((c >> 2) & 1)))) * S;
+    const int64_t child0 = ((2 * pi) + nc * ((2 * pj) + nc * (2 * pk))) * S;  // child c = 0
     const int orow = rt * 16 + col;  // A row held by this lane
     const bool rowok = orow < P2;
+    const int arow = rowok ? orow : 0;
     f64x4_t acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    // fixed trip count and unconditional (clamped) loads, so that the loads
+    // of several K-chunks are in flight at once
+#pragma unroll
+    for (int it = 0; it < NITW; ++it) {
         double a[4], b[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int kk = k0 + 4 * j + q;
-            a[j] = 0.0;
-            b[j] = 0.0;
-            if (kk < K) {
-                const int c = kk / P2, k = kk - c * P2;
-                if (rowok) a[j] = tab[((size_t)c * P2 + k) * P2 + orow];
-                b[j] = (double)in[child[c] + k];
-            }
+            const int kk = 16 * (wave * NITW + it) + 4 * j + q;
+            const bool ok = kk < K;
+            const int kc = ok ? kk : K - 1;
+            const int c = kc / P2, k = kc - c * P2;
+            const int64_t ch = child0 + ((c & 1) + nc * (((c >> 1) & 1) + nc * (c >> 2))) * S;
+            const double av = tab[((size_t)c * P2 + k) * P2 + arow];
+            const double bv = (double)in[ch + k];
+            a[j] = (ok && rowok) ? av : 0.0;
+            b[j] = ok ? bv : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
     }
-    if (!valid) return;
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0 || !valid) return;
+    f64x4_t sum = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) sum += red[w][lane];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int o = rt * 16 + q + 4 * i;
-        if (o < P2) out[par * S + o] = (Tout)acc[i];
+        if (o < P2) out[par * S + o] = (Tout)sum[i];
     }
 }
 
 // rows of the stacked [8 p^2] output (child-major); K = p^2
-template <typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_down(int P, int lp, const Tin *__restrict__ in,
-                                              Tout *__restrict__ out, const double *__restrict__ tab) {
-    const int P2 = P * P, S = coef_stride(P), M = 8 * P2;
+template <int P, typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_down(int lp, const Tin *__restrict__ in, Tout *__restrict__ out,
+                                              const double *__restrict__ tab) {
+    constexpr int P2 = P * P, S = coef_stride(P), M = 8 * P2, NIT = (P2 + 15) / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = lane >> 4, col = lane & 15;
     const int rt = blockIdx.y * 4 + wave;
@@ -314,17 +325,18 @@ __global__ __launch_bounds__(256) void k_down(int P, int lp, const Tin *__restri
     const bool rowok = arow < M;
     const int ac = rowok ? arow / P2 : 0, ao = rowok ? arow - ac * P2 : 0;
     f64x4_t acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < P2; k0 += 16) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
         double a[4], b[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int k = k0 + 4 * j + q;
-            a[j] = 0.0;
-            b[j] = 0.0;
-            if (k < P2) {
-                if (rowok) a[j] = tab[((size_t)ac * P2 + k) * P2 + ao];
-                b[j] = (double)in[pc * S + k];
-            }
+            const int kk = 16 * it + 4 * j + q;
+            const bool ok = kk < P2;
+            const int k = ok ? kk : P2 - 1;
+            const double av = tab[((size_t)ac * P2 + k) * P2 + ao];
+            const double bv = (double)in[pc * S + k];
+            a[j] = (ok && rowok) ? av : 0.0;
+            b[j] = ok ? bv : 0.0;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
@@ -344,58 +356,22 @@ __global__ __launch_bounds__(256) void k_down(int P, int lp, const Tin *__restri
 
 // -------------------------------------------------------------- M2L operand
 // Pack level-l multipoles into a zero-padded grid with a 3-box halo
-// [(n+6)^3][S]: FP64 for the plain form; for the mixed form NSPLIT bf16
-// parts [part][(n+6)^3][S] with x = x0 + x1 (+ x2), each part the
-// round-to-nearest-even bf16 of what the previous parts leave (hardware
-// v_cvt_pk_bf16_f32), computed from the value rounded to FP32.
-__device__ inline void pad_index(int64_t e, int S, int64_t n, int64_t g, int &c, int64_t &src,
-                                 bool &inside) {
-    c = (int)(e % S);
-    const int64_t b = e / S;
-    const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
-    inside = x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n;
-    src = inside ? (x + n * (y + n * z)) * S + c : 0;
-}
-
-__global__ void k_pack_f64(int P, int l, const double *__restrict__ in, double *__restrict__ out) {
+// [(n+6)^3][S]: FP64 for the plain form, FP32 for the mixed form (the M2L
+// kernel splits it into bf16 parts in registers).
+template <typename Tin, typename Tout>
+__global__ void k_pack(int P, int l, const Tin *__restrict__ in, Tout *__restrict__ out) {
     const int S = coef_stride(P), P2 = P * P;
     const int64_t n = 1 << l, g = n + 6;
     const int64_t total = g * g * g * S;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
-    int c;
-    int64_t src;
-    bool inside;
-    pad_index(e, S, n, g, c, src, inside);
-    out[e] = (inside && c < P2) ? in[src] : 0.0;
-}
-
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
-
-// two coefficients per thread (S is even)
-template <typename Tin>
-__global__ void k_pack_bf16(int P, int l, int parts, const Tin *__restrict__ in,
-                            uint16_t *__restrict__ out, size_t part_stride) {
-    const int S = coef_stride(P), P2 = P * P;
-    const int64_t n = 1 << l, g = n + 6;
-    const int64_t total = g * g * g * S;
-    const int64_t e = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (e >= total) return;
-    int c;
-    int64_t src;
-    bool inside;
-    pad_index(e, S, n, g, c, src, inside);
-    f32x2_t v = {0.0f, 0.0f};
-    if (inside && c < P2) v.x = (float)in[src];
-    if (inside && c + 1 < P2) v.y = (float)in[src + 1];
-    for (int s = 0; s < parts; ++s) {
-        const bf16x2_t hb = __builtin_convertvector(v, bf16x2_t);
-        const uint32_t w = __builtin_bit_cast(uint32_t, hb);
-        *(uint32_t *)(out + s * part_stride + e) = w;
-        v.x -= __uint_as_float(w << 16);
-        v.y -= __uint_as_float(w & 0xffff0000u);
-    }
+    const int c = (int)(e % S);
+    const int64_t b = e / S;
+    const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
+    Tout v = Tout(0);
+    if (c < P2 && x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n)
+        v = (Tout)in[(x + n * (y + n * z)) * S + c];
+    out[e] = v;
 }
 
 // ------------------------------------------------------------ gather/combine
@@ -507,19 +483,19 @@ hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *s
 }
 
 // in/out storage precisions: 0 = f32, 1 = f64 (the arithmetic is FP64)
-hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
-                           void *out, const void *tab32, const void *tab64, hipStream_t st) {
-    (void)tab32;
+template <int P>
+static void transfer_p(bool up, int lp, int in_f64, int out_f64, const void *in, void *out,
+                       const double *tab, hipStream_t st) {
     const int64_t np = (int64_t)1 << (3 * lp);
-    const int rows = up ? P * P : 8 * P * P;
-    const dim3 grid((unsigned)((np + 15) / 16), (unsigned)((rows + 63) / 64));
-    const double *tab = (const double *)tab64;
-#define LAUNCH(TI, TO)                                                                           \
-    do {                                                                                         \
-        if (up)                                                                                  \
-            k_up<TI, TO><<<grid, 256, 0, st>>>(P, lp, (const TI *)in, (TO *)out, tab);          \
-        else                                                                                     \
-            k_down<TI, TO><<<grid, 256, 0, st>>>(P, lp, (const TI *)in, (TO *)out, tab);        \
+    // UP: one block per 16 rows (its waves split K); DOWN: one wave per 16 rows
+    const dim3 grid((unsigned)((np + 15) / 16),
+                    up ? (unsigned)((P * P + 15) / 16) : (unsigned)((8 * P * P + 63) / 64));
+#define LAUNCH(TI, TO)                                                                      \
+    do {                                                                                    \
+        if (up)                                                                             \
+            k_up<P, TI, TO><<<grid, 256, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);     \
+        else                                                                                \
+            k_down<P, TI, TO><<<grid, 256, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);   \
     } while (0)
     if (in_f64 && out_f64)
         LAUNCH(double, double);
@@ -530,25 +506,35 @@ hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, cons
     else
         LAUNCH(float, float);
 #undef LAUNCH
+}
+
+hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
+                           void *out, const void *tab32, const void *tab64, hipStream_t st) {
+    (void)tab32;
+    const double *tab = (const double *)tab64;
+    switch (P) {
+#define CASE(PP) \
+    case PP: transfer_p<PP>(up, lp, in_f64, out_f64, in, out, tab, st); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-// parts == 0: FP64 grid (plain form); otherwise `parts` bf16 grids spaced
-// part_stride elements apart (mixed form)
-hipError_t launch_pack(int P, int l, bool in_f64, int parts, const void *in, void *out,
-                       size_t part_stride, hipStream_t st) {
+// f64_out: FP64 grid (plain form); otherwise FP32 (mixed form)
+hipError_t launch_pack(int P, int l, bool in_f64, bool f64_out, const void *in, void *out,
+                       hipStream_t st) {
     const int64_t g = ((int64_t)1 << l) + 6;
     const int64_t total = g * g * g * coef_stride(P);
-    if (parts == 0) {
-        k_pack_f64<<<nblk(total, 256), 256, 0, st>>>(P, l, (const double *)in, (double *)out);
-    } else {
-        if (part_stride < (size_t)total) return hipErrorInvalidValue;
-        const unsigned gr = nblk(total / 2, 256);
-        if (in_f64)
-            k_pack_bf16<double><<<gr, 256, 0, st>>>(P, l, parts, (const double *)in, (uint16_t *)out, part_stride);
-        else
-            k_pack_bf16<float><<<gr, 256, 0, st>>>(P, l, parts, (const float *)in, (uint16_t *)out, part_stride);
-    }
+    const unsigned gr = nblk(total, 256);
+    if (f64_out)
+        k_pack<double, double><<<gr, 256, 0, st>>>(P, l, (const double *)in, (double *)out);
+    else if (in_f64)
+        k_pack<double, float><<<gr, 256, 0, st>>>(P, l, (const double *)in, (float *)out);
+    else
+        k_pack<float, float><<<gr, 256, 0, st>>>(P, l, (const float *)in, (float *)out);
     return hipGetLastError();
 }
 

@@ -32,8 +32,8 @@ hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *s
                       const void *Lc, double4 *out, hipStream_t st);
 hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
                            void *out, const void *tab32, const void *tab64, hipStream_t st);
-hipError_t launch_pack(int P, int l, bool in_f64, int parts, const void *in, void *out,
-                       size_t part_stride, hipStream_t st);
+hipError_t launch_pack(int P, int l, bool in_f64, bool f64_out, const void *in, void *out,
+                       hipStream_t st);
 hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm, const void *q,
                            void *xyzq, hipStream_t st);
 hipError_t launch_combine(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
@@ -44,14 +44,13 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
                                const void *Eq, void *gq, void *gx, hipStream_t st);
 
 // m2l.hip: every level 2..L in one launch; B[l], Lc[l] indexed by level.
-// Mixed form: A = bf16 operator parts spaced astride elements apart, B[l] =
-// bf16 multipole parts spaced bstride[l] elements apart (>= the level's padded
-// grid), `partial` >= m2l_partial_bytes() of FP64 scratch.
+// Mixed form: A = bf16 operator parts spaced astride elements apart (layout
+// [part][317][R/16][S/8][16][8]), B[l] = FP32 padded multipole grid,
+// `partial` >= m2l_partial_bytes() of FP64 scratch.
 size_t m2l_partial_bytes(int P, int L, bool f64, int ncu);
 constexpr int kMixedSplit3PMax = 13;  // LDS holds the 3-part operator ring up to p = 13
-hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, const size_t *bstride,
-                      void *const *Lc, const int *out_f64, const void *A, size_t astride,
-                      const int2 *cls, double *partial, size_t partial_bytes, int ncu,
+hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
+                      const int *out_f64, const void *A, size_t astride, const int2 *cls, double *partial, size_t partial_bytes, int ncu,
                       hipStream_t st);
 
 }  // namespace fmm

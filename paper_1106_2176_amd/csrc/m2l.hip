@@ -15,9 +15,10 @@
 // grid with a 3-box halo, so t + d is always a valid address and the shift
 // of every column is the same constant for a given offset.
 //
-// Mixed form: both operands are stored pre-split into bf16 parts
-// x = x0 + x1 (+ x2) (operators once at set-up, multipoles by the packing
-// kernel); the products x_i y_j with i + j < parts are accumulated by
+// Mixed form: operands split into bf16 parts x = x0 + x1 (+ x2), each part
+// the round-to-nearest-even bf16 of what the previous parts leave
+// (operators once at set-up, multipoles in registers from FP32); the
+// products x_i y_j with i + j < parts are accumulated by
 // v_mfma_f32_16x16x32_bf16 in FP32 and merged into FP64 accumulators every
 // 256 K terms.  Plain form: v_mfma_f64_16x16x4_f64.
 // MFMA operand layout (16 x 16 tiles, 64 lanes): A lane l holds row l%16,
@@ -66,7 +67,6 @@ struct M2LPlan {
     int nsplit[kMaxLev];         // K parts per tile
     int64_t part0[kMaxLev];      // first partial slot of the level
     const void *B[kMaxLev];      // padded operand grid of the level
-    int64_t bstride[kMaxLev];    // elements between its bf16 parts (mixed form)
     void *L[kMaxLev];            // local expansions of the level
     int out_f64[kMaxLev];
     int64_t fix0[kMaxLev + 1];   // first fix-up block of each level
@@ -159,6 +159,37 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// bf16 parts of 8 FP32 values (one MFMA operand piece), hardware
+// v_cvt_pk_bf16_f32 (round to nearest even) on what the previous parts leave
+template <int NSPLIT>
+__device__ __forceinline__ void split8(const float4 lo4, const float4 hi4, bf16x8 (&out)[NSPLIT]) {
+    f32x2_t v[4] = {{lo4.x, lo4.y}, {lo4.z, lo4.w}, {hi4.x, hi4.y}, {hi4.z, hi4.w}};
+#pragma unroll
+    for (int s = 0; s < NSPLIT; ++s) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            w[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector(v[i], bf16x2_t));
+            if (s + 1 < NSPLIT) {
+                v[i].x -= __uint_as_float(w[i] << 16);
+                v[i].y -= __uint_as_float(w[i] & 0xffff0000u);
+            }
+        }
+        out[s] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+    }
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
 template <int NSPLIT, int P>
 struct MixCfg {
     static constexpr int P2 = P * P, S = coef_stride(P), PPO = S / 8;
@@ -167,26 +198,33 @@ struct MixCfg {
     static constexpr int NCHK = NSPLIT * RT;         // 1 KB operator chunks per K-step
     static constexpr int CPW = (NCHK + 3) / 4;       // chunks loaded per wave
     static constexpr int STAGE = 4 * CPW;            // chunk slots per ring stage
-    static constexpr int NA = 4;                     // operator ring stages in LDS
-    static constexpr int D = 4;                      // multipole register ring stages
-    static constexpr int NBL = NB * NSPLIT;          // multipole loads per K-step
-    // loads this wave issues after the operator chunks of step kc, counted at
-    // the top of step kc: the multipole loads of the step that issued them and
-    // everything of the NA - 2 steps between
+    // operator ring stages in LDS (4; deeper rings, 6 or 8 where LDS holds
+    // them, measured no faster and spill registers at p = 10); multipole ring
+    // stages in registers: 4.  The step loop is unrolled over both rings
+    // (UNROLL = lcm) with an FP64 merge every MERGE <= 8 steps.
+    static constexpr int NA = 4;
+    static constexpr int D = 4;
+    static constexpr int UNROLL = NA == 6 ? 12 : 8;
+    static constexpr int MERGE = NA == 6 ? 6 : 8;
+    static constexpr int NBL = NB * 2;               // multipole loads per K-step
+    // loads this wave issues after its operator chunks of step kc + 1 (issued
+    // in step kc + 1 - NA), counted at the top of step kc: the multipole loads
+    // of that step and everything of the NA - 2 steps between
     static constexpr int VMW = NBL + (NA - 2) * (CPW + NBL);
     static constexpr int NPC = kOffsetsPerClass * PPO;  // K pieces of a class
-    static constexpr int NCH = ((NPC + 3) / 4 + 7) / 8 * 8;  // K-steps, padded to 8
+    static constexpr int NCH = ((NPC + 3) / 4 + UNROLL - 1) / UNROLL * UNROLL;  // K-steps, padded
     static_assert(VMW < 64, "vmcnt range");
     static_assert(NA * STAGE <= 150, "LDS");
 };
 
-// Operators: pre-split bf16 parts [part][317][R][S] (operator 316 is zero);
-// multipoles: pre-split bf16 parts [part][G^3][S] of the padded grid (box 0
-// is a halo box, all zero).  K-step kc covers the 4 pieces (8 K each)
-// 4 kc .. 4 kc + 3 of the class's concatenated K range; a lane's piece is
-// g = 4 kc + q.  The operator chunk (part s, row tile r) of a K-step is
-// copied to LDS in MFMA fragment order (lane L = (g4, c): row 16 r + c,
-// piece 4 kc + g4), so a wave's A fragment read is one contiguous kilobyte.
+// Operators: pre-split bf16 parts [part][317][R/16][S/8][16][8] (operator
+// 316 is zero); multipoles: the FP32 padded grid [G^3][S] (box 0 is a halo
+// box, all zero).  K-step kc covers the 4 pieces (8 K each) 4 kc .. 4 kc + 3
+// of the class's concatenated K range; a lane's piece is g = 4 kc + q.  The
+// operator chunk (part s, row tile r) of a K-step is copied to LDS in MFMA
+// fragment order (lane L = (g4, c): row 16 r + c, piece 4 kc + g4): one
+// contiguous kilobyte of the operator table unless the 4 pieces straddle two
+// offsets, and one contiguous kilobyte of LDS for the wave's fragment read.
 // All loads are unconditional: pieces past the end read the zero operator
 // and the zero box.
 template <int NSPLIT, int P>
@@ -196,34 +234,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     using C = MixCfg<NSPLIT, P>;
     constexpr int P2 = C::P2, S = C::S, PPO = C::PPO, RT = C::RT, R = C::R, NB = C::NB;
     constexpr int NCHK = C::NCHK, CPW = C::CPW, STAGE = C::STAGE, NA = C::NA, D = C::D;
-    constexpr int NPC = C::NPC, NCH = C::NCH;
+    constexpr int NPC = C::NPC, NCH = C::NCH, UNROLL = C::UNROLL, MERGE = C::MERGE;
+    // one LDS array per ring stage (arrays of stages the ring does not use
+    // are never referenced and take no space)
     __shared__ __align__(16) uint4 ring0[STAGE * 64];
     __shared__ __align__(16) uint4 ring1[STAGE * 64];
     __shared__ __align__(16) uint4 ring2[STAGE * 64];
     __shared__ __align__(16) uint4 ring3[STAGE * 64];
-    __shared__ int sA[kOffsetsPerClass], sB[kOffsetsPerClass];
-    static_assert(NA == 4 && D == 4, "the ring below is written out for four stages");
+    __shared__ __align__(16) uint4 ring4[STAGE * 64];
+    __shared__ __align__(16) uint4 ring5[STAGE * 64];
+    __shared__ __align__(16) uint4 ring6[STAGE * 64];
+    __shared__ __align__(16) uint4 ring7[STAGE * 64];
+    auto stage = [&](auto ic) __attribute__((always_inline)) -> uint4 * {
+        constexpr int i = decltype(ic)::value % NA;
+        if constexpr (i == 0) return ring0;
+        else if constexpr (i == 1) return ring1;
+        else if constexpr (i == 2) return ring2;
+        else if constexpr (i == 3) return ring3;
+        else if constexpr (i == 4) return ring4;
+        else if constexpr (i == 5) return ring5;
+        else if constexpr (i == 6) return ring6;
+        else return ring7;
+    };
+    // per offset slot: operator base and source shift; slot 189 (pieces past
+    // the end) holds the zero operator
+    __shared__ int sA[kOffsetsPerClass + 1], sB[kOffsetsPerClass + 1];
 
     const M2LUnit u = m2l_unit(pl);
     const int l = u.l, k = u.k;
-    const uint16_t *__restrict__ B = (const uint16_t *)pick(pl.B, u.li);
+    const float *__restrict__ B = (const float *)pick(pl.B, u.li);
     const int nsplit = pick(pl.nsplit, u.li);
-    const int64_t bstride = pick(pl.bstride, u.li);
     const int n = 1 << l, h = n >> 1;
     const int64_t G = n + 6;
     const int64_t npar = (int64_t)h * h * h;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = lane >> 4, col = lane & 15;
-    // K range of this part, in whole groups of 8 K-steps
-    const int kbeg = (int)((int64_t)u.part * (NCH / 8) / nsplit) * 8;
-    const int kend = (int)((int64_t)(u.part + 1) * (NCH / 8) / nsplit) * 8;
-    const int zeroA = kNumOffsets * R * S;
-
-    for (int i = tid; i < kOffsetsPerClass; i += 256) {
-        const int2 e = cls[k * kOffsetsPerClass + i];
-        sA[i] = e.y * R * S;
-        sB[i] = (int)unpack_delta(e.x, G) * S;
+    // K range of this part, in whole unrolled groups of steps
+    const int kbeg = (int)((int64_t)u.part * (NCH / UNROLL) / nsplit) * UNROLL;
+    const int kend = (int)((int64_t)(u.part + 1) * (NCH / UNROLL) / nsplit) * UNROLL;
+    for (int i = tid; i <= kOffsetsPerClass; i += 256) {
+        if (i == kOffsetsPerClass) {
+            sA[i] = kNumOffsets * R * S;
+            sB[i] = 0;
+        } else {
+            const int2 e = cls[k * kOffsetsPerClass + i];
+            sA[i] = e.y * R * S;
+            sB[i] = (int)unpack_delta(e.x, G) * S;
+        }
     }
     int64_t tpad[NB], trow[NB];
     bool cvalid[NB];
@@ -236,12 +294,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __syncthreads();
 
     // per lane and K-step: operator base + piece offset, multipole offset
+    // (table reads are unconditional: a branch here would split the step
+    // into basic blocks)
     auto piece = [&](int kc, int &aoff, int &boff, bool &inb) __attribute__((always_inline)) {
         const int g = 4 * kc + q;
         inb = g < NPC;
-        const int gs = inb ? g : 0;
-        const int slot = gs / PPO, cp = gs - slot * PPO;
-        aoff = (inb ? sA[slot] : zeroA) + col * S + 8 * cp;
+        const int q8 = g / PPO;
+        const int slot = inb ? q8 : kOffsetsPerClass;
+        const int cp = inb ? g - q8 * PPO : 0;
+        aoff = sA[slot] + 128 * cp + 8 * col;
         boff = sB[slot] + 8 * cp;
     };
     auto issue_a = [&](int kc, uint4 *stage) __attribute__((always_inline)) {
@@ -256,16 +317,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             dma16(A + sp * astride + aoff + 16 * r * S, stage + ch * 64);
         }
     };
-    auto issue_b = [&](int kc, uint4 (&bv)[NB][NSPLIT]) __attribute__((always_inline)) {
+    auto issue_b = [&](int kc, float4 (&bv)[NB][2]) __attribute__((always_inline)) {
         int aoff, boff;
         bool inb;
         piece(kc, aoff, boff, inb);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int64_t off = inb ? tpad[b] + boff : 0;
-#pragma unroll
-            for (int sp = 0; sp < NSPLIT; ++sp)
-                bv[b][sp] = *(const uint4 *)(B + sp * bstride + off);
+            const float *src = B + (inb ? tpad[b] + boff : 0);
+            bv[b][0] = *(const float4 *)src;
+            bv[b][1] = *(const float4 *)(src + 4);
         }
     };
 
@@ -279,54 +339,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             acc64[r][b] = f64x4{0, 0, 0, 0};
         }
 
-    // prologue: operators of the first NA - 1 steps, multipoles of the first D
-    uint4 bv[D][NB][NSPLIT];
-    issue_a(kbeg + 0, ring0);
-    issue_a(kbeg + 1, ring1);
-    issue_a(kbeg + 2, ring2);
+    // Pipeline: an NA-stage operator ring in LDS and a D-stage multipole ring
+    // in registers.  At the top of step kc the A fragments and the bf16
+    // parts of the multipoles of step kc are already in registers (read and
+    // split during step kc - 1), so the matrix cores start right after the
+    // barrier.  Step kc: wait until this wave's copies for step kc + 1 are in
+    // LDS; barrier (everyone's are, and everyone has read stage kc); start
+    // the copy of step kc + NA into stage kc; issue the MFMAs of step kc
+    // while reading the A fragments of step kc + 1 and splitting its
+    // multipoles; load the multipoles of step kc + D.  i (the step's
+    // position in the unrolled group, hence both ring stages) is a
+    // compile-time constant.
+    auto read_a = [&](const uint4 *st, bf16x8 (&af)[RT][NSPLIT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int sp = 0; sp < NSPLIT; ++sp)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+                af[r][sp] = __builtin_bit_cast(bf16x8, st[(sp * RT + r) * 64 + lane]);
+    };
+    float4 bv[D][NB][2];
+    bf16x8 af[RT][NSPLIT], bf[NB][NSPLIT];
+    static_for<0, NA>([&](auto ic) __attribute__((always_inline)) {
+        issue_a(kbeg + decltype(ic)::value, stage(ic));
+    });
 #pragma unroll
     for (int d = 0; d < D; ++d) issue_b(kbeg + d, bv[d]);
+    // Drain the prologue once: with loads from before the loop still pending
+    // at the loop header, the compiler cannot tell them from the loop's own
+    // and waits for every load in flight at each pass through the header.
+    wait_vm<0>();
+    lds_barrier();
+    read_a(stage(std::integral_constant<int, 0>{}), af);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[0][b][0], bv[0][b][1], bf[b]);
 
-    // one K-step; d (ring stage of both rings) is a compile-time constant
     auto step = [&](int kc, auto dc) __attribute__((always_inline)) {
-        constexpr int d = decltype(dc)::value;
-        uint4 *const cur = d == 0 ? ring0 : d == 1 ? ring1 : d == 2 ? ring2 : ring3;
-        uint4 *const nxt = d == 0 ? ring3 : d == 1 ? ring0 : d == 2 ? ring1 : ring2;
-        wait_vm<C::VMW>();  // this wave's operator chunks of step kc are in LDS
-        lds_barrier();      // ... and everyone's; step kc - 1 is done with its stage
-        issue_a(kc + NA - 1, nxt);
-        bf16x8 bf[NB][NSPLIT];
+        constexpr int i = decltype(dc)::value;
+        constexpr int d = i % D, dn = (i + 1) % D;
+        uint4 *const cur = stage(std::integral_constant<int, i>{});
+        uint4 *const nxt = stage(std::integral_constant<int, i + 1>{});
+        wait_vm<C::VMW>();  // this wave's operator chunks of step kc + 1 are in LDS
+        lds_barrier();      // ... and everyone's; stage d has been read by all
+        issue_a(kc + NA, cur);
+        bf16x8 an[RT][NSPLIT], bn[NB][NSPLIT];
+        read_a(nxt, an);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[dn][b][0], bv[dn][b][1], bn[b]);
+        // the small cross products first; consecutive MFMAs update different
+        // accumulators (RT * NB independent chains)
+#pragma unroll
+        for (int t = NSPLIT - 1; t >= 0; --t)
+#pragma unroll
+            for (int a = 0; a <= t; ++a)
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r][a], bf[b][t - a], acc[r][b], 0, 0, 0);
+        issue_b(kc + D, bv[d]);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int sp = 0; sp < NSPLIT; ++sp) af[r][sp] = an[r][sp];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int sp = 0; sp < NSPLIT; ++sp) bf[b][sp] = __builtin_bit_cast(bf16x8, bv[d][b][sp]);
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            bf16x8 af[NSPLIT];
-#pragma unroll
-            for (int sp = 0; sp < NSPLIT; ++sp)
-                af[sp] = __builtin_bit_cast(bf16x8, cur[(sp * RT + r) * 64 + lane]);
-            // the small cross products first
-#pragma unroll
-            for (int t = NSPLIT - 1; t >= 0; --t)
-#pragma unroll
-                for (int a = 0; a <= t; ++a)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b][t - a], acc[r][b], 0, 0, 0);
-        }
-        issue_b(kc + D, bv[d]);
+            for (int sp = 0; sp < NSPLIT; ++sp) bf[b][sp] = bn[b][sp];
     };
-    for (int kc = kbeg; kc < kend; kc += 8) {
-        step(kc + 0, std::integral_constant<int, 0>{});
-        step(kc + 1, std::integral_constant<int, 1>{});
-        step(kc + 2, std::integral_constant<int, 2>{});
-        step(kc + 3, std::integral_constant<int, 3>{});
-        step(kc + 4, std::integral_constant<int, 0>{});
-        step(kc + 5, std::integral_constant<int, 1>{});
-        step(kc + 6, std::integral_constant<int, 2>{});
-        step(kc + 7, std::integral_constant<int, 3>{});
-        // merge every 256 K terms
+    auto merge = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -335,6 +415,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 for (int i = 0; i < 4; ++i) acc64[r][b][i] += (double)acc[r][b][i];
                 acc[r][b] = f32x4{0, 0, 0, 0};
             }
+    };
+    for (int kc = kbeg; kc < kend; kc += UNROLL) {
+        static_for<0, UNROLL>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            step(kc + i, ic);
+            if constexpr ((i + 1) % MERGE == 0) merge();  // every MERGE * 32 <= 256 K terms
+        });
     }
     wait_vm<0>();  // no copy into LDS outlives the block
 
@@ -372,33 +459,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     }
 }
 
-// Sum of the K parts of a split tile, in part order.  One block per tile.
-__global__ __launch_bounds__(256) void k_m2l_fixup(int P, M2LPlan pl, const double *__restrict__ partial) {
-    const int64_t b = blockIdx.x;
-    const int li = find_level(pl.fix0, pl.nlev, b);
+// Sum of the K parts of a split tile, in part order.  One thread per output
+// coefficient (tile, target column, row).
+__global__ __launch_bounds__(256) void k_m2l_fixup(int P, M2LPlan pl, const double *__restrict__ partial,
+                                                   int64_t total) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total) return;
+    const int P2 = P * P, S = coef_stride(P);
+    const int64_t per_tile = (int64_t)kTile * P2;
+    const int64_t ft = g / per_tile;
+    const int e = (int)(g - ft * per_tile);
+    const int li = find_level(pl.fix0, pl.nlev, ft);
     const int l = pick(pl.level, li), ns = pick(pl.nsplit, li);
-    const int64_t nt = pick(pl.ntile, li), lt = b - pick(pl.fix0, li);
+    const int64_t nt = pick(pl.ntile, li), lt = ft - pick(pl.fix0, li);
     int k;
     int64_t pbase;
     tile_place(l, lt, k, pbase);
-    const int n = 1 << l, h = n >> 1, S = coef_stride(P), P2 = P * P;
+    const int n = 1 << l, h = n >> 1;
     const int64_t npar = (int64_t)h * h * h;
-    void *Lout = pick(pl.L, li);
-    const int out_f64 = pick(pl.out_f64, li);
-    const double *src = partial + (pick(pl.part0, li) + lt) * kTile * P2;
-    for (int e = threadIdx.x; e < kTile * P2; e += 256) {
-        const int c = e / P2, row = e - c * P2;
-        const int64_t pid = pbase + c;
-        if (pid >= npar) continue;
-        double v = 0.0;
-        for (int j = 0; j < ns; ++j) v += src[(int64_t)j * nt * kTile * P2 + e];
-        int64_t tpad, trow;
-        target_of(pid, k, n, n + 6, S, tpad, trow);
-        if (out_f64)
-            ((double *)Lout)[trow * S + row] = v;
-        else
-            ((float *)Lout)[trow * S + row] = (float)v;
-    }
+    const int c = e / P2, row = e - c * P2;
+    const int64_t pid = pbase + c;
+    if (pid >= npar) return;
+    const double *src = partial + (pick(pl.part0, li) + lt) * per_tile + e;
+    double v = 0.0;
+    for (int j = 0; j < ns; ++j) v += src[(int64_t)j * nt * per_tile];
+    int64_t tpad, trow;
+    target_of(pid, k, n, n + 6, S, tpad, trow);
+    if (pick(pl.out_f64, li))
+        ((double *)pick(pl.L, li))[trow * S + row] = v;
+    else
+        ((float *)pick(pl.L, li))[trow * S + row] = (float)v;
 }
 
 // ------------------------------------------------------------ plain form
@@ -611,16 +701,14 @@ size_t m2l_partial_bytes(int P, int L, bool f64, int ncu) {
     return (size_t)np * kTile * P * P * sizeof(double);
 }
 
-hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, const size_t *bstride,
-                      void *const *Lc, const int *out_f64, const void *A, size_t astride,
-                      const int2 *cls, double *partial, size_t partial_bytes, int ncu,
-                      hipStream_t st) {
+hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
+                      const int *out_f64, const void *A, size_t astride, const int2 *cls,
+                      double *partial, size_t partial_bytes, int ncu, hipStream_t st) {
     if (L < 2) return hipSuccess;
     M2LPlan pl = make_plan(P, L, !f64, ncu);
     for (int i = 0; i < pl.nlev; ++i) {
         const int l = pl.level[i];
         pl.B[i] = B[l];
-        pl.bstride[i] = f64 ? 0 : (int64_t)bstride[l];
         pl.L[i] = Lc[l];
         pl.out_f64[i] = out_f64[l];
     }
@@ -662,7 +750,8 @@ hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, const 
 #undef CASE2
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nfix == 0) return e;
-    k_m2l_fixup<<<nfix, 256, 0, st>>>(P, pl, partial);
+    const int64_t total = (int64_t)nfix * kTile * P * P;
+    k_m2l_fixup<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(P, pl, partial, total);
     return hipGetLastError();
 }
 
