@@ -9,13 +9,19 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
   p2p_gint_s   P2P Ginteractions/s (mixed), pairs from the tree / P2P time
   fp64         the plain FP64 form measured the same way
   rel_l2       errors vs the FP64 direct sum on 1000 sampled targets
-  roofline     dominant kernel, from HIP events recorded by the library on
-               the stream its kernels run on
-  cpu_baseline the CPU oracle FMM on a bounded sample, host cores
+  roofline     dominant kernel of the mixed step; its duration is the mean of
+               HIP events that the library records around each stage on the
+               stream its kernels run on, during the timed steps
+  roofline_p2p the same for the P2P kernel
+  cpu_baseline the CPU oracle FMM on the host cores
   adjoint      forward + backward throughput of the differentiable form
                (N = 1e6, p = 8, leaf <= 64)
+
+--copy-probe runs a device-to-device copy of a known size (for scaling the
+FETCH_SIZE / WRITE_SIZE counters of rocprofv3 to bytes).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +37,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 P2P_FLOP_PER_PAIR = 19
+COPY_PROBE_BYTES = 1 << 30
 
 
 def parse():
@@ -42,8 +49,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="particles for the CPU oracle baseline (0: the whole workload)")
     ap.add_argument("--splits", type=int, default=3, help="bf16 parts of the mixed M2L (2 or 3)")
+    ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
 
 
@@ -58,12 +67,49 @@ def timed_steps(step, steps, warmup, sync):
     return (time.perf_counter() - t0) / steps
 
 
+def traffic_from_profile(kernel_file, summary):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_1106_2176_amd", "csrc", kernel_file)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha:
+        return None
+    try:
+        fetch = float(kv["fetch_kib_per_dispatch"]) / float(kv["copy_fetch_factor"])
+        write = float(kv["write_kib_per_dispatch"]) / float(kv["copy_write_factor"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return (fetch + write) * 1024.0
+
+
+def copy_probe():
+    import torch
+    x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import torch
 
     import paper_1106_2176_amd as fmm
@@ -75,34 +121,28 @@ def main():
     pos = torch.from_numpy(pos_np).to(dev)
     q = torch.from_numpy(q_np).to(dev)
     sync = torch.cuda.synchronize
-    out = {}
 
     def run_form(precision, steps, warmup):
         tree = fmm.Tree(pos, p=wl.p, leaf_max=wl.leaf_max, precision=precision, profile=True,
                         bf16_splits=args.splits)
         phi = torch.empty_like(q)
         E = torch.empty_like(pos)
-        stage_sum = {}
-        nrec = [0]
 
         def step():
             tree.rebuild(pos)
             tree.evaluate(q, vec="field", phi=phi, out_vec=E)
 
-        def step_rec():
+        def warm():
             step()
-            st = tree.stage_times()
-            for k, v in st.items():
-                stage_sum[k] = stage_sum.get(k, 0.0) + v
-            nrec[0] += 1
+            tree.stage_times_reset()
 
-        sec = timed_steps(step, steps, warmup, sync)
-        # stage times over the same number of steps (events are recorded by
-        # the library around each stage on the evaluation stream)
-        for _ in range(steps):
-            step_rec()
+        for _ in range(warmup):
+            warm()
+        # stage times: library events over the timed steps (mean of the last
+        # min(steps, 32) of them)
+        sec = timed_steps(step, steps, 0, sync)
+        stages = tree.stage_times()
         info = tree.info()
-        stages = {k: v / nrec[0] for k, v in stage_sum.items()}
         res = {"sec": sec, "stages_ms": stages, "info": info, "phi": phi.clone(), "E": E.clone()}
         tree.close()
         return res
@@ -117,14 +157,19 @@ def main():
     m2l_pairs = info["m2l_pairs"]
     p2p_tflops = P2P_FLOP_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
     m2l_tflops = 2.0 * wl.p ** 4 * m2l_pairs / (m2l_ms * 1e-3) / 1e12
-    if p2p_ms >= m2l_ms:
-        roof = {"kernel": "k_p2p<float>", "bound": "alu", "achieved": p2p_tflops,
+    roof_p2p = {"kernel": "k_p2p<float>", "bound": "alu", "achieved": p2p_tflops,
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": p2p_tflops / PEAK_FP32_VECTOR_TFLOPS, "traffic": None}
-    else:
-        roof = {"kernel": "k_m2l_bf16", "bound": "mfma", "achieved": m2l_tflops,
-                "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": m2l_tflops / PEAK_BF16_MFMA_TFLOPS, "traffic": None}
+                "frac": p2p_tflops / PEAK_FP32_VECTOR_TFLOPS,
+                "traffic": traffic_from_profile("p2p.hip", "p2p_C2_traffic.txt"),
+                "ms": p2p_ms, "flop_per_launch": P2P_FLOP_PER_PAIR * pairs}
+    split_products = {3: 6, 2: 3}.get(args.splits, 6)
+    roof_m2l = {"kernel": "k_m2l_bf16<%d,%d>" % (args.splits, wl.p), "bound": "mfma",
+                "achieved": m2l_tflops, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": m2l_tflops / PEAK_BF16_MFMA_TFLOPS,
+                "traffic": traffic_from_profile("m2l.hip", "m2l_bf16_C2_traffic.txt"),
+                "ms": m2l_ms, "flop_per_launch": 2.0 * wl.p ** 4 * m2l_pairs,
+                "bf16_products_per_term": split_products}
+    roof = roof_m2l if m2l_ms >= p2p_ms else roof_p2p
 
     # accuracy on sampled targets vs the FP64 direct sum
     t_idx = inputs.targets(n, wl.seed)
@@ -172,15 +217,16 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        ns = args.cpu_sample
+        ns = args.cpu_sample if args.cpu_sample > 0 else n
         ps, qs = inputs.particles(ns, wl.seed, wl.charges, wl.dtype)
         t0 = time.perf_counter()
         oracle.fmm(ps.astype(np.float64), qs.astype(np.float64), wl.p, wl.leaf_max)
         tc = time.perf_counter() - t0
+        what = "the whole workload" if ns == n else "a sample of N=%d particles" % ns
         cpu = {"value": ns / tc, "unit": "particles/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": "FP64 Cartesian-Taylor oracle FMM on N=%d particles of the same "
-                         "distribution, p=%d, leaf<=%d (%.1f s)" % (ns, wl.p, wl.leaf_max, tc)}
+               "sample": "FP64 Cartesian-Taylor oracle FMM (OpenMP) on %s of the same "
+                         "distribution, p=%d, leaf<=%d: %.1f s" % (what, wl.p, wl.leaf_max, tc)}
 
     line = {
         "metric": "particles/s + P2P Ginteractions/s at 1e-6 rel-L2, mixed vs FP64 on 1 GPU",
@@ -201,6 +247,7 @@ def main():
         "p2p_gint_s": pairs / (p2p_ms * 1e-3) / 1e9,
         "stages_ms": mixed["stages_ms"],
         "roofline": roof,
+        "roofline_p2p": roof_p2p,
         "rel_l2": rel,
         "cpu_baseline": cpu,
         "adjoint": adj,

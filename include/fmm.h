@@ -183,13 +183,21 @@ fmm_status fmm_backward(fmm_tree *tree, const void *q, const void *w, const void
  * library copies back at the end of fmm_build_tree). */
 fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
 
-/* Stage timings (milliseconds) of the most recent fmm_evaluate or
- * fmm_backward on a tree built with cfg.profile != 0.  Synchronises the
- * stream of that call.  Stages, in order:
+/* Stage timings (milliseconds) on a tree built with cfg.profile != 0: HIP
+ * events are recorded around each stage on the stream of every
+ * fmm_evaluate / fmm_backward, and this returns the mean over the most recent
+ * min(calls, 32) calls since the tree was created or fmm_stage_times_reset
+ * (rebuilding the tree does not reset it).  Waits for those calls' events.
+ * Stages, in order:
  *   0 gather   1 P2M   2 M2M   3 pack (M2L operand)   4 M2L   5 L2L
  *   6 L2P      7 P2P   8 combine
- * `ms` receives min(n_stages, 9) values.  FMM_EINVAL if profiling is off. */
+ * `ms` receives min(n_stages, 9) values.  FMM_EINVAL if profiling is off or
+ * no call was recorded. */
 fmm_status fmm_stage_times(const fmm_tree *tree, double *ms, int32_t n_stages);
+
+/* Forget the recorded stage timings of `tree` (the next fmm_stage_times
+ * averages only calls made after this one). */
+fmm_status fmm_stage_times_reset(fmm_tree *tree);
 
 /* Copy the tree's sorting results to host memory (any pointer may be NULL):
  * perm[n] (sorted position -> input index, uint32), leaf_start[8^L + 1]

@@ -79,6 +79,7 @@ _SIGS = {
     "fmm_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmm_tree_info": (ctypes.c_int, [_vp, ctypes.POINTER(TreeInfo)]),
     "fmm_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    "fmm_stage_times_reset": (ctypes.c_int, [_vp]),
     "fmm_tree_export": (ctypes.c_int, [_vp, _vp, _vp]),
     "fmm_tree_destroy": (None, [_vp]),
     "fmm_operator_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp]),
@@ -225,9 +226,13 @@ class Tree:
         return {k: getattr(i, k) for k, _ in TreeInfo._fields_}
 
     def stage_times(self):
+        """Mean stage times (ms) over the last min(calls, 32) profiled calls."""
         ms = (ctypes.c_double * len(STAGES))()
         _check(lib().fmm_stage_times(self._h, ms, len(STAGES)))
         return dict(zip(STAGES, list(ms)))
+
+    def stage_times_reset(self):
+        _check(lib().fmm_stage_times_reset(self._h))
 
     def export(self):
         """(perm [n], leaf_start [8^L+1]) as numpy uint32 (synchronous)."""

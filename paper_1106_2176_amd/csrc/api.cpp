@@ -193,6 +193,7 @@ fmm_status build_ops(int p, Ops **out) {
 }
 
 constexpr int kStages = 9;
+constexpr int kTimeRing = 32;  // event sets: stage times of the last 32 profiled calls
 
 }  // namespace
 
@@ -211,9 +212,10 @@ struct fmm_tree {
     Buf M[FMM_MAX_LEVEL + 1], Lc[FMM_MAX_LEVEL + 1], pack[FMM_MAX_LEVEL + 1];
     unsigned int *host_counters = nullptr;  // pinned [4]
     Ops *ops = nullptr;
-    hipEvent_t ev[kStages + 1] = {};
+    hipEvent_t ev[kTimeRing][kStages + 1] = {};
     bool ev_ready = false;
-    bool have_times = false;
+    int64_t ncalls = 0;  // profiled calls since the last reset
+    int cur = 0;         // event set of the call in progress
     hipStream_t last_stream = nullptr;
 };
 
@@ -288,10 +290,11 @@ fmm_status validate_cfg(const fmm_config *c) {
 fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
     if (!t->cfg.profile) return FMM_OK;
     if (!t->ev_ready) {
-        for (int i = 0; i <= kStages; ++i) HIPCHK(hipEventCreate(&t->ev[i]));
+        for (int j = 0; j < kTimeRing; ++j)
+            for (int i = 0; i <= kStages; ++i) HIPCHK(hipEventCreate(&t->ev[j][i]));
         t->ev_ready = true;
     }
-    HIPCHK(hipEventRecord(t->ev[stage], st));
+    HIPCHK(hipEventRecord(t->ev[t->cur][stage], st));
     return FMM_OK;
 }
 
@@ -309,7 +312,7 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     void *src = f64 ? t->xyz64.p : t->xyz32.p;
     const uint32_t *start = (const uint32_t *)t->start.p;
     const int nsplit = t->cfg.bf16_splits == 2 ? 2 : 3;
-    t->have_times = false;
+    t->cur = (int)(t->ncalls % kTimeRing);
     t->last_stream = st;
 
     // guards: every buffer a kernel will touch holds what that kernel assumes
@@ -446,7 +449,6 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     t->al.fa = cfg->alloc;
     t->al.ff = cfg->free;
     t->al.ctx = cfg->alloc_ctx;
-    t->have_times = false;
     if (hipGetDevice(&t->dev) != hipSuccess) return bail(fail(FMM_EDEVICE, "hipGetDevice failed"));
     if (hipDeviceGetAttribute(&t->ncu, hipDeviceAttributeMultiprocessorCount, t->dev) != hipSuccess ||
         t->ncu < 1)
@@ -522,7 +524,7 @@ fmm_status fmm_evaluate(fmm_tree *t, const void *q, void *phi, void *vec, int32_
                           (t->L >= 2 && do_far) ? (const double4 *)t->farf.p : nullptr, inv_w, q, phi,
                           vec, kind, st));
     CHK(rec(t, kStages, st));
-    t->have_times = t->cfg.profile != 0;
+    if (t->cfg.profile) ++t->ncalls;
     return FMM_OK;
 }
 
@@ -539,7 +541,7 @@ fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *f
                                t->L >= 2 ? (const double4 *)t->farf.p : nullptr, inv_w, q, w,
                                field_fwd, grad_q, grad_pos, st));
     CHK(rec(t, kStages, st));
-    t->have_times = t->cfg.profile != 0;
+    if (t->cfg.profile) ++t->ncalls;
     return FMM_OK;
 }
 
@@ -583,13 +585,26 @@ fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
 
 fmm_status fmm_stage_times(const fmm_tree *t, double *ms, int32_t n_stages) {
     if (!t || !ms) return fail(FMM_EINVAL, "tree and ms are required");
-    if (!t->cfg.profile || !t->have_times) return fail(FMM_EINVAL, "profiling is off or nothing was recorded");
-    HIPCHK(hipEventSynchronize(t->ev[kStages]));
-    for (int i = 0; i < std::min<int>(n_stages, kStages); ++i) {
-        float f = 0.f;
-        HIPCHK(hipEventElapsedTime(&f, t->ev[i], t->ev[i + 1]));
-        ms[i] = f;
+    if (!t->cfg.profile || t->ncalls == 0) return fail(FMM_EINVAL, "profiling is off or nothing was recorded");
+    const int ns = std::min<int>(n_stages, kStages);
+    const int64_t nset = std::min<int64_t>(t->ncalls, kTimeRing);
+    for (int i = 0; i < ns; ++i) ms[i] = 0.0;
+    for (int64_t c = t->ncalls - nset; c < t->ncalls; ++c) {
+        const int j = (int)(c % kTimeRing);
+        HIPCHK(hipEventSynchronize(t->ev[j][kStages]));
+        for (int i = 0; i < ns; ++i) {
+            float f = 0.f;
+            HIPCHK(hipEventElapsedTime(&f, t->ev[j][i], t->ev[j][i + 1]));
+            ms[i] += f;
+        }
     }
+    for (int i = 0; i < ns; ++i) ms[i] /= (double)nset;
+    return FMM_OK;
+}
+
+fmm_status fmm_stage_times_reset(fmm_tree *t) {
+    if (!t) return fail(FMM_EINVAL, "tree is NULL");
+    t->ncalls = 0;
     return FMM_OK;
 }
 
@@ -615,7 +630,8 @@ void fmm_tree_destroy(fmm_tree *t) {
         release(t, t->pack[l], st);
     }
     if (t->ev_ready)
-        for (int i = 0; i <= kStages; ++i) (void)hipEventDestroy(t->ev[i]);
+        for (int j = 0; j < kTimeRing; ++j)
+            for (int i = 0; i <= kStages; ++i) (void)hipEventDestroy(t->ev[j][i]);
     if (t->host_counters) (void)hipHostFree(t->host_counters);
     delete t;
 }
