@@ -175,6 +175,59 @@ def test_c2_sampled_fp64_and_mixed(oracle_mod):
     assert rel_l2(Em[t], E_d) < 1e-5
 
 
+def _mixed_vs_fp64(pos, q, p, leaf):
+    """Mixed and FP64 forms on all N, and the error scales of the sums."""
+    phi, E, info = gpu_eval(pos, q, p, leaf, "fp64")
+    phm, Em, _ = gpu_eval(pos, q, p, leaf, "mixed")
+    # rounding errors scale with the sums of |terms|: with zero-mean charges
+    # the potential and force cancel far below them.  The same FMM with
+    # charges |q| gives that scale (kappa >= 1; 1 for positive charges).
+    qa = np.abs(q)
+    phia, Ea, _ = gpu_eval(pos, qa, p, leaf, "fp64")
+    qq, qqa = q.astype(np.float64)[:, None], qa.astype(np.float64)[:, None]
+    kphi = np.linalg.norm(phia) / np.linalg.norm(phi)
+    kF = np.linalg.norm(qqa * Ea) / np.linalg.norm(qq * E)
+    return (phi, E, info), (phm, Em), max(1.0, kphi), max(1.0, kF)
+
+
+def test_c3_sampled_fp64_and_mixed(oracle_mod):
+    """N = 1e7, p = 10, leaf <= 128, zero-mean charges U[-1,1) (full size);
+    FP64 form against the oracle on 1000 sampled targets, mixed against FP64
+    on all N within 1e-6 of the scale of the summed terms."""
+    w = inputs.WORKLOADS["C3"]
+    pos, q = inputs.workload("C3")
+    t = inputs.targets(w.n, w.seed)
+    ref = oracle_mod.fmm(pos, q, w.p, w.leaf_max, targets=t)
+    (phi, E, info), (phm, Em), kphi, kF = _mixed_vs_fp64(pos, q, w.p, w.leaf_max)
+    assert info["levels"] == 6
+    assert rel_l2(phi[t], ref["phi"]) < 1e-10
+    assert rel_l2(E[t], ref["E"]) < 1e-10
+    assert rel_l2(phm, phi) < 1e-6 * kphi
+    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6 * kF
+
+
+def test_c4_sampled_fp32_inputs(oracle_mod):
+    """N = 1e8 FP32 positions and charges, p = 8, leaf <= 128 (full size):
+    FP64 form against the oracle (inputs widened exactly) on 1000 sampled
+    targets; mixed against FP64 on all N."""
+    w = inputs.WORKLOADS["C4"]
+    pos, q = inputs.workload("C4")
+    assert pos.dtype == np.float32
+    t = inputs.targets(w.n, w.seed)
+    # outputs come back in the caller's dtype: the FP64 check runs on the
+    # exactly widened inputs, the mixed form on the FP32 inputs themselves
+    pos64, q64 = pos.astype(np.float64), q.astype(np.float64)
+    ref = oracle_mod.fmm(pos64, q64, w.p, w.leaf_max, targets=t)
+    phi, E, info = gpu_eval(pos64, q64, w.p, w.leaf_max, "fp64")
+    del pos64
+    assert info["levels"] == 7
+    assert rel_l2(phi[t], ref["phi"]) < 1e-10
+    assert rel_l2(E[t], ref["E"]) < 1e-10
+    phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed")
+    assert rel_l2(phm, phi) < 1e-6
+    assert rel_l2(q64[:, None] * Em, q64[:, None] * E) < 1e-6
+
+
 def test_box_and_dtype_options(oracle_mod):
     rng = np.random.default_rng(30)
     lo = np.array([-2.0, 1.0, 0.5])
