@@ -91,7 +91,12 @@ typedef struct {
     void *alloc_ctx;
     int32_t profile;           /* nonzero: record HIP events around each stage of
                                   fmm_evaluate (read with fmm_stage_times) */
-    int32_t reserved[7];       /* zero */
+    int32_t overlap_near;      /* nonzero: run the near field (P2P) concurrently
+                                  with the far field on a stream of the library's
+                                  own, forked from and joined back into the
+                                  caller's stream within each call (same results);
+                                  zero (default): after the far field */
+    int32_t reserved[6];       /* zero */
 } fmm_config;
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed

@@ -43,7 +43,8 @@ class Config(ctypes.Structure):
         ("free", FREE_FN),
         ("alloc_ctx", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("overlap_near", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -114,7 +115,7 @@ def _check(rc):
 
 
 def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
-                box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False):
+                box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False):
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)
@@ -127,6 +128,7 @@ def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3
         c.box_lo[a] = float(box_lo[a])
     c.box_size = float(box_size)
     c.profile = 1 if profile else 0
+    c.overlap_near = 1 if overlap_near else 0
     return c
 
 
@@ -175,10 +177,10 @@ class Tree:
     """An octree built on the GPU; owns library memory until close()."""
 
     def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
-                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False):
+                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,
-                               profile)
+                               profile, overlap_near)
         self.rebuild(pos)
 
     def rebuild(self, pos):

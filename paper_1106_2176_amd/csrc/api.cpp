@@ -194,6 +194,7 @@ fmm_status build_ops(int p, Ops **out) {
 
 constexpr int kStages = 9;
 constexpr int kTimeRing = 32;  // event sets: stage times of the last 32 profiled calls
+constexpr int kEvents = kStages + 3;  // stage boundaries + start/end of a concurrent P2P
 
 }  // namespace
 
@@ -208,12 +209,16 @@ struct fmm_tree {
     int ncu = 0;  // compute units of the device
     hipStream_t stream = nullptr;
     Alloc al;
-    Buf key10, cnt, start, fill, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs, m2lpart;
+    Buf key10, rank, cnt, start, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs, m2lpart;
+    hipEvent_t ev_counters = nullptr;  // after the copy of the build counters
     Buf M[FMM_MAX_LEVEL + 1], Lc[FMM_MAX_LEVEL + 1], pack[FMM_MAX_LEVEL + 1];
     unsigned int *host_counters = nullptr;  // pinned [4]
     Ops *ops = nullptr;
-    hipEvent_t ev[kTimeRing][kStages + 1] = {};
+    hipEvent_t ev[kTimeRing][kEvents] = {};
+    bool p2p_side[kTimeRing] = {};  // the call's P2P ran on the side stream
     bool ev_ready = false;
+    hipStream_t side = nullptr;         // stream of the concurrent near field
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t ncalls = 0;  // profiled calls since the last reset
     int cur = 0;         // event set of the call in progress
     hipStream_t last_stream = nullptr;
@@ -291,7 +296,7 @@ fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
     if (!t->cfg.profile) return FMM_OK;
     if (!t->ev_ready) {
         for (int j = 0; j < kTimeRing; ++j)
-            for (int i = 0; i <= kStages; ++i) HIPCHK(hipEventCreate(&t->ev[j][i]));
+            for (int i = 0; i < kEvents; ++i) HIPCHK(hipEventCreate(&t->ev[j][i]));
         t->ev_ready = true;
     }
     HIPCHK(hipEventRecord(t->ev[t->cur][stage], st));
@@ -326,6 +331,24 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     CHK(rec(t, 0, st));
     HIPCHK(launch_gather_q(t->n, t->dtype, f64, (const uint32_t *)t->perm.p, charges, src, st));
     CHK(ensure(t, t->nearf, sizeof(double4) * (size_t)t->n, st));
+    // Near field concurrently with the far field: P2P needs only the sorted
+    // particles and writes its own buffer, so it is forked onto the library's
+    // side stream after the gather and joined back before the combine.
+    const bool side = do_near && do_far && L >= 2 && t->cfg.overlap_near;
+    t->p2p_side[t->cur] = side;
+    if (side) {
+        if (!t->side) {
+            HIPCHK(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(t->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
+        CHK(rec(t, kStages + 1, t->side));
+        HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, t->side));
+        CHK(rec(t, kStages + 2, t->side));
+        HIPCHK(hipEventRecord(t->ev_join, t->side));
+    }
     if (L >= 2 && do_far) {
         if (!t->ops) CHK(build_ops(P, &t->ops));
         const Ops *o = t->ops;
@@ -384,7 +407,8 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
         for (int s = 1; s <= 6; ++s) CHK(rec(t, s, st));
     }
     CHK(rec(t, 7, st));
-    if (do_near) HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, st));
+    if (side) HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
+    else if (do_near) HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, st));
     else HIPCHK(hipMemsetAsync(t->nearf.p, 0, sizeof(double4) * (size_t)t->n, st));
     CHK(rec(t, 8, st));
     return FMM_OK;
@@ -459,38 +483,21 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
             return bail(fail(FMM_EDEVICE, "hipHostMalloc failed"));
     }
     fmm_status s;
-    if ((s = ensure(t, t->key10, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
-    if ((s = ensure(t, t->counters, 4 * sizeof(unsigned int), st)) != FMM_OK) return bail(s);
-    unsigned int *dc = (unsigned int *)t->counters.p;
-    hipError_t e = hipMemsetAsync(dc, 0, 4 * sizeof(unsigned int), st);
-    if (e == hipSuccess) e = launch_keys(n, dtype, pos, cfg->box_lo, cfg->box_size, (uint32_t *)t->key10.p, dc, st);
-    if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("key kernel: ") + hipGetErrorString(e)));
     // S1: smallest level whose fullest leaf holds <= leaf_max; the coarsest
     // candidate is the first level with 8^l * leaf_max >= n (fewer boxes
-    // cannot hold n particles under the cap)
+    // cannot hold n particles under the cap).  For the uniform inputs of the
+    // method it is also the answer almost surely, so the sort at that level
+    // is queued before the host has read the counters: the host waits only
+    // for the counter copy, and queues a rebuild at a finer level in the rare
+    // case that the candidate's fullest leaf is over the cap.
     int lev = 0;
     while (lev < cfg->max_level && ((int64_t)1 << (3 * lev)) * (int64_t)cfg->leaf_max < n) ++lev;
-    for (;;) {
-        const size_t nb = (size_t)1 << (3 * lev);
-        if ((s = ensure(t, t->cnt, sizeof(uint32_t) * nb, st)) != FMM_OK) return bail(s);
-        e = launch_hist(n, (const uint32_t *)t->key10.p, lev, (uint32_t *)t->cnt.p, dc + 1, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(t->host_counters, dc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("level selection: ") + hipGetErrorString(e)));
-        if (t->host_counters[0] != 0)
-            return bail(fail(FMM_EDOMAIN, std::to_string(t->host_counters[0]) +
-                                              " positions outside the root cube or not finite"));
-        t->max_count = t->host_counters[1];
-        if (t->max_count <= cfg->leaf_max || lev >= cfg->max_level) break;
-        ++lev;
-    }
-    t->L = lev;
-    t->nleaf = (int64_t)1 << (3 * lev);
-    const size_t nb = (size_t)t->nleaf;
+    if (!t->ev_counters && hipEventCreateWithFlags(&t->ev_counters, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(FMM_EDEVICE, "hipEventCreate failed"));
     const bool f64 = is_f64_form(t);
-    if ((s = ensure(t, t->start, sizeof(uint32_t) * (nb + 1), st)) != FMM_OK) return bail(s);
-    if ((s = ensure(t, t->scan, sizeof(uint32_t) * scan_scratch_words(nb), st)) != FMM_OK) return bail(s);
-    if ((s = ensure(t, t->fill, sizeof(uint32_t) * nb, st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->key10, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->rank, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
+    if ((s = ensure(t, t->counters, 4 * sizeof(unsigned int), st)) != FMM_OK) return bail(s);
     if ((s = ensure(t, t->tmp, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
     if ((s = ensure(t, t->perm, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
     if (f64) {
@@ -498,13 +505,58 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     } else {
         if ((s = ensure(t, t->xyz32, sizeof(int4) * n, st)) != FMM_OK) return bail(s);
     }
-    e = launch_scan((int64_t)nb, (const uint32_t *)t->cnt.p, (uint32_t *)t->start.p, (uint32_t *)t->scan.p, st);
-    if (e == hipSuccess)
-        e = launch_sort(n, lev, (const uint32_t *)t->key10.p, (const uint32_t *)t->start.p,
-                        (uint32_t *)t->fill.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
-                        cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (int4 *)t->xyz32.p,
-                        f64 ? (double4 *)t->xyz64.p : nullptr, st);
-    if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("sort: ") + hipGetErrorString(e)));
+    auto level_buffers = [&](int l) -> fmm_status {
+        const size_t nb = (size_t)1 << (3 * l);
+        fmm_status r;
+        if ((r = ensure(t, t->cnt, sizeof(uint32_t) * nb, st)) != FMM_OK) return r;
+        if ((r = ensure(t, t->start, sizeof(uint32_t) * (nb + 1), st)) != FMM_OK) return r;
+        return ensure(t, t->scan, sizeof(uint32_t) * scan_scratch_words((int64_t)nb), st);
+    };
+    unsigned int *dc = (unsigned int *)t->counters.p;
+    auto read_counters = [&](int l) -> hipError_t {
+        hipError_t r = launch_max(l, (const uint32_t *)t->cnt.p, dc + 1, st);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(t->host_counters, dc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+        if (r == hipSuccess) r = hipEventRecord(t->ev_counters, st);
+        return r;
+    };
+    auto sort_at = [&](int l) -> hipError_t {
+        hipError_t r = launch_scan((int64_t)1 << (3 * l), (const uint32_t *)t->cnt.p,
+                                   (uint32_t *)t->start.p, (uint32_t *)t->scan.p, st);
+        if (r == hipSuccess)
+            r = launch_sort(n, l, (const uint32_t *)t->key10.p, (const uint32_t *)t->rank.p,
+                            (const uint32_t *)t->start.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
+                            cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (int4 *)t->xyz32.p,
+                            f64 ? (double4 *)t->xyz64.p : nullptr, st);
+        return r;
+    };
+    if ((s = level_buffers(lev)) != FMM_OK) return bail(s);
+    hipError_t e = launch_keys(n, dtype, pos, cfg->box_lo, cfg->box_size, lev, (uint32_t *)t->key10.p,
+                               (uint32_t *)t->cnt.p, (uint32_t *)t->rank.p, dc, st);
+    if (e == hipSuccess) e = read_counters(lev);
+    if (e == hipSuccess) e = sort_at(lev);
+    if (e == hipSuccess) e = hipEventSynchronize(t->ev_counters);
+    if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("tree build: ") + hipGetErrorString(e)));
+    if (t->host_counters[0] != 0)
+        return bail(fail(FMM_EDOMAIN, std::to_string(t->host_counters[0]) +
+                                          " positions outside the root cube or not finite"));
+    t->max_count = t->host_counters[1];
+    if (t->max_count > cfg->leaf_max && lev < cfg->max_level) {
+        do {
+            ++lev;
+            if ((s = level_buffers(lev)) != FMM_OK) return bail(s);
+            e = launch_hist(n, (const uint32_t *)t->key10.p, lev, (uint32_t *)t->cnt.p,
+                            (uint32_t *)t->rank.p, dc, st);
+            if (e == hipSuccess) e = read_counters(lev);
+            if (e == hipSuccess) e = hipEventSynchronize(t->ev_counters);
+            if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("level selection: ") + hipGetErrorString(e)));
+            t->max_count = t->host_counters[1];
+        } while (t->max_count > cfg->leaf_max && lev < cfg->max_level);
+        e = sort_at(lev);
+        if (e != hipSuccess) return bail(fail(FMM_EDEVICE, std::string("sort: ") + hipGetErrorString(e)));
+    }
+    t->L = lev;
+    t->nleaf = (int64_t)1 << (3 * lev);
     *out = t;
     return FMM_OK;
 }
@@ -575,7 +627,7 @@ fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
     }
     info->m2l_pairs = m2l;
     size_t ws = 0;
-    const Buf *bufs[] = {&t->key10, &t->cnt, &t->start, &t->fill, &t->tmp, &t->perm, &t->scan,
+    const Buf *bufs[] = {&t->key10, &t->rank, &t->cnt, &t->start, &t->tmp, &t->perm, &t->scan,
                          &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};
     for (const Buf *b : bufs) ws += b->cap;
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) ws += t->M[l].cap + t->Lc[l].cap + t->pack[l].cap;
@@ -594,7 +646,12 @@ fmm_status fmm_stage_times(const fmm_tree *t, double *ms, int32_t n_stages) {
         HIPCHK(hipEventSynchronize(t->ev[j][kStages]));
         for (int i = 0; i < ns; ++i) {
             float f = 0.f;
-            HIPCHK(hipEventElapsedTime(&f, t->ev[j][i], t->ev[j][i + 1]));
+            if (i == 7 && t->p2p_side[j]) {  // P2P ran on the side stream
+                HIPCHK(hipEventSynchronize(t->ev[j][kStages + 2]));
+                HIPCHK(hipEventElapsedTime(&f, t->ev[j][kStages + 1], t->ev[j][kStages + 2]));
+            } else {
+                HIPCHK(hipEventElapsedTime(&f, t->ev[j][i], t->ev[j][i + 1]));
+            }
             ms[i] += f;
         }
     }
@@ -621,7 +678,7 @@ fmm_status fmm_tree_export(const fmm_tree *t, uint32_t *perm, uint32_t *leaf_sta
 void fmm_tree_destroy(fmm_tree *t) {
     if (!t) return;
     hipStream_t st = t->stream;
-    Buf *bufs[] = {&t->key10, &t->cnt, &t->start, &t->fill, &t->tmp, &t->perm, &t->scan,
+    Buf *bufs[] = {&t->key10, &t->rank, &t->cnt, &t->start, &t->tmp, &t->perm, &t->scan,
                    &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};
     for (Buf *b : bufs) release(t, *b, st);
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) {
@@ -631,7 +688,14 @@ void fmm_tree_destroy(fmm_tree *t) {
     }
     if (t->ev_ready)
         for (int j = 0; j < kTimeRing; ++j)
-            for (int i = 0; i <= kStages; ++i) (void)hipEventDestroy(t->ev[j][i]);
+            for (int i = 0; i < kEvents; ++i) (void)hipEventDestroy(t->ev[j][i]);
+    if (t->side) {
+        (void)hipStreamSynchronize(t->side);
+        (void)hipStreamDestroy(t->side);
+        (void)hipEventDestroy(t->ev_fork);
+        (void)hipEventDestroy(t->ev_join);
+    }
+    if (t->ev_counters) (void)hipEventDestroy(t->ev_counters);
     if (t->host_counters) (void)hipHostFree(t->host_counters);
     delete t;
 }

@@ -7,15 +7,19 @@
 namespace fmm {
 
 // tree.hip
+// keys + leaf counts + ranks at `level` (zeroes cnt and counters[0..1] first)
 hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3], double size,
-                       uint32_t *key10, unsigned int *nbad, hipStream_t st);
-hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt,
-                       unsigned int *mx, hipStream_t st);
+                       int level, uint32_t *key10, uint32_t *cnt, uint32_t *rank,
+                       unsigned int *counters, hipStream_t st);
+// leaf counts + ranks at another level from the keys (counters[1] restarts)
+hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt, uint32_t *rank,
+                       unsigned int *counters, hipStream_t st);
+hipError_t launch_max(int level, const uint32_t *cnt, unsigned int *mx, hipStream_t st);
 int64_t scan_scratch_words(int64_t nb);
 hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
                        hipStream_t st);
-hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *start,
-                       uint32_t *fill, uint32_t *tmp, int dtype, const void *pos,
+hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *rank,
+                       const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st);
 hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long long *out,

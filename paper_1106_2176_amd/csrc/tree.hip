@@ -17,27 +17,44 @@ __device__ inline uint32_t box10(double x, double lo, double size) {
     return (uint32_t)v;
 }
 
+// Zero the leaf counters of a level (nb words) and nctr build counters.
+__global__ void k_zero(int64_t nb, uint32_t *__restrict__ cnt, unsigned int *__restrict__ ctr,
+                       int nctr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) cnt[i] = 0;
+    if (i < nctr) ctr[i] = 0;
+}
+
+// Key of every particle, and its leaf count at the level of `shift`: the
+// value returned by the count's atomic add is the particle's rank within its
+// leaf (arrival order; the leaf is put in input order afterwards by k_fixup).
+// A position outside the root cube or not finite is counted in nbad and
+// given key 0, so that the rest of the build stays in bounds.
 template <typename T>
 __global__ void k_keys(int64_t n, const T *__restrict__ pos, double lo0, double lo1, double lo2,
-                       double size, uint32_t *__restrict__ key10, unsigned int *__restrict__ nbad) {
+                       double size, int shift, uint32_t *__restrict__ key10,
+                       uint32_t *__restrict__ cnt, uint32_t *__restrict__ rank,
+                       unsigned int *__restrict__ nbad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double x = (double)pos[3 * i], y = (double)pos[3 * i + 1], z = (double)pos[3 * i + 2];
     const bool ok = (x >= lo0 && x <= lo0 + size) && (y >= lo1 && y <= lo1 + size) &&
                     (z >= lo2 && z <= lo2 + size);  // false for NaN
-    if (!ok) {
+    uint32_t k = 0;
+    if (ok)
+        k = morton3(box10(x, lo0, size), box10(y, lo1, size), box10(z, lo2, size));
+    else
         atomicAdd(nbad, 1u);
-        key10[i] = 0;
-        return;
-    }
-    key10[i] = morton3(box10(x, lo0, size), box10(y, lo1, size), box10(z, lo2, size));
+    key10[i] = k;
+    rank[i] = atomicAdd(&cnt[k >> shift], 1u);
 }
 
+// Leaf counts and ranks at another level, from the keys.
 __global__ void k_hist(int64_t n, const uint32_t *__restrict__ key10, int shift,
-                       uint32_t *__restrict__ cnt) {
+                       uint32_t *__restrict__ cnt, uint32_t *__restrict__ rank) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    atomicAdd(&cnt[key10[i] >> shift], 1u);
+    rank[i] = atomicAdd(&cnt[key10[i] >> shift], 1u);
 }
 
 __global__ void k_max(int64_t nb, const uint32_t *__restrict__ cnt, unsigned int *__restrict__ mx) {
@@ -92,19 +109,22 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t nb, const uint32_t
     if (threadIdx.x == 1023 && sums) sums[blockIdx.x] = excl;
 }
 
-__global__ void k_scan_add(int64_t nb, uint32_t *__restrict__ out, const uint32_t *__restrict__ sums) {
+// adds the scanned block sums; also writes the total (sums[nblocks]) to out[nb]
+__global__ void k_scan_add(int64_t nb, int64_t nblocks, uint32_t *__restrict__ out,
+                           const uint32_t *__restrict__ sums) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) out[nb] = sums[nblocks];
     if (i >= nb) return;
     out[i] += sums[i / 4096];
 }
 
-__global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key10, int shift,
-                          const uint32_t *__restrict__ start, uint32_t *__restrict__ fill,
-                          uint32_t *__restrict__ tmp) {
+// Counting sort placement: leaf start + rank within the leaf (no atomics).
+__global__ void k_place(int64_t n, const uint32_t *__restrict__ key10, int shift,
+                        const uint32_t *__restrict__ rank, const uint32_t *__restrict__ start,
+                        uint32_t *__restrict__ tmp) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t k = key10[i] >> shift;
-    tmp[start[k] + atomicAdd(&fill[k], 1u)] = (uint32_t)i;
+    tmp[start[key10[i] >> shift] + rank[i]] = (uint32_t)i;
 }
 
 // One 256-thread block per leaf: orders the leaf's particles by input index
@@ -185,24 +205,32 @@ __global__ void k_pair_count(int L, const uint32_t *__restrict__ start,
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3], double size,
-                       uint32_t *key10, unsigned int *nbad, hipStream_t st) {
+                       int level, uint32_t *key10, uint32_t *cnt, uint32_t *rank,
+                       unsigned int *counters, hipStream_t st) {
+    const int64_t nb = (int64_t)1 << (3 * level);
+    // counters: [0] positions out of the domain, [1] largest leaf count
+    k_zero<<<nblk(std::max<int64_t>(nb, 2), 256), 256, 0, st>>>(nb, cnt, counters, 2);
+    const int shift = 3 * (10 - level);
     if (dtype == FMM_F64)
         k_keys<double><<<nblk(n, 256), 256, 0, st>>>(n, (const double *)pos, lo[0], lo[1], lo[2],
-                                                      size, key10, nbad);
+                                                      size, shift, key10, cnt, rank, counters);
     else
         k_keys<float><<<nblk(n, 256), 256, 0, st>>>(n, (const float *)pos, lo[0], lo[1], lo[2],
-                                                     size, key10, nbad);
+                                                     size, shift, key10, cnt, rank, counters);
     return hipGetLastError();
 }
 
-hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt,
-                       unsigned int *mx, hipStream_t st) {
+hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt, uint32_t *rank,
+                       unsigned int *counters, hipStream_t st) {
     const int64_t nb = (int64_t)1 << (3 * level);
-    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * nb, st);
-    if (e != hipSuccess) return e;
-    e = hipMemsetAsync(mx, 0, sizeof(unsigned int), st);
-    if (e != hipSuccess) return e;
-    k_hist<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), cnt);
+    // counters[1] (the largest leaf count) restarts; counters[0] keeps its value
+    k_zero<<<nblk(nb, 256), 256, 0, st>>>(nb, cnt, counters + 1, 1);
+    k_hist<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), cnt, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_max(int level, const uint32_t *cnt, unsigned int *mx, hipStream_t st) {
+    const int64_t nb = (int64_t)1 << (3 * level);
     const unsigned g = (unsigned)std::min<int64_t>(1024, (nb + 255) / 256);
     k_max<<<g, 256, 0, st>>>(nb, cnt, mx);
     return hipGetLastError();
@@ -229,19 +257,16 @@ hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *
     k_scan_blocks<<<(unsigned)nblocks, 1024, 0, st>>>(nb, in, out, sums);
     hipError_t e = launch_scan(nblocks, sums, sums_scan, sums_scan + nblocks + 1, st);
     if (e != hipSuccess) return e;
-    k_scan_add<<<nblk(nb, 256), 256, 0, st>>>(nb, out, sums_scan);
-    e = hipMemcpyAsync(out + nb, sums_scan + nblocks, sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-    return e != hipSuccess ? e : hipGetLastError();
+    k_scan_add<<<nblk(nb, 256), 256, 0, st>>>(nb, nblocks, out, sums_scan);
+    return hipGetLastError();
 }
 
-hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *start,
-                       uint32_t *fill, uint32_t *tmp, int dtype, const void *pos,
+hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *rank,
+                       const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st) {
     const int64_t nb = (int64_t)1 << (3 * level);
-    hipError_t e = hipMemsetAsync(fill, 0, sizeof(uint32_t) * nb, st);
-    if (e != hipSuccess) return e;
-    k_scatter<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), start, fill, tmp);
+    k_place<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), rank, start, tmp);
     if (dtype == FMM_F64)
         k_fixup<double><<<(unsigned)nb, 256, 0, st>>>(level, start, tmp, (const double *)pos, lo[0],
                                                        lo[1], lo[2], size, perm, xyz32, xyz64);

@@ -267,6 +267,28 @@ def test_deterministic_and_rebuild():
     assert np.array_equal(c.cpu().numpy(), d) and np.array_equal(Ec.cpu().numpy(), Ed)
 
 
+def test_concurrent_near_field_is_identical():
+    """P2P on the library's side stream (overlap_near) gives the same bits as
+    the serial order, forward and adjoint, across repeated calls."""
+    pos, q = inputs.particles(60_000, 41)
+    w = np.random.default_rng(42).standard_normal(60_000)
+    out = {}
+    for ov in (False, True):
+        with fmm.Tree(dev(pos), p=6, leaf_max=32, precision="mixed", overlap_near=ov) as t:
+            res = []
+            for _ in range(3):
+                phi, E = t.evaluate(dev(q))
+                gq, gx = t.backward(dev(q), dev(w), E)
+                res.append([x.cpu().numpy() for x in (phi, E, gq, gx)])
+            torch.cuda.synchronize()
+        for r in res[1:]:
+            for a, b in zip(r, res[0]):
+                np.testing.assert_array_equal(a, b)
+        out[ov] = res[0]
+    for a, b in zip(out[False], out[True]):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_domain_errors():
     pos, q = inputs.particles(1000, 34)
     for bad in (np.nan, 1.5, -0.25, np.inf):
