@@ -148,8 +148,8 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
 /*
  * Evaluate potentials (and optionally fields or forces) for charges `q`
  * (device [n] in the tree's dtype) at the tree's particles, in the caller's
- * particle order: P2M, M2M (upward sweep), M2L at every level >= 2 (no
- * barrier between levels, Sec. 5 "hierarchical synchronization"), L2L
+ * particle order: P2M, M2M (upward sweep), M2L at every level >= 2 (the
+ * levels are independent and run in one launch, Sec. 5), L2L
  * (downward sweep), L2P, P2P and the far + near sum (Fig. 1, Fig. 3).
  *   phi  device [n] output (tree dtype), required.
  *   vec  device [n][3] output (tree dtype), required unless the vector

@@ -9,23 +9,23 @@
  * spherical harmonics, this file uses Cartesian Taylor series.
  *
  * What it computes (Sec. 2.1 of the paper: N sources of a 1/r potential,
- * "gravitational or electrostatic"):
+ * the gravitational or electrostatic N-body problem):
  *     phi_i = sum_{j != i, x_j != x_i} q_j / |x_i - x_j|
  *     E_i   = sum_{j != i, x_j != x_i} q_j (x_i - x_j) / |x_i - x_j|^3  (= -grad phi)
  * once exactly (oracle_direct, O(N^2)) and once through the FMM
  * (oracle_fmm), step by step:
  *   S1  uniform tree: the smallest level L whose fullest box holds at most
- *       leaf_max particles (Sec. 5, "Morton index for a prescribed maximum
- *       level"; the uniform tree of the future-directions paragraph);
+ *       leaf_max particles (Sec. 5, future directions: for uniform particle
+ *       distributions the tree is a Morton index at a fixed maximum level);
  *   S2  box index of a particle: i = min(floor(((x-lo)/size) * 2^L), 2^L-1);
  *   S3  near list: the <= 27 leaves with |di|_inf <= 1 (Sec. 2.1, near/far);
  *   S4  interaction list at level l >= 2: children of the parent's near
- *       boxes that are not near boxes themselves (Fig. 1 caption: M2L for the
- *       siblings at all levels deeper than level 1);
+ *       boxes that are not near boxes themselves (Fig. 1 caption: M2L runs
+ *       between same-level boxes at every level below level 1);
  *   S5  P2M, S6 M2M, S7 M2L, S8 L2L, S9 L2P (Fig. 1 and Fig. 3), with
- *       multipole and local expansions truncated after p terms, read as total
- *       degree 0..p-1 (Sec. 2.1: "series ... truncated after p terms", "e.g.
- *       Taylor series"), centred on the geometric box centre;
+ *       multipole and local expansions of p terms, read as total degree
+ *       0..p-1 (Sec. 2.1 defines both expansions as p-term series, Taylor
+ *       series being one example), centred on the geometric box centre;
  *   S10 P2P over the near list (Sec. 3.1);
  *   S11 phi = far + near, E likewise.
  *

@@ -1,6 +1,6 @@
-"""Seeded synthetic workloads: particles placed at random in a cube.
+"""Seeded synthetic workloads: uniformly random particles in a cube.
 
-The paper's every test problem is "points placed at random in a cube"
+Every test problem of the paper is a set of uniformly random points in a cube
 (captions of Fig. 4-9).  This module only draws random numbers; it holds none
 of the method's arithmetic and is shared by the tests, the benchmark and the
 CPU oracle's callers alike.
