@@ -19,8 +19,9 @@
  *    by the caller, which must keep them alive until the stream work that
  *    uses them has completed.  "host" pointers are ordinary CPU memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *    fmm_build_tree performs exactly one blocking stream synchronisation (it
- *    reads the level-selection and validation counters); fmm_evaluate and
+ *    fmm_build_tree blocks once, until two counters (the level-selection
+ *    maximum and the count of invalid positions) have reached the host; the
+ *    rest of the build stays queued on `stream`.  fmm_evaluate and
  *    fmm_backward are asynchronous on `stream`.  A tree is used by one stream
  *    at a time.
  *  - Every call returns an fmm_status; after a non-OK status the outputs are
@@ -127,9 +128,11 @@ typedef struct {
  *          library with the same p, precision and dtype, it is rebuilt in
  *          place and its memory reused when large enough; otherwise *out
  *          must be NULL and a new tree is created.
- * Steps: Morton key per particle, leaf-occupancy histogram, level selection
- * (one host synchronisation), exclusive scan of leaf counts, stable counting
- * sort (ties keep input order) and a gather of leaf-relative coordinates.
+ * Steps: Morton key per particle with the leaf-occupancy histogram at the
+ * predicted level, level selection (one host wait; a finer level is tried
+ * when the predicted one's fullest leaf exceeds leaf_max), exclusive scan of
+ * leaf counts, stable counting sort (ties keep input order) and a gather of
+ * leaf-relative coordinates.
  * Errors: FMM_EINVAL, FMM_EDOMAIN (detected at the synchronisation; a
  * coordinate equal to lo + size is clamped into the last box), FMM_ENOMEM,
  * FMM_EDEVICE.  On error a newly created tree is destroyed and *out is left
