@@ -16,6 +16,9 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
   cpu_baseline the CPU oracle FMM on the host cores
   adjoint      forward + backward throughput of the differentiable form
                (N = 1e6, p = 8, leaf <= 64)
+  small        the small case (N = 1e4, p = 4, leaf <= 64), where launch
+               latency dominates: evaluate and build + evaluate, eager, with
+               a replayed HIP graph, and with the concurrent near field
 
 --copy-probe runs a device-to-device copy of a known size (for scaling the
 FETCH_SIZE / WRITE_SIZE counters of rocprofv3 to bytes).
@@ -49,6 +52,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="particles for the CPU oracle baseline (0: the whole workload)")
     ap.add_argument("--splits", type=int, default=3, help="bf16 parts of the mixed M2L (2 or 3)")
@@ -215,6 +219,29 @@ def main():
         adj = {"workload": w5.describe() + ", loss sum w_i phi_i, w ~ N(0,1)",
                "fwd_bwd_particles_per_s": w5.n / s5, "ms_per_step": s5 * 1e3}
 
+    small = None
+    if not args.no_small:
+        w1 = inputs.WORKLOADS["C1"]
+        p1, q1 = inputs.workload("C1")
+        P1, Q1 = torch.from_numpy(p1).to(dev), torch.from_numpy(q1).to(dev)
+        phi1 = torch.empty_like(Q1)
+        E1 = torch.empty_like(P1)
+        small = {"workload": w1.describe()}
+        for name, kw in (("eager", {}), ("graph", {"graph": True}),
+                         ("graph_overlap", {"graph": True, "overlap_near": True})):
+            t1 = fmm.Tree(P1, p=w1.p, leaf_max=w1.leaf_max, precision="mixed", **kw)
+
+            def ev():
+                t1.evaluate(Q1, vec="field", phi=phi1, out_vec=E1)
+
+            def st():
+                t1.rebuild(P1)
+                ev()
+
+            small[name] = {"evaluate_us": 1e6 * timed_steps(ev, 200, 10, sync),
+                           "step_us": 1e6 * timed_steps(st, 100, 5, sync)}
+            t1.close()
+
     cpu = None
     if not args.no_cpu:
         ns = args.cpu_sample if args.cpu_sample > 0 else n
@@ -251,6 +278,7 @@ def main():
         "rel_l2": rel,
         "cpu_baseline": cpu,
         "adjoint": adj,
+        "small": small,
     }
     if fp64 is not None:
         line["fp64"] = {"particles_per_s": n / fp64["sec"], "ms_per_step": fp64["sec"] * 1e3,

@@ -97,7 +97,18 @@ typedef struct {
                                   own, forked from and joined back into the
                                   caller's stream within each call (same results);
                                   zero (default): after the far field */
-    int32_t reserved[6];       /* zero */
+    int32_t graph;             /* nonzero: fmm_evaluate and fmm_backward replay a
+                                  HIP graph of their kernel chain.  A call whose
+                                  arguments (pointers, flags, stream-independent)
+                                  differ from the cached graph's, or that follows
+                                  a rebuild that changed the level, the particle
+                                  count or the tree's memory, runs eagerly and then
+                                  captures the chain on a stream of the library's
+                                  own (capture executes nothing); later calls
+                                  launch the graph on their stream.  Same kernels,
+                                  same results.  Exclusive with `profile`
+                                  (FMM_EINVAL). */
+    int32_t reserved[5];       /* zero */
 } fmm_config;
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed

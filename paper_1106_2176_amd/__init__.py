@@ -44,7 +44,8 @@ class Config(ctypes.Structure):
         ("alloc_ctx", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
         ("overlap_near", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -115,7 +116,8 @@ def _check(rc):
 
 
 def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
-                box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False):
+                box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
+                graph=False):
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)
@@ -129,6 +131,7 @@ def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3
     c.box_size = float(box_size)
     c.profile = 1 if profile else 0
     c.overlap_near = 1 if overlap_near else 0
+    c.graph = 1 if graph else 0
     return c
 
 
@@ -174,13 +177,18 @@ def _check_tensor(t, name, shape, dtype):
 
 
 class Tree:
-    """An octree built on the GPU; owns library memory until close()."""
+    """An octree built on the GPU; owns library memory until close().
+
+    graph=True replays a HIP graph of the evaluate/backward chain; it is reused
+    while the output tensors passed in (phi, out_vec, gradients) and the
+    tree's memory stay the same, so pass preallocated outputs."""
 
     def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
-                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False):
+                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
+                 graph=False):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,
-                               profile, overlap_near)
+                               profile, overlap_near, graph)
         self.rebuild(pos)
 
     def rebuild(self, pos):
@@ -210,12 +218,20 @@ class Tree:
                                   flags | pf, _stream_ptr()))
         return phi, (out_vec if flags else None)
 
-    def backward(self, q, w, field, grad_q=True, grad_pos=True):
+    def backward(self, q, w, field, grad_q=True, grad_pos=True, out_q=None, out_pos=None):
+        """(dLoss/dq, dLoss/dpos) for Loss = sum w phi; out_q / out_pos are
+        optional preallocated outputs."""
         torch = _torch()
         _check_tensor(q, "q", (self.n,), self.dtype)
         _check_tensor(w, "w", (self.n,), self.dtype)
-        gq = torch.empty(self.n, dtype=self.dtype, device=q.device) if grad_q else None
-        gx = torch.empty(self.n, 3, dtype=self.dtype, device=q.device) if grad_pos else None
+        gq = gx = None
+        if grad_q:
+            gq = out_q if out_q is not None else torch.empty(self.n, dtype=self.dtype, device=q.device)
+            _check_tensor(gq, "out_q", (self.n,), self.dtype)
+        if grad_pos:
+            gx = out_pos if out_pos is not None else \
+                torch.empty(self.n, 3, dtype=self.dtype, device=q.device)
+            _check_tensor(gx, "out_pos", (self.n, 3), self.dtype)
         if grad_pos:
             _check_tensor(field, "field", (self.n, 3), self.dtype)
         _check(lib().fmm_backward(self._h, _dptr(q), _dptr(w), _dptr(field) if field is not None else None,

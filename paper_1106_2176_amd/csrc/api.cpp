@@ -164,6 +164,10 @@ fmm_status build_ops(int p, Ops **out) {
     std::vector<float> t32;
 #define UP64(field, vec) \
     if (e == hipSuccess) e = upload((void **)&o->field, vec.data(), vec.size() * sizeof(vec[0]));
+    // the transfer kernels read up to 4 p^2 + 16 entries past a table's end:
+    // rows of the last row tile past p^2 (whose results are discarded) and K
+    // steps past p^2 (multiplied by zero)
+    for (auto *v : {&up, &down, &aup, &adown}) v->resize(v->size() + 4 * (size_t)P2 + 16, 0.0);
     UP64(up64, up) UP64(down64, down) UP64(aup64, aup) UP64(adown64, adown)
     t32 = up32f(up); UP64(up32, t32)
     t32 = up32f(down); UP64(down32, t32)
@@ -196,6 +200,19 @@ constexpr int kStages = 9;
 constexpr int kTimeRing = 32;  // event sets: stage times of the last 32 profiled calls
 constexpr int kEvents = kStages + 3;  // stage boundaries + start/end of a concurrent P2P
 
+// An instantiated graph of one evaluate or backward chain and the arguments
+// it was captured with (graph mode).
+struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;  // stream of its latest launch
+    uint64_t gen = 0;            // tree memory generation at capture
+    int L = -1;
+    int64_t n = 0;
+    fmm_config cfg{};
+    const void *arg[5] = {};
+    int32_t flags = 0;
+};
+
 }  // namespace
 
 struct fmm_tree {
@@ -221,7 +238,10 @@ struct fmm_tree {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t ncalls = 0;  // profiled calls since the last reset
     int cur = 0;         // event set of the call in progress
-    hipStream_t last_stream = nullptr;
+    uint64_t gen = 0;    // bumped whenever a buffer is allocated or released
+    hipStream_t cap = nullptr;  // capture stream of graph mode
+    bool capturing = false;
+    GraphSlot gfwd, gbwd;       // graphs of fmm_evaluate and fmm_backward
 };
 
 namespace {
@@ -240,6 +260,10 @@ int level_f64(const fmm_tree *t, int l) {
 fmm_status ensure(fmm_tree *t, Buf &b, size_t bytes, hipStream_t st) {
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return FMM_OK;
+    // a graph is captured right after an eager run of the same chain, which
+    // allocated everything it needs
+    if (t->capturing) return fail(FMM_EDEVICE, "internal: allocation during graph capture");
+    ++t->gen;
     if (b.p) {
         if (t->al.fa)
             t->al.ff(b.p, st, t->al.ctx);
@@ -264,6 +288,7 @@ fmm_status ensure(fmm_tree *t, Buf &b, size_t bytes, hipStream_t st) {
 
 void release(fmm_tree *t, Buf &b, hipStream_t st) {
     if (!b.p) return;
+    ++t->gen;
     if (t->al.fa)
         t->al.ff(b.p, st, t->al.ctx);
     else
@@ -287,13 +312,14 @@ fmm_status validate_cfg(const fmm_config *c) {
     if (!(c->box_size > 0.0) || !std::isfinite(c->box_size)) return fail(FMM_EINVAL, "box_size must be > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->box_lo[a])) return fail(FMM_EINVAL, "box_lo must be finite");
+    if (c->graph && c->profile) return fail(FMM_EINVAL, "graph and profile are exclusive");
     if ((c->alloc == nullptr) != (c->free == nullptr))
         return fail(FMM_EINVAL, "alloc and free callbacks must be given together");
     return FMM_OK;
 }
 
 fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
-    if (!t->cfg.profile) return FMM_OK;
+    if (!t->cfg.profile || t->capturing) return FMM_OK;
     if (!t->ev_ready) {
         for (int j = 0; j < kTimeRing; ++j)
             for (int i = 0; i < kEvents; ++i) HIPCHK(hipEventCreate(&t->ev[j][i]));
@@ -318,7 +344,6 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     const uint32_t *start = (const uint32_t *)t->start.p;
     const int nsplit = t->cfg.bf16_splits == 2 ? 2 : 3;
     t->cur = (int)(t->ncalls % kTimeRing);
-    t->last_stream = st;
 
     // guards: every buffer a kernel will touch holds what that kernel assumes
     const size_t src_bytes = (f64 ? sizeof(double4) : sizeof(int4)) * (size_t)t->n;
@@ -409,8 +434,93 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     CHK(rec(t, 7, st));
     if (side) HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
     else if (do_near) HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, st));
-    else HIPCHK(hipMemsetAsync(t->nearf.p, 0, sizeof(double4) * (size_t)t->n, st));
+    else HIPCHK(launch_zero((uint32_t *)t->nearf.p, 8 * t->n, st));
     CHK(rec(t, 8, st));
+    return FMM_OK;
+}
+
+// ---------------------------------------------------------------- graphs
+bool slot_matches(const fmm_tree *t, const GraphSlot &g, const void *const arg[5], int32_t flags) {
+    if (!g.exec || g.gen != t->gen || g.L != t->L || g.n != t->n || g.flags != flags) return false;
+    if (std::memcmp(&g.cfg, &t->cfg, sizeof(fmm_config)) != 0) return false;
+    for (int i = 0; i < 5; ++i)
+        if (g.arg[i] != arg[i]) return false;
+    return true;
+}
+
+fmm_status drop_graph(GraphSlot &g) {
+    if (!g.exec) return FMM_OK;
+    // the previous graph may still run on the stream of its latest launch
+    if (g.last) HIPCHK(hipStreamSynchronize(g.last));
+    HIPCHK(hipGraphExecDestroy(g.exec));
+    g.exec = nullptr;
+    g.last = nullptr;
+    return FMM_OK;
+}
+
+// Capture `chain` (the launches of one call, issued on the stream it is
+// given) into `g`.  Capturing executes nothing.
+template <typename Chain>
+fmm_status capture_graph(fmm_tree *t, GraphSlot &g, const void *const arg[5], int32_t flags,
+                         Chain chain) {
+    CHK(drop_graph(g));
+    if (!t->cap) HIPCHK(hipStreamCreateWithFlags(&t->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(t->cap, hipStreamCaptureModeThreadLocal));
+    t->capturing = true;
+    const fmm_status s = chain(t->cap);
+    t->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(t->cap, &graph);
+    if (s != FMM_OK) {
+        if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(FMM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        g.exec = nullptr;
+        return fail(FMM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    g.gen = t->gen;
+    g.L = t->L;
+    g.n = t->n;
+    g.cfg = t->cfg;
+    g.flags = flags;
+    for (int i = 0; i < 5; ++i) g.arg[i] = arg[i];
+    return FMM_OK;
+}
+
+fmm_status launch_graph(GraphSlot &g, hipStream_t st) {
+    HIPCHK(hipGraphLaunch(g.exec, st));
+    g.last = st;
+    return FMM_OK;
+}
+
+fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int32_t flags,
+                          hipStream_t st) {
+    const int kind = flags & 3, part = flags & ~3;
+    const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
+    CHK(run_chain(t, q, false, do_far, do_near, st));
+    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
+    HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, (const double4 *)t->nearf.p,
+                          (t->L >= 2 && do_far) ? (const double4 *)t->farf.p : nullptr, inv_w, q, phi,
+                          vec, kind, st));
+    CHK(rec(t, kStages, st));
+    if (t->cfg.profile) ++t->ncalls;
+    return FMM_OK;
+}
+
+fmm_status backward_chain(fmm_tree *t, const void *q, const void *w, const void *field_fwd,
+                          void *grad_q, void *grad_pos, hipStream_t st) {
+    CHK(run_chain(t, w, true, true, true, st));
+    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
+    HIPCHK(launch_combine_grad(t->n, t->dtype, (const uint32_t *)t->perm.p,
+                               (const double4 *)t->nearf.p,
+                               t->L >= 2 ? (const double4 *)t->farf.p : nullptr, inv_w, q, w,
+                               field_fwd, grad_q, grad_pos, st));
+    CHK(rec(t, kStages, st));
+    if (t->cfg.profile) ++t->ncalls;
     return FMM_OK;
 }
 
@@ -569,15 +679,13 @@ fmm_status fmm_evaluate(fmm_tree *t, const void *q, void *phi, void *vec, int32_
         return fail(FMM_EINVAL, "unknown flags");
     if (kind != FMM_VEC_NONE && !vec) return fail(FMM_EINVAL, "vec is NULL");
     hipStream_t st = (hipStream_t)stream;
-    const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
-    CHK(run_chain(t, q, false, do_far, do_near, st));
-    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
-    HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, (const double4 *)t->nearf.p,
-                          (t->L >= 2 && do_far) ? (const double4 *)t->farf.p : nullptr, inv_w, q, phi,
-                          vec, kind, st));
-    CHK(rec(t, kStages, st));
-    if (t->cfg.profile) ++t->ncalls;
-    return FMM_OK;
+    if (!t->cfg.graph) return evaluate_chain(t, q, phi, vec, flags, st);
+    const void *arg[5] = {q, phi, vec, nullptr, nullptr};
+    if (slot_matches(t, t->gfwd, arg, flags)) return launch_graph(t->gfwd, st);
+    CHK(evaluate_chain(t, q, phi, vec, flags, st));
+    return capture_graph(t, t->gfwd, arg, flags, [&](hipStream_t cs) {
+        return evaluate_chain(t, q, phi, vec, flags, cs);
+    });
 }
 
 fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *field_fwd,
@@ -586,15 +694,13 @@ fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *f
     if (grad_pos && !field_fwd) return fail(FMM_EINVAL, "field_fwd is required for grad_pos");
     if (!grad_q && !grad_pos) return FMM_OK;
     hipStream_t st = (hipStream_t)stream;
-    CHK(run_chain(t, w, true, true, true, st));
-    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
-    HIPCHK(launch_combine_grad(t->n, t->dtype, (const uint32_t *)t->perm.p,
-                               (const double4 *)t->nearf.p,
-                               t->L >= 2 ? (const double4 *)t->farf.p : nullptr, inv_w, q, w,
-                               field_fwd, grad_q, grad_pos, st));
-    CHK(rec(t, kStages, st));
-    if (t->cfg.profile) ++t->ncalls;
-    return FMM_OK;
+    if (!t->cfg.graph) return backward_chain(t, q, w, field_fwd, grad_q, grad_pos, st);
+    const void *arg[5] = {q, w, field_fwd, grad_q, grad_pos};
+    if (slot_matches(t, t->gbwd, arg, 0)) return launch_graph(t->gbwd, st);
+    CHK(backward_chain(t, q, w, field_fwd, grad_q, grad_pos, st));
+    return capture_graph(t, t->gbwd, arg, 0, [&](hipStream_t cs) {
+        return backward_chain(t, q, w, field_fwd, grad_q, grad_pos, cs);
+    });
 }
 
 fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
@@ -677,6 +783,9 @@ fmm_status fmm_tree_export(const fmm_tree *t, uint32_t *perm, uint32_t *leaf_sta
 
 void fmm_tree_destroy(fmm_tree *t) {
     if (!t) return;
+    (void)drop_graph(t->gfwd);
+    (void)drop_graph(t->gbwd);
+    if (t->cap) (void)hipStreamDestroy(t->cap);
     hipStream_t st = t->stream;
     Buf *bufs[] = {&t->key10, &t->rank, &t->cnt, &t->start, &t->tmp, &t->perm, &t->scan,
                    &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};

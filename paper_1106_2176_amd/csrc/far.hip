@@ -245,112 +245,136 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
 // ------------------------------------------------------- M2M / L2L transfers
 // UP:   out[parent][o]  = sum_c sum_k tab[c][k][o] in[child c][k]
 // DOWN: out[child c][o] += sum_k tab[c][k][o] in[parent][k]
-// tab is [8][p^2][p^2] input-major.  Both are small GEMMs (rows = output
-// coefficients, columns = parents) run on the FP64 matrix cores whatever the
-// storage precision of the levels, in tiles of 16 output rows x 16
+// tab is [8][p^2][p^2] input-major, padded with 4 p^2 + 16 zeros so that the
+// last row tile and K step read in bounds.  Both are small GEMMs (rows =
+// output coefficients, columns = parents) on the FP64 matrix cores whatever
+// the storage precision of the levels: tiles of 16 output rows x 16
 // consecutive parents, K in steps of 4 (v_mfma_f64_16x16x4_f64; A lane l
 // holds row l%16, K l/16; B lane l holds K l/16, column l%16; result lane l,
 // item i holds row l/16 + 4i of column l%16).
+// A block is 8 waves over 16 parents, wave c taking child octant c, and NT
+// row tiles starting at row tile blockIdx.y * NT (NT = all of them, or one
+// for coarse levels with few parents): each B value a wave loads feeds NT
+// MFMAs.  Every load is unconditional, so that the loads of a K step and the
+// next are in flight together.
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
-// UP: a block = one tile of 16 output rows x 16 parents; its 4 waves take a
-// quarter of K = 8 p^2 each and their partial tiles are summed in wave order
-// through LDS.
-template <int P, typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_up(int lp, const Tin *__restrict__ in, Tout *__restrict__ out,
-                                            const double *__restrict__ tab) {
-    constexpr int P2 = P * P, S = coef_stride(P), K = 8 * P2, NIT = (K + 15) / 16;
-    constexpr int NITW = (NIT + 3) / 4;  // K-chunks per wave
-    __shared__ f64x4_t red[4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = lane >> 4, col = lane & 15;
-    const int rt = blockIdx.y;  // row tile
-    const int64_t np = (int64_t)1 << lp, nc = 2 * np, npar = np * np * np;
-    const int64_t par = (int64_t)blockIdx.x * 16 + col;
-    const bool valid = par < npar;
-    const int64_t pc = valid ? par : 0;
-    const int64_t pi = pc % np, pj = (pc / np) % np, pk = pc / (np * np);
-    const int64_t child0 = ((2 * pi) + nc * ((2 * pj) + nc * (2 * pk))) * S;  // child c = 0
-    const int orow = rt * 16 + col;  // A row held by this lane
-    const bool rowok = orow < P2;
-    const int arow = rowok ? orow : 0;
-    f64x4_t acc = {0, 0, 0, 0};
-    // fixed trip count and unconditional (clamped) loads, so that the loads
-    // of several K-chunks are in flight at once
+template <int P>
+__device__ __forceinline__ int64_t child_box(int64_t par, int64_t np, int c) {
+    const int64_t nc = 2 * np;
+    const int64_t pi = par % np, pj = (par / np) % np, pk = par / (np * np);
+    return (2 * pi + (c & 1)) + nc * ((2 * pj + ((c >> 1) & 1)) + nc * (2 * pk + (c >> 2)));
+}
+
+// acc[i] += A(row tile rt0 + i) * B over K = p^2 in steps of 4.  The loads
+// of step s are issued D steps before its MFMAs (the K loop is unrolled and
+// a scheduling barrier after each step keeps the loads where they are).  ap
+// points at this lane's A element of row tile rt0 and K step 0; bload(s)
+// returns this lane's B value of step s (k = 4 s + q < S, in bounds), masked
+// here for k >= p^2.
+template <int P, int NT, typename TB, typename BLoad>
+__device__ __forceinline__ void transfer_gemm(f64x4_t (&acc)[NT], const double *__restrict__ ap,
+                                              int q, BLoad bload) {
+    constexpr int P2 = P * P, NKS = (P2 + 3) / 4;
+    constexpr int D = NT <= 8 ? 3 : 2;
+    double av[D][NT];
+    TB bv[D];
 #pragma unroll
-    for (int it = 0; it < NITW; ++it) {
-        double a[4], b[4];
+    for (int s = 0; s < NKS + D; ++s) {
+        if (s >= D) {
+            const int t = s - D, d = t % D;
+            const bool use = P2 % 4 == 0 || 4 * t + q < P2;
+            const double b = use ? (double)bv[d] : 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int kk = 16 * (wave * NITW + it) + 4 * j + q;
-            const bool ok = kk < K;
-            const int kc = ok ? kk : K - 1;
-            const int c = kc / P2, k = kc - c * P2;
-            const int64_t ch = child0 + ((c & 1) + nc * (((c >> 1) & 1) + nc * (c >> 2))) * S;
-            const double av = tab[((size_t)c * P2 + k) * P2 + arow];
-            const double bv = (double)in[ch + k];
-            a[j] = (ok && rowok) ? av : 0.0;
-            b[j] = ok ? bv : 0.0;
+            for (int i = 0; i < NT; ++i)
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][i], b, acc[i], 0, 0, 0);
         }
+        if (s < NKS) {
+            const int d = s % D;
+            const double *a = ap + (size_t)4 * s * P2;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
-    }
-    red[wave][lane] = acc;
-    __syncthreads();
-    if (wave != 0 || !valid) return;
-    f64x4_t sum = red[0][lane];
-#pragma unroll
-    for (int w = 1; w < 4; ++w) sum += red[w][lane];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int o = rt * 16 + q + 4 * i;
-        if (o < P2) out[par * S + o] = (Tout)sum[i];
+            for (int i = 0; i < NT; ++i) av[d][i] = a[16 * i];
+            bv[d] = bload(s);
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// rows of the stacked [8 p^2] output (child-major); K = p^2
-template <int P, typename Tin, typename Tout>
-__global__ __launch_bounds__(256) void k_down(int lp, const Tin *__restrict__ in, Tout *__restrict__ out,
-                                              const double *__restrict__ tab) {
-    constexpr int P2 = P * P, S = coef_stride(P), M = 8 * P2, NIT = (P2 + 15) / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// UP: wave c accumulates child c's contribution (K = p^2); the 8 partial
+// tiles are summed through LDS in child order 0..7.
+template <int P, int NT, typename Tin, typename Tout>
+__global__ __launch_bounds__(512) void k_up(int lp, const Tin *__restrict__ in,
+                                            Tout *__restrict__ out, const double *__restrict__ tab) {
+    constexpr int P2 = P * P, S = coef_stride(P);
+    __shared__ f64x4_t red[7][64];
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
     const int q = lane >> 4, col = lane & 15;
-    const int rt = blockIdx.y * 4 + wave;
-    if (rt * 16 >= M) return;
-    const int64_t np = (int64_t)1 << lp, nc = 2 * np, npar = np * np * np;
+    const int rt0 = blockIdx.y * NT;
+    const int64_t np = (int64_t)1 << lp, npar = np * np * np;
     const int64_t par = (int64_t)blockIdx.x * 16 + col;
     const bool valid = par < npar;
-    const int64_t pc = valid ? par : 0;
-    const int arow = rt * 16 + col;  // stacked row held by this lane as A row
-    const bool rowok = arow < M;
-    const int ac = rowok ? arow / P2 : 0, ao = rowok ? arow - ac * P2 : 0;
-    f64x4_t acc = {0, 0, 0, 0};
+    const Tin *bp = in + child_box<P>(valid ? par : 0, np, c) * S + q;
+    const double *ap = tab + ((size_t)c * P2 + q) * P2 + rt0 * 16 + col;
+    f64x4_t acc[NT];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        double a[4], b[4];
+    for (int i = 0; i < NT; ++i) acc[i] = f64x4_t{0, 0, 0, 0};
+    // k = 4 s + q < S (S is a multiple of 8 >= p^2); the stride padding of a
+    // coefficient row is not initialised and is masked in transfer_gemm
+    transfer_gemm<P, NT, Tin>(acc, ap, q, [&](int s) { return bp[4 * s]; });
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        if (c > 0) red[c - 1][lane] = acc[i];
+        __syncthreads();
+        if (c == 0 && valid) {
+            f64x4_t sum = acc[i];
+#pragma unroll
+            for (int w = 0; w < 7; ++w) sum += red[w][lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = (rt0 + i) * 16 + q + 4 * j;
+                if (o < P2) out[par * S + o] = (Tout)sum[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// DOWN: the 16 parents' coefficients are staged in LDS (one contiguous run);
+// wave c writes child c's rows.
+template <int P, int NT, typename Tin, typename Tout>
+__global__ __launch_bounds__(512) void k_down(int lp, const Tin *__restrict__ in,
+                                              Tout *__restrict__ out, const double *__restrict__ tab) {
+    constexpr int P2 = P * P, S = coef_stride(P);
+    constexpr int SP = S + 1;  // odd stride: the 16 columns of a B read hit distinct banks
+    __shared__ double sB[16 * SP];
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    const int rt0 = blockIdx.y * NT;
+    const int64_t np = (int64_t)1 << lp, npar = np * np * np;
+    const int64_t par0 = (int64_t)blockIdx.x * 16;
+    const int ncol = (int)min((int64_t)16, npar - par0);
+    for (int e = threadIdx.x; e < 16 * S; e += 512) {
+        const int j = e / S, k = e - j * S;
+        double v = 0.0;
+        if (j < ncol && k < P2) v = (double)in[(par0 + j) * S + k];
+        sB[j * SP + k] = v;
+    }
+    __syncthreads();
+    const double *ap = tab + ((size_t)c * P2 + q) * P2 + rt0 * 16 + col;
+    f64x4_t acc[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = f64x4_t{0, 0, 0, 0};
+    const double *bcol = sB + col * SP + q;
+    transfer_gemm<P, NT, double>(acc, ap, q, [&](int s) { return bcol[4 * s]; });
+    if (col >= ncol) return;
+    Tout *dst = out + child_box<P>(par0 + col, np, c) * S;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int kk = 16 * it + 4 * j + q;
-            const bool ok = kk < P2;
-            const int k = ok ? kk : P2 - 1;
-            const double av = tab[((size_t)ac * P2 + k) * P2 + ao];
-            const double bv = (double)in[pc * S + k];
-            a[j] = (ok && rowok) ? av : 0.0;
-            b[j] = ok ? bv : 0.0;
+            const int o = (rt0 + i) * 16 + q + 4 * j;
+            if (o < P2) dst[o] = (Tout)((double)dst[o] + acc[i][j]);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[j], acc, 0, 0, 0);
-    }
-    if (!valid) return;
-    const int64_t pi = pc % np, pj = (pc / np) % np, pk = pc / (np * np);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = rt * 16 + q + 4 * i;
-        if (row >= M) continue;
-        const int c = row / P2, o = row - c * P2;
-        const int64_t ch = (2 * pi + (c & 1)) + nc * ((2 * pj + ((c >> 1) & 1)) + nc * (2 * pk + ((c >> 2) & 1)));
-        Tout *dst = out + ch * S + o;
-        *dst = (Tout)((double)*dst + acc[i]);
     }
 }
 
@@ -487,15 +511,22 @@ template <int P>
 static void transfer_p(bool up, int lp, int in_f64, int out_f64, const void *in, void *out,
                        const double *tab, hipStream_t st) {
     const int64_t np = (int64_t)1 << (3 * lp);
-    // UP: one block per 16 rows (its waves split K); DOWN: one wave per 16 rows
-    const dim3 grid((unsigned)((np + 15) / 16),
-                    up ? (unsigned)((P * P + 15) / 16) : (unsigned)((8 * P * P + 63) / 64));
-#define LAUNCH(TI, TO)                                                                      \
-    do {                                                                                    \
-        if (up)                                                                             \
-            k_up<P, TI, TO><<<grid, 256, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);     \
-        else                                                                                \
-            k_down<P, TI, TO><<<grid, 256, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);   \
+    // blocks of 16 parents; all row tiles in one block when there are enough
+    // parent tiles to fill the chip, else one row tile per block
+    constexpr int NRT = (P * P + 15) / 16;
+    const unsigned ncol = (unsigned)((np + 15) / 16);
+    const bool all = ncol >= 128;
+    const dim3 grid(ncol, all ? 1u : (unsigned)NRT);
+#define LAUNCH(TI, TO)                                                                           \
+    do {                                                                                         \
+        if (up && all)                                                                           \
+            k_up<P, NRT, TI, TO><<<grid, 512, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);     \
+        else if (up)                                                                             \
+            k_up<P, 1, TI, TO><<<grid, 512, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);       \
+        else if (all)                                                                            \
+            k_down<P, NRT, TI, TO><<<grid, 512, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);   \
+        else                                                                                     \
+            k_down<P, 1, TI, TO><<<grid, 512, 0, st>>>(lp, (const TI *)in, (TO *)out, tab);     \
     } while (0)
     if (in_f64 && out_f64)
         LAUNCH(double, double);

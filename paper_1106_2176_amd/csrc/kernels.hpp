@@ -14,6 +14,8 @@ hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3]
 // leaf counts + ranks at another level from the keys (counters[1] restarts)
 hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt, uint32_t *rank,
                        unsigned int *counters, hipStream_t st);
+// zero `words` 32-bit words with a kernel (not a memset node when captured)
+hipError_t launch_zero(uint32_t *p, int64_t words, hipStream_t st);
 hipError_t launch_max(int level, const uint32_t *cnt, unsigned int *mx, hipStream_t st);
 int64_t scan_scratch_words(int64_t nb);
 hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,

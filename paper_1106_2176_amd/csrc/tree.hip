@@ -220,6 +220,12 @@ hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3]
     return hipGetLastError();
 }
 
+hipError_t launch_zero(uint32_t *p, int64_t words, hipStream_t st) {
+    if (words <= 0) return hipSuccess;
+    k_zero<<<nblk(words, 256), 256, 0, st>>>(words, p, nullptr, 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cnt, uint32_t *rank,
                        unsigned int *counters, hipStream_t st) {
     const int64_t nb = (int64_t)1 << (3 * level);

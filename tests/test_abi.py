@@ -35,7 +35,7 @@ def test_status_strings_and_defaults():
     assert c.abi_version == fmm.FMM_ABI_VERSION
     assert (c.p, c.leaf_max, c.max_level, c.precision, c.bf16_splits) == (8, 64, 10, 1, 3)
     assert c.box_size == 1.0 and list(c.box_lo) == [0.0, 0.0, 0.0]
-    # 6 int32 (24) + double[3] (24) + double (8) + 3 pointers (24) + int32 + int32[7] (32)
+    # 6 int32 (24) + double[3] (24) + double (8) + 3 pointers (24) + int32[8] (32)
     assert ctypes.sizeof(fmm.Config) == 112
 
 
@@ -57,6 +57,13 @@ def test_build_rejects_bad_config(field, value):
     assert rc == fmm.FMM_EINVAL
     assert not h.value
     assert fmm.lib().fmm_last_error_message()
+
+
+def test_graph_and_profile_are_exclusive():
+    cfg = fmm.make_config(graph=True, profile=True)
+    rc, h = _build(cfg)
+    assert rc == fmm.FMM_EINVAL and not h.value
+    assert b"exclusive" in fmm.lib().fmm_last_error_message()
 
 
 def test_build_rejects_bad_arguments():
