@@ -11,11 +11,13 @@
 
 namespace fmm {
 
-// Regular harmonics of one point written with a stride (LDS transposition)
+// Regular harmonics of one point times `seed`, written with a stride (LDS
+// transposition).  The recurrences are linear in the degree-0 term, so
+// starting them from `seed` instead of 1 scales every harmonic by it.
 template <int P, typename T>
-__device__ __forceinline__ void rho_strided(T x, T y, T z, T *out, int stride) {
+__device__ __forceinline__ void rho_strided(T x, T y, T z, T seed, T *out, int stride) {
     const T r2 = x * x + y * y + z * z;
-    T dr = T(1), di = T(0);
+    T dr = seed, di = T(0);
 #pragma unroll
     for (int m = 0; m < P; ++m) {
         if (m > 0) {
@@ -59,53 +61,69 @@ template <> struct V4T<float> { using type = int4; };
 template <> struct V4T<double> { using type = double4; };
 
 // ---------------------------------------------------------------- P2M
-// mu(leaf) = scale * sum_j q_j rho(u_j).  One 64-lane block per leaf; rounds
-// of RS particles write their harmonics into LDS [coef][particle], then lanes
-// sum rows (fixed order, deterministic).
+// mu(leaf) = scale * sum_j q_j rho(u_j).  Two Morton-consecutive leaves per
+// 64-lane block, 32 lanes each: rounds of RS particles per leaf write q rho
+// into LDS [coef][particle]; then the 64 lanes sum the rows of both leaves'
+// coefficients (fixed order, deterministic).
+template <int P, typename T>
+constexpr int p2m_rows() {
+    constexpr int P2 = P * P;
+    return 2 * P2 * 33 * (int)sizeof(T) <= 40960 ? 32 : 2 * P2 * 17 * (int)sizeof(T) <= 40960 ? 16 : 8;
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_p2m(int L, const typename V4T<T>::type *__restrict__ src,
                                             const uint32_t *__restrict__ start, T *__restrict__ M,
                                             double scale) {
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
-    constexpr int RSraw = 16384 / (P2 * (int)sizeof(T));
-    constexpr int RS = RSraw >= 64 ? 64 : RSraw >= 32 ? 32 : RSraw >= 16 ? 16 : 8;
-    constexpr int NA = (P2 + 63) / 64;
-    __shared__ T buf[P2 * (RS + 1)];
-    const int lane = threadIdx.x;
-    const uint32_t leaf = blockIdx.x;
-    const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
-    const int side = 1 << L;
-    const size_t row = (size_t)compact3(leaf) +
-                       (size_t)side * (compact3(leaf >> 1) + (size_t)side * compact3(leaf >> 2));
-    T acc[NA];
+    constexpr int RS = p2m_rows<P, T>();
+    constexpr int NI = (2 * P2 + 63) / 64;  // (leaf, coefficient) items per lane
+    __shared__ T buf[2][P2 * (RS + 1)];
+    const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+    const uint32_t nleaf = 1u << (3 * L), l0 = 2 * blockIdx.x;
+    // both leaves' ranges, uniform over the block (the second is empty past the end)
+    const uint32_t sa = start[l0], sb = start[min(l0 + 1, nleaf)], se = start[min(l0 + 2, nleaf)];
+    const uint32_t ca = sb - sa, cb = se - sb;
+    const uint32_t my0 = half ? sb : sa, myc = half ? cb : ca;
+    const uint32_t rounds = (max(ca, cb) + RS - 1) / RS;
+    T acc[NI];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = T(0);
-    for (uint32_t c0 = 0; c0 < cnt; c0 += RS) {
-        const int nr = (int)min((uint32_t)RS, cnt - c0);
-        __syncthreads();
-        if (lane < nr) {
+    for (int a = 0; a < NI; ++a) acc[a] = T(0);
+    for (uint32_t r = 0; r < rounds; ++r) {
+        const uint32_t c0 = r * RS;
+        if (r > 0) __syncthreads();
+        if (hl < RS && c0 + hl < myc) {
             T x, y, z, q;
-            unpack_rec(src[s0 + c0 + lane], x, y, z, q);
-            rho_strided<P, T>(x, y, z, buf + lane, RS + 1);
-#pragma unroll
-            for (int c = 0; c < P2; ++c) buf[c * (RS + 1) + lane] *= q;
+            unpack_rec(src[my0 + c0 + hl], x, y, z, q);
+            rho_strided<P, T>(x, y, z, q, buf[half] + hl, RS + 1);
         }
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const int c = lane + 64 * a;
-            if (c < P2) {
-                T s = T(0);
-                for (int j = 0; j < nr; ++j) s += buf[c * (RS + 1) + j];
-                acc[a] += s;
+        for (int a = 0; a < NI; ++a) {
+            const int item = lane + 64 * a;
+            if (item < 2 * P2) {
+                const int h = item >= P2, c = item - h * P2;
+                const uint32_t ch = h ? cb : ca;
+                const int nr = ch > c0 ? (int)min((uint32_t)RS, ch - c0) : 0;
+                const T *row = buf[h] + c * (RS + 1);
+                T sum = T(0);
+                for (int j = 0; j < nr; ++j) sum += row[j];
+                acc[a] += sum;
             }
         }
     }
+    const int side = 1 << L;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        const int c = lane + 64 * a;
-        if (c < P2) M[row * S + c] = (T)(acc[a] * (T)scale);
+    for (int a = 0; a < NI; ++a) {
+        const int item = lane + 64 * a;
+        const int h = item >= P2, c = item - h * P2;
+        const uint32_t leaf = l0 + h;
+        if (item < 2 * P2 && leaf < nleaf) {
+            const size_t row = (size_t)compact3(leaf) +
+                               (size_t)side * (compact3(leaf >> 1) + (size_t)side * compact3(leaf >> 2));
+            M[row * S + c] = (T)(acc[a] * (T)scale);
+        }
     }
 }
 
@@ -136,25 +154,31 @@ __device__ inline void getL(const T *ell, int P, int n, int m, T &re, T &im) {
     }
 }
 
+// Two Morton-consecutive leaves per 64-lane block, 32 lanes each (a leaf
+// holds a few tens of particles).  The harmonic loops are fully unrolled, so
+// that every recurrence coefficient is a compile-time constant.
 template <int P, typename T>
 __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *__restrict__ src,
                                             const uint32_t *__restrict__ start,
                                             const T *__restrict__ Lc, double4 *__restrict__ out) {
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
+    constexpr int HL = 32;  // lanes per leaf
     using V = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
-    __shared__ T ell[P2];
-    __shared__ V coef[P2];  // (ell, Gx, Gy, Gz) per slot
-    const int lane = threadIdx.x;
-    const uint32_t leaf = blockIdx.x;
-    const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
-    if (cnt == 0) return;
+    __shared__ T ells[2][P2];
+    __shared__ V coefs[2][P2];  // (ell, Gx, Gy, Gz) per slot
+    const int hl = threadIdx.x & (HL - 1), half = threadIdx.x / HL;
+    const uint32_t leaf = 2 * blockIdx.x + half;
+    const bool live = leaf < (1u << (3 * L));  // the second half is idle at level 0
+    const uint32_t s0 = live ? start[leaf] : 0u, cnt = live ? start[leaf + 1] - s0 : 0u;
+    T *const ell = ells[half];
+    V *const coef = coefs[half];
     const int side = 1 << L;
     const size_t row = (size_t)compact3(leaf) +
                        (size_t)side * (compact3(leaf >> 1) + (size_t)side * compact3(leaf >> 2));
-    for (int c = lane; c < P2; c += 64) ell[c] = Lc[row * S + c];
+    for (int c = hl; c < P2; c += HL) ell[c] = live ? Lc[row * S + c] : T(0);
     __syncthreads();
-    for (int c = lane; c < P2; c += 64) {
+    for (int c = hl; c < P2; c += HL) {
         // slot c -> (j, v, part)
         int j = 0;
         while ((j + 1) * (j + 1) <= c) ++j;
@@ -190,13 +214,16 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
         coef[c] = w;
     }
     __syncthreads();
-    for (uint32_t j0 = lane; j0 < cnt; j0 += 64) {
+    for (uint32_t j0 = hl; j0 < cnt; j0 += HL) {
+        // keep the coefficient reads in the loop: hoisted, all p^2 of them
+        // would be held in registers
+        __asm__ volatile("" ::: "memory");
         T x, y, z, qq;
         unpack_rec(src[s0 + j0], x, y, z, qq);
         const T r2 = x * x + y * y + z * z;
         T phi = T(0), gx = T(0), gy = T(0), gz = T(0);
         T dr = T(1), di = T(0);
-#pragma unroll 1
+#pragma unroll
         for (int m = 0; m < P; ++m) {
             if (m > 0) {
                 const T inv = T(-1) / T(2 * m);
@@ -465,7 +492,7 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 template <typename T>
 static hipError_t p2m_dispatch(int P, int L, const void *src, const uint32_t *start, T *M,
                                double scale, hipStream_t st) {
-    const unsigned g = 1u << (3 * L);
+    const unsigned g = ((1u << (3 * L)) + 1) / 2;  // two leaves per block
     using V = typename V4T<T>::type;
     switch (P) {
 #define CASE(PP) \
@@ -487,7 +514,7 @@ hipError_t launch_p2m(int P, int L, bool f64, const void *src, const uint32_t *s
 template <typename T>
 static hipError_t l2p_dispatch(int P, int L, const void *src, const uint32_t *start, const T *Lc,
                                double4 *out, hipStream_t st) {
-    const unsigned g = 1u << (3 * L);
+    const unsigned g = ((1u << (3 * L)) + 1) / 2;  // two leaves per block
     using V = typename V4T<T>::type;
     switch (P) {
 #define CASE(PP) \
