@@ -411,18 +411,30 @@ __global__ __launch_bounds__(512) void k_down(int lp, const Tin *__restrict__ in
 // kernel splits it into bf16 parts in registers).
 template <typename Tin, typename Tout>
 __global__ void k_pack(int P, int l, const Tin *__restrict__ in, Tout *__restrict__ out) {
-    const int S = coef_stride(P), P2 = P * P;
-    const int64_t n = 1 << l, g = n + 6;
-    const int64_t total = g * g * g * S;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    const int c = (int)(e % S);
-    const int64_t b = e / S;
-    const int64_t x = b % g - 3, y = (b / g) % g - 3, z = b / (g * g) - 3;
-    Tout v = Tout(0);
-    if (c < P2 && x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n)
-        v = (Tout)in[(x + n * (y + n * z)) * S + c];
-    out[e] = v;
+    // block (bx, y, z): four consecutive elements per thread of padded row
+    // (y, z); a row is g boxes x S coefficients, contiguous in both arrays
+    const int S = coef_stride(P), P2 = P * P, S4 = S / 4;
+    const int n = 1 << l, g = n + 6;
+    const int e4 = blockIdx.x * blockDim.x + threadIdx.x;  // float4 index within the row
+    if (e4 >= g * S4) return;
+    const int y = (int)blockIdx.y - 3, z = (int)blockIdx.z - 3;
+    const int bx = e4 / S4, c = 4 * (e4 - bx * S4), x = bx - 3;
+    const size_t orow = ((size_t)blockIdx.z * g + blockIdx.y) * g;
+    Tout v[4] = {Tout(0), Tout(0), Tout(0), Tout(0)};
+    if (x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n) {
+        const Tin *src = in + ((size_t)x + (size_t)n * ((size_t)y + (size_t)n * z)) * S + c;
+        if (c + 4 <= P2) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = (Tout)src[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c + k < P2) v[k] = (Tout)src[k];
+        }
+    }
+    Tout *dst = out + (orow + bx) * S + c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = v[k];
 }
 
 // ------------------------------------------------------------ gather/combine
@@ -585,8 +597,7 @@ hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, cons
 hipError_t launch_pack(int P, int l, bool in_f64, bool f64_out, const void *in, void *out,
                        hipStream_t st) {
     const int64_t g = ((int64_t)1 << l) + 6;
-    const int64_t total = g * g * g * coef_stride(P);
-    const unsigned gr = nblk(total, 256);
+    const dim3 gr(nblk(g * (coef_stride(P) / 4), 256), (unsigned)g, (unsigned)g);
     if (f64_out)
         k_pack<double, double><<<gr, 256, 0, st>>>(P, l, (const double *)in, (double *)out);
     else if (in_f64)

@@ -27,7 +27,10 @@
 // the FP64 instruction lane l, item i holds row l/16 + 4i of column l%16
 // (both layouts measured on gfx950).
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <queue>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -634,7 +637,7 @@ static int64_t level_tiles(int l) {
 // unsplit; the others share one split factor s, chosen by simulating the
 // in-order dispatch of blocks onto ncu one-block-per-CU slots (a whole tile
 // takes time 1, a part 1/s plus a small fixed overhead).
-static M2LPlan make_plan(int P, int L, bool allow_split, int ncu) {
+static M2LPlan compute_plan(int P, int L, bool allow_split, int ncu) {
     M2LPlan pl{};
     pl.nlev = L - 1;
     const int S = coef_stride(P);
@@ -690,6 +693,18 @@ static M2LPlan make_plan(int P, int L, bool allow_split, int ncu) {
     pl.unit0[pl.nlev] = nu;
     pl.fix0[pl.nlev] = nf;
     return pl;
+}
+
+// The plan depends only on (p, L, split allowed, CU count); the dispatch
+// simulation costs tens of microseconds of host time, so plans are memoised.
+static M2LPlan make_plan(int P, int L, bool allow_split, int ncu) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, bool, int>, M2LPlan> memo;
+    const auto key = std::make_tuple(P, L, allow_split, ncu);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = memo.find(key);
+    if (it == memo.end()) it = memo.emplace(key, compute_plan(P, L, allow_split, ncu)).first;
+    return it->second;
 }
 
 size_t m2l_partial_bytes(int P, int L, bool f64, int ncu) {

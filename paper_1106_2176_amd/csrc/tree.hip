@@ -127,12 +127,14 @@ __global__ void k_place(int64_t n, const uint32_t *__restrict__ key10, int shift
     tmp[start[key10[i] >> shift] + rank[i]] = (uint32_t)i;
 }
 
-// One 256-thread block per leaf: orders the leaf's particles by input index
-// (making the counting sort stable and the whole build deterministic), writes
-// perm and the particles' coordinates relative to the leaf centre in units of
-// the leaf width, u = s 2^L - (i + 1/2) in [-1/2, 1/2], computed in FP64 and
-// stored as FP64 (plain form) or rounded to 32-bit fixed point (mixed form).
-constexpr int kFixupCache = 4096;
+// One wave per leaf (four leaves per 256-thread block): orders the leaf's
+// particles by input index (making the counting sort stable and the whole
+// build deterministic), writes perm and the particles' coordinates relative
+// to the leaf centre in units of the leaf width, u = s 2^L - (i + 1/2) in
+// [-1/2, 1/2], computed in FP64 and stored as FP64 (plain form) or rounded to
+// 32-bit fixed point (mixed form).  A leaf of more than kFixupCache particles
+// (possible only at the deepest level) ranks from global memory.
+constexpr int kFixupCache = 512;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict__ start,
@@ -140,18 +142,23 @@ __global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict
                                                const T *__restrict__ pos, double lo0, double lo1,
                                                double lo2, double size, uint32_t *__restrict__ perm,
                                                int4 *__restrict__ xyz32, double4 *__restrict__ xyz64) {
-    __shared__ uint32_t idx[kFixupCache];
-    const uint32_t leaf = blockIdx.x;
+    __shared__ uint32_t idxs[4][kFixupCache];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t leaf = 4 * blockIdx.x + wave;
+    if (leaf >= (1u << (3 * L))) return;  // no block barrier below
+    uint32_t *const idx = idxs[wave];
     const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
     if (cnt == 0) return;
     const bool cached = cnt <= (uint32_t)kFixupCache;
     if (cached)
-        for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) idx[j] = tmp[s0 + j];
-    __syncthreads();
+        for (uint32_t j = lane; j < cnt; j += 64) idx[j] = tmp[s0 + j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double scale = (double)(1u << L);
     const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
                  bz = (double)compact3(leaf >> 2) + 0.5;
-    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+    for (uint32_t j = lane; j < cnt; j += 64) {
         const uint32_t me = cached ? idx[j] : tmp[s0 + j];
         uint32_t rank = 0;
         if (cached) {
@@ -274,10 +281,10 @@ hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32
     const int64_t nb = (int64_t)1 << (3 * level);
     k_place<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), rank, start, tmp);
     if (dtype == FMM_F64)
-        k_fixup<double><<<(unsigned)nb, 256, 0, st>>>(level, start, tmp, (const double *)pos, lo[0],
+        k_fixup<double><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, start, tmp, (const double *)pos, lo[0],
                                                        lo[1], lo[2], size, perm, xyz32, xyz64);
     else
-        k_fixup<float><<<(unsigned)nb, 256, 0, st>>>(level, start, tmp, (const float *)pos, lo[0],
+        k_fixup<float><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, start, tmp, (const float *)pos, lo[0],
                                                       lo[1], lo[2], size, perm, xyz32, xyz64);
     return hipGetLastError();
 }
