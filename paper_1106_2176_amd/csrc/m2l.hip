@@ -48,8 +48,10 @@ __device__ inline int64_t unpack_delta(int e, int64_t G) {
 
 // ------------------------------------------------------------ work plan
 // A tile is 128 targets of one class at one level (128 consecutive parents
-// in Morton order) and all p^2 output rows; a block of four waves owns one
-// tile, each wave 32 targets (two 16-column MFMA blocks).  Every level runs
+// in Morton order) and all p^2 output rows; a block owns one tile: eight
+// waves of 16 targets each (two waves per SIMD, so that one wave's MFMAs run
+// while the other waits on a load), or, where that operator ring does not
+// fit in LDS, four waves of 32 targets (two 16-column MFMA blocks).  Every level runs
 // in the same launch.  A tile's K range (the 189 offsets) may be cut into
 // `nsplit` parts, each a block of its own, so that the small levels fill the
 // chip after the largest level's tiles: the parts write FP64 partial sums
@@ -193,31 +195,32 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
-template <int NSPLIT, int P>
+template <int NSPLIT, int P, int NW>
 struct MixCfg {
     static constexpr int P2 = P * P, S = coef_stride(P), PPO = S / 8;
     static constexpr int RT = m2l_rows(P) / 16, R = RT * 16;
-    static constexpr int NB = 2;                     // 16-column blocks per wave
+    static constexpr int NB = 8 / NW;                // 16-column blocks per wave (128 columns per tile)
     static constexpr int NCHK = NSPLIT * RT;         // 1 KB operator chunks per K-step
-    static constexpr int CPW = (NCHK + 3) / 4;       // chunks loaded per wave
-    static constexpr int STAGE = 4 * CPW;            // chunk slots per ring stage
+    static constexpr int CPW = (NCHK + NW - 1) / NW; // chunks loaded per wave
+    static constexpr int STAGE = NW * CPW;           // chunk slots per ring stage
     // operator ring stages in LDS (4; deeper rings, 6 or 8 where LDS holds
     // them, measured no faster and spill registers at p = 10); multipole ring
-    // stages in registers: 4.  The step loop is unrolled over both rings
-    // (UNROLL = lcm) with an FP64 merge every MERGE <= 8 steps.
+    // stages in registers: 4 (8 measured no faster with eight waves).  The
+    // step loop is unrolled over both rings (UNROLL = lcm) with an FP64 merge
+    // every MERGE <= 8 steps.
     static constexpr int NA = 4;
     static constexpr int D = 4;
     static constexpr int UNROLL = NA == 6 ? 12 : 8;
     static constexpr int MERGE = NA == 6 ? 6 : 8;
     static constexpr int NBL = NB * 2;               // multipole loads per K-step
-    // loads this wave issues after its operator chunks of step kc + 1 (issued
-    // in step kc + 1 - NA), counted at the top of step kc: the multipole loads
-    // of that step and everything of the NA - 2 steps between
+    // loads this wave issues after the operator chunks it waits for at the
+    // top of step kc (those of step kc + 1 with four waves, of step kc with
+    // eight, issued NA - 1 steps earlier either way): the multipole loads of
+    // that step and everything of the NA - 2 steps between
     static constexpr int VMW = NBL + (NA - 2) * (CPW + NBL);
     static constexpr int NPC = kOffsetsPerClass * PPO;  // K pieces of a class
     static constexpr int NCH = ((NPC + 3) / 4 + UNROLL - 1) / UNROLL * UNROLL;  // K-steps, padded
     static_assert(VMW < 64, "vmcnt range");
-    static_assert(NA * STAGE <= 150, "LDS");
 };
 
 // Operators: pre-split bf16 parts [part][317][R/16][S/8][16][8] (operator
@@ -230,11 +233,12 @@ struct MixCfg {
 // offsets, and one contiguous kilobyte of LDS for the wave's fragment read.
 // All loads are unconditional: pieces past the end read the zero operator
 // and the zero box.
-template <int NSPLIT, int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_m2l_bf16(
+template <int NSPLIT, int P, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void k_m2l_bf16(
     M2LPlan pl, const uint16_t *__restrict__ A, size_t astride, const int2 *__restrict__ cls,
     double *__restrict__ partial) {
-    using C = MixCfg<NSPLIT, P>;
+    using C = MixCfg<NSPLIT, P, NW>;
+    static_assert(C::NA * C::STAGE <= 150, "LDS");
     constexpr int P2 = C::P2, S = C::S, PPO = C::PPO, RT = C::RT, R = C::R, NB = C::NB;
     constexpr int NCHK = C::NCHK, CPW = C::CPW, STAGE = C::STAGE, NA = C::NA, D = C::D;
     constexpr int NPC = C::NPC, NCH = C::NCH, UNROLL = C::UNROLL, MERGE = C::MERGE;
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // K range of this part, in whole unrolled groups of steps
     const int kbeg = (int)((int64_t)u.part * (NCH / UNROLL) / nsplit) * UNROLL;
     const int kend = (int)((int64_t)(u.part + 1) * (NCH / UNROLL) / nsplit) * UNROLL;
-    for (int i = tid; i <= kOffsetsPerClass; i += 256) {
+    for (int i = tid; i <= kOffsetsPerClass; i += 64 * NW) {
         if (i == kOffsetsPerClass) {
             sA[i] = kNumOffsets * R * S;
             sB[i] = 0;
@@ -314,7 +318,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         piece(kc, aoff, boff, inb);
 #pragma unroll
         for (int i = 0; i < CPW; ++i) {
-            const int ch = 4 * i + wave;  // wave-uniform
+            const int ch = NW * i + wave;  // wave-uniform
             const int c0 = ch < NCHK ? ch : 0;
             const int sp = c0 / RT, r = c0 - sp * RT;
             dma16(A + sp * astride + aoff + 16 * r * S, stage + ch * 64);
@@ -362,7 +366,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     };
     float4 bv[D][NB][2];
     bf16x8 af[RT][NSPLIT], bf[NB][NSPLIT];
-    static_for<0, NA>([&](auto ic) __attribute__((always_inline)) {
+    // NW = 8 reads each step's A fragments from its own stage during the step
+    // (one split part at a time, to fit two waves per SIMD), so its ring is
+    // one step shorter: step kc copies step kc + NA - 1 into the stage of
+    // step kc - 1, which every wave has finished reading by step kc's barrier
+    constexpr int PRE = NW == 8 ? NA - 1 : NA;
+    static_for<0, PRE>([&](auto ic) __attribute__((always_inline)) {
         issue_a(kbeg + decltype(ic)::value, stage(ic));
     });
 #pragma unroll
@@ -372,9 +381,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // and waits for every load in flight at each pass through the header.
     wait_vm<0>();
     lds_barrier();
-    read_a(stage(std::integral_constant<int, 0>{}), af);
+    if constexpr (NW != 8) read_a(stage(std::integral_constant<int, 0>{}), af);
 #pragma unroll
     for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[0][b][0], bv[0][b][1], bf[b]);
+
+    // A fragments of split part sp of a stage
+    auto read_part = [&](const uint4 *st, int sp, bf16x8 (&ap)[RT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) ap[r] = __builtin_bit_cast(bf16x8, st[(sp * RT + r) * 64 + lane]);
+    };
+    auto step8 = [&](int kc, auto dc) __attribute__((always_inline)) {
+        constexpr int i = decltype(dc)::value;
+        constexpr int d = i % D, dn = (i + 1) % D;
+        const uint4 *const cur = stage(std::integral_constant<int, i>{});
+        uint4 *const prev = stage(std::integral_constant<int, i + NA - 1>{});
+        wait_vm<C::VMW>();  // this wave's operator chunks of step kc are in LDS
+        lds_barrier();      // ... and everyone's; the stage of step kc - 1 is free
+        issue_a(kc + NA - 1, prev);
+        bf16x8 ap[2][RT], bn[NB][NSPLIT];
+        read_part(cur, NSPLIT - 1, ap[0]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[dn][b][0], bv[dn][b][1], bn[b]);
+        // A parts from the smallest; within a part, the small B parts first
+        static_for<0, NSPLIT>([&](auto jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value, a = NSPLIT - 1 - j;
+            if constexpr (j + 1 < NSPLIT) read_part(cur, a - 1, ap[(j + 1) & 1]);
+#pragma unroll
+            for (int t = NSPLIT - 1 - a; t >= 0; --t)
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[j & 1][r], bf[b][t], acc[r][b], 0, 0, 0);
+        });
+        issue_b(kc + D, bv[d]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int sp = 0; sp < NSPLIT; ++sp) bf[b][sp] = bn[b][sp];
+    };
 
     auto step = [&](int kc, auto dc) __attribute__((always_inline)) {
         constexpr int i = decltype(dc)::value;
@@ -422,7 +467,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int kc = kbeg; kc < kend; kc += UNROLL) {
         static_for<0, UNROLL>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            step(kc + i, ic);
+            if constexpr (NW == 8)
+                step8(kc + i, ic);
+            else
+                step(kc + i, ic);
             if constexpr ((i + 1) % MERGE == 0) merge();  // every MERGE * 32 <= 256 K terms
         });
     }
@@ -716,6 +764,18 @@ size_t m2l_partial_bytes(int P, int L, bool f64, int ncu) {
     return (size_t)np * kTile * P * P * sizeof(double);
 }
 
+// Eight waves (two per SIMD) wherever their operator ring fits in LDS; four
+// (one per SIMD) otherwise, i.e. for the 3-part split at p = 13.
+template <int NSPLIT, int P>
+static void launch_bf16(unsigned nb, const M2LPlan &pl, const uint16_t *A, size_t astride,
+                        const int2 *cls, double *partial, hipStream_t st) {
+    constexpr bool fits8 = MixCfg<NSPLIT, P, 8>::NA * MixCfg<NSPLIT, P, 8>::STAGE <= 150;
+    if constexpr (fits8)
+        k_m2l_bf16<NSPLIT, P, 8><<<nb, 512, 0, st>>>(pl, A, astride, cls, partial);
+    else
+        k_m2l_bf16<NSPLIT, P, 4><<<nb, 256, 0, st>>>(pl, A, astride, cls, partial);
+}
+
 hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
                       const int *out_f64, const void *A, size_t astride, const int2 *cls,
                       double *partial, size_t partial_bytes, int ncu, hipStream_t st) {
@@ -745,9 +805,9 @@ hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *
     }
     if (nsplit == 3 && P > kMixedSplit3PMax) return hipErrorInvalidValue;
 #define CASE3(PP) \
-    case PP: k_m2l_bf16<3, PP><<<nb, 256, 0, st>>>(pl, (const uint16_t *)A, astride, cls, partial); break;
+    case PP: launch_bf16<3, PP>(nb, pl, (const uint16_t *)A, astride, cls, partial, st); break;
 #define CASE2(PP) \
-    case PP: k_m2l_bf16<2, PP><<<nb, 256, 0, st>>>(pl, (const uint16_t *)A, astride, cls, partial); break;
+    case PP: launch_bf16<2, PP>(nb, pl, (const uint16_t *)A, astride, cls, partial, st); break;
     if (nsplit == 3) {
         switch (P) {
             CASE3(1) CASE3(2) CASE3(3) CASE3(4) CASE3(5) CASE3(6) CASE3(7) CASE3(8)
