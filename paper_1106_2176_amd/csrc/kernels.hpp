@@ -51,8 +51,9 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
 
 // m2l.hip: every level 2..L in one launch; B[l], Lc[l] indexed by level.
 // Mixed form: A = bf16 operator parts spaced astride elements apart (layout
-// [part][317][R/16][S/8][16][8]), B[l] = FP32 padded multipole grid,
-// `partial` >= m2l_partial_bytes() of FP64 scratch.
+// [part][317][R/16][S/8][16][8]), B[l] = FP32 padded multipole grid.  Both
+// forms cut the small levels into K parts: `partial` >= m2l_partial_bytes()
+// of FP64 scratch.
 size_t m2l_partial_bytes(int P, int L, bool f64, int ncu);
 constexpr int kMixedSplit3PMax = 13;  // LDS holds the 3-part operator ring up to p = 13
 hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,

@@ -544,10 +544,12 @@ __global__ __launch_bounds__(256) void k_m2l_fixup(int P, M2LPlan pl, const doub
 
 // ------------------------------------------------------------ plain form
 // K-chunks of 16 (four MFMA K-steps); lane group q takes K index
-// 16 kc + 4 j + q in step j.  Tiles as above, never split.
+// 16 kc + 4 j + q in step j.  Tiles and K parts as above (a part writes its
+// FP64 partial sums for the fix-up kernel).
 template <int RT>
 __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double *__restrict__ A,
-                                                 const int2 *__restrict__ cls) {
+                                                 const int2 *__restrict__ cls,
+                                                 double *__restrict__ partial) {
     constexpr int NB = 2, R = RT * 16, KC = 16, ROWP = KC + 1;
     constexpr int NEL = R * KC;
     constexpr int EPT = (NEL + 255) / 256;
@@ -580,6 +582,9 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double
     __syncthreads();
     const int NK = kOffsetsPerClass * P2;
     const int NCH = (NK + KC - 1) / KC;
+    const int nsplit = pick(pl.nsplit, u.li);
+    const int kbeg = (int)((int64_t)u.part * NCH / nsplit);
+    const int kend = (int)((int64_t)(u.part + 1) * NCH / nsplit);
 
     double areg[EPT];
     auto load_a = [&](int kc) {
@@ -630,13 +635,13 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[r][b] = f64x4{0, 0, 0, 0};
 
-    load_a(0);
+    load_a(kbeg);
     store_a(0);
-    load_b(0, bcur);
+    load_b(kbeg, bcur);
     __syncthreads();
     int cur = 0;
-    for (int kc = 0; kc < NCH; ++kc) {
-        const bool more = kc + 1 < NCH;
+    for (int kc = kbeg; kc < kend; ++kc) {
+        const bool more = kc + 1 < kend;
         if (more) {
             load_a(kc + 1);
             load_b(kc + 1, bnext);
@@ -660,18 +665,32 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double
                 for (int b = 0; b < NB; ++b) bcur[j][b] = bnext[j][b];
         }
     }
-    double *Lout = (double *)pick(pl.L, u.li);
+    // FP64 MFMA result layout: lane l, item i holds row l/16 + 4 i
+    if (nsplit == 1) {
+        double *Lout = (double *)pick(pl.L, u.li);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        if (!cvalid[b]) continue;
+        for (int b = 0; b < NB; ++b) {
+            if (!cvalid[b]) continue;
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+            for (int r = 0; r < RT; ++r)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                // FP64 MFMA result layout: lane l, item i holds row l/16 + 4 i
-                const int row = 16 * r + q + 4 * i;
-                if (row < P2) Lout[trow[b] * S + row] = acc[r][b][i];
-            }
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + q + 4 * i;
+                    if (row < P2) Lout[trow[b] * S + row] = acc[r][b][i];
+                }
+        }
+    } else {
+        const int64_t slot = pick(pl.part0, u.li) + (int64_t)u.part * pick(pl.ntile, u.li) + u.tile;
+        double *dst = partial + slot * kTile * P2;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + q + 4 * i;
+                    if (row < P2) dst[(wave * NB * 16 + b * 16 + col) * P2 + row] = acc[r][b][i];
+                }
     }
 }
 
@@ -756,7 +775,8 @@ static M2LPlan make_plan(int P, int L, bool allow_split, int ncu) {
 }
 
 size_t m2l_partial_bytes(int P, int L, bool f64, int ncu) {
-    if (L < 2 || f64) return 0;
+    (void)f64;  // both forms split the small levels and keep FP64 partial sums
+    if (L < 2) return 0;
     const M2LPlan pl = make_plan(P, L, true, ncu);
     int64_t np = 0;
     for (int i = 0; i < pl.nlev; ++i)
@@ -776,11 +796,20 @@ static void launch_bf16(unsigned nb, const M2LPlan &pl, const uint16_t *A, size_
         k_m2l_bf16<NSPLIT, P, 4><<<nb, 256, 0, st>>>(pl, A, astride, cls, partial);
 }
 
+// sum the K parts of the split tiles (after either form's kernel)
+static hipError_t fixup(int P, const M2LPlan &pl, unsigned nfix, const double *partial, hipStream_t st) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nfix == 0) return e;
+    const int64_t total = (int64_t)nfix * kTile * P * P;
+    k_m2l_fixup<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(P, pl, partial, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
                       const int *out_f64, const void *A, size_t astride, const int2 *cls,
                       double *partial, size_t partial_bytes, int ncu, hipStream_t st) {
     if (L < 2) return hipSuccess;
-    M2LPlan pl = make_plan(P, L, !f64, ncu);
+    M2LPlan pl = make_plan(P, L, true, ncu);
     for (int i = 0; i < pl.nlev; ++i) {
         const int l = pl.level[i];
         pl.B[i] = B[l];
@@ -789,19 +818,19 @@ hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *
     }
     const unsigned nb = (unsigned)pl.unit0[pl.nlev];
     const unsigned nfix = (unsigned)pl.fix0[pl.nlev];
-    if (!f64 && nfix > 0 && (!partial || partial_bytes < m2l_partial_bytes(P, L, f64, ncu)))
+    if (nfix > 0 && (!partial || partial_bytes < m2l_partial_bytes(P, L, f64, ncu)))
         return hipErrorInvalidValue;
     const int RT = m2l_rows(P) / 16;
     if (f64) {
         switch (RT) {
 #define CASE(RR) \
-    case RR: k_m2l_f64<RR><<<nb, 256, 0, st>>>(P, pl, (const double *)A, cls); break;
+    case RR: k_m2l_f64<RR><<<nb, 256, 0, st>>>(P, pl, (const double *)A, cls, partial); break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
             CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
             default: return hipErrorInvalidValue;
         }
-        return hipGetLastError();
+        return fixup(P, pl, nfix, partial, st);
     }
     if (nsplit == 3 && P > kMixedSplit3PMax) return hipErrorInvalidValue;
 #define CASE3(PP) \
@@ -823,11 +852,7 @@ hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *
     }
 #undef CASE3
 #undef CASE2
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nfix == 0) return e;
-    const int64_t total = (int64_t)nfix * kTile * P * P;
-    k_m2l_fixup<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(P, pl, partial, total);
-    return hipGetLastError();
+    return fixup(P, pl, nfix, partial, st);
 }
 
 }  // namespace fmm
