@@ -543,28 +543,36 @@ __global__ __launch_bounds__(256) void k_m2l_fixup(int P, M2LPlan pl, const doub
 }
 
 // ------------------------------------------------------------ plain form
-// K-chunks of 16 (four MFMA K-steps); lane group q takes K index
-// 16 kc + 4 j + q in step j.  Tiles and K parts as above (a part writes its
-// FP64 partial sums for the fix-up kernel).
-template <int RT>
-__global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double *__restrict__ A,
-                                                 const int2 *__restrict__ cls,
-                                                 double *__restrict__ partial) {
-    constexpr int NB = 2, R = RT * 16, KC = 16, ROWP = KC + 1;
-    constexpr int NEL = R * KC;
-    constexpr int EPT = (NEL + 255) / 256;
-    __shared__ double As[2][R][ROWP];
+// FP64 operators [317][R][S] and the FP64 padded multipole grid.  K runs over
+// the 189 offsets x S coefficients (entries past p^2 are zero in both), in
+// chunks of 8 that never straddle an offset, so a chunk's operator and
+// source shift are uniform over the block.  A chunk: R x 8 operator values
+// staged in LDS (each thread loads EPT of them one chunk ahead, two register
+// sets), then per wave RT x NB x 2 MFMAs (v_mfma_f64_16x16x4_f64, lane group
+// q takes K index 4 j + q of the chunk).  Registers fit two blocks per CU up
+// to p = 11 (one beyond).
+template <int P, int WPE = (P <= 11 ? 2 : 1)>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void k_m2l_f64(
+    M2LPlan pl, const double *__restrict__ A, const int2 *__restrict__ cls,
+    double *__restrict__ partial) {
+    constexpr int P2 = P * P, S = coef_stride(P), RT = m2l_rows(P) / 16, R = RT * 16;
+    constexpr int NB = 2, KC = 8, ROWP = KC + 1, CPO = S / KC;  // chunks per offset
+    constexpr int NEL = R * KC, EPT = (NEL + 255) / 256;
+    constexpr int NCH = kOffsetsPerClass * CPO;
+    __shared__ double As[2][R * ROWP];
     __shared__ int sA[kOffsetsPerClass], sB[kOffsetsPerClass];
 
     const M2LUnit u = m2l_unit(pl);
     const int l = u.l, k = u.k;
     const double *__restrict__ B = (const double *)pick(pl.B, u.li);
-    const int S = coef_stride(P), P2 = P * P;
     const int n = 1 << l, h = n >> 1;
     const int64_t G = n + 6;
     const int64_t npar = (int64_t)h * h * h;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, col = lane & 15;
+    const int nsplit = pick(pl.nsplit, u.li);
+    const int kbeg = (int)((int64_t)u.part * NCH / nsplit);
+    const int kend = (int)((int64_t)(u.part + 1) * NCH / nsplit);
 
     for (int i = tid; i < kOffsetsPerClass; i += 256) {
         const int2 e = cls[k * kOffsetsPerClass + i];
@@ -580,91 +588,81 @@ __global__ __launch_bounds__(256) void k_m2l_f64(int P, M2LPlan pl, const double
         target_of(cvalid[b] ? pid : 0, k, n, G, S, tpad[b], trow[b]);
     }
     __syncthreads();
-    const int NK = kOffsetsPerClass * P2;
-    const int NCH = (NK + KC - 1) / KC;
-    const int nsplit = pick(pl.nsplit, u.li);
-    const int kbeg = (int)((int64_t)u.part * NCH / nsplit);
-    const int kend = (int)((int64_t)(u.part + 1) * NCH / nsplit);
 
-    double areg[EPT];
-    auto load_a = [&](int kc) {
+    // this thread's elements of an A chunk: (row, kk) = (e / KC, e % KC)
+    auto load_a = [&](int kc, double (&dst)[EPT]) __attribute__((always_inline)) {
+        const int slot = kc / CPO, c0 = KC * (kc - slot * CPO);
+        const double *a = A + sA[slot] + c0;
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + 256 * i;
-            double v = 0.0;
-            if (e < NEL) {
-                const int row = e / KC, kk = e - row * KC;
-                const int g = KC * kc + kk;
-                if (g < NK) {
-                    const int slot = g / P2, c = g - slot * P2;
-                    v = A[sA[slot] + row * S + c];
-                }
-            }
-            areg[i] = v;
+            dst[i] = (NEL % 256 == 0 || e < NEL) ? a[(e / KC) * S + e % KC] : 0.0;
         }
     };
-    auto store_a = [&](int buf) {
+    auto store_a = [&](int buf, const double (&src)[EPT]) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + 256 * i;
-            if (e < NEL) {
-                const int row = e / KC, kk = e - row * KC;
-                As[buf][row][kk] = areg[i];
-            }
+            if (NEL % 256 == 0 || e < NEL) As[buf][(e / KC) * ROWP + e % KC] = src[i];
         }
     };
-    double bcur[4][NB], bnext[4][NB];
-    auto load_b = [&](int kc, double (&dst)[4][NB]) {
+    auto load_b = [&](int kc, double (&dst)[2][NB]) __attribute__((always_inline)) {
+        const int slot = kc / CPO, c0 = KC * (kc - slot * CPO);
+        const int64_t off = sB[slot] + c0 + q;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int g = KC * kc + 4 * j + q;
-            if (g < NK) {
-                const int slot = g / P2, c = g - slot * P2;
-                const int64_t off = sB[slot] + c;
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) dst[j][b] = B[tpad[b] + off];
-            } else {
-#pragma unroll
-                for (int b = 0; b < NB; ++b) dst[j][b] = 0.0;
-            }
-        }
+            for (int b = 0; b < NB; ++b) dst[j][b] = B[tpad[b] + off + 4 * j];
     };
+
     f64x4 acc[RT][NB];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[r][b] = f64x4{0, 0, 0, 0};
 
-    load_a(kbeg);
-    store_a(0);
-    load_b(kbeg, bcur);
+    // step t = kc - kbeg: chunk kc is in LDS buffer t & 1, chunk kc + 1 in
+    // register set t & 1 and chunk kc + 2 in the other (the last chunk is
+    // loaded again past the end of the range)
+    double ar[2][EPT], br[2][2][NB], bc[2][NB];
+    load_a(kbeg, ar[0]);
+    store_a(0, ar[0]);
+    load_b(kbeg, bc);
+    load_a(min(kbeg + 1, kend - 1), ar[0]);
+    load_b(min(kbeg + 1, kend - 1), br[0]);
+    load_a(min(kbeg + 2, kend - 1), ar[1]);
+    load_b(min(kbeg + 2, kend - 1), br[1]);
     __syncthreads();
-    int cur = 0;
-    for (int kc = kbeg; kc < kend; ++kc) {
-        const bool more = kc + 1 < kend;
-        if (more) {
-            load_a(kc + 1);
-            load_b(kc + 1, bnext);
-        }
+    auto chunk = [&](int kc, auto pc) __attribute__((always_inline)) {
+        constexpr int ph = decltype(pc)::value;  // (kc - kbeg) & 1
+        const double *as = As[ph];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
-                const double av = As[cur][16 * r + col][4 * j + q];
+                const double av = as[(16 * r + col) * ROWP + 4 * j + q];
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
-                    acc[r][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bcur[j][b], acc[r][b], 0, 0, 0);
+                    acc[r][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bc[j][b], acc[r][b], 0, 0, 0);
             }
-        if (more) store_a(cur ^ 1);
+        store_a(ph ^ 1, ar[ph]);  // chunk kc + 1 into the other buffer, read by
+                                  // every wave up to the last barrier
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) bc[j][b] = br[ph][j][b];
+        load_a(min(kc + 3, kend - 1), ar[ph]);
+        load_b(min(kc + 3, kend - 1), br[ph]);
         __syncthreads();
-        cur ^= 1;
-        if (more) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) bcur[j][b] = bnext[j][b];
-        }
+    };
+    // a pair of chunks per pass keeps the parity a compile-time constant
+    int kc = kbeg;
+    for (; kc + 1 < kend; kc += 2) {
+        chunk(kc, std::integral_constant<int, 0>{});
+        chunk(kc + 1, std::integral_constant<int, 1>{});
     }
+    if (kc < kend) chunk(kc, std::integral_constant<int, 0>{});
+
     // FP64 MFMA result layout: lane l, item i holds row l/16 + 4 i
     if (nsplit == 1) {
         double *Lout = (double *)pick(pl.L, u.li);
@@ -820,11 +818,10 @@ hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *
     const unsigned nfix = (unsigned)pl.fix0[pl.nlev];
     if (nfix > 0 && (!partial || partial_bytes < m2l_partial_bytes(P, L, f64, ncu)))
         return hipErrorInvalidValue;
-    const int RT = m2l_rows(P) / 16;
     if (f64) {
-        switch (RT) {
-#define CASE(RR) \
-    case RR: k_m2l_f64<RR><<<nb, 256, 0, st>>>(P, pl, (const double *)A, cls, partial); break;
+        switch (P) {
+#define CASE(PP) \
+    case PP: k_m2l_f64<PP><<<nb, 256, 0, st>>>(pl, (const double *)A, cls, partial); break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
             CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
