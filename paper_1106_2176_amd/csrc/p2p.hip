@@ -100,17 +100,39 @@ __device__ __forceinline__ double4 shifted(double4 v, int dx, int dy, int dz) {
     return v;
 }
 
+// Synchronisation of one wave's LDS traffic: a wave's LDS operations run in
+// order, so a compiler fence suffices (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // src: sorted particles (u_x, u_y, u_z, q) in leaf units; start: Morton leaf
 // ranges; out: (phi, E) per sorted particle in leaf units (phi * w, E * w^2).
-template <typename T>
-__global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
-                                            const typename V4<T>::type *__restrict__ src,
-                                            const uint32_t *__restrict__ start,
-                                            double4 *__restrict__ out) {
+// NP = 1: one wave per target leaf.  NP = 3 (few leaves, too few waves to
+// hide the serial walk over 27 neighbours): a block of three waves per
+// target leaf, wave w taking the neighbour plane dz = w - 1; wave 0 adds the
+// three planes' sums in plane order.
+template <typename T, int NP>
+__global__ __launch_bounds__(64 * NP) void k_p2p(int L, uint32_t per_xcd,
+                                                 const typename V4<T>::type *__restrict__ src,
+                                                 const uint32_t *__restrict__ start,
+                                                 double4 *__restrict__ out) {
     using V = typename V4<T>::type;
-    __shared__ V tile[64];
-    __shared__ double4 red[2][64];
-    const int lane = threadIdx.x;
+    __shared__ V tiles[NP][64];
+    __shared__ double4 reds[NP][2][64];
+    __shared__ double4 planes[NP > 1 ? (NP - 1) * 128 : 1];  // [plane - 1][a/b][target]
+    const int lane = NP == 1 ? (int)threadIdx.x : (int)threadIdx.x & 63;
+    const int wave = NP == 1 ? 0 : (int)threadIdx.x >> 6;
+    V *const tile = tiles[wave];
+    double4 (*const red)[64] = reds[wave];
+    auto sync = [&]() __attribute__((always_inline)) {
+        if constexpr (NP == 1)
+            __syncthreads();
+        else
+            wave_sync();
+    };
     // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
     // run of Morton leaves so its L2 holds the shared neighbour sources
     const uint32_t leaf = (blockIdx.x & 7u) * per_xcd + (blockIdx.x >> 3);
@@ -132,6 +154,7 @@ __global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
         const V tb = src[t0 + tc + (hasb ? r + G : min(r, ntc - 1))];
         double a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
         for (int dz = -1; dz <= 1; ++dz) {
+            if (NP > 1 && dz != wave - 1) continue;
             if (iz + dz < 0 || iz + dz >= side) continue;
             for (int dy = -1; dy <= 1; ++dy) {
                 if (iy + dy < 0 || iy + dy >= side) continue;
@@ -142,9 +165,9 @@ __global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
                     const bool self = (dx | dy | dz) == 0;
                     for (uint32_t sc = 0; sc < ns; sc += 64) {
                         const int nsc = (int)min(64u, ns - sc);
-                        __syncthreads();
+                        sync();
                         if (lane < nsc) tile[lane] = shifted(src[s0 + sc + lane], dx, dy, dz);
-                        __syncthreads();
+                        sync();
                         T pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
                         if (act) {
                             if (self) {
@@ -174,29 +197,60 @@ __global__ __launch_bounds__(64) void k_p2p(int L, uint32_t per_xcd,
             }
         }
         // sum the K source-split groups (fixed order: group 0, 1, ..., K-1)
-        __syncthreads();
+        sync();
         red[0][lane] = make_double4(a0, a1, a2, a3);
         red[1][lane] = make_double4(b0, b1, b2, b3);
-        __syncthreads();
-        if (grp == 0) {
-            double4 sa = red[0][r], sb = red[1][r];
-            if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
-                const double s1 = kFixScale, s3 = kFixScale * kFixScale;
+        sync();
+        if constexpr (NP == 1) {
+            if (grp == 0) {
+                double4 sa = red[0][r], sb = red[1][r];
                 for (int g = 1; g < K; ++g) {
                     const double4 xa = red[0][g * G + r], xb = red[1][g * G + r];
                     sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
                     sb.x += xb.x; sb.y += xb.y; sb.z += xb.z; sb.w += xb.w;
                 }
-                sa = make_double4(sa.x * s1, sa.y * s3, sa.z * s3, sa.w * s3);
-                sb = make_double4(sb.x * s1, sb.y * s3, sb.z * s3, sb.w * s3);
+                if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
+                    const double s1 = kFixScale, s3 = kFixScale * kFixScale;
+                    sa = make_double4(sa.x * s1, sa.y * s3, sa.z * s3, sa.w * s3);
+                    sb = make_double4(sb.x * s1, sb.y * s3, sb.z * s3, sb.w * s3);
+                }
                 out[t0 + tc + r] = sa;
                 if (hasb) out[t0 + tc + r + G] = sb;
-                continue;
             }
+            continue;
+        }
+        double4 sa = make_double4(0, 0, 0, 0), sb = sa;
+        if (grp == 0) {
+            sa = red[0][r];
+            sb = red[1][r];
             for (int g = 1; g < K; ++g) {
                 const double4 xa = red[0][g * G + r], xb = red[1][g * G + r];
                 sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
                 sb.x += xb.x; sb.y += xb.y; sb.z += xb.z; sb.w += xb.w;
+            }
+        }
+        {
+            // every wave reaches both barriers (the chunk loop is the same
+            // in all waves of the block)
+            __syncthreads();
+            if (wave > 0 && grp == 0) {
+                planes[(wave - 1) * 128 + r] = sa;
+                planes[(wave - 1) * 128 + 64 + r] = sb;
+            }
+            __syncthreads();
+            if (wave != 0) continue;
+            if (grp == 0)
+                for (int w = 0; w < NP - 1; ++w) {
+                    const double4 xa = planes[w * 128 + r], xb = planes[w * 128 + 64 + r];
+                    sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
+                    sb.x += xb.x; sb.y += xb.y; sb.z += xb.z; sb.w += xb.w;
+                }
+        }
+        if (grp == 0) {
+            if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
+                const double s1 = kFixScale, s3 = kFixScale * kFixScale;
+                sa = make_double4(sa.x * s1, sa.y * s3, sa.z * s3, sa.w * s3);
+                sb = make_double4(sb.x * s1, sb.y * s3, sb.z * s3, sb.w * s3);
             }
             out[t0 + tc + r] = sa;
             if (hasb) out[t0 + tc + r + G] = sb;
@@ -209,10 +263,18 @@ hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, d
     const uint32_t nleaf = 1u << (3 * L);
     const uint32_t per = (nleaf + 7) / 8;
     const unsigned grid = per * 8;
-    if (f64)
-        k_p2p<double><<<grid, 64, 0, st>>>(L, per, (const double4 *)src, start, out);
-    else
-        k_p2p<float><<<grid, 64, 0, st>>>(L, per, (const int4 *)src, start, out);
+    // below 4 waves per SIMD with one wave per leaf, split the neighbours
+    if (nleaf <= 4096) {
+        if (f64)
+            k_p2p<double, 3><<<grid, 192, 0, st>>>(L, per, (const double4 *)src, start, out);
+        else
+            k_p2p<float, 3><<<grid, 192, 0, st>>>(L, per, (const int4 *)src, start, out);
+    } else {
+        if (f64)
+            k_p2p<double, 1><<<grid, 64, 0, st>>>(L, per, (const double4 *)src, start, out);
+        else
+            k_p2p<float, 1><<<grid, 64, 0, st>>>(L, per, (const int4 *)src, start, out);
+    }
     return hipGetLastError();
 }
 
