@@ -623,22 +623,22 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
         return ensure(t, t->scan, sizeof(uint32_t) * scan_scratch_words((int64_t)nb), st);
     };
     unsigned int *dc = (unsigned int *)t->counters.p;
+    // leaf starts (scan of the counts) and the fullest leaf, then the copy
+    // of the two build counters that the host reads
     auto read_counters = [&](int l) -> hipError_t {
-        hipError_t r = launch_max(l, (const uint32_t *)t->cnt.p, dc + 1, st);
+        hipError_t r = launch_scan_max((int64_t)1 << (3 * l), (const uint32_t *)t->cnt.p,
+                                       (uint32_t *)t->start.p, (uint32_t *)t->scan.p, dc + 1, st);
         if (r == hipSuccess)
             r = hipMemcpyAsync(t->host_counters, dc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st);
         if (r == hipSuccess) r = hipEventRecord(t->ev_counters, st);
         return r;
     };
+    // placement and the in-leaf ordering (after read_counters at level l)
     auto sort_at = [&](int l) -> hipError_t {
-        hipError_t r = launch_scan((int64_t)1 << (3 * l), (const uint32_t *)t->cnt.p,
-                                   (uint32_t *)t->start.p, (uint32_t *)t->scan.p, st);
-        if (r == hipSuccess)
-            r = launch_sort(n, l, (const uint32_t *)t->key10.p, (const uint32_t *)t->rank.p,
-                            (const uint32_t *)t->start.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
-                            cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (int4 *)t->xyz32.p,
-                            f64 ? (double4 *)t->xyz64.p : nullptr, st);
-        return r;
+        return launch_sort(n, l, (const uint32_t *)t->key10.p, (const uint32_t *)t->rank.p,
+                           (const uint32_t *)t->start.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
+                           cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (int4 *)t->xyz32.p,
+                           f64 ? (double4 *)t->xyz64.p : nullptr, st);
     };
     if ((s = level_buffers(lev)) != FMM_OK) return bail(s);
     hipError_t e = launch_keys(n, dtype, pos, cfg->box_lo, cfg->box_size, lev, (uint32_t *)t->key10.p,

@@ -16,10 +16,13 @@ hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cn
                        unsigned int *counters, hipStream_t st);
 // zero `words` 32-bit words with a kernel (not a memset node when captured)
 hipError_t launch_zero(uint32_t *p, int64_t words, hipStream_t st);
-hipError_t launch_max(int level, const uint32_t *cnt, unsigned int *mx, hipStream_t st);
 int64_t scan_scratch_words(int64_t nb);
 hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
                        hipStream_t st);
+// exclusive scan (out[0..nb], total at out[nb]) and the maximum count into
+// *mx (one kernel up to 32768 counts; *mx must be zero before a larger scan)
+hipError_t launch_scan_max(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
+                           unsigned int *mx, hipStream_t st);
 hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *rank,
                        const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,

@@ -109,6 +109,52 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t nb, const uint32_t
     if (threadIdx.x == 1023 && sums) sums[blockIdx.x] = excl;
 }
 
+// Exclusive scan and maximum of up to kScan1 counts in one block: thread t
+// takes counts 32 t .. 32 t + 31; out[nb] receives the total, *mx the maximum.
+constexpr int64_t kScan1 = 32768;
+
+__global__ __launch_bounds__(1024) void k_scan_max1(int64_t nb, const uint32_t *__restrict__ in,
+                                                    uint32_t *__restrict__ out,
+                                                    unsigned int *__restrict__ mx) {
+    __shared__ uint32_t ws[16], wm[16];
+    const int64_t base = 32 * (int64_t)threadIdx.x;
+    uint32_t v[32], t = 0, m = 0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        v[k] = (base + k < nb) ? in[base + k] : 0u;
+        t += v[k];
+        m = max(m, v[k]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = t;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+        m = max(m, (uint32_t)__shfl_xor(m, d, 64));
+    }
+    if (lane == 63) ws[wave] = x;
+    if (lane == 0) wm[wave] = m;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        uint32_t s = ws[threadIdx.x], mm = wm[threadIdx.x];
+        for (int d = 1; d < 16; d <<= 1) {
+            const uint32_t y = __shfl_up(s, d, 16);
+            if ((int)threadIdx.x >= d) s += y;
+            mm = max(mm, (uint32_t)__shfl_xor(mm, d, 16));
+        }
+        ws[threadIdx.x] = s;
+        if (threadIdx.x == 0) *mx = mm;
+    }
+    __syncthreads();
+    uint32_t excl = x - t + (wave > 0 ? ws[wave - 1] : 0u);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        if (base + k < nb) out[base + k] = excl;
+        excl += v[k];
+    }
+    if (threadIdx.x == 1023) out[nb] = excl;
+}
+
 // adds the scanned block sums; also writes the total (sums[nblocks]) to out[nb]
 __global__ void k_scan_add(int64_t nb, int64_t nblocks, uint32_t *__restrict__ out,
                            const uint32_t *__restrict__ sums) {
@@ -242,13 +288,6 @@ hipError_t launch_hist(int64_t n, const uint32_t *key10, int level, uint32_t *cn
     return hipGetLastError();
 }
 
-hipError_t launch_max(int level, const uint32_t *cnt, unsigned int *mx, hipStream_t st) {
-    const int64_t nb = (int64_t)1 << (3 * level);
-    const unsigned g = (unsigned)std::min<int64_t>(1024, (nb + 255) / 256);
-    k_max<<<g, 256, 0, st>>>(nb, cnt, mx);
-    return hipGetLastError();
-}
-
 // scratch must hold scan_scratch_words(nb) words: per recursion level the
 // block sums and their scan (with total), then the next level's scratch
 int64_t scan_scratch_words(int64_t nb) {
@@ -272,6 +311,20 @@ hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *
     if (e != hipSuccess) return e;
     k_scan_add<<<nblk(nb, 256), 256, 0, st>>>(nb, nblocks, out, sums_scan);
     return hipGetLastError();
+}
+
+hipError_t launch_scan_max(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
+                           unsigned int *mx, hipStream_t st) {
+    if (nb <= kScan1) {
+        k_scan_max1<<<1, 1024, 0, st>>>(nb, in, out, mx);
+        return hipGetLastError();
+    }
+    // larger trees: the maximum (into *mx, zeroed by the key or histogram
+    // pass) and the multi-block scan
+    k_max<<<(unsigned)std::min<int64_t>(1024, (nb + 255) / 256), 256, 0, st>>>(nb, in, mx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_scan(nb, in, out, scratch, st);
 }
 
 hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *rank,
