@@ -109,23 +109,36 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int64_t nb, const uint32_t
     if (threadIdx.x == 1023 && sums) sums[blockIdx.x] = excl;
 }
 
-// Exclusive scan and maximum of up to kScan1 counts in one block: thread t
-// takes counts 32 t .. 32 t + 31; out[nb] receives the total, *mx the maximum.
+// Exclusive scan and maximum of up to kScan1 counts in one block, staged in
+// LDS: coalesced load, thread t scans counts 32 t .. 32 t + 31 (LDS word
+// i + i / 32, so the 32-word stride hits distinct banks), coalesced store;
+// out[nb] receives the total, *mx the maximum.
 constexpr int64_t kScan1 = 32768;
+
+__device__ __forceinline__ int scan1_slot(int i) { return i + (i >> 5); }
 
 __global__ __launch_bounds__(1024) void k_scan_max1(int64_t nb, const uint32_t *__restrict__ in,
                                                     uint32_t *__restrict__ out,
                                                     unsigned int *__restrict__ mx) {
+    __shared__ uint32_t buf[kScan1 + kScan1 / 32];
     __shared__ uint32_t ws[16], wm[16];
-    const int64_t base = 32 * (int64_t)threadIdx.x;
+    const int n = (int)nb, tid = threadIdx.x;
     uint32_t v[32], t = 0, m = 0;
 #pragma unroll
+    for (int k = 0; k < 32; ++k) {  // all 32 loads in flight at once
+        const int i = tid + 1024 * k;
+        v[k] = i < n ? in[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) buf[scan1_slot(tid + 1024 * k)] = v[k];
+    __syncthreads();
+#pragma unroll
     for (int k = 0; k < 32; ++k) {
-        v[k] = (base + k < nb) ? in[base + k] : 0u;
+        v[k] = buf[scan1_slot(32 * tid + k)];
         t += v[k];
         m = max(m, v[k]);
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     uint32_t x = t;
     for (int d = 1; d < 64; d <<= 1) {
         const uint32_t y = __shfl_up(x, d, 64);
@@ -135,24 +148,26 @@ __global__ __launch_bounds__(1024) void k_scan_max1(int64_t nb, const uint32_t *
     if (lane == 63) ws[wave] = x;
     if (lane == 0) wm[wave] = m;
     __syncthreads();
-    if (threadIdx.x < 16) {
-        uint32_t s = ws[threadIdx.x], mm = wm[threadIdx.x];
+    if (tid < 16) {
+        uint32_t s = ws[tid], mm = wm[tid];
         for (int d = 1; d < 16; d <<= 1) {
             const uint32_t y = __shfl_up(s, d, 16);
-            if ((int)threadIdx.x >= d) s += y;
+            if (tid >= d) s += y;
             mm = max(mm, (uint32_t)__shfl_xor(mm, d, 16));
         }
-        ws[threadIdx.x] = s;
-        if (threadIdx.x == 0) *mx = mm;
+        ws[tid] = s;
+        if (tid == 0) *mx = mm;
     }
     __syncthreads();
     uint32_t excl = x - t + (wave > 0 ? ws[wave - 1] : 0u);
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
-        if (base + k < nb) out[base + k] = excl;
+        buf[scan1_slot(32 * tid + k)] = excl;
         excl += v[k];
     }
-    if (threadIdx.x == 1023) out[nb] = excl;
+    if (tid == 1023) out[n] = excl;
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) out[i] = buf[scan1_slot(i)];
 }
 
 // adds the scanned block sums; also writes the total (sums[nblocks]) to out[nb]
