@@ -65,10 +65,15 @@ template <> struct V4T<double> { using type = double4; };
 // 64-lane block, 32 lanes each: rounds of RS particles per leaf write q rho
 // into LDS [coef][particle]; then the 64 lanes sum the rows of both leaves'
 // coefficients (fixed order, deterministic).
+// Rows per round: 32 while the two leaves' LDS buffers stay within 16 KB,
+// else 16 (up to 40 KB), else 8.  At p = 10 that is 16 in both forms: the
+// 32-row FP32 buffer (26 KB) held a CU to six blocks, and the kernel is
+// bound by the latency of the harmonic recurrence (16 rows: 62 -> 51 us at
+// N = 1e6).
 template <int P, typename T>
 constexpr int p2m_rows() {
     constexpr int P2 = P * P;
-    return 2 * P2 * 33 * (int)sizeof(T) <= 40960 ? 32 : 2 * P2 * 17 * (int)sizeof(T) <= 40960 ? 16 : 8;
+    return 2 * P2 * 33 * (int)sizeof(T) <= 16384 ? 32 : 2 * P2 * 17 * (int)sizeof(T) <= 40960 ? 16 : 8;
 }
 
 template <int P, typename T>
