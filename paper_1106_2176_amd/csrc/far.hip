@@ -308,7 +308,9 @@ template <int P, int NT, typename TB, typename BLoad>
 __device__ __forceinline__ void transfer_gemm(f64x4_t (&acc)[NT], const double *__restrict__ ap,
                                               int q, BLoad bload) {
     constexpr int P2 = P * P, NKS = (P2 + 3) / 4;
-    constexpr int D = NT <= 8 ? 3 : 2;
+    // one row tile (coarse levels, a few hundred parents): the wave's work is
+    // a latency chain, so up to 16 steps of loads are kept in flight
+    constexpr int D = NT == 1 ? (NKS < 16 ? NKS : 16) : NT <= 8 ? 3 : 2;
     double av[D][NT];
     TB bv[D];
 #pragma unroll
