@@ -3,7 +3,8 @@
 //
 // One 64-lane wavefront per target leaf.  The 27 (or fewer, at the domain
 // boundary) near leaves are streamed through LDS in tiles of 64 sources,
-// already shifted into the target leaf's frame: coordinates are stored in
+// consecutive neighbour leaves packed into one tile, already shifted into
+// the target leaf's frame: coordinates are stored in
 // leaf units relative to the leaf centre, so a source in the neighbour at
 // offset d is at u_j + d and every difference is formed from numbers of
 // magnitude <= 3/2 (no cancellation against absolute positions).
@@ -153,6 +154,41 @@ __global__ __launch_bounds__(64 * NP) void k_p2p(int L, uint32_t per_xcd,
         const V ta = src[t0 + tc + min(r, ntc - 1)];
         const V tb = src[t0 + tc + (hasb ? r + G : min(r, ntc - 1))];
         double a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+        // pairs with the tile's first nsc sources, FP32 partial sums merged
+        // into FP64; every compute ends with a sync, so the tile is free for
+        // the next write
+        auto compute = [&](int nsc, auto selfc) __attribute__((always_inline)) {
+            constexpr bool SELF = decltype(selfc)::value;
+            T pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
+            if (act) {
+                for (int j = grp; j < nsc; j += K) {
+                    const V sj = tile[j];
+                    pair<SELF>(ta, sj, pa0, pa1, pa2, pa3);
+                    pair<SELF>(tb, sj, pb0, pb1, pb2, pb3);
+                }
+            }
+            a0 += (double)pa0;
+            a1 += (double)pa1;
+            a2 += (double)pa2;
+            a3 += (double)pa3;
+            b0 += (double)pb0;
+            b1 += (double)pb1;
+            b2 += (double)pb2;
+            b3 += (double)pb3;
+            sync();
+        };
+        // other leaves are packed back to back into the tile (each source
+        // already shifted into the target's frame) and computed when the
+        // next one would not fit; the target's own leaf, whose pairs need
+        // the r^2 == 0 mask, takes tiles of its own
+        int pend = 0;
+        auto flush = [&]() __attribute__((always_inline)) {
+            if (pend > 0) {
+                sync();
+                compute(pend, std::false_type{});
+                pend = 0;
+            }
+        };
         for (int dz = -1; dz <= 1; ++dz) {
             if (NP > 1 && dz != wave - 1) continue;
             if (iz + dz < 0 || iz + dz >= side) continue;
@@ -162,40 +198,26 @@ __global__ __launch_bounds__(64 * NP) void k_p2p(int L, uint32_t per_xcd,
                     if (ix + dx < 0 || ix + dx >= side) continue;
                     const uint32_t s = morton3(ix + dx, iy + dy, iz + dz);
                     const uint32_t s0 = start[s], ns = start[s + 1] - s0;
-                    const bool self = (dx | dy | dz) == 0;
+                    if ((dx | dy | dz) == 0) {
+                        flush();
+                        for (uint32_t sc = 0; sc < ns; sc += 64) {
+                            const int nsc = (int)min(64u, ns - sc);
+                            if (lane < nsc) tile[lane] = src[s0 + sc + lane];
+                            sync();
+                            compute(nsc, std::true_type{});
+                        }
+                        continue;
+                    }
                     for (uint32_t sc = 0; sc < ns; sc += 64) {
                         const int nsc = (int)min(64u, ns - sc);
-                        sync();
-                        if (lane < nsc) tile[lane] = shifted(src[s0 + sc + lane], dx, dy, dz);
-                        sync();
-                        T pa0 = 0, pa1 = 0, pa2 = 0, pa3 = 0, pb0 = 0, pb1 = 0, pb2 = 0, pb3 = 0;
-                        if (act) {
-                            if (self) {
-                                for (int j = grp; j < nsc; j += K) {
-                                    const V sj = tile[j];
-                                    pair<true>(ta, sj, pa0, pa1, pa2, pa3);
-                                    pair<true>(tb, sj, pb0, pb1, pb2, pb3);
-                                }
-                            } else {
-                                for (int j = grp; j < nsc; j += K) {
-                                    const V sj = tile[j];
-                                    pair<false>(ta, sj, pa0, pa1, pa2, pa3);
-                                    pair<false>(tb, sj, pb0, pb1, pb2, pb3);
-                                }
-                            }
-                        }
-                        a0 += (double)pa0;
-                        a1 += (double)pa1;
-                        a2 += (double)pa2;
-                        a3 += (double)pa3;
-                        b0 += (double)pb0;
-                        b1 += (double)pb1;
-                        b2 += (double)pb2;
-                        b3 += (double)pb3;
+                        if (pend + nsc > 64) flush();
+                        if (lane < nsc) tile[pend + lane] = shifted(src[s0 + sc + lane], dx, dy, dz);
+                        pend += nsc;
                     }
                 }
             }
         }
+        flush();
         // sum the K source-split groups (fixed order: group 0, 1, ..., K-1)
         sync();
         red[0][lane] = make_double4(a0, a1, a2, a3);
