@@ -92,6 +92,9 @@ typedef struct {
     void *alloc_ctx;
     int32_t profile;           /* nonzero: record HIP events around each stage of
                                   fmm_evaluate (read with fmm_stage_times) */
+    uint32_t profile_stages;   /* with profile: bit i selects stage i (numbering
+                                  of fmm_stage_times); events are recorded only
+                                  at the boundaries of selected stages.  0: all */
     int32_t overlap_near;      /* nonzero: run the near field (P2P) concurrently
                                   with the far field on a stream of the library's
                                   own, forked from and joined back into the
@@ -108,7 +111,7 @@ typedef struct {
                                   launch the graph on their stream.  Same kernels,
                                   same results.  Exclusive with `profile`
                                   (FMM_EINVAL). */
-    int32_t reserved[5];       /* zero */
+    int32_t reserved[4];       /* zero */
 } fmm_config;
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
@@ -210,8 +213,9 @@ fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
  * Stages, in order:
  *   0 gather   1 P2M   2 M2M   3 pack (M2L operand)   4 M2L   5 L2L
  *   6 L2P      7 P2P   8 combine
- * `ms` receives min(n_stages, 9) values.  FMM_EINVAL if profiling is off or
- * no call was recorded. */
+ * `ms` receives min(n_stages, 9) values; stages outside cfg.profile_stages
+ * (when it is nonzero) receive NaN.  FMM_EINVAL if profiling is off or no
+ * call was recorded. */
 fmm_status fmm_stage_times(const fmm_tree *tree, double *ms, int32_t n_stages);
 
 /* Forget the recorded stage timings of `tree` (the next fmm_stage_times

@@ -43,9 +43,10 @@ class Config(ctypes.Structure):
         ("free", FREE_FN),
         ("alloc_ctx", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
+        ("profile_stages", ctypes.c_uint32),
         ("overlap_near", ctypes.c_int32),
         ("graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -117,7 +118,9 @@ def _check(rc):
 
 def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
-                graph=False):
+                graph=False, profile_stages=None):
+    """profile_stages: None (all) or an iterable of stage names (STAGES) whose
+    boundaries get profiling events."""
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)
@@ -132,6 +135,8 @@ def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3
     c.profile = 1 if profile else 0
     c.overlap_near = 1 if overlap_near else 0
     c.graph = 1 if graph else 0
+    c.profile_stages = 0 if profile_stages is None else \
+        sum(1 << STAGES.index(s) for s in profile_stages)
     return c
 
 
@@ -185,10 +190,10 @@ class Tree:
 
     def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                  box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
-                 graph=False):
+                 graph=False, profile_stages=None):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,
-                               profile, overlap_near, graph)
+                               profile, overlap_near, graph, profile_stages)
         self.rebuild(pos)
 
     def rebuild(self, pos):

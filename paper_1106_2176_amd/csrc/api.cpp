@@ -313,13 +313,25 @@ fmm_status validate_cfg(const fmm_config *c) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->box_lo[a])) return fail(FMM_EINVAL, "box_lo must be finite");
     if (c->graph && c->profile) return fail(FMM_EINVAL, "graph and profile are exclusive");
+    if (c->profile_stages >> kStages) return fail(FMM_EINVAL, "profile_stages has bits past stage 8");
     if ((c->alloc == nullptr) != (c->free == nullptr))
         return fail(FMM_EINVAL, "alloc and free callbacks must be given together");
     return FMM_OK;
 }
 
+bool stage_on(const fmm_tree *t, int i) {
+    return t->cfg.profile_stages == 0 || ((t->cfg.profile_stages >> i) & 1u);
+}
+
+// Event at stage boundary b (start of stage b, end of stage b - 1), or at the
+// start / end (kStages + 1 / + 2) of a P2P on the side stream; only where a
+// selected stage begins or ends.
 fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
     if (!t->cfg.profile || t->capturing) return FMM_OK;
+    const bool want = stage > kStages ? stage_on(t, 7)
+                                      : (stage < kStages && stage_on(t, stage)) ||
+                                            (stage > 0 && stage_on(t, stage - 1));
+    if (!want) return FMM_OK;
     if (!t->ev_ready) {
         for (int j = 0; j < kTimeRing; ++j)
             for (int i = 0; i < kEvents; ++i) HIPCHK(hipEventCreate(&t->ev[j][i]));
@@ -749,19 +761,20 @@ fmm_status fmm_stage_times(const fmm_tree *t, double *ms, int32_t n_stages) {
     for (int i = 0; i < ns; ++i) ms[i] = 0.0;
     for (int64_t c = t->ncalls - nset; c < t->ncalls; ++c) {
         const int j = (int)(c % kTimeRing);
-        HIPCHK(hipEventSynchronize(t->ev[j][kStages]));
         for (int i = 0; i < ns; ++i) {
+            if (!stage_on(t, i)) continue;
             float f = 0.f;
             if (i == 7 && t->p2p_side[j]) {  // P2P ran on the side stream
                 HIPCHK(hipEventSynchronize(t->ev[j][kStages + 2]));
                 HIPCHK(hipEventElapsedTime(&f, t->ev[j][kStages + 1], t->ev[j][kStages + 2]));
             } else {
+                HIPCHK(hipEventSynchronize(t->ev[j][i + 1]));
                 HIPCHK(hipEventElapsedTime(&f, t->ev[j][i], t->ev[j][i + 1]));
             }
             ms[i] += f;
         }
     }
-    for (int i = 0; i < ns; ++i) ms[i] /= (double)nset;
+    for (int i = 0; i < ns; ++i) ms[i] = stage_on(t, i) ? ms[i] / (double)nset : std::nan("");
     return FMM_OK;
 }
 

@@ -59,6 +59,14 @@ def test_build_rejects_bad_config(field, value):
     assert fmm.lib().fmm_last_error_message()
 
 
+def test_profile_stages_past_the_last_stage_rejected():
+    cfg = fmm.make_config(profile=True)
+    cfg.profile_stages = 1 << 9
+    rc, h = _build(cfg)
+    assert rc == fmm.FMM_EINVAL and not h.value
+    assert fmm.make_config(profile=True, profile_stages=["M2L", "P2P"]).profile_stages == (1 << 4) | (1 << 7)
+
+
 def test_graph_and_profile_are_exclusive():
     cfg = fmm.make_config(graph=True, profile=True)
     rc, h = _build(cfg)

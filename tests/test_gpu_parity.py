@@ -306,3 +306,17 @@ def test_bf16_three_way_split_is_more_accurate():
     b, Eb, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=3)
     assert rel_l2(b, ref) <= rel_l2(a, ref)
     assert rel_l2(a, ref) < 1e-6
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_profiled_stage_subset(overlap):
+    """profile_stages: events only around the selected stages; their times
+    are positive, the others are NaN."""
+    pos, q = inputs.particles(60_000, 44)
+    with fmm.Tree(dev(pos), p=6, leaf_max=32, precision="mixed", profile=True,
+                  profile_stages=("M2L", "P2P"), overlap_near=overlap) as t:
+        for _ in range(3):
+            t.evaluate(dev(q))
+        st = t.stage_times()
+    assert st["M2L"] > 0 and st["P2P"] > 0
+    assert all(np.isnan(v) for k, v in st.items() if k not in ("M2L", "P2P"))
