@@ -411,9 +411,19 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
                                    t->M[l].p, adjoint ? o->aup32 : o->up32,
                                    adjoint ? o->aup64 : o->up64, st));
         CHK(rec(t, 3, st));
-        for (int l = 2; l <= L; ++l) {
-            const size_t g = ((size_t)1 << l) + 6;
-            HIPCHK(launch_pack(P, l, level_f64(t, l), f64, t->M[l].p, t->pack[l].p, st));
+        {
+            PackPlan pk{};
+            pk.nlev = L - 1;
+            for (int l = 2; l <= L; ++l) {
+                const int i = l - 2;
+                const int64_t g = ((int64_t)1 << l) + 6;
+                pk.level[i] = l;
+                pk.in_f64[i] = level_f64(t, l);
+                pk.in[i] = t->M[l].p;
+                pk.out[i] = t->pack[l].p;
+                pk.row0[i + 1] = pk.row0[i] + g * g;
+            }
+            HIPCHK(launch_pack(P, f64, pk, st));
         }
         CHK(rec(t, 4, st));
         // M2L at every level >= 2 in one launch (the levels are independent)

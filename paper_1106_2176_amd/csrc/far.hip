@@ -413,35 +413,67 @@ __global__ __launch_bounds__(512) void k_down(int lp, const Tin *__restrict__ in
 }
 
 // -------------------------------------------------------------- M2L operand
-// Pack level-l multipoles into a zero-padded grid with a 3-box halo
-// [(n+6)^3][S]: FP64 for the plain form, FP32 for the mixed form (the M2L
-// kernel splits it into bf16 parts in registers).
+// Pack the multipoles of levels 2..L into zero-padded grids with a 3-box
+// halo [(n+6)^3][S]: FP64 for the plain form, FP32 for the mixed form (the
+// M2L kernel splits it into bf16 parts in registers).  One launch for all
+// levels: block b packs padded row b (a row is g boxes x S coefficients,
+// contiguous in both arrays) of the level whose rows it falls in, four
+// consecutive elements per thread.
 template <typename Tin, typename Tout>
-__global__ void k_pack(int P, int l, const Tin *__restrict__ in, Tout *__restrict__ out) {
-    // block (bx, y, z): four consecutive elements per thread of padded row
-    // (y, z); a row is g boxes x S coefficients, contiguous in both arrays
-    const int S = coef_stride(P), P2 = P * P, S4 = S / 4;
-    const int n = 1 << l, g = n + 6;
-    const int e4 = blockIdx.x * blockDim.x + threadIdx.x;  // float4 index within the row
-    if (e4 >= g * S4) return;
-    const int y = (int)blockIdx.y - 3, z = (int)blockIdx.z - 3;
-    const int bx = e4 / S4, c = 4 * (e4 - bx * S4), x = bx - 3;
-    const size_t orow = ((size_t)blockIdx.z * g + blockIdx.y) * g;
-    Tout v[4] = {Tout(0), Tout(0), Tout(0), Tout(0)};
-    if (x >= 0 && y >= 0 && z >= 0 && x < n && y < n && z < n) {
-        const Tin *src = in + ((size_t)x + (size_t)n * ((size_t)y + (size_t)n * z)) * S + c;
-        if (c + 4 <= P2) {
+__device__ __forceinline__ void pack_row(int P, int n, int y, int z, const Tin *__restrict__ in,
+                                         Tout *__restrict__ orow) {
+    const int S = coef_stride(P), P2 = P * P, S4 = S / 4, g = n + 6;
+    const bool yz = y >= 0 && z >= 0 && y < n && z < n;
+    for (int e4 = threadIdx.x; e4 < g * S4; e4 += blockDim.x) {
+        const int bx = e4 / S4, c = 4 * (e4 - bx * S4), x = bx - 3;
+        Tout v[4] = {Tout(0), Tout(0), Tout(0), Tout(0)};
+        if (yz && x >= 0 && x < n) {
+            const Tin *src = in + ((size_t)x + (size_t)n * ((size_t)y + (size_t)n * z)) * S + c;
+            if (c + 4 <= P2) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = (Tout)src[k];
-        } else {
+                for (int k = 0; k < 4; ++k) v[k] = (Tout)src[k];
+            } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (c + k < P2) v[k] = (Tout)src[k];
+                for (int k = 0; k < 4; ++k)
+                    if (c + k < P2) v[k] = (Tout)src[k];
+            }
         }
-    }
-    Tout *dst = out + (orow + bx) * S + c;
+        Tout *dst = orow + (size_t)bx * S + c;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) dst[k] = v[k];
+        for (int k = 0; k < 4; ++k) dst[k] = v[k];
+    }
+}
+
+template <typename Tout>
+__global__ __launch_bounds__(256) void k_pack(int P, PackPlan pl) {
+    const int64_t b = blockIdx.x;
+    int li = 0;
+#pragma unroll
+    for (int j = 1; j < kMaxPackLev; ++j)
+        if (j < pl.nlev && b >= pl.row0[j]) li = j;
+    // uniform selection from the per-level arrays (no dynamic indexing of
+    // the argument struct)
+    int l = pl.level[0], in_f64 = pl.in_f64[0];
+    int64_t r0 = pl.row0[0];
+    const void *in = pl.in[0];
+    void *out = pl.out[0];
+#pragma unroll
+    for (int j = 1; j < kMaxPackLev; ++j)
+        if (j == li) {
+            l = pl.level[j];
+            in_f64 = pl.in_f64[j];
+            r0 = pl.row0[j];
+            in = pl.in[j];
+            out = pl.out[j];
+        }
+    const int n = 1 << l, g = n + 6;
+    const int row = (int)(b - r0);  // z g + y of the padded grid (< 2^31)
+    const int y = row % g - 3, z = row / g - 3;
+    Tout *orow = (Tout *)out + (size_t)row * g * coef_stride(P);
+    if (in_f64)
+        pack_row(P, n, y, z, (const double *)in, orow);
+    else
+        pack_row(P, n, y, z, (const float *)in, orow);
 }
 
 // ------------------------------------------------------------ gather/combine
@@ -601,16 +633,13 @@ hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, cons
 }
 
 // f64_out: FP64 grid (plain form); otherwise FP32 (mixed form)
-hipError_t launch_pack(int P, int l, bool in_f64, bool f64_out, const void *in, void *out,
-                       hipStream_t st) {
-    const int64_t g = ((int64_t)1 << l) + 6;
-    const dim3 gr(nblk(g * (coef_stride(P) / 4), 256), (unsigned)g, (unsigned)g);
+hipError_t launch_pack(int P, bool f64_out, const PackPlan &pl, hipStream_t st) {
+    if (pl.nlev < 1 || pl.nlev > kMaxPackLev) return hipErrorInvalidValue;
+    const unsigned rows = (unsigned)pl.row0[pl.nlev];
     if (f64_out)
-        k_pack<double, double><<<gr, 256, 0, st>>>(P, l, (const double *)in, (double *)out);
-    else if (in_f64)
-        k_pack<double, float><<<gr, 256, 0, st>>>(P, l, (const double *)in, (float *)out);
+        k_pack<double><<<rows, 256, 0, st>>>(P, pl);
     else
-        k_pack<float, float><<<gr, 256, 0, st>>>(P, l, (const float *)in, (float *)out);
+        k_pack<float><<<rows, 256, 0, st>>>(P, pl);
     return hipGetLastError();
 }
 

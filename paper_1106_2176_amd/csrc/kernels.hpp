@@ -41,8 +41,20 @@ hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *s
                       const void *Lc, double4 *out, hipStream_t st);
 hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
                            void *out, const void *tab32, const void *tab64, hipStream_t st);
-hipError_t launch_pack(int P, int l, bool in_f64, bool f64_out, const void *in, void *out,
-                       hipStream_t st);
+// M2L operand grids of levels 2..L in one launch; level i of the plan:
+// multipoles in[i] (FP64 when in_f64[i]) -> padded grid out[i] (FP64 when
+// f64_out, else FP32); row0 = first padded row of each level, row0[nlev] =
+// all rows
+constexpr int kMaxPackLev = FMM_MAX_LEVEL;
+struct PackPlan {
+    int nlev;
+    int level[kMaxPackLev];
+    int in_f64[kMaxPackLev];
+    int64_t row0[kMaxPackLev + 1];
+    const void *in[kMaxPackLev];
+    void *out[kMaxPackLev];
+};
+hipError_t launch_pack(int P, bool f64_out, const PackPlan &pl, hipStream_t st);
 hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm, const void *q,
                            void *xyzq, hipStream_t st);
 hipError_t launch_combine(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
