@@ -366,12 +366,16 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     if (L >= 2 && level_f64(t, L) != (int)f64)
         return fail(FMM_EDEVICE, "internal: leaf-level precision differs from the particle precision");
     CHK(rec(t, 0, st));
-    HIPCHK(launch_gather_q(t->n, t->dtype, f64, (const uint32_t *)t->perm.p, charges, src, st));
     CHK(ensure(t, t->nearf, sizeof(double4) * (size_t)t->n, st));
+    const bool side = do_near && do_far && L >= 2 && t->cfg.overlap_near;
+    // The charges go into the sorted records before anything reads them:
+    // by P2M when it runs first (far field, P2P after it), else by a gather.
+    const bool p2m_gathers = do_far && L >= 2 && !side;
+    if (!p2m_gathers)
+        HIPCHK(launch_gather_q(t->n, t->dtype, f64, (const uint32_t *)t->perm.p, charges, src, st));
     // Near field concurrently with the far field: P2P needs only the sorted
     // particles and writes its own buffer, so it is forked onto the library's
     // side stream after the gather and joined back before the combine.
-    const bool side = do_near && do_far && L >= 2 && t->cfg.overlap_near;
     t->p2p_side[t->cur] = side;
     if (side) {
         if (!t->side) {
@@ -403,7 +407,8 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
         if (pbytes) CHK(ensure(t, t->m2lpart, pbytes, st));
         CHK(rec(t, 1, st));
         // P2M at the leaves (for the adjoint: L2P^T, the same sum with w)
-        HIPCHK(launch_p2m(P, L, f64, src, start, t->M[L].p, 1.0, st));
+        HIPCHK(launch_p2m(P, L, f64, src, start, t->M[L].p, 1.0,
+                          p2m_gathers ? (const uint32_t *)t->perm.p : nullptr, charges, t->dtype, st));
         CHK(rec(t, 2, st));
         // upward sweep (adjoint: L2L^T)
         for (int l = L - 1; l >= 2; --l)

@@ -76,10 +76,17 @@ constexpr int p2m_rows() {
     return 2 * P2 * 33 * (int)sizeof(T) <= 16384 ? 32 : 2 * P2 * 17 * (int)sizeof(T) <= 40960 ? 16 : 8;
 }
 
+// With perm given, each particle's charge is first gathered from the
+// caller's array (q, FP64 when q64) through perm and stored into its record
+// (the charge gather folded into P2M, which reads every record anyway).
+__device__ __forceinline__ void set_charge(int4 &r, float q) { r.w = __float_as_int(q); }
+__device__ __forceinline__ void set_charge(double4 &r, double q) { r.w = q; }
+
 template <int P, typename T>
-__global__ __launch_bounds__(64) void k_p2m(int L, const typename V4T<T>::type *__restrict__ src,
+__global__ __launch_bounds__(64) void k_p2m(int L, typename V4T<T>::type *__restrict__ src,
                                             const uint32_t *__restrict__ start, T *__restrict__ M,
-                                            double scale) {
+                                            double scale, const uint32_t *__restrict__ perm,
+                                            const void *__restrict__ qin, int q64) {
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
     constexpr int RS = p2m_rows<P, T>();
@@ -100,7 +107,15 @@ __global__ __launch_bounds__(64) void k_p2m(int L, const typename V4T<T>::type *
         if (r > 0) __syncthreads();
         if (hl < RS && c0 + hl < myc) {
             T x, y, z, q;
-            unpack_rec(src[my0 + c0 + hl], x, y, z, q);
+            const uint32_t d = my0 + c0 + hl;
+            auto rec = src[d];
+            if (perm) {
+                const uint32_t o = perm[d];
+                const T qv = q64 ? (T)((const double *)qin)[o] : (T)((const float *)qin)[o];
+                set_charge(rec, qv);
+                src[d] = rec;
+            }
+            unpack_rec(rec, x, y, z, q);
             rho_strided<P, T>(x, y, z, q, buf[half] + hl, RS + 1);
         }
         __syncthreads();
@@ -541,13 +556,14 @@ __global__ void k_combine_grad(int64_t n, const uint32_t *__restrict__ perm,
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <typename T>
-static hipError_t p2m_dispatch(int P, int L, const void *src, const uint32_t *start, T *M,
-                               double scale, hipStream_t st) {
+static hipError_t p2m_dispatch(int P, int L, void *src, const uint32_t *start, T *M,
+                               double scale, const uint32_t *perm, const void *q, int q64,
+                               hipStream_t st) {
     const unsigned g = ((1u << (3 * L)) + 1) / 2;  // two leaves per block
     using V = typename V4T<T>::type;
     switch (P) {
 #define CASE(PP) \
-    case PP: k_p2m<PP, T><<<g, 64, 0, st>>>(L, (const V *)src, start, M, scale); break;
+    case PP: k_p2m<PP, T><<<g, 64, 0, st>>>(L, (V *)src, start, M, scale, perm, q, q64); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
@@ -556,10 +572,12 @@ static hipError_t p2m_dispatch(int P, int L, const void *src, const uint32_t *st
     return hipGetLastError();
 }
 
-hipError_t launch_p2m(int P, int L, bool f64, const void *src, const uint32_t *start, void *M,
-                      double scale, hipStream_t st) {
-    return f64 ? p2m_dispatch<double>(P, L, src, start, (double *)M, scale, st)
-               : p2m_dispatch<float>(P, L, src, start, (float *)M, scale, st);
+hipError_t launch_p2m(int P, int L, bool f64, void *src, const uint32_t *start, void *M,
+                      double scale, const uint32_t *perm, const void *q, int q_dtype,
+                      hipStream_t st) {
+    const int q64 = q_dtype == FMM_F64;
+    return f64 ? p2m_dispatch<double>(P, L, src, start, (double *)M, scale, perm, q, q64, st)
+               : p2m_dispatch<float>(P, L, src, start, (float *)M, scale, perm, q, q64, st);
 }
 
 template <typename T>

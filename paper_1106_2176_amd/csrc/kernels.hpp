@@ -35,8 +35,11 @@ hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, d
                       hipStream_t st);
 
 // far.hip
-hipError_t launch_p2m(int P, int L, bool f64, const void *src, const uint32_t *start, void *M,
-                      double scale, hipStream_t st);
+// P2M at the leaves; with perm non-NULL it first stores each particle's
+// charge q[perm[i]] (caller dtype q_dtype) into its sorted record i
+hipError_t launch_p2m(int P, int L, bool f64, void *src, const uint32_t *start, void *M,
+                      double scale, const uint32_t *perm, const void *q, int q_dtype,
+                      hipStream_t st);
 hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *start,
                       const void *Lc, double4 *out, hipStream_t st);
 hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
