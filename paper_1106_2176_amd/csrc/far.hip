@@ -11,45 +11,66 @@
 
 namespace fmm {
 
-// Regular harmonics of one point times `seed`, written with a stride (LDS
-// transposition).  The recurrences are linear in the degree-0 term, so
-// starting them from `seed` instead of 1 scales every harmonic by it.
-template <int P, typename T>
-__device__ __forceinline__ void rho_strided(T x, T y, T z, T seed, T *out, int stride) {
-    const T r2 = x * x + y * y + z * z;
-    T dr = seed, di = T(0);
+// Regular harmonics of NPT points, each times its `seed`, summed over the
+// points in order and written with a stride (LDS transposition).  The
+// recurrences are linear in the degree-0 term, so starting them from `seed`
+// instead of 1 scales every harmonic by it.  The NPT recurrences are
+// independent chains, which the latency-bound recurrence needs.
+template <int P, typename T, int NPT>
+__device__ __forceinline__ void rho_strided(const T (&x)[NPT], const T (&y)[NPT], const T (&z)[NPT],
+                                            const T (&seed)[NPT], T *out, int stride) {
+    T r2[NPT], dr[NPT], di[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        r2[j] = x[j] * x[j] + y[j] * y[j] + z[j] * z[j];
+        dr[j] = seed[j];
+        di[j] = T(0);
+    }
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-        if (m > 0) {
-            const T inv = T(-1) / T(2 * m);
-            const T nr = (dr * x + di * y) * inv;
-            const T ni = (di * x - dr * y) * inv;
-            dr = nr;
-            di = ni;
+        T ar[NPT], ai[NPT], br[NPT], bi[NPT];
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            if (m > 0) {
+                const T inv = T(-1) / T(2 * m);
+                const T nr = (dr[j] * x[j] + di[j] * y[j]) * inv;
+                const T ni = (di[j] * x[j] - dr[j] * y[j]) * inv;
+                dr[j] = nr;
+                di[j] = ni;
+            }
+            ar[j] = dr[j];
+            ai[j] = di[j];
+            br[j] = T(0);
+            bi[j] = T(0);
         }
-        T ar = dr, ai = di, br = T(0), bi = T(0);
 #pragma unroll
         for (int n = m; n < P; ++n) {
-            T cr = ar, ci = ai;
-            if (n == m + 1) {
-                cr = z * ar;
-                ci = z * ai;
-            } else if (n > m + 1) {
-                const T inv = T(1) / T((n - m) * (n + m));
-                cr = (T(2 * n - 1) * z * ar - r2 * br) * inv;
-                ci = (T(2 * n - 1) * z * ai - r2 * bi) * inv;
-            }
-            if (n > m) {
-                br = ar;
-                bi = ai;
-                ar = cr;
-                ai = ci;
+            T sr = T(0), si = T(0);
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                T cr = ar[j], ci = ai[j];
+                if (n == m + 1) {
+                    cr = z[j] * ar[j];
+                    ci = z[j] * ai[j];
+                } else if (n > m + 1) {
+                    const T inv = T(1) / T((n - m) * (n + m));
+                    cr = (T(2 * n - 1) * z[j] * ar[j] - r2[j] * br[j]) * inv;
+                    ci = (T(2 * n - 1) * z[j] * ai[j] - r2[j] * bi[j]) * inv;
+                }
+                if (n > m) {
+                    br[j] = ar[j];
+                    bi[j] = ai[j];
+                    ar[j] = cr;
+                    ai[j] = ci;
+                }
+                sr += cr;
+                si += ci;
             }
             if (m == 0) {
-                out[(n * n) * stride] = cr;
+                out[(n * n) * stride] = sr;
             } else {
-                out[(n * n + 2 * m - 1) * stride] = cr;
-                out[(n * n + 2 * m) * stride] = ci;
+                out[(n * n + 2 * m - 1) * stride] = sr;
+                out[(n * n + 2 * m) * stride] = si;
             }
         }
     }
@@ -62,9 +83,10 @@ template <> struct V4T<double> { using type = double4; };
 
 // ---------------------------------------------------------------- P2M
 // mu(leaf) = scale * sum_j q_j rho(u_j).  Two Morton-consecutive leaves per
-// 64-lane block, 32 lanes each: rounds of RS particles per leaf write q rho
-// into LDS [coef][particle]; then the 64 lanes sum the rows of both leaves'
-// coefficients (fixed order, deterministic).
+// 64-lane block, 32 lanes each: rounds of RS rows per leaf, each row the
+// sum of q rho over two particles of one lane (two independent recurrence
+// chains), written into LDS [coef][row]; then the 64 lanes sum the rows of
+// both leaves' coefficients (fixed order, deterministic).
 // Rows per round: 32 while the two leaves' LDS buffers stay within 16 KB,
 // else 16 (up to 40 KB), else 8.  At p = 10 that is 16 in both forms: the
 // 32-row FP32 buffer (26 KB) held a CU to six blocks, and the kernel is
@@ -90,6 +112,7 @@ __global__ __launch_bounds__(64) void k_p2m(int L, typename V4T<T>::type *__rest
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
     constexpr int RS = p2m_rows<P, T>();
+    constexpr int NPT = 2;                  // particles per lane and round (rows hold their sums)
     constexpr int NI = (2 * P2 + 63) / 64;  // (leaf, coefficient) items per lane
     __shared__ T buf[2][P2 * (RS + 1)];
     const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
@@ -98,25 +121,33 @@ __global__ __launch_bounds__(64) void k_p2m(int L, typename V4T<T>::type *__rest
     const uint32_t sa = start[l0], sb = start[min(l0 + 1, nleaf)], se = start[min(l0 + 2, nleaf)];
     const uint32_t ca = sb - sa, cb = se - sb;
     const uint32_t my0 = half ? sb : sa, myc = half ? cb : ca;
-    const uint32_t rounds = (max(ca, cb) + RS - 1) / RS;
+    const uint32_t rounds = (max(ca, cb) + NPT * RS - 1) / (NPT * RS);
     T acc[NI];
 #pragma unroll
     for (int a = 0; a < NI; ++a) acc[a] = T(0);
     for (uint32_t r = 0; r < rounds; ++r) {
-        const uint32_t c0 = r * RS;
+        const uint32_t c0 = r * NPT * RS;
         if (r > 0) __syncthreads();
+        // row hl of the round: particles c0 + hl + j RS (a missing one has
+        // charge 0 and adds nothing)
         if (hl < RS && c0 + hl < myc) {
-            T x, y, z, q;
-            const uint32_t d = my0 + c0 + hl;
-            auto rec = src[d];
-            if (perm) {
-                const uint32_t o = perm[d];
-                const T qv = q64 ? (T)((const double *)qin)[o] : (T)((const float *)qin)[o];
-                set_charge(rec, qv);
-                src[d] = rec;
+            T x[NPT], y[NPT], z[NPT], q[NPT];
+#pragma unroll
+            for (int j = 0; j < NPT; ++j) {
+                x[j] = y[j] = z[j] = q[j] = T(0);
+                if (c0 + hl + j * RS < myc) {
+                    const uint32_t d = my0 + c0 + hl + j * RS;
+                    auto rec = src[d];
+                    if (perm) {
+                        const uint32_t o = perm[d];
+                        const T qv = q64 ? (T)((const double *)qin)[o] : (T)((const float *)qin)[o];
+                        set_charge(rec, qv);
+                        src[d] = rec;
+                    }
+                    unpack_rec(rec, x[j], y[j], z[j], q[j]);
+                }
             }
-            unpack_rec(rec, x, y, z, q);
-            rho_strided<P, T>(x, y, z, q, buf[half] + hl, RS + 1);
+            rho_strided<P, T, NPT>(x, y, z, q, buf[half] + hl, RS + 1);
         }
         __syncthreads();
 #pragma unroll
