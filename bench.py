@@ -10,12 +10,13 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
   fp64         the plain FP64 form measured the same way
   rel_l2       errors vs the FP64 direct sum on 1000 sampled targets
   roofline     dominant kernel of the mixed step; its duration is the mean of
-               HIP events that the library records around the M2L and P2P
-               stages (only those, to keep the instrumentation small) on the
-               stream their kernels run on, during the timed steps
+               HIP events that the library records around the M2L stage
+               (only that one: each event marker idles the GPU for a few
+               microseconds) on the stream its kernels run on, during the
+               timed steps
   stages_ms    all stages, from a separate fully profiled run after the
                timed steps
-  roofline_p2p the same for the P2P kernel
+  roofline_p2p the same for the P2P kernel, its duration from stages_ms
   cpu_baseline the CPU oracle FMM on the host cores
   adjoint      forward + backward throughput of the differentiable form
                (N = 1e6, p = 8, leaf <= 64)
@@ -152,8 +153,8 @@ def main():
             tree.close()
             return sec, st, info
 
-        # the timed steps: events only around the two roofline stages
-        sec, roof_st, info = timed(("M2L", "P2P"), steps, warmup)
+        # the timed steps: events only around the dominant (roofline) stage
+        sec, roof_st, info = timed(("M2L",), steps, warmup)
         res = {"sec": sec, "roof_ms": roof_st, "info": info, "phi": phi.clone(), "E": E.clone()}
         # every stage, outside the timed region
         res["stages_ms"] = timed(None, max(5, steps // 2), 1)[1]
@@ -163,7 +164,7 @@ def main():
     info = mixed["info"]
     n = wl.n
     value = n / mixed["sec"]
-    p2p_ms = mixed["roof_ms"]["P2P"]
+    p2p_ms = mixed["stages_ms"]["P2P"]
     m2l_ms = mixed["roof_ms"]["M2L"]
     pairs = info["p2p_pairs"]
     m2l_pairs = info["m2l_pairs"]
@@ -290,7 +291,7 @@ def main():
     }
     if fp64 is not None:
         line["fp64"] = {"particles_per_s": n / fp64["sec"], "ms_per_step": fp64["sec"] * 1e3,
-                        "p2p_gint_s": pairs / (fp64["roof_ms"]["P2P"] * 1e-3) / 1e9,
+                        "p2p_gint_s": pairs / (fp64["stages_ms"]["P2P"] * 1e-3) / 1e9,
                         "stages_ms": fp64["stages_ms"]}
     print(json.dumps(line), flush=True)
 
