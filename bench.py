@@ -9,14 +9,16 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
   p2p_gint_s   P2P Ginteractions/s (mixed), pairs from the tree / P2P time
   fp64         the plain FP64 form measured the same way
   rel_l2       errors vs the FP64 direct sum on 1000 sampled targets
-  roofline     dominant kernel of the mixed step; its duration is the mean of
-               HIP events that the library records around the M2L stage
-               (only that one: each event marker idles the GPU for a few
-               microseconds) on the stream its kernels run on, during the
+  roofline     dominant kernel of the mixed step (M2L or P2P, whichever
+               stage is longer in stages_ms); its duration is the mean of
+               HIP events that the library records around that stage only
+               (each event marker idles the GPU for a few microseconds) on
+               the stream its kernels run on, during the timed steps
+  stages_ms    all stages, from a separate fully profiled run before the
                timed steps
-  stages_ms    all stages, from a separate fully profiled run after the
-               timed steps
-  roofline_p2p the same for the P2P kernel, its duration from stages_ms
+  roofline_p2p the same for the other kernel (roofline_m2l when P2P
+               dominates), its duration from stages_ms; traffic only on the
+               workload the counter summaries were taken on
   cpu_baseline the CPU oracle FMM on the host cores
   adjoint      forward + backward throughput of the differentiable form
                (N = 1e6, p = 8, leaf <= 64)
@@ -153,19 +155,25 @@ def main():
             tree.close()
             return sec, st, info
 
+        # every stage, outside the timed region; it names the dominant stage
+        stages_ms = timed(None, max(5, steps // 2), max(1, warmup))[1]
+        dom = "M2L" if stages_ms["M2L"] >= stages_ms["P2P"] else "P2P"
         # the timed steps: events only around the dominant (roofline) stage
-        sec, roof_st, info = timed(("M2L",), steps, warmup)
-        res = {"sec": sec, "roof_ms": roof_st, "info": info, "phi": phi.clone(), "E": E.clone()}
-        # every stage, outside the timed region
-        res["stages_ms"] = timed(None, max(5, steps // 2), 1)[1]
-        return res
+        sec, roof_st, info = timed((dom,), steps, warmup)
+        return {"sec": sec, "dom": dom, "dom_ms": roof_st[dom], "stages_ms": stages_ms, "info": info,
+                "phi": phi.clone(), "E": E.clone()}
 
     mixed = run_form("mixed", args.steps, args.warmup)
     info = mixed["info"]
     n = wl.n
     value = n / mixed["sec"]
-    p2p_ms = mixed["stages_ms"]["P2P"]
-    m2l_ms = mixed["roof_ms"]["M2L"]
+    # the dominant stage's time from the events of the timed steps, the
+    # other's from the profiled run
+    dom = mixed["dom"]
+    p2p_ms = mixed["dom_ms"] if dom == "P2P" else mixed["stages_ms"]["P2P"]
+    m2l_ms = mixed["dom_ms"] if dom == "M2L" else mixed["stages_ms"]["M2L"]
+    # the counter summaries were taken on the default workload only
+    on_profiled = args.workload == "C2" and args.splits == 3
     pairs = info["p2p_pairs"]
     m2l_pairs = info["m2l_pairs"]
     p2p_tflops = P2P_FLOP_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
@@ -173,16 +181,16 @@ def main():
     roof_p2p = {"kernel": "k_p2p<float>", "bound": "alu", "achieved": p2p_tflops,
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": p2p_tflops / PEAK_FP32_VECTOR_TFLOPS,
-                "traffic": traffic_from_profile("p2p.hip", "p2p_C2_traffic.txt"),
+                "traffic": traffic_from_profile("p2p.hip", "p2p_C2_traffic.txt") if on_profiled else None,
                 "ms": p2p_ms, "flop_per_launch": P2P_FLOP_PER_PAIR * pairs}
     split_products = {3: 6, 2: 3}.get(args.splits, 6)
     roof_m2l = {"kernel": "k_m2l_bf16<%d,%d>" % (args.splits, wl.p), "bound": "mfma",
                 "achieved": m2l_tflops, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": m2l_tflops / PEAK_BF16_MFMA_TFLOPS,
-                "traffic": traffic_from_profile("m2l.hip", "m2l_bf16_C2_traffic.txt"),
+                "traffic": traffic_from_profile("m2l.hip", "m2l_bf16_C2_traffic.txt") if on_profiled else None,
                 "ms": m2l_ms, "flop_per_launch": 2.0 * wl.p ** 4 * m2l_pairs,
                 "bf16_products_per_term": split_products}
-    roof = roof_m2l if m2l_ms >= p2p_ms else roof_p2p
+    roof = roof_m2l if dom == "M2L" else roof_p2p
 
     # accuracy on sampled targets vs the FP64 direct sum
     t_idx = inputs.targets(n, wl.seed)
@@ -283,7 +291,7 @@ def main():
         "p2p_gint_s": pairs / (p2p_ms * 1e-3) / 1e9,
         "stages_ms": mixed["stages_ms"],
         "roofline": roof,
-        "roofline_p2p": roof_p2p,
+        ("roofline_p2p" if dom == "M2L" else "roofline_m2l"): roof_p2p if dom == "M2L" else roof_m2l,
         "rel_l2": rel,
         "cpu_baseline": cpu,
         "adjoint": adj,
