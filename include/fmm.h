@@ -83,8 +83,9 @@ typedef struct {
     int32_t precision;         /* fmm_precision */
     int32_t bf16_splits;       /* mixed form only: 2 (hi+lo, 3 MFMA products) or
                                   3 (hi+mid+lo, 6 products); 0 selects 3.  The
-                                  mixed form with 3 parts supports p <= 13
-                                  (FMM_EUNSUPPORTED above: use 2 parts or FP64) */
+                                  mixed form supports p <= 13 with 3 parts and
+                                  p <= 10 with 2 parts (FMM_EUNSUPPORTED
+                                  otherwise: use the FP64 form) */
     double box_lo[3];          /* root cube corner */
     double box_size;           /* root cube edge, > 0 */
     fmm_alloc_fn alloc;        /* optional, see above */
@@ -136,21 +137,32 @@ typedef struct {
 /*
  * Build the octree for `n` particles (Sec. 2.1 hierarchical subdivision;
  * Morton keys and the sorted start/offset particle layout of Sec. 5).
- *   pos    device [n][3] row-major, in `dtype`; read during the call only
- *          (everything the tree needs is copied into library memory).
+ *   pos    device [n][3] row-major, in `dtype`.  The build's sort kernels
+ *          read it after the call has returned, in stream order on `stream`:
+ *          keep it valid and unchanged until that stream work has completed.
+ *          The tree keeps its own copy (sorted, leaf-relative), so later
+ *          calls on the tree do not read `pos`.
  *   out    receives the tree.  If *out is a tree previously built by this
- *          library with the same p, precision and dtype, it is rebuilt in
- *          place and its memory reused when large enough; otherwise *out
- *          must be NULL and a new tree is created.
+ *          library, it is rebuilt in place and its memory reused when large
+ *          enough; its p, precision, bf16_splits (mixed form), dtype and
+ *          allocator callbacks (alloc, free, alloc_ctx) must equal the ones it
+ *          was created with, else the call returns FMM_EINVAL before any
+ *          allocation or launch and leaves the tree as it was.  Otherwise *out
+ *          must be NULL and a new tree is created.  The translation tables of
+ *          p (made once per device and p, held until the process ends) are
+ *          ready when the call returns.
  * Steps: Morton key per particle with the leaf-occupancy histogram at the
  * predicted level, level selection (one host wait; a finer level is tried
  * when the predicted one's fullest leaf exceeds leaf_max), exclusive scan of
  * leaf counts, stable counting sort (ties keep input order) and a gather of
  * leaf-relative coordinates.
  * Errors: FMM_EINVAL, FMM_EDOMAIN (detected at the synchronisation; a
- * coordinate equal to lo + size is clamped into the last box), FMM_ENOMEM,
- * FMM_EDEVICE.  On error a newly created tree is destroyed and *out is left
- * NULL; a tree passed in for reuse stays valid for fmm_tree_destroy only.
+ * coordinate equal to lo + size is clamped into the last box), FMM_ENOMEM
+ * (the allocator callback returned NULL, or hipMallocAsync failed),
+ * FMM_EDEVICE.  On error a newly created tree is destroyed and *out is set
+ * to NULL; a tree passed in for reuse stays valid for fmm_tree_destroy only
+ * (except after the FMM_EINVAL of a settings mismatch, which leaves it
+ * untouched).
  */
 fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const void *pos,
                           void *stream, fmm_tree **out);

@@ -116,11 +116,45 @@ def _check(rc):
         raise FMMError(rc, msg.decode() if msg else "")
 
 
+# Workspace memory through torch's caching allocator: the library asks for
+# device memory with these callbacks (stream-ordered on the call's stream), so
+# torch sees, reuses and can release it.  One pair for the whole process: a
+# tree must be rebuilt with the allocator it was created with, which these
+# fixed pointers guarantee.
+_ALLOC_CB = None
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    torch = _torch()
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  int(stream or 0))
+    except Exception:  # out of memory (or no device): reported as FMM_ENOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        _torch().cuda.caching_allocator_delete(int(ptr))
+    except Exception:  # interpreter shutdown: torch already torn down
+        pass
+
+
+def torch_allocator():
+    """(alloc, free) ctypes callbacks backed by torch's caching allocator."""
+    global _ALLOC_CB
+    if _ALLOC_CB is None:
+        _ALLOC_CB = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+    return _ALLOC_CB
+
+
 def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
-                graph=False, profile_stages=None):
+                graph=False, profile_stages=None, allocator="torch"):
     """profile_stages: None (all) or an iterable of stage names (STAGES) whose
-    boundaries get profiling events."""
+    boundaries get profiling events.  allocator: "torch" (workspace from
+    torch's caching allocator), "library" (the library's own stream-ordered
+    hipMallocAsync pool) or an (alloc, free) pair of ctypes callbacks."""
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)
@@ -137,6 +171,10 @@ def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3
     c.graph = 1 if graph else 0
     c.profile_stages = 0 if profile_stages is None else \
         sum(1 << STAGES.index(s) for s in profile_stages)
+    if allocator == "torch":
+        c.alloc, c.free = torch_allocator()
+    elif allocator != "library":
+        c.alloc, c.free = allocator
     return c
 
 
@@ -184,16 +222,24 @@ def _check_tensor(t, name, shape, dtype):
 class Tree:
     """An octree built on the GPU; owns library memory until close().
 
+    With allocator="torch" (the default) the tree's workspace is taken from
+    torch's caching allocator on the stream current at the call that grows
+    it, and given back to it by close(); as with any memory torch hands out
+    for one stream, use the tree on streams ordered after that one.
+
     graph=True replays a HIP graph of the evaluate/backward chain; it is reused
     while the output tensors passed in (phi, out_vec, gradients) and the
     tree's memory stay the same, so pass preallocated outputs."""
 
     def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                  box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
-                 graph=False, profile_stages=None):
+                 graph=False, profile_stages=None, allocator="torch"):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,
-                               profile, overlap_near, graph, profile_stages)
+                               profile, overlap_near, graph, profile_stages, allocator)
+        # the callback objects must outlive every call that can allocate or
+        # free (the torch pair is held by the module)
+        self._allocator = allocator
         self.rebuild(pos)
 
     def rebuild(self, pos):

@@ -1,7 +1,8 @@
 """Build the gfx950 HIP library paper_1106_2176_amd/libfmm.so with hipcc.
 
-Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
-selection disabled; host C++ sources are compiled by hipcc as host code.
+Every source is compiled by hipcc for gfx950 only (hipcc treats the .cpp
+host sources as HIP as well), with packed-FP32 instruction selection
+disabled.
 """
 import os
 import subprocess
@@ -24,10 +25,8 @@ HIPFLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
-    if src.endswith(".hip"):
-        cmd = [HIPCC] + COMMON + HIPFLAGS + ["-c", path, "-o", obj]
-    else:
-        cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
+    # hipcc compiles .cpp sources as HIP too: every source targets gfx950 only
+    cmd = [HIPCC] + COMMON + HIPFLAGS + ["-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

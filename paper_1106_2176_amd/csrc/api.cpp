@@ -246,7 +246,20 @@ struct fmm_tree {
 
 namespace {
 
+// Device buffers of one evaluate or backward call, taken from the tree's
+// workspace.
+struct Work {
+    double4 *nearf = nullptr, *farf = nullptr;  // near / far partial results, sorted order
+    void *M[FMM_MAX_LEVEL + 1] = {}, *Lc[FMM_MAX_LEVEL + 1] = {};  // coefficient grids
+    void *pack[FMM_MAX_LEVEL + 1] = {};                            // M2L operand grids
+    double *m2lpart = nullptr;                                     // M2L K-split partial sums
+    size_t m2lpart_bytes = 0;
+};
+
 bool is_f64_form(const fmm_tree *t) { return t->cfg.precision == FMM_PREC_FP64; }
+
+// bf16 parts of the mixed M2L (0 selects the default, 3)
+int split_parts(const fmm_config &c) { return c.bf16_splits == 2 ? 2 : 3; }
 
 // Storage precision of the coefficients of level l: FP64 in the plain form;
 // in the mixed form FP64 for coarse levels (<= 4096 boxes) except the leaf
@@ -255,6 +268,31 @@ bool is_f64_form(const fmm_tree *t) { return t->cfg.precision == FMM_PREC_FP64; 
 int level_f64(const fmm_tree *t, int l) {
     if (is_f64_form(t)) return 1;
     return (l <= 4 && l != t->L) ? 1 : 0;
+}
+
+// Byte sizes of the per-call buffers (the far-field ones are zero without a
+// far field, L < 2).
+struct WorkSizes {
+    size_t nearf = 0, farf = 0, m2lpart = 0;
+    size_t M[FMM_MAX_LEVEL + 1] = {}, Lc[FMM_MAX_LEVEL + 1] = {}, pack[FMM_MAX_LEVEL + 1] = {};
+};
+
+WorkSizes work_sizes(const fmm_tree *t, bool far) {
+    WorkSizes z;
+    const int P = t->cfg.p, S = coef_stride(P), L = t->L;
+    const bool f64 = is_f64_form(t);
+    z.nearf = sizeof(double4) * (size_t)t->n;
+    if (!far || L < 2) return z;
+    z.farf = sizeof(double4) * (size_t)t->n;
+    for (int l = 2; l <= L; ++l) {
+        const size_t nb = (size_t)1 << (3 * l);
+        const size_t es = level_f64(t, l) ? 8 : 4;
+        z.M[l] = z.Lc[l] = nb * S * es;
+        const size_t g = ((size_t)1 << l) + 6;
+        z.pack[l] = g * g * g * S * (f64 ? 8 : 4);
+    }
+    z.m2lpart = m2l_partial_bytes(P, L, f64, t->ncu);
+    return z;
 }
 
 fmm_status ensure(fmm_tree *t, Buf &b, size_t bytes, hipStream_t st) {
@@ -309,6 +347,9 @@ fmm_status validate_cfg(const fmm_config *c) {
         return fail(FMM_EINVAL, "bf16_splits must be 0, 2 or 3");
     if (c->precision == FMM_PREC_MIXED && c->bf16_splits != 2 && c->p > kMixedSplit3PMax)
         return fail(FMM_EUNSUPPORTED, "the mixed form with a 3-part split supports p <= 13");
+    if (c->precision == FMM_PREC_MIXED && c->bf16_splits == 2 && c->p > kMixedSplit2PMax)
+        return fail(FMM_EUNSUPPORTED, "the mixed form with a 2-part bf16 split supports p <= 10 "
+                                      "(above it the force misses the 1e-6 budget)");
     if (!(c->box_size > 0.0) || !std::isfinite(c->box_size)) return fail(FMM_EINVAL, "box_size must be > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->box_lo[a])) return fail(FMM_EINVAL, "box_lo must be finite");
@@ -347,14 +388,38 @@ fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
         if (s_ != FMM_OK) return s_;     \
     } while (0)
 
+// Per-call buffers from the tree's workspace, grown through its allocator.
+fmm_status work_from_tree(fmm_tree *t, bool far, hipStream_t st, Work &w) {
+    const WorkSizes z = work_sizes(t, far);
+    CHK(ensure(t, t->nearf, z.nearf, st));
+    w.nearf = (double4 *)t->nearf.p;
+    if (!z.farf) return FMM_OK;
+    CHK(ensure(t, t->farf, z.farf, st));
+    w.farf = (double4 *)t->farf.p;
+    for (int l = 2; l <= t->L; ++l) {
+        CHK(ensure(t, t->M[l], z.M[l], st));
+        CHK(ensure(t, t->Lc[l], z.Lc[l], st));
+        CHK(ensure(t, t->pack[l], z.pack[l], st));
+        w.M[l] = t->M[l].p;
+        w.Lc[l] = t->Lc[l].p;
+        w.pack[l] = t->pack[l].p;
+    }
+    if (z.m2lpart) {
+        CHK(ensure(t, t->m2lpart, z.m2lpart, st));
+        w.m2lpart = (double *)t->m2lpart.p;
+        w.m2lpart_bytes = t->m2lpart.cap;
+    }
+    return FMM_OK;
+}
+
 // The far + near chain shared by the forward evaluation and the adjoint.
-fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far, bool do_near,
-                     hipStream_t st) {
-    const int P = t->cfg.p, S = coef_stride(P), L = t->L;
+fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoint, bool do_far,
+                     bool do_near, hipStream_t st) {
+    const int P = t->cfg.p, L = t->L;
     const bool f64 = is_f64_form(t);
     void *src = f64 ? t->xyz64.p : t->xyz32.p;
     const uint32_t *start = (const uint32_t *)t->start.p;
-    const int nsplit = t->cfg.bf16_splits == 2 ? 2 : 3;
+    const int nsplit = split_parts(t->cfg);
     t->cur = (int)(t->ncalls % kTimeRing);
 
     // guards: every buffer a kernel will touch holds what that kernel assumes
@@ -366,7 +431,6 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
     if (L >= 2 && level_f64(t, L) != (int)f64)
         return fail(FMM_EDEVICE, "internal: leaf-level precision differs from the particle precision");
     CHK(rec(t, 0, st));
-    CHK(ensure(t, t->nearf, sizeof(double4) * (size_t)t->n, st));
     const bool side = do_near && do_far && L >= 2 && t->cfg.overlap_near;
     // The charges go into the sorted records before anything reads them:
     // by P2M when it runs first (far field, P2P after it), else by a gather.
@@ -386,34 +450,23 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
         HIPCHK(hipEventRecord(t->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
         CHK(rec(t, kStages + 1, t->side));
-        HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, t->side));
+        HIPCHK(launch_p2p(L, f64, src, start, w.nearf, t->side));
         CHK(rec(t, kStages + 2, t->side));
         HIPCHK(hipEventRecord(t->ev_join, t->side));
     }
     if (L >= 2 && do_far) {
-        if (!t->ops) CHK(build_ops(P, &t->ops));
+        if (!t->ops) return fail(FMM_EDEVICE, "internal: the tree has no translation tables");
         const Ops *o = t->ops;
-        CHK(ensure(t, t->farf, sizeof(double4) * (size_t)t->n, st));
-        for (int l = 2; l <= L; ++l) {
-            const size_t nb = (size_t)1 << (3 * l);
-            const size_t es = level_f64(t, l) ? 8 : 4;
-            CHK(ensure(t, t->M[l], nb * S * es, st));
-            CHK(ensure(t, t->Lc[l], nb * S * es, st));
-            const size_t g = ((size_t)1 << l) + 6;
-            const size_t pk = g * g * g * S * (f64 ? 8 : 4);
-            CHK(ensure(t, t->pack[l], pk, st));
-        }
-        const size_t pbytes = m2l_partial_bytes(P, L, f64, t->ncu);
-        if (pbytes) CHK(ensure(t, t->m2lpart, pbytes, st));
+        if (!w.farf) return fail(FMM_EDEVICE, "internal: no far-field buffers");
         CHK(rec(t, 1, st));
         // P2M at the leaves (for the adjoint: L2P^T, the same sum with w)
-        HIPCHK(launch_p2m(P, L, f64, src, start, t->M[L].p, 1.0,
+        HIPCHK(launch_p2m(P, L, f64, src, start, w.M[L], 1.0,
                           p2m_gathers ? (const uint32_t *)t->perm.p : nullptr, charges, t->dtype, st));
         CHK(rec(t, 2, st));
         // upward sweep (adjoint: L2L^T)
         for (int l = L - 1; l >= 2; --l)
-            HIPCHK(launch_transfer(true, P, l, level_f64(t, l + 1), level_f64(t, l), t->M[l + 1].p,
-                                   t->M[l].p, adjoint ? o->aup32 : o->up32,
+            HIPCHK(launch_transfer(true, P, l, level_f64(t, l + 1), level_f64(t, l), w.M[l + 1],
+                                   w.M[l], adjoint ? o->aup32 : o->up32,
                                    adjoint ? o->aup64 : o->up64, st));
         CHK(rec(t, 3, st));
         {
@@ -424,8 +477,8 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
                 const int64_t g = ((int64_t)1 << l) + 6;
                 pk.level[i] = l;
                 pk.in_f64[i] = level_f64(t, l);
-                pk.in[i] = t->M[l].p;
-                pk.out[i] = t->pack[l].p;
+                pk.in[i] = w.M[l];
+                pk.out[i] = w.pack[l];
                 pk.row0[i + 1] = pk.row0[i] + g * g;
             }
             HIPCHK(launch_pack(P, f64, pk, st));
@@ -436,32 +489,32 @@ fmm_status run_chain(fmm_tree *t, const void *charges, bool adjoint, bool do_far
             void *Bp[FMM_MAX_LEVEL + 1] = {}, *Lp[FMM_MAX_LEVEL + 1] = {};
             int of64[FMM_MAX_LEVEL + 1] = {};
             for (int l = 2; l <= L; ++l) {
-                Bp[l] = t->pack[l].p;
-                Lp[l] = t->Lc[l].p;
+                Bp[l] = w.pack[l];
+                Lp[l] = w.Lc[l];
                 of64[l] = level_f64(t, l);
             }
             const void *A = f64 ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
                                 : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
             HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, o->bf_part, o->cls,
-                              (double *)t->m2lpart.p, t->m2lpart.cap, t->ncu, st));
+                              w.m2lpart, w.m2lpart_bytes, t->ncu, st));
         }
         CHK(rec(t, 5, st));
         // downward sweep (adjoint: M2M^T)
         for (int l = 2; l < L; ++l)
-            HIPCHK(launch_transfer(false, P, l, level_f64(t, l), level_f64(t, l + 1), t->Lc[l].p,
-                                   t->Lc[l + 1].p, adjoint ? o->adown32 : o->down32,
+            HIPCHK(launch_transfer(false, P, l, level_f64(t, l), level_f64(t, l + 1), w.Lc[l],
+                                   w.Lc[l + 1], adjoint ? o->adown32 : o->down32,
                                    adjoint ? o->adown64 : o->down64, st));
         CHK(rec(t, 6, st));
         // L2P (adjoint: P2M^T with its position derivative)
         // leaf-level coefficients share the particle precision (level_f64)
-        HIPCHK(launch_l2p(P, L, f64, src, start, t->Lc[L].p, (double4 *)t->farf.p, st));
+        HIPCHK(launch_l2p(P, L, f64, src, start, w.Lc[L], w.farf, st));
     } else {
         for (int s = 1; s <= 6; ++s) CHK(rec(t, s, st));
     }
     CHK(rec(t, 7, st));
     if (side) HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
-    else if (do_near) HIPCHK(launch_p2p(L, f64, src, start, (double4 *)t->nearf.p, st));
-    else HIPCHK(launch_zero((uint32_t *)t->nearf.p, 8 * t->n, st));
+    else if (do_near) HIPCHK(launch_p2p(L, f64, src, start, w.nearf, st));
+    else HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
     CHK(rec(t, 8, st));
     return FMM_OK;
 }
@@ -528,11 +581,12 @@ fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int3
                           hipStream_t st) {
     const int kind = flags & 3, part = flags & ~3;
     const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
-    CHK(run_chain(t, q, false, do_far, do_near, st));
+    Work w;
+    CHK(work_from_tree(t, do_far, st, w));
+    CHK(run_chain(t, w, q, false, do_far, do_near, st));
     const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
-    HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, (const double4 *)t->nearf.p,
-                          (t->L >= 2 && do_far) ? (const double4 *)t->farf.p : nullptr, inv_w, q, phi,
-                          vec, kind, st));
+    HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, w.nearf,
+                          (t->L >= 2 && do_far) ? w.farf : nullptr, inv_w, q, phi, vec, kind, st));
     CHK(rec(t, kStages, st));
     if (t->cfg.profile) ++t->ncalls;
     return FMM_OK;
@@ -540,12 +594,13 @@ fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int3
 
 fmm_status backward_chain(fmm_tree *t, const void *q, const void *w, const void *field_fwd,
                           void *grad_q, void *grad_pos, hipStream_t st) {
-    CHK(run_chain(t, w, true, true, true, st));
+    Work wk;
+    CHK(work_from_tree(t, true, st, wk));
+    CHK(run_chain(t, wk, w, true, true, true, st));
     const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
-    HIPCHK(launch_combine_grad(t->n, t->dtype, (const uint32_t *)t->perm.p,
-                               (const double4 *)t->nearf.p,
-                               t->L >= 2 ? (const double4 *)t->farf.p : nullptr, inv_w, q, w,
-                               field_fwd, grad_q, grad_pos, st));
+    HIPCHK(launch_combine_grad(t->n, t->dtype, (const uint32_t *)t->perm.p, wk.nearf,
+                               t->L >= 2 ? wk.farf : nullptr, inv_w, q, w, field_fwd, grad_q,
+                               grad_pos, st));
     CHK(rec(t, kStages, st));
     if (t->cfg.profile) ++t->ncalls;
     return FMM_OK;
@@ -592,6 +647,19 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     hipStream_t st = (hipStream_t)stream;
     fmm_tree *t = *out;
     const bool fresh = (t == nullptr);
+    // A tree is rebuilt in place only under the settings its operator tables,
+    // particle records and buffers were made for: checked before anything
+    // is allocated or launched, so that a rejected call leaves it untouched.
+    if (!fresh) {
+        const fmm_config &o = t->cfg;
+        const bool mixed = cfg->precision == FMM_PREC_MIXED;
+        if (o.p != cfg->p || o.precision != cfg->precision || t->dtype != dtype ||
+            (mixed && split_parts(o) != split_parts(*cfg)))
+            return fail(FMM_EINVAL, "a tree is rebuilt only with the p, precision, bf16_splits and "
+                                    "dtype it was created with");
+        if (o.alloc != cfg->alloc || o.free != cfg->free || o.alloc_ctx != cfg->alloc_ctx)
+            return fail(FMM_EINVAL, "a tree is rebuilt only with the allocator it was created with");
+    }
     if (fresh) {
         t = new (std::nothrow) fmm_tree();
         if (!t) return fail(FMM_ENOMEM, "host allocation failed");
@@ -694,6 +762,9 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     }
     t->L = lev;
     t->nleaf = (int64_t)1 << (3 * lev);
+    // translation tables of this p (made once per device and p): a tree with
+    // a far field has them before its first evaluation
+    if (lev >= 2 && !t->ops && (s = build_ops(cfg->p, &t->ops)) != FMM_OK) return bail(s);
     *out = t;
     return FMM_OK;
 }

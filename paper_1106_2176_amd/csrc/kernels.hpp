@@ -74,6 +74,10 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
 // of FP64 scratch.
 size_t m2l_partial_bytes(int P, int L, bool f64, int ncu);
 constexpr int kMixedSplit3PMax = 13;  // LDS holds the 3-part operator ring up to p = 13
+// The 2-part bf16 split (about 16 bits per operand) keeps the mixed force
+// within 1e-6 of the FP64 form up to p = 10 only (measured 1.2e-6 at
+// p = 11 and 16).
+constexpr int kMixedSplit2PMax = 10;
 hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
                       const int *out_f64, const void *A, size_t astride, const int2 *cls, double *partial, size_t partial_bytes, int ncu,
                       hipStream_t st);

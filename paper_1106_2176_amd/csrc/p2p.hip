@@ -115,12 +115,15 @@ __device__ __forceinline__ void wave_sync() {
 // hide the serial walk over 27 neighbours): a block of three waves per
 // target leaf, wave w taking the neighbour plane dz = w - 1; wave 0 adds the
 // three planes' sums in plane order.
-// The one-wave kernel asks for eight waves per SIMD (64 registers; its LDS,
-// 5 KB, allows as many): the loop is bound by instruction issue and LDS
-// latency, which more resident waves hide.
+// The one-wave FP32 kernel asks for eight waves per SIMD (64 registers; its
+// LDS, 5 KB, allows as many): the loop is bound by instruction issue and LDS
+// latency, which more resident waves hide.  The FP64 kernel holds twice the
+// data per pair and fits four (128 registers).
+template <typename T>
+constexpr int p2p_waves(int NP) { return NP == 1 ? (sizeof(T) == 4 ? 8 : 4) : 1; }
 template <typename T, int NP>
 __global__ __launch_bounds__(64 * NP)
-__attribute__((amdgpu_waves_per_eu(NP == 1 ? 8 : 1, NP == 1 ? 8 : 10))) void k_p2p(int L, uint32_t per_xcd,
+__attribute__((amdgpu_waves_per_eu(p2p_waves<T>(NP), NP == 1 ? p2p_waves<T>(NP) : 10))) void k_p2p(int L, uint32_t per_xcd,
                                                  const typename V4<T>::type *__restrict__ src,
                                                  const uint32_t *__restrict__ start,
                                                  double4 *__restrict__ out) {

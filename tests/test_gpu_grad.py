@@ -5,7 +5,8 @@ Loss = sum_i w_i phi_i.  Pins:
       pinned by finite differences of its own loss in test_oracle.py)
   dot-product test <w, A q> = <A^T w, q>  1e-12 relative (FP64)
   w = q (held fixed): dL/dq = A q = phi, dL/dx = -2 q E   1e-12 (FP64)
-  mixed adjoint vs FP64 adjoint           1e-6
+  mixed adjoint vs FP64 adjoint           1e-6 (each gradient's cancellation
+      factor is printed beside its error)
 """
 import numpy as np
 import pytest
@@ -59,19 +60,32 @@ def test_dot_product_and_symmetric_cases():
 
 def test_c5_mixed_vs_fp64_and_direct(oracle_mod):
     """N = 1e6, p = 8, leaf <= 64: mixed adjoint against the FP64 adjoint and
-    the analytic direct-sum gradient on sampled particles."""
+    the analytic direct-sum gradient on sampled particles.
+
+    Both gradients are held to the plain 1e-6 budget.  Rounding errors scale
+    with the sums of the magnitudes of the terms, and the weights w are
+    zero-mean, so each gradient's own cancellation factor is printed beside
+    its error (they would justify a looser bar; none is needed):
+      dL/dq = phi_w, the potential of w:
+          kappa_q = ||phi_|w| || / ||dL/dq||            (about 510)
+      dL/dx = -(w E_q + q E_w), componentwise:
+          kappa_x = || |w| |E_|q|| + |q| |E_|w|| || / ||dL/dx||   (about 1.7)
+    (phi_|w|, E_|w|: the FP64 FMM with charges |w|; E_|q| likewise)."""
     wl = inputs.WORKLOADS["C5"]
     pos, q = inputs.workload("C5")
     w = inputs.weights(wl.n, wl.seed)
     _, _, gq64, gx64 = grads(pos, q, w, wl.p, wl.leaf_max, "fp64")
     _, _, gqm, gxm = grads(pos, q, w, wl.p, wl.leaf_max, "mixed")
-    # w is zero-mean, so dL/dq (the potential of w) is a cancelling sum:
-    # rounding errors scale with the potential of |w|, not of w.  The
-    # tolerance is the 1e-6 budget times that cancellation factor.
-    phi_abs, _, _, _ = grads(pos, np.abs(w), w, wl.p, wl.leaf_max, "fp64")
-    kappa = max(1.0, np.linalg.norm(phi_abs) / np.linalg.norm(gq64))
-    assert rel_l2(gqm, gq64) < 1e-6 * kappa
-    assert rel_l2(gxm, gx64) < 1e-6 * kappa
+    phi_aw, E_aw, _, _ = grads(pos, np.abs(w), w, wl.p, wl.leaf_max, "fp64")
+    _, E_aq, _, _ = grads(pos, np.abs(q), w, wl.p, wl.leaf_max, "fp64")
+    kappa_q = max(1.0, np.linalg.norm(phi_aw) / np.linalg.norm(gq64))
+    scale_x = np.abs(w)[:, None] * np.abs(E_aq) + np.abs(q)[:, None] * np.abs(E_aw)
+    kappa_x = max(1.0, np.linalg.norm(scale_x) / np.linalg.norm(gx64))
+    e_q, e_x = rel_l2(gqm, gq64), rel_l2(gxm, gx64)
+    print("C5 mixed vs FP64: dL/dq %.3e (kappa_q %.1f), dL/dx %.3e (kappa_x %.2f)"
+          % (e_q, kappa_q, e_x, kappa_x))
+    assert e_q < 1e-6
+    assert e_x < 1e-6
     t = inputs.targets(wl.n, wl.seed, 300)
     phw, Ew = oracle_mod.direct(pos, w, t)
     phq, Eq = oracle_mod.direct(pos, q, t)
@@ -82,6 +96,9 @@ def test_c5_mixed_vs_fp64_and_direct(oracle_mod):
     oq = oracle_mod.fmm(pos, q, wl.p, wl.leaf_max, targets=t)
     eps_q = rel_l2(ow["phi"], phw)
     eps_x = rel_l2(-(w[t, None] * oq["E"] + q[t, None] * ow["E"]), gx_d)
+    print("C5 vs direct-sum gradient: FP64 dL/dq %.3e dL/dx %.3e, mixed dL/dq %.3e dL/dx %.3e, "
+          "oracle FMM %.3e %.3e" % (rel_l2(gq64[t], phw), rel_l2(gx64[t], gx_d), rel_l2(gqm[t], phw),
+                                    rel_l2(gxm[t], gx_d), eps_q, eps_x))
     assert rel_l2(gq64[t], phw) < 1.01 * eps_q + 1e-12
     assert rel_l2(gx64[t], gx_d) < 1.01 * eps_x + 1e-12
 

@@ -175,35 +175,24 @@ def test_c2_sampled_fp64_and_mixed(oracle_mod):
     assert rel_l2(Em[t], E_d) < 1e-5
 
 
-def _mixed_vs_fp64(pos, q, p, leaf):
-    """Mixed and FP64 forms on all N, and the error scales of the sums."""
-    phi, E, info = gpu_eval(pos, q, p, leaf, "fp64")
-    phm, Em, _ = gpu_eval(pos, q, p, leaf, "mixed")
-    # rounding errors scale with the sums of |terms|: with zero-mean charges
-    # the potential and force cancel far below them.  The same FMM with
-    # charges |q| gives that scale (kappa >= 1; 1 for positive charges).
-    qa = np.abs(q)
-    phia, Ea, _ = gpu_eval(pos, qa, p, leaf, "fp64")
-    qq, qqa = q.astype(np.float64)[:, None], qa.astype(np.float64)[:, None]
-    kphi = np.linalg.norm(phia) / np.linalg.norm(phi)
-    kF = np.linalg.norm(qqa * Ea) / np.linalg.norm(qq * E)
-    return (phi, E, info), (phm, Em), max(1.0, kphi), max(1.0, kF)
-
-
 def test_c3_sampled_fp64_and_mixed(oracle_mod):
-    """N = 1e7, p = 10, leaf <= 128, zero-mean charges U[-1,1) (full size);
+    """N = 1e7, p = 10, leaf <= 128, zero-mean charges U[-1,1) (full size):
     FP64 form against the oracle on 1000 sampled targets, mixed against FP64
-    on all N within 1e-6 of the scale of the summed terms."""
+    on all N within 1e-6 for phi and for F."""
     w = inputs.WORKLOADS["C3"]
     pos, q = inputs.workload("C3")
     t = inputs.targets(w.n, w.seed)
     ref = oracle_mod.fmm(pos, q, w.p, w.leaf_max, targets=t)
-    (phi, E, info), (phm, Em), kphi, kF = _mixed_vs_fp64(pos, q, w.p, w.leaf_max)
+    phi, E, info = gpu_eval(pos, q, w.p, w.leaf_max, "fp64")
     assert info["levels"] == 6
     assert rel_l2(phi[t], ref["phi"]) < 1e-10
     assert rel_l2(E[t], ref["E"]) < 1e-10
-    assert rel_l2(phm, phi) < 1e-6 * kphi
-    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6 * kF
+    phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed")
+    e_phi = rel_l2(phm, phi)
+    e_F = rel_l2(q[:, None] * Em, q[:, None] * E)
+    print("C3 mixed vs FP64 on all N: phi %.3e F %.3e" % (e_phi, e_F))
+    assert e_phi < 1e-6
+    assert e_F < 1e-6
 
 
 def test_c4_sampled_fp32_inputs(oracle_mod):
@@ -320,3 +309,107 @@ def test_profiled_stage_subset(overlap):
         st = t.stage_times()
     assert st["M2L"] > 0 and st["P2P"] > 0
     assert all(np.isnan(v) for k, v in st.items() if k not in ("M2L", "P2P"))
+
+
+# ------------------------------------------------------- orders above 10
+
+@pytest.mark.parametrize("p", [11, 12, 13, 14, 15, 16])
+def test_high_order_fp64_vs_oracle_and_mixed(oracle_mod, p):
+    """Every order above the workloads' p = 10 that the library accepts: the
+    FP64 form against the oracle (level 3, so that the oracle's Cartesian
+    M2L of p(p+1)(p+2)/6 terms stays in seconds), and the mixed form in
+    each split it supports (3 parts up to p = 13) against the FP64 form;
+    the splits it does not support are rejected."""
+    n, leaf = 4000, 32
+    pos, q = inputs.particles(n, 100 + p)
+    ref = oracle_mod.fmm(pos, q, p, leaf)
+    phi, E, info = gpu_eval(pos, q, p, leaf, "fp64")
+    assert info["levels"] == ref["level"] == 3
+    assert rel_l2(phi, ref["phi"]) < 1e-10
+    assert rel_l2(E, ref["E"]) < 1e-10
+    phf, Ef, _ = gpu_eval(pos, q, p, leaf, "fp64", part="far")
+    assert rel_l2(phf, ref["phi_far"]) < 1e-10
+    assert rel_l2(Ef, ref["E_far"]) < 1e-10
+    for splits in (2, 3):
+        if (splits == 3 and p > 13) or splits == 2:
+            with pytest.raises(fmm.FMMError) as e:
+                gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=3)
+            assert e.value.status == fmm.FMM_EUNSUPPORTED
+            continue
+        phm, Em, _ = gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=splits)
+        assert rel_l2(phm, phi) < 1e-6
+        assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+
+
+@pytest.mark.parametrize("p,splits", [(13, 3), (11, 3), (12, 3)])
+def test_high_order_mixed_at_level5(p, splits):
+    """Mixed against FP64 on a level-5 tree (whole M2L tiles of 128
+    targets, not only the K-split small levels)."""
+    pos, q = inputs.particles(300_000, 120 + p)
+    phi, E, info = gpu_eval(pos, q, p, 32, "fp64")
+    assert info["levels"] == 5
+    phm, Em, _ = gpu_eval(pos, q, p, 32, "mixed", bf16_splits=splits)
+    assert rel_l2(phm, phi) < 1e-6
+    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+
+
+# --------------------------------------- graph replay, concurrent near field
+
+def _modes_run(pos, q, w, p, leaf, precision, graph, overlap, reps=3):
+    """Evaluate and backward `reps` times on one tree in the given launch
+    mode (graph: replayed from the second call on); every call's outputs."""
+    n = len(q)
+    qd, wd = dev(q), dev(w)
+    out = []
+    with fmm.Tree(dev(pos), p=p, leaf_max=leaf, precision=precision, graph=graph,
+                  overlap_near=overlap) as t:
+        phi = torch.empty(n, dtype=torch.float64, device="cuda")
+        E = torch.empty(n, 3, dtype=torch.float64, device="cuda")
+        gq = torch.empty_like(phi)
+        gx = torch.empty_like(E)
+        for _ in range(reps):
+            for x in (phi, E, gq, gx):
+                x.fill_(float("nan"))
+            t.evaluate(qd, phi=phi, out_vec=E)
+            t.backward(qd, wd, E, out_q=gq, out_pos=gx)
+            torch.cuda.synchronize()
+            out.append([x.cpu().numpy() for x in (phi, E, gq, gx)])
+    return out
+
+
+@pytest.mark.parametrize("graph,overlap", [(False, False), (True, False), (False, True), (True, True)])
+def test_launch_modes_fp64_match_oracle(oracle_mod, graph, overlap):
+    """C1 (N = 1e4, p = 4) in the FP64 form with graph replay and/or the
+    concurrent near field: every call's potential and field against the
+    oracle FMM, and its gradients against the oracle's FMM gradient (which
+    finite differences pin), within 1e-10."""
+    wl = inputs.WORKLOADS["C1"]
+    pos, q = inputs.workload("C1")
+    w = inputs.weights(wl.n, wl.seed)
+    ref = oracle_mod.fmm(pos, q, wl.p, wl.leaf_max)
+    gq_o, gx_o, _ = oracle_mod.fmm_grad(pos, q, w, wl.p, wl.leaf_max)
+    for phi, E, gq, gx in _modes_run(pos, q, w, wl.p, wl.leaf_max, "fp64", graph, overlap):
+        assert rel_l2(phi, ref["phi"]) < 1e-10
+        assert rel_l2(E, ref["E"]) < 1e-10
+        assert rel_l2(gq, gq_o) < 1e-10
+        assert rel_l2(gx, gx_o) < 1e-10
+
+
+@pytest.mark.parametrize("graph,overlap", [(True, False), (False, True), (True, True)])
+def test_launch_modes_c2_mixed_vs_fp64_and_oracle(oracle_mod, graph, overlap):
+    """C2 (N = 1e6, p = 10, leaf <= 64): the FP64 form in the mode against
+    the oracle FMM on 1000 sampled targets (1e-10), and the mixed form in the
+    mode against the FP64 form on all N (1e-6, phi and F), every call."""
+    wl = inputs.WORKLOADS["C2"]
+    pos, q = inputs.workload("C2")
+    w = inputs.weights(wl.n, wl.seed)
+    t = inputs.targets(wl.n, wl.seed)
+    ref = oracle_mod.fmm(pos, q, wl.p, wl.leaf_max, targets=t)
+    f64 = _modes_run(pos, q, w, wl.p, wl.leaf_max, "fp64", graph, overlap, reps=2)
+    for phi, E, _, _ in f64:
+        assert rel_l2(phi[t], ref["phi"]) < 1e-10
+        assert rel_l2(E[t], ref["E"]) < 1e-10
+    phi, E, gq, gx = f64[0]
+    for phm, Em, gqm, gxm in _modes_run(pos, q, w, wl.p, wl.leaf_max, "mixed", graph, overlap, reps=2):
+        assert rel_l2(phm, phi) < 1e-6
+        assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
