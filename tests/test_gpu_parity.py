@@ -333,7 +333,7 @@ def test_high_order_fp64_vs_oracle_and_mixed(oracle_mod, p):
     for splits in (2, 3):
         if (splits == 3 and p > 13) or splits == 2:
             with pytest.raises(fmm.FMMError) as e:
-                gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=3)
+                gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=splits)
             assert e.value.status == fmm.FMM_EUNSUPPORTED
             continue
         phm, Em, _ = gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=splits)
