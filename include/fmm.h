@@ -192,6 +192,34 @@ fmm_status fmm_evaluate(fmm_tree *tree, const void *q, void *phi, void *vec, int
                         void *stream);
 
 /*
+ * fmm_evaluate for callers that cannot allocate device memory: code under
+ * HIP graph capture, serving loops and harnesses that forbid hipMalloc.
+ * Same arguments, outputs and errors as fmm_evaluate, and the same kernels in
+ * the same order (bitwise equal results), but every buffer of the call (near
+ * and far partial results, multipole and local coefficient grids, M2L
+ * operand grids and K-split partial sums) is carved from the library's
+ * static device array of FMM_NOALLOC_SCRATCH_BYTES instead of the tree's
+ * workspace: the call allocates nothing, creates no stream or event and
+ * captures no graph.  It runs the near field after the far field on
+ * `stream` whatever cfg.overlap_near says, and records no profiling events.
+ * The tree itself comes from fmm_build_tree, which does allocate (its
+ * sorted particles and, for a far field, the translation tables of p).
+ *   - A tree whose evaluation needs more scratch than the array holds is
+ *     rejected with FMM_EINVAL before any launch (the message gives the
+ *     size).  Roughly: 64 B per particle plus the coefficient and M2L grids
+ *     of the levels, e.g. N <= 10^5 at p = 10, leaf_max = 64.
+ *   - Every call on one device uses that device's one array, which keeps
+ *     the last call's contents; nothing in it needs clearing.  Calls that
+ *     overlap on one device (on different streams or host threads) race
+ *     on it: the caller orders them.
+ *   - Each device the library runs on holds its array from the library's
+ *     load until the process ends.
+ */
+#define FMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+fmm_status fmm_evaluate_noalloc(fmm_tree *tree, const void *q, void *phi, void *vec, int32_t flags,
+                                void *stream);
+
+/*
  * Gradient of the weighted-potential loss  Loss = sum_i w_i phi_i  of the
  * FMM as computed by fmm_evaluate on the same tree and charges, with respect
  * to the charges and positions.  Hand-written adjoint: the transposed

@@ -79,6 +79,7 @@ _SIGS = {
     "fmm_build_tree": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int64, ctypes.c_int32, _vp, _vp,
                                       ctypes.POINTER(_vp)]),
     "fmm_evaluate": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
+    "fmm_evaluate_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]),
     "fmm_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fmm_tree_info": (ctypes.c_int, [_vp, ctypes.POINTER(TreeInfo)]),
     "fmm_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),

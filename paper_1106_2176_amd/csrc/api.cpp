@@ -242,12 +242,14 @@ struct fmm_tree {
     hipStream_t cap = nullptr;  // capture stream of graph mode
     bool capturing = false;
     GraphSlot gfwd, gbwd;       // graphs of fmm_evaluate and fmm_backward
+    bool quiet = false;         // a call that records no profiling events
 };
 
 namespace {
 
-// Device buffers of one evaluate or backward call, taken from the tree's
-// workspace.
+// Device buffers of one evaluate or backward call: taken from the tree's
+// workspace (fmm_evaluate, fmm_backward) or carved from the library's static
+// scratch array (fmm_evaluate_noalloc).
 struct Work {
     double4 *nearf = nullptr, *farf = nullptr;  // near / far partial results, sorted order
     void *M[FMM_MAX_LEVEL + 1] = {}, *Lc[FMM_MAX_LEVEL + 1] = {};  // coefficient grids
@@ -368,7 +370,7 @@ bool stage_on(const fmm_tree *t, int i) {
 // start / end (kStages + 1 / + 2) of a P2P on the side stream; only where a
 // selected stage begins or ends.
 fmm_status rec(fmm_tree *t, int stage, hipStream_t st) {
-    if (!t->cfg.profile || t->capturing) return FMM_OK;
+    if (!t->cfg.profile || t->capturing || t->quiet) return FMM_OK;
     const bool want = stage > kStages ? stage_on(t, 7)
                                       : (stage < kStages && stage_on(t, stage)) ||
                                             (stage > 0 && stage_on(t, stage - 1));
@@ -412,6 +414,45 @@ fmm_status work_from_tree(fmm_tree *t, bool far, hipStream_t st, Work &w) {
     return FMM_OK;
 }
 
+// Per-call buffers carved, 256-byte aligned, from the static scratch array
+// of the current device (FMM_NOALLOC_SCRATCH_BYTES).  Nothing in them needs
+// clearing: every kernel writes each element before any kernel reads it.
+fmm_status work_from_scratch(fmm_tree *t, bool far, Work &w) {
+    const WorkSizes z = work_sizes(t, far);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> size_t {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_near = take(z.nearf), o_far = take(z.farf), o_part = take(z.m2lpart);
+    size_t oM[FMM_MAX_LEVEL + 1] = {}, oL[FMM_MAX_LEVEL + 1] = {}, oP[FMM_MAX_LEVEL + 1] = {};
+    for (int l = 2; l <= t->L && z.farf; ++l) {
+        oM[l] = take(z.M[l]);
+        oL[l] = take(z.Lc[l]);
+        oP[l] = take(z.pack[l]);
+    }
+    if (off > (size_t)FMM_NOALLOC_SCRATCH_BYTES)
+        return fail(FMM_EINVAL, "this tree's evaluation needs " + std::to_string(off) +
+                                    " bytes of scratch, more than FMM_NOALLOC_SCRATCH_BYTES (" +
+                                    std::to_string((size_t)FMM_NOALLOC_SCRATCH_BYTES) + ")");
+    unsigned char *base = nullptr;
+    HIPCHK(noalloc_scratch((void **)&base));
+    w.nearf = (double4 *)(base + o_near);
+    if (!z.farf) return FMM_OK;
+    w.farf = (double4 *)(base + o_far);
+    if (z.m2lpart) {
+        w.m2lpart = (double *)(base + o_part);
+        w.m2lpart_bytes = z.m2lpart;
+    }
+    for (int l = 2; l <= t->L; ++l) {
+        w.M[l] = base + oM[l];
+        w.Lc[l] = base + oL[l];
+        w.pack[l] = base + oP[l];
+    }
+    return FMM_OK;
+}
+
 // The far + near chain shared by the forward evaluation and the adjoint.
 fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoint, bool do_far,
                      bool do_near, hipStream_t st) {
@@ -431,7 +472,7 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
     if (L >= 2 && level_f64(t, L) != (int)f64)
         return fail(FMM_EDEVICE, "internal: leaf-level precision differs from the particle precision");
     CHK(rec(t, 0, st));
-    const bool side = do_near && do_far && L >= 2 && t->cfg.overlap_near;
+    const bool side = do_near && do_far && L >= 2 && t->cfg.overlap_near && !t->quiet;
     // The charges go into the sorted records before anything reads them:
     // by P2M when it runs first (far field, P2P after it), else by a gather.
     const bool p2m_gathers = do_far && L >= 2 && !side;
@@ -578,17 +619,17 @@ fmm_status launch_graph(GraphSlot &g, hipStream_t st) {
 }
 
 fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int32_t flags,
-                          hipStream_t st) {
+                          hipStream_t st, bool noalloc = false) {
     const int kind = flags & 3, part = flags & ~3;
     const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
     Work w;
-    CHK(work_from_tree(t, do_far, st, w));
+    CHK(noalloc ? work_from_scratch(t, do_far, w) : work_from_tree(t, do_far, st, w));
     CHK(run_chain(t, w, q, false, do_far, do_near, st));
     const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
     HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, w.nearf,
                           (t->L >= 2 && do_far) ? w.farf : nullptr, inv_w, q, phi, vec, kind, st));
     CHK(rec(t, kStages, st));
-    if (t->cfg.profile) ++t->ncalls;
+    if (t->cfg.profile && !t->quiet) ++t->ncalls;
     return FMM_OK;
 }
 
@@ -784,6 +825,22 @@ fmm_status fmm_evaluate(fmm_tree *t, const void *q, void *phi, void *vec, int32_
     return capture_graph(t, t->gfwd, arg, flags, [&](hipStream_t cs) {
         return evaluate_chain(t, q, phi, vec, flags, cs);
     });
+}
+
+fmm_status fmm_evaluate_noalloc(fmm_tree *t, const void *q, void *phi, void *vec, int32_t flags,
+                                void *stream) {
+    if (!t || !q || !phi) return fail(FMM_EINVAL, "tree, q and phi are required");
+    const int kind = flags & 3, part = flags & ~3;
+    if (kind == 3 || (part != 0 && part != FMM_PART_NEAR_ONLY && part != FMM_PART_FAR_ONLY))
+        return fail(FMM_EINVAL, "unknown flags");
+    if (kind != FMM_VEC_NONE && !vec) return fail(FMM_EINVAL, "vec is NULL");
+    if (t->L >= 2 && !t->ops) return fail(FMM_EINVAL, "the tree has no translation tables");
+    // serial order, no events, no graph: nothing here creates a stream, an
+    // event or a buffer
+    t->quiet = true;
+    const fmm_status s = evaluate_chain(t, q, phi, vec, flags, (hipStream_t)stream, true);
+    t->quiet = false;
+    return s;
 }
 
 fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *field_fwd,

@@ -67,6 +67,10 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
                                const double4 *farf, double inv_w, const void *q, const void *w,
                                const void *Eq, void *gq, void *gx, hipStream_t st);
 
+// scratch.hip: device address of the current device's static scratch array
+// (FMM_NOALLOC_SCRATCH_BYTES), looked up on the first call per device
+hipError_t noalloc_scratch(void **ptr);
+
 // m2l.hip: every level 2..L in one launch; B[l], Lc[l] indexed by level.
 // Mixed form: A = bf16 operator parts spaced astride elements apart (layout
 // [part][317][R/16][S/8][16][8]), B[l] = FP32 padded multipole grid.  Both
