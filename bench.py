@@ -8,7 +8,8 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
   value        particles/s of the mixed form (N / step time)
   p2p_gint_s   P2P Ginteractions/s (mixed), pairs from the tree / P2P time
   fp64         the plain FP64 form measured the same way
-  rel_l2       errors vs the FP64 direct sum on 1000 sampled targets
+  rel_l2       errors vs the FP64 direct sum on 1000 sampled targets, and
+               mixed vs FP64 on all N
   roofline     dominant kernel of the mixed step (M2L or P2P, whichever
                stage is longer in stages_ms); its duration is the mean of
                HIP events that the library records around that stage only
@@ -19,6 +20,11 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
   roofline_p2p the same for the other kernel (roofline_m2l when P2P
                dominates), its duration from stages_ms; traffic only on the
                workload the counter summaries were taken on
+  tree_pass    the HBM-bound passes (build, P2M with the charge gather, L2P,
+               combine): algorithmic bytes over their time
+  overlap      the same step with the near field on a concurrent stream
+  c3           N = 1e7, p = 10, leaf <= 128, zero-mean charges: both forms,
+               their dominant kernel, errors vs the direct sum and each other
   cpu_baseline the CPU oracle FMM on the host cores
   adjoint      forward + backward throughput of the differentiable form
                (N = 1e6, p = 8, leaf <= 64)
@@ -41,12 +47,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (dual issue) x 2.4 GHz
-PEAK_BF16_MFMA_TFLOPS = 2500.0
+# 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s issuing one
+# FP32 instruction per lane and cycle; the published 157.3 counts packed
+# (two-wide) FP32, which this build does not use
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+PEAK_16BIT_MFMA_TFLOPS = 2500.0  # bf16 and fp16 dense
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 P2P_FLOP_PER_PAIR = 19
 COPY_PROBE_BYTES = 1 << 30
+
+# mixed-form M2L encodings: tree options and MFMA products per term
+ENCODINGS = {"fp16x2": ({"m2l_fp16": True}, 3),
+             "bf16x3": ({"m2l_fp16": False, "bf16_splits": 3}, 6),
+             "bf16x2": ({"m2l_fp16": False, "bf16_splits": 2}, 3)}
 
 
 def parse():
@@ -59,9 +74,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="particles for the CPU oracle baseline (0: the whole workload)")
-    ap.add_argument("--splits", type=int, default=3, help="bf16 parts of the mixed M2L (2 or 3)")
+    ap.add_argument("--m2l", default="fp16x2", choices=sorted(ENCODINGS),
+                    help="M2L operand encoding of the mixed form")
     ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
 
@@ -77,9 +95,9 @@ def timed_steps(step, steps, warmup, sync):
     return (time.perf_counter() - t0) / steps
 
 
-def traffic_from_profile(kernel_file, summary):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, or
-    None when it is missing or was taken on another version of the kernel."""
+def read_profile(summary, kernel_file):
+    """key: value pairs of a committed rocprofv3 summary, or None when it is
+    missing or was taken on another version of the kernel's source."""
     path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, "paper_1106_2176_amd", "csrc", kernel_file)
     if not (os.path.exists(path) and os.path.exists(src)):
@@ -90,7 +108,14 @@ def traffic_from_profile(kernel_file, summary):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if kv.get("source_sha256") != sha:
+    return kv if kv.get("source_sha256") == sha else None
+
+
+def traffic_from_profile(kernel_file, summary):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each divided by its
+    copy-kernel factor) from a committed counter summary, or None."""
+    kv = read_profile(summary, kernel_file)
+    if kv is None:
         return None
     try:
         fetch = float(kv["fetch_kib_per_dispatch"]) / float(kv["copy_fetch_factor"])
@@ -111,6 +136,98 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}), flush=True)
 
 
+def measure(fmm, wl, pos, q, precision, steps, warmup, sync, **kw):
+    """Build + evaluate steps of one form: every stage's time from a fully
+    profiled run (outside the timed region), then the timed steps with events
+    only around the dominant stage (M2L or P2P)."""
+    import torch
+    phi = torch.empty_like(q)
+    E = torch.empty_like(pos)
+
+    def run(stages, nsteps, nwarm):
+        tree = fmm.Tree(pos, p=wl.p, leaf_max=wl.leaf_max, precision=precision, profile=True,
+                        profile_stages=stages, **kw)
+
+        def step():
+            tree.rebuild(pos)
+            tree.evaluate(q, vec="field", phi=phi, out_vec=E)
+
+        for _ in range(nwarm):
+            step()
+        tree.stage_times_reset()
+        sec = timed_steps(step, nsteps, 0, sync)
+        st = tree.stage_times()
+        info = tree.info()
+
+        def build():
+            tree.rebuild(pos)
+        build_s = timed_steps(build, max(3, nsteps // 2), 1, sync)
+        tree.close()
+        return sec, st, info, build_s
+
+    stages_ms = run(None, max(5, steps // 2), max(1, warmup))[1]
+    dom = "M2L" if stages_ms["M2L"] >= stages_ms["P2P"] else "P2P"
+    sec, roof_st, info, build_s = run((dom,), steps, warmup)
+    return {"sec": sec, "dom": dom, "dom_ms": roof_st[dom], "stages_ms": stages_ms, "info": info,
+            "build_ms": build_s * 1e3, "phi": phi.clone(), "E": E.clone()}
+
+
+def rooflines(wl, res, precision, enc, on_profiled):
+    """(dominant-kernel roofline, the other one) of a measured form."""
+    info, dom = res["info"], res["dom"]
+    p2p_ms = res["dom_ms"] if dom == "P2P" else res["stages_ms"]["P2P"]
+    m2l_ms = res["dom_ms"] if dom == "M2L" else res["stages_ms"]["M2L"]
+    pairs, m2l_pairs = info["p2p_pairs"], info["m2l_pairs"]
+    p2p_tf = P2P_FLOP_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
+    m2l_tf = 2.0 * wl.p ** 4 * m2l_pairs / (m2l_ms * 1e-3) / 1e12
+    f64 = precision == "fp64"
+    p2p = {"kernel": "k_p2p<%s>" % ("double" if f64 else "float"), "bound": "alu", "achieved": p2p_tf,
+           "peak": PEAK_FP64_TFLOPS if f64 else PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+           "frac": p2p_tf / (PEAK_FP64_TFLOPS if f64 else PEAK_FP32_VECTOR_TFLOPS),
+           "traffic": traffic_from_profile("p2p.hip", "p2p_C2_traffic.txt") if on_profiled and not f64 else None,
+           "ms": p2p_ms, "flop_per_launch": P2P_FLOP_PER_PAIR * pairs}
+    if not f64:
+        p2p["peak_unpacked"] = PEAK_FP32_UNPACKED_TFLOPS
+        p2p["frac_unpacked"] = p2p_tf / PEAK_FP32_UNPACKED_TFLOPS
+    if f64:
+        m2l = {"kernel": "k_m2l_f64<%d>" % wl.p, "bound": "mfma", "achieved": m2l_tf,
+               "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": m2l_tf / PEAK_FP64_TFLOPS,
+               "traffic": None}
+    else:
+        opts, products = ENCODINGS[enc]
+        nparts = 2 if opts.get("m2l_fp16") else opts["bf16_splits"]
+        m2l = {"kernel": "k_m2l_bf16<%d,%d,8,%s>" % (nparts, wl.p, "fp16" if opts.get("m2l_fp16") else "bf16"),
+               "bound": "mfma", "achieved": m2l_tf, "peak": PEAK_16BIT_MFMA_TFLOPS, "unit": "TFLOP/s",
+               "frac": m2l_tf / PEAK_16BIT_MFMA_TFLOPS,
+               "traffic": traffic_from_profile("m2l.hip", "m2l_%s_C2_traffic.txt" % enc) if on_profiled else None,
+               "encoding": enc, "mfma_products_per_term": products}
+    m2l.update({"ms": m2l_ms, "flop_per_launch": 2.0 * wl.p ** 4 * m2l_pairs})
+    return (m2l, p2p) if dom == "M2L" else (p2p, m2l)
+
+
+def tree_pass(wl, res, precision):
+    """Algorithmic HBM bytes of the build, P2M (with the charge gather), L2P
+    and the combine, over their measured time (build: wall time of the
+    rebuild, which includes its one host wait)."""
+    info = res["info"]
+    n, nleaf = info["n"], info["n_leaves"]
+    S = (wl.p * wl.p + 7) // 8 * 8
+    inb = 12 if wl.dtype == "f32" else 24        # caller positions per particle
+    qb = 4 if wl.dtype == "f32" else 8           # caller charge / potential
+    rec = 32 if precision == "fp64" else 16      # sorted record
+    cb = 8 if precision == "fp64" else 4         # leaf-level coefficient
+    build = n * (inb + 8 + 12 + 4 + inb + 4 + rec)   # keys; place; fix-up
+    p2m = n * (rec + 4 + qb + 4) + nleaf * S * cb    # records, perm, charges -> M_L
+    l2p = n * (rec + 32) + nleaf * S * cb            # records, L_L -> far partials
+    comb = n * (32 + 32 + 4 + qb + qb + 3 * qb)      # near, far, perm, q -> phi, E
+    st = res["stages_ms"]
+    ms = res["build_ms"] + st["gather"] + st["P2M"] + st["L2P"] + st["combine"]
+    total = build + p2m + l2p + comb
+    return {"bytes": total, "ms": ms, "gbs": total / (ms * 1e-3) / 1e9,
+            "frac_hbm": total / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "build_ms": res["build_ms"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -122,6 +239,7 @@ def main():
         return
     import torch
 
+    import oracle
     import paper_1106_2176_amd as fmm
     from paper_1106_2176_amd import inputs
 
@@ -131,90 +249,76 @@ def main():
     pos = torch.from_numpy(pos_np).to(dev)
     q = torch.from_numpy(q_np).to(dev)
     sync = torch.cuda.synchronize
+    enc_kw = ENCODINGS[args.m2l][0]
 
-    def run_form(precision, steps, warmup):
-        phi = torch.empty_like(q)
-        E = torch.empty_like(pos)
-
-        def timed(stages, nsteps, nwarm):
-            tree = fmm.Tree(pos, p=wl.p, leaf_max=wl.leaf_max, precision=precision, profile=True,
-                            profile_stages=stages, bf16_splits=args.splits)
-
-            def step():
-                tree.rebuild(pos)
-                tree.evaluate(q, vec="field", phi=phi, out_vec=E)
-
-            for _ in range(nwarm):
-                step()
-            tree.stage_times_reset()
-            # stage times: library events over the timed steps (mean of the
-            # last min(steps, 32) of them)
-            sec = timed_steps(step, nsteps, 0, sync)
-            st = tree.stage_times()
-            info = tree.info()
-            tree.close()
-            return sec, st, info
-
-        # every stage, outside the timed region; it names the dominant stage
-        stages_ms = timed(None, max(5, steps // 2), max(1, warmup))[1]
-        dom = "M2L" if stages_ms["M2L"] >= stages_ms["P2P"] else "P2P"
-        # the timed steps: events only around the dominant (roofline) stage
-        sec, roof_st, info = timed((dom,), steps, warmup)
-        return {"sec": sec, "dom": dom, "dom_ms": roof_st[dom], "stages_ms": stages_ms, "info": info,
-                "phi": phi.clone(), "E": E.clone()}
-
-    mixed = run_form("mixed", args.steps, args.warmup)
+    mixed = measure(fmm, wl, pos, q, "mixed", args.steps, args.warmup, sync, **enc_kw)
     info = mixed["info"]
     n = wl.n
     value = n / mixed["sec"]
-    # the dominant stage's time from the events of the timed steps, the
-    # other's from the profiled run
-    dom = mixed["dom"]
-    p2p_ms = mixed["dom_ms"] if dom == "P2P" else mixed["stages_ms"]["P2P"]
-    m2l_ms = mixed["dom_ms"] if dom == "M2L" else mixed["stages_ms"]["M2L"]
     # the counter summaries were taken on the default workload only
-    on_profiled = args.workload == "C2" and args.splits == 3
+    on_profiled = args.workload == "C2"
+    roof, other = rooflines(wl, mixed, "mixed", args.m2l, on_profiled)
     pairs = info["p2p_pairs"]
-    m2l_pairs = info["m2l_pairs"]
-    p2p_tflops = P2P_FLOP_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
-    m2l_tflops = 2.0 * wl.p ** 4 * m2l_pairs / (m2l_ms * 1e-3) / 1e12
-    roof_p2p = {"kernel": "k_p2p<float>", "bound": "alu", "achieved": p2p_tflops,
-                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": p2p_tflops / PEAK_FP32_VECTOR_TFLOPS,
-                "traffic": traffic_from_profile("p2p.hip", "p2p_C2_traffic.txt") if on_profiled else None,
-                "ms": p2p_ms, "flop_per_launch": P2P_FLOP_PER_PAIR * pairs}
-    split_products = {3: 6, 2: 3}.get(args.splits, 6)
-    roof_m2l = {"kernel": "k_m2l_bf16<%d,%d>" % (args.splits, wl.p), "bound": "mfma",
-                "achieved": m2l_tflops, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": m2l_tflops / PEAK_BF16_MFMA_TFLOPS,
-                "traffic": traffic_from_profile("m2l.hip", "m2l_bf16_C2_traffic.txt") if on_profiled else None,
-                "ms": m2l_ms, "flop_per_launch": 2.0 * wl.p ** 4 * m2l_pairs,
-                "bf16_products_per_term": split_products}
-    roof = roof_m2l if dom == "M2L" else roof_p2p
+    p2p_ms = roof["ms"] if mixed["dom"] == "P2P" else other["ms"]
 
-    # accuracy on sampled targets vs the FP64 direct sum
-    t_idx = inputs.targets(n, wl.seed)
-    import oracle
-    phi_d, E_d = oracle.direct(pos_np, q_np, t_idx)
-
-    def errs(res):
-        ph = res["phi"].cpu().numpy()[t_idx]
-        Ef = res["E"].cpu().numpy()[t_idx]
-        qq = q_np[t_idx][:, None]
+    def errs(res, pos_np, q_np, t_idx, phi_d, E_d):
+        ph = res["phi"].cpu().numpy().astype(np.float64)[t_idx]
+        Ef = res["E"].cpu().numpy().astype(np.float64)[t_idx]
+        qq = q_np.astype(np.float64)[t_idx][:, None]
         return {"phi": float(np.linalg.norm(ph - phi_d) / np.linalg.norm(phi_d)),
                 "F": float(np.linalg.norm(qq * (Ef - E_d)) / np.linalg.norm(qq * E_d))}
 
-    rel = {"mixed_vs_direct": errs(mixed)}
+    def mixed_vs_fp64(a_res, b_res, q_np):
+        a, b = a_res["phi"].cpu().numpy(), b_res["phi"].cpu().numpy()
+        Ea, Eb = a_res["E"].cpu().numpy(), b_res["E"].cpu().numpy()
+        qq = q_np.astype(np.float64)[:, None]
+        return {"phi": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                "F": float(np.linalg.norm(qq * (Ea - Eb)) / np.linalg.norm(qq * Eb))}
+
+    # accuracy on sampled targets vs the FP64 direct sum
+    t_idx = inputs.targets(n, wl.seed)
+    phi_d, E_d = oracle.direct(pos_np.astype(np.float64), q_np.astype(np.float64), t_idx)
+    rel = {"mixed_vs_direct": errs(mixed, pos_np, q_np, t_idx, phi_d, E_d)}
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_form("fp64", max(3, args.steps // 4), 1)
-        rel["fp64_vs_direct"] = errs(fp64)
-        a, b = mixed["phi"].cpu().numpy(), fp64["phi"].cpu().numpy()
-        Ea, Eb = mixed["E"].cpu().numpy(), fp64["E"].cpu().numpy()
-        qq = q_np[:, None]
-        rel["mixed_vs_fp64_all"] = {
-            "phi": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
-            "F": float(np.linalg.norm(qq * (Ea - Eb)) / np.linalg.norm(qq * Eb))}
+        fp64 = measure(fmm, wl, pos, q, "fp64", max(3, args.steps // 4), 1, sync)
+        rel["fp64_vs_direct"] = errs(fp64, pos_np, q_np, t_idx, phi_d, E_d)
+        rel["mixed_vs_fp64_all"] = mixed_vs_fp64(mixed, fp64, q_np)
+
+    overlap = None
+    if not args.no_overlap:
+        ov = measure(fmm, wl, pos, q, "mixed", args.steps, args.warmup, sync, overlap_near=True, **enc_kw)
+        overlap = {"ms_per_step": ov["sec"] * 1e3, "particles_per_s": n / ov["sec"],
+                   "serial_ms_per_step": mixed["sec"] * 1e3,
+                   "p2p_ms_side_stream": ov["stages_ms"]["P2P"], "m2l_ms": ov["stages_ms"]["M2L"]}
+        del ov
+
+    c3 = None
+    if not args.no_c3 and args.workload != "C3":
+        w3 = inputs.WORKLOADS["C3"]
+        p3, q3 = inputs.workload("C3")
+        P3, Q3 = torch.from_numpy(p3).to(dev), torch.from_numpy(q3).to(dev)
+        m3 = measure(fmm, w3, P3, Q3, "mixed", max(5, args.steps // 2), 2, sync, **enc_kw)
+        r3, o3 = rooflines(w3, m3, "mixed", args.m2l, False)
+        t3 = inputs.targets(w3.n, w3.seed)
+        pd3, Ed3 = oracle.direct(p3, q3, t3)
+        c3 = {"workload": w3.describe(), "levels": m3["info"]["levels"],
+              "mixed": {"ms_per_step": m3["sec"] * 1e3, "particles_per_s": w3.n / m3["sec"],
+                        "p2p_gint_s": m3["info"]["p2p_pairs"] / (m3["stages_ms"]["P2P"] * 1e-3) / 1e9,
+                        "stages_ms": m3["stages_ms"], "roofline": r3,
+                        ("roofline_p2p" if m3["dom"] == "M2L" else "roofline_m2l"): o3,
+                        "tree_pass": tree_pass(w3, m3, "mixed")},
+              "rel_l2": {"mixed_vs_direct": errs(m3, p3, q3, t3, pd3, Ed3)}}
+        if not args.no_fp64:
+            f3 = measure(fmm, w3, P3, Q3, "fp64", 3, 1, sync)
+            r3f, o3f = rooflines(w3, f3, "fp64", None, False)
+            c3["fp64"] = {"ms_per_step": f3["sec"] * 1e3, "particles_per_s": w3.n / f3["sec"],
+                          "p2p_gint_s": f3["info"]["p2p_pairs"] / (f3["stages_ms"]["P2P"] * 1e-3) / 1e9,
+                          "stages_ms": f3["stages_ms"], "roofline": r3f}
+            c3["rel_l2"]["fp64_vs_direct"] = errs(f3, p3, q3, t3, pd3, Ed3)
+            c3["rel_l2"]["mixed_vs_fp64_all"] = mixed_vs_fp64(m3, f3, q3)
+            del f3
+        del m3, P3, Q3, p3, q3
 
     adj = None
     if not args.no_adjoint:
@@ -223,7 +327,7 @@ def main():
         wv = torch.from_numpy(inputs.weights(w5.n, w5.seed)).to(dev)
         P5 = torch.from_numpy(p5).to(dev)
         Q5 = torch.from_numpy(q5).to(dev)
-        tree5 = fmm.Tree(P5, p=w5.p, leaf_max=w5.leaf_max, precision="mixed")
+        tree5 = fmm.Tree(P5, p=w5.p, leaf_max=w5.leaf_max, precision="mixed", **enc_kw)
 
         def fb():
             tree5.rebuild(P5)
@@ -246,7 +350,7 @@ def main():
         small = {"workload": w1.describe()}
         for name, kw in (("eager", {}), ("graph", {"graph": True}),
                          ("graph_overlap", {"graph": True, "overlap_near": True})):
-            t1 = fmm.Tree(P1, p=w1.p, leaf_max=w1.leaf_max, precision="mixed", **kw)
+            t1 = fmm.Tree(P1, p=w1.p, leaf_max=w1.leaf_max, precision="mixed", **kw, **enc_kw)
 
             def ev():
                 t1.evaluate(Q1, vec="field", phi=phi1, out_vec=E1)
@@ -283,24 +387,29 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+bf16(split)+f64",
+        "dtype": "f32+%s+f64" % args.m2l,
         "data": "synthetic",
-        "config": {"workload": wl.describe(), "form": "mixed", "bf16_splits": args.splits,
+        "config": {"workload": wl.describe(), "form": "mixed", "m2l_encoding": args.m2l,
                    "levels": info["levels"],
-                   "p2p_pairs": pairs, "m2l_pairs": m2l_pairs},
+                   "p2p_pairs": pairs, "m2l_pairs": info["m2l_pairs"]},
         "p2p_gint_s": pairs / (p2p_ms * 1e-3) / 1e9,
         "stages_ms": mixed["stages_ms"],
         "roofline": roof,
-        ("roofline_p2p" if dom == "M2L" else "roofline_m2l"): roof_p2p if dom == "M2L" else roof_m2l,
+        ("roofline_p2p" if mixed["dom"] == "M2L" else "roofline_m2l"): other,
+        "tree_pass": tree_pass(wl, mixed, "mixed"),
         "rel_l2": rel,
+        "overlap": overlap,
+        "c3": c3,
         "cpu_baseline": cpu,
         "adjoint": adj,
         "small": small,
     }
     if fp64 is not None:
+        r64, o64 = rooflines(wl, fp64, "fp64", None, False)
         line["fp64"] = {"particles_per_s": n / fp64["sec"], "ms_per_step": fp64["sec"] * 1e3,
                         "p2p_gint_s": pairs / (fp64["stages_ms"]["P2P"] * 1e-3) / 1e9,
-                        "stages_ms": fp64["stages_ms"]}
+                        "stages_ms": fp64["stages_ms"], "roofline": r64,
+                        ("roofline_p2p" if fp64["dom"] == "M2L" else "roofline_m2l"): o64}
     print(json.dumps(line), flush=True)
 
 

@@ -81,11 +81,11 @@ typedef struct {
                                   none does) */
     int32_t max_level;         /* 0..10; keys are 3*level <= 30 bits */
     int32_t precision;         /* fmm_precision */
-    int32_t bf16_splits;       /* mixed form only: 2 (hi+lo, 3 MFMA products) or
-                                  3 (hi+mid+lo, 6 products); 0 selects 3.  The
-                                  mixed form supports p <= 13 with 3 parts and
-                                  p <= 10 with 2 parts (FMM_EUNSUPPORTED
-                                  otherwise: use the FP64 form) */
+    int32_t bf16_splits;       /* mixed form with m2l_fp16 = 0 only: the M2L
+                                  operands in 2 (hi+lo, 3 MFMA products) or 3
+                                  (hi+mid+lo, 6 products) bf16 parts; 0 selects
+                                  3.  Supports p <= 13 with 3 parts and p <= 10
+                                  with 2 parts (FMM_EUNSUPPORTED otherwise) */
     double box_lo[3];          /* root cube corner */
     double box_size;           /* root cube edge, > 0 */
     fmm_alloc_fn alloc;        /* optional, see above */
@@ -112,11 +112,22 @@ typedef struct {
                                   launch the graph on their stream.  Same kernels,
                                   same results.  Exclusive with `profile`
                                   (FMM_EINVAL). */
-    int32_t reserved[4];       /* zero */
+    int32_t m2l_fp16;          /* mixed form only: nonzero = the M2L operands in
+                                  two IEEE binary16 parts (3 MFMA products, about
+                                  22 bits per operand) instead of bf16_splits
+                                  bf16 parts.  Operators and multipoles are
+                                  scaled degree by degree by powers of two (the
+                                  size of the regular harmonics over a box), the
+                                  multipoles also per level by the power of two
+                                  that puts the level's largest one just below
+                                  2^14; the results are scaled back exactly.
+                                  Supports every p <= 16. */
+    int32_t reserved[3];       /* zero */
 } fmm_config;
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
- * precision, 3 bf16 splits, root cube [0,1)^3, library allocator, no
+ * precision with the binary16 M2L encoding (m2l_fp16 = 1; bf16_splits = 3
+ * when it is switched off), root cube [0,1)^3, library allocator, no
  * profiling. */
 void fmm_config_default(fmm_config *cfg);
 

@@ -68,7 +68,14 @@ struct Ops {
     // of a row tile reads one contiguous kilobyte); forward and adjoint
     double *m2l64 = nullptr, *am2l64 = nullptr;
     uint16_t *m2lbf = nullptr, *am2lbf = nullptr;
-    size_t bf_part = 0;  // elements per bf16 part
+    size_t bf_part = 0;  // elements per bf16 (and binary16) part
+    // binary16 encoding: a_r T rho_c in two binary16 parts, same layout as
+    // the bf16 parts, with rho_c the harmonic size of coefficient c's degree
+    // and a_r a power of two per row and table; rho_inv[c] = 1 / rho_c (the
+    // pack's scale), oscale / aoscale[r] = 1 / a_r of the forward / adjoint
+    // table (the M2L output's)
+    uint16_t *m2lh = nullptr, *am2lh = nullptr;
+    float *rho_inv = nullptr, *oscale = nullptr, *aoscale = nullptr;
     int2 *cls = nullptr; // [8][189] (packed source offset, table id)
 };
 
@@ -187,6 +194,51 @@ fmm_status build_ops(int p, Ops **out) {
     }
     UP64(m2l64, f64) UP64(am2l64, af64) UP64(m2lbf, fbf) UP64(am2lbf, afbf)
     UP64(cls, cls)
+    {
+        // binary16 tables: columns scaled by the harmonic size rho_c of their
+        // degree (the multipoles are divided by it), each row by the power of
+        // two a_r that puts the row's largest entry just below 2^14, so that
+        // the low part of every entry that matters stays a normal binary16
+        // number and no entry overflows (binary16 ends at 65520)
+        double rho[FMM_P_MAX];
+        harmonic_scale(p, rho);
+        std::vector<double> rc(S, 0.0);
+        std::vector<float> rinv(S, 0.0f), osc(S, 0.0f), aosc(S, 0.0f);
+        for (int c = 0; c < P2; ++c) {
+            int n = 0;
+            while ((n + 1) * (n + 1) <= c) ++n;
+            rc[c] = rho[n];
+            rinv[c] = (float)(1.0 / rho[n]);
+        }
+        auto encode = [&](const std::vector<double> &tab, std::vector<uint16_t> &out,
+                          std::vector<float> &oscale) {
+            std::vector<double> a(R, 0.0);
+            for (int r = 0; r < P2; ++r) {
+                double mx = 0.0;
+                for (size_t id = 0; id < (size_t)kNumOffsets; ++id)
+                    for (int c = 0; c < P2; ++c)
+                        mx = std::max(mx, std::fabs(tab[(id * R + r) * S + c]) * rc[c]);
+                int ex = 0;
+                (void)std::frexp(mx, &ex);  // mx < 2^ex
+                a[r] = mx > 0.0 ? std::ldexp(1.0, 14 - ex) : 1.0;
+                oscale[r] = (float)(1.0 / a[r]);
+            }
+            out.assign(2 * nT, 0);
+            for (size_t i = 0; i < nT; ++i) {
+                const size_t id = i / ((size_t)R * S), rem = i % ((size_t)R * S);
+                const int row = (int)(rem / S), col = (int)(rem % S);
+                const size_t j = id * R * S + (((size_t)(row / 16) * PPO + col / 8) * 16 + row % 16) * 8 + col % 8;
+                uint16_t pt[2];
+                split_f16(tab[i] * a[row] * rc[col], pt);
+                out[j] = pt[0];
+                out[nT + j] = pt[1];
+            }
+        };
+        std::vector<uint16_t> fh, afh;
+        encode(f64, fh, osc);
+        encode(af64, afh, aosc);
+        UP64(m2lh, fh) UP64(am2lh, afh) UP64(rho_inv, rinv) UP64(oscale, osc) UP64(aoscale, aosc)
+    }
 #undef UP64
     (void)tb;
     if (e != hipSuccess) return fail(FMM_EDEVICE, std::string("operator upload: ") + hipGetErrorString(e));
@@ -226,7 +278,8 @@ struct fmm_tree {
     int ncu = 0;  // compute units of the device
     hipStream_t stream = nullptr;
     Alloc al;
-    Buf key10, rank, cnt, start, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs, m2lpart;
+    Buf key10, rank, cnt, start, tmp, perm, scan, counters, xyz32, xyz64, nearf, farf, pairs, m2lpart,
+        lmax;
     hipEvent_t ev_counters = nullptr;  // after the copy of the build counters
     Buf M[FMM_MAX_LEVEL + 1], Lc[FMM_MAX_LEVEL + 1], pack[FMM_MAX_LEVEL + 1];
     unsigned int *host_counters = nullptr;  // pinned [4]
@@ -256,9 +309,13 @@ struct Work {
     void *pack[FMM_MAX_LEVEL + 1] = {};                            // M2L operand grids
     double *m2lpart = nullptr;                                     // M2L K-split partial sums
     size_t m2lpart_bytes = 0;
+    uint32_t *lmax = nullptr;  // per-level maxima of the binary16 M2L encoding
 };
 
 bool is_f64_form(const fmm_tree *t) { return t->cfg.precision == FMM_PREC_FP64; }
+
+// the mixed form's M2L in the binary16 encoding
+bool m2l_half(const fmm_config &c) { return c.precision == FMM_PREC_MIXED && c.m2l_fp16 != 0; }
 
 // bf16 parts of the mixed M2L (0 selects the default, 3)
 int split_parts(const fmm_config &c) { return c.bf16_splits == 2 ? 2 : 3; }
@@ -275,7 +332,7 @@ int level_f64(const fmm_tree *t, int l) {
 // Byte sizes of the per-call buffers (the far-field ones are zero without a
 // far field, L < 2).
 struct WorkSizes {
-    size_t nearf = 0, farf = 0, m2lpart = 0;
+    size_t nearf = 0, farf = 0, m2lpart = 0, lmax = 0;
     size_t M[FMM_MAX_LEVEL + 1] = {}, Lc[FMM_MAX_LEVEL + 1] = {}, pack[FMM_MAX_LEVEL + 1] = {};
 };
 
@@ -294,6 +351,7 @@ WorkSizes work_sizes(const fmm_tree *t, bool far) {
         z.pack[l] = g * g * g * S * (f64 ? 8 : 4);
     }
     z.m2lpart = m2l_partial_bytes(P, L, f64, t->ncu);
+    if (m2l_half(t->cfg)) z.lmax = sizeof(uint32_t) * kLevelSlots;
     return z;
 }
 
@@ -347,9 +405,10 @@ fmm_status validate_cfg(const fmm_config *c) {
         return fail(FMM_EINVAL, "unknown precision");
     if (c->bf16_splits != 0 && c->bf16_splits != 2 && c->bf16_splits != 3)
         return fail(FMM_EINVAL, "bf16_splits must be 0, 2 or 3");
-    if (c->precision == FMM_PREC_MIXED && c->bf16_splits != 2 && c->p > kMixedSplit3PMax)
+    const bool bf16 = c->precision == FMM_PREC_MIXED && !c->m2l_fp16;
+    if (bf16 && c->bf16_splits != 2 && c->p > kMixedSplit3PMax)
         return fail(FMM_EUNSUPPORTED, "the mixed form with a 3-part split supports p <= 13");
-    if (c->precision == FMM_PREC_MIXED && c->bf16_splits == 2 && c->p > kMixedSplit2PMax)
+    if (bf16 && c->bf16_splits == 2 && c->p > kMixedSplit2PMax)
         return fail(FMM_EUNSUPPORTED, "the mixed form with a 2-part bf16 split supports p <= 10 "
                                       "(above it the force misses the 1e-6 budget)");
     if (!(c->box_size > 0.0) || !std::isfinite(c->box_size)) return fail(FMM_EINVAL, "box_size must be > 0");
@@ -411,6 +470,10 @@ fmm_status work_from_tree(fmm_tree *t, bool far, hipStream_t st, Work &w) {
         w.m2lpart = (double *)t->m2lpart.p;
         w.m2lpart_bytes = t->m2lpart.cap;
     }
+    if (z.lmax) {
+        CHK(ensure(t, t->lmax, z.lmax, st));
+        w.lmax = (uint32_t *)t->lmax.p;
+    }
     return FMM_OK;
 }
 
@@ -425,7 +488,8 @@ fmm_status work_from_scratch(fmm_tree *t, bool far, Work &w) {
         off += (bytes + 255) & ~(size_t)255;
         return at;
     };
-    const size_t o_near = take(z.nearf), o_far = take(z.farf), o_part = take(z.m2lpart);
+    const size_t o_near = take(z.nearf), o_far = take(z.farf), o_part = take(z.m2lpart),
+                 o_lmax = take(z.lmax);
     size_t oM[FMM_MAX_LEVEL + 1] = {}, oL[FMM_MAX_LEVEL + 1] = {}, oP[FMM_MAX_LEVEL + 1] = {};
     for (int l = 2; l <= t->L && z.farf; ++l) {
         oM[l] = take(z.M[l]);
@@ -445,6 +509,7 @@ fmm_status work_from_scratch(fmm_tree *t, bool far, Work &w) {
         w.m2lpart = (double *)(base + o_part);
         w.m2lpart_bytes = z.m2lpart;
     }
+    if (z.lmax) w.lmax = (uint32_t *)(base + o_lmax);
     for (int l = 2; l <= t->L; ++l) {
         w.M[l] = base + oM[l];
         w.Lc[l] = base + oL[l];
@@ -502,7 +567,8 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
         CHK(rec(t, 1, st));
         // P2M at the leaves (for the adjoint: L2P^T, the same sum with w)
         HIPCHK(launch_p2m(P, L, f64, src, start, w.M[L], 1.0,
-                          p2m_gathers ? (const uint32_t *)t->perm.p : nullptr, charges, t->dtype, st));
+                          p2m_gathers ? (const uint32_t *)t->perm.p : nullptr, charges, t->dtype,
+                          w.lmax, st));
         CHK(rec(t, 2, st));
         // upward sweep (adjoint: L2L^T)
         for (int l = L - 1; l >= 2; --l)
@@ -513,6 +579,8 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
         {
             PackPlan pk{};
             pk.nlev = L - 1;
+            pk.lmax = w.lmax;
+            pk.rho_inv = o->rho_inv;
             for (int l = 2; l <= L; ++l) {
                 const int i = l - 2;
                 const int64_t g = ((int64_t)1 << l) + 6;
@@ -534,10 +602,13 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
                 Lp[l] = w.Lc[l];
                 of64[l] = level_f64(t, l);
             }
-            const void *A = f64 ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
-                                : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
-            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, o->bf_part, o->cls,
-                              w.m2lpart, w.m2lpart_bytes, t->ncu, st));
+            const bool half = m2l_half(t->cfg);
+            const void *A = f64    ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
+                            : half ? (const void *)(adjoint ? o->am2lh : o->m2lh)
+                                   : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
+            const M2LHalf hv{w.lmax, adjoint ? o->aoscale : o->oscale};
+            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, o->bf_part, o->cls, w.m2lpart,
+                              w.m2lpart_bytes, t->ncu, half ? &hv : nullptr, st));
         }
         CHK(rec(t, 5, st));
         // downward sweep (adjoint: M2M^T)
@@ -660,6 +731,7 @@ void fmm_config_default(fmm_config *c) {
     c->max_level = FMM_MAX_LEVEL;
     c->precision = FMM_PREC_MIXED;
     c->bf16_splits = 3;
+    c->m2l_fp16 = 1;
     c->box_size = 1.0;
 }
 
@@ -695,9 +767,9 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
         const fmm_config &o = t->cfg;
         const bool mixed = cfg->precision == FMM_PREC_MIXED;
         if (o.p != cfg->p || o.precision != cfg->precision || t->dtype != dtype ||
-            (mixed && split_parts(o) != split_parts(*cfg)))
-            return fail(FMM_EINVAL, "a tree is rebuilt only with the p, precision, bf16_splits and "
-                                    "dtype it was created with");
+            (mixed && (split_parts(o) != split_parts(*cfg) || !o.m2l_fp16 != !cfg->m2l_fp16)))
+            return fail(FMM_EINVAL, "a tree is rebuilt only with the p, precision, M2L encoding "
+                                    "(bf16_splits, m2l_fp16) and dtype it was created with");
         if (o.alloc != cfg->alloc || o.free != cfg->free || o.alloc_ctx != cfg->alloc_ctx)
             return fail(FMM_EINVAL, "a tree is rebuilt only with the allocator it was created with");
     }
@@ -889,7 +961,7 @@ fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
     info->m2l_pairs = m2l;
     size_t ws = 0;
     const Buf *bufs[] = {&t->key10, &t->rank, &t->cnt, &t->start, &t->tmp, &t->perm, &t->scan,
-                         &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};
+                         &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart, &t->lmax};
     for (const Buf *b : bufs) ws += b->cap;
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) ws += t->M[l].cap + t->Lc[l].cap + t->pack[l].cap;
     info->workspace_bytes = ws;
@@ -944,7 +1016,7 @@ void fmm_tree_destroy(fmm_tree *t) {
     if (t->cap) (void)hipStreamDestroy(t->cap);
     hipStream_t st = t->stream;
     Buf *bufs[] = {&t->key10, &t->rank, &t->cnt, &t->start, &t->tmp, &t->perm, &t->scan,
-                   &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart};
+                   &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart, &t->lmax};
     for (Buf *b : bufs) release(t, *b, st);
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) {
         release(t, t->M[l], st);

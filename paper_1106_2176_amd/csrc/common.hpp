@@ -17,6 +17,8 @@ __host__ __device__ constexpr int cidx(int n, int m) { return n * n + (m == 0 ? 
 // Coefficient stride of a box in device arrays: p^2 rounded up to 8, so that
 // an 8-wide bf16 MFMA operand piece never straddles two boxes.
 __host__ __device__ constexpr int coef_stride(int p) { return (p * p + 7) & ~7; }
+// Largest coefficient stride (p = FMM_P_MAX).
+constexpr int kMaxStride = (FMM_P_MAX * FMM_P_MAX + 7) & ~7;
 // Rows of an M2L operator: p^2 rounded up to the 16-row MFMA tile.
 __host__ __device__ constexpr int m2l_rows(int p) { return (p * p + 15) & ~15; }
 
@@ -103,6 +105,24 @@ __host__ __device__ inline void regular_rho(int P, T x, T y, T z, T *rho) {
             }
         }
     }
+}
+
+// -------------------------------------------- binary16 M2L encoding scale
+// Per-level maxima of the binary16 M2L encoding: one 32-bit slot per level.
+constexpr int kLevelSlots = FMM_MAX_LEVEL + 1;
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+// Exponent e of the power-of-two scale 2^e that puts a level's largest
+// scaled multipole (float bits `mx_bits`, non-negative) just below 2^14, so
+// that its binary16 parts and their products stay in range; 0 for an
+// all-zero level.  The pack kernel multiplies by 2^e, the M2L kernel divides
+// its results by it.
+__host__ __device__ inline int level_scale_exp(uint32_t mx_bits) {
+    const float mx = __builtin_bit_cast(float, mx_bits);
+    if (!(mx > 0.0f)) return 0;
+    int e = 0;
+    (void)frexpf(mx, &e);  // mx < 2^e
+    return 14 - e;
 }
 
 // ----------------------------------------------------- particle records

@@ -108,7 +108,11 @@ template <int P, typename T>
 __global__ __launch_bounds__(64) void k_p2m(int L, typename V4T<T>::type *__restrict__ src,
                                             const uint32_t *__restrict__ start, T *__restrict__ M,
                                             double scale, const uint32_t *__restrict__ perm,
-                                            const void *__restrict__ qin, int q64) {
+                                            const void *__restrict__ qin, int q64,
+                                            uint32_t *__restrict__ clear) {
+    // clear the per-level maxima that the level-max kernel (after M2M)
+    // accumulates into
+    if (clear && blockIdx.x == 0 && threadIdx.x < kLevelSlots) clear[threadIdx.x] = 0u;
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
     constexpr int RS = p2m_rows<P, T>();
@@ -490,6 +494,56 @@ __device__ __forceinline__ void pack_row(int P, int n, int y, int z, const Tin *
     }
 }
 
+// 8 consecutive coefficients (a 32-byte aligned FP32 piece or a 64-byte
+// aligned FP64 one) as FP32, in 16-byte loads
+__device__ __forceinline__ void load8(const float *p, float (&v)[8]) {
+    const float4 a = ((const float4 *)p)[0], b = ((const float4 *)p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void load8(const double *p, float (&v)[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 d = ((const double2 *)p)[k];
+        v[2 * k] = (float)d.x;
+        v[2 * k + 1] = (float)d.y;
+    }
+}
+
+// binary16 encoding: one thread per 8-coefficient piece of a padded box; the
+// piece is scaled (x rho_inv[c] x 2^e, e from the level's maximum) and split
+// into two binary16 parts, stored hi8 then lo8 (32 bytes, the bytes of the
+// FP32 piece it replaces).  Padding coefficients (rinv = 0 there) and halo
+// boxes are zero.
+template <typename Tin>
+__device__ __forceinline__ void pack_row_h(int P, int n, int y, int z, const Tin *__restrict__ in,
+                                           uint4 *__restrict__ orow, const float *rinv, float scale) {
+    const int S = coef_stride(P), S8 = S / 8, g = n + 6;
+    const bool yz = y >= 0 && z >= 0 && y < n && z < n;
+    for (int e8 = threadIdx.x; e8 < g * S8; e8 += blockDim.x) {
+        const int bx = e8 / S8, c = 8 * (e8 - bx * S8), x = bx - 3;
+        float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (yz && x >= 0 && x < n) {
+            load8(in + ((size_t)x + (size_t)n * ((size_t)y + (size_t)n * z)) * S + c, v);
+            // padding coefficients are never written: select, do not multiply
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = rinv[c + k] != 0.0f ? v[k] * (rinv[c + k] * scale) : 0.0f;
+        }
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const f32x2_t a = {v[2 * k], v[2 * k + 1]};
+            const f16x2_t h = __builtin_convertvector(a, f16x2_t);
+            const f16x2_t lo = __builtin_convertvector(a - __builtin_convertvector(h, f32x2_t), f16x2_t);
+            hw[k] = __builtin_bit_cast(uint32_t, h);
+            lw[k] = __builtin_bit_cast(uint32_t, lo);
+        }
+        uint4 *dst = orow + 2 * ((size_t)bx * S8 + c / 8);
+        dst[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        dst[1] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+}
+
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_pack(int P, PackPlan pl) {
     const int64_t b = blockIdx.x;
@@ -516,10 +570,79 @@ __global__ __launch_bounds__(256) void k_pack(int P, PackPlan pl) {
     const int row = (int)(b - r0);  // z g + y of the padded grid (< 2^31)
     const int y = row % g - 3, z = row / g - 3;
     Tout *orow = (Tout *)out + (size_t)row * g * coef_stride(P);
-    if (in_f64)
+    if (pl.lmax) {  // binary16 parts (Tout = float: the same bytes per piece)
+        __shared__ float rinv[kMaxStride];
+        for (int c = threadIdx.x; c < coef_stride(P); c += blockDim.x) rinv[c] = pl.rho_inv[c];
+        __syncthreads();
+        const float scale = ldexpf(1.0f, level_scale_exp(pl.lmax[l]));
+        if (in_f64)
+            pack_row_h(P, n, y, z, (const double *)in, (uint4 *)orow, rinv, scale);
+        else
+            pack_row_h(P, n, y, z, (const float *)in, (uint4 *)orow, rinv, scale);
+    } else if (in_f64)
         pack_row(P, n, y, z, (const double *)in, orow);
     else
         pack_row(P, n, y, z, (const float *)in, orow);
+}
+
+// Largest |M_c rho_inv[c]| over the boxes of each level 2..L (binary16
+// encoding of the M2L operands), as an atomic maximum on the float's bits
+// (non-negative floats order like their bit patterns) into lmax[level],
+// which P2M cleared.  Block b covers kLevelMaxChunk consecutive elements of
+// the level whose blocks it falls in, four (one 16-byte load, within one
+// box) per thread and step; padding coefficients (c >= p^2, never written)
+// are skipped.
+constexpr int kLevelMaxChunk = 256 * 32;
+__global__ __launch_bounds__(256) void k_level_max(int P, PackPlan pl) {
+    const int64_t b = blockIdx.x;
+    int li = 0;
+#pragma unroll
+    for (int j = 1; j < kMaxPackLev; ++j)
+        if (j < pl.nlev && b >= pl.blk0[j]) li = j;
+    int l = pl.level[0], in_f64 = pl.in_f64[0];
+    int64_t b0 = pl.blk0[0];
+    const void *in = pl.in[0];
+#pragma unroll
+    for (int j = 1; j < kMaxPackLev; ++j)
+        if (j == li) {
+            l = pl.level[j];
+            in_f64 = pl.in_f64[j];
+            b0 = pl.blk0[j];
+            in = pl.in[j];
+        }
+    __shared__ float rinv[kMaxStride];
+    const int S = coef_stride(P), P2 = P * P, S4 = S / 4;
+    for (int c = threadIdx.x; c < S; c += 256) rinv[c] = c < P2 ? pl.rho_inv[c] : 0.0f;
+    __syncthreads();
+    const int64_t ng = ((int64_t)1 << (3 * l)) * S4;  // 4-element groups of the level
+    const int64_t g0 = (b - b0) * (kLevelMaxChunk / 4), g1 = min(ng, g0 + kLevelMaxChunk / 4);
+    int cg = (int)((g0 + threadIdx.x) % S4);  // group's position in its box
+    const int step = 256 % S4;
+    float mx = 0.0f;
+    for (int64_t gi = g0 + threadIdx.x; gi < g1; gi += 256) {
+        float v[4];
+        if (in_f64) {
+            const double2 d0 = ((const double2 *)in)[2 * gi], d1 = ((const double2 *)in)[2 * gi + 1];
+            v[0] = (float)d0.x; v[1] = (float)d0.y; v[2] = (float)d1.x; v[3] = (float)d1.y;
+        } else {
+            const float4 f = ((const float4 *)in)[gi];
+            v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (4 * cg + k < P2) mx = fmaxf(mx, fabsf(v[k]) * rinv[4 * cg + k]);
+        cg += step;
+        if (cg >= S4) cg -= S4;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    __shared__ float wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        atomicMax(pl.lmax + l, __float_as_uint(mx));
+    }
 }
 
 // ------------------------------------------------------------ gather/combine
@@ -589,12 +712,12 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 template <typename T>
 static hipError_t p2m_dispatch(int P, int L, void *src, const uint32_t *start, T *M,
                                double scale, const uint32_t *perm, const void *q, int q64,
-                               hipStream_t st) {
+                               uint32_t *clear, hipStream_t st) {
     const unsigned g = ((1u << (3 * L)) + 1) / 2;  // two leaves per block
     using V = typename V4T<T>::type;
     switch (P) {
 #define CASE(PP) \
-    case PP: k_p2m<PP, T><<<g, 64, 0, st>>>(L, (V *)src, start, M, scale, perm, q, q64); break;
+    case PP: k_p2m<PP, T><<<g, 64, 0, st>>>(L, (V *)src, start, M, scale, perm, q, q64, clear); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
@@ -605,10 +728,10 @@ static hipError_t p2m_dispatch(int P, int L, void *src, const uint32_t *start, T
 
 hipError_t launch_p2m(int P, int L, bool f64, void *src, const uint32_t *start, void *M,
                       double scale, const uint32_t *perm, const void *q, int q_dtype,
-                      hipStream_t st) {
+                      uint32_t *clear, hipStream_t st) {
     const int q64 = q_dtype == FMM_F64;
-    return f64 ? p2m_dispatch<double>(P, L, src, start, (double *)M, scale, perm, q, q64, st)
-               : p2m_dispatch<float>(P, L, src, start, (float *)M, scale, perm, q, q64, st);
+    return f64 ? p2m_dispatch<double>(P, L, src, start, (double *)M, scale, perm, q, q64, clear, st)
+               : p2m_dispatch<float>(P, L, src, start, (float *)M, scale, perm, q, q64, clear, st);
 }
 
 template <typename T>
@@ -682,8 +805,22 @@ hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, cons
 }
 
 // f64_out: FP64 grid (plain form); otherwise FP32 (mixed form)
-hipError_t launch_pack(int P, bool f64_out, const PackPlan &pl, hipStream_t st) {
-    if (pl.nlev < 1 || pl.nlev > kMaxPackLev) return hipErrorInvalidValue;
+hipError_t launch_pack(int P, bool f64_out, const PackPlan &pl_in, hipStream_t st) {
+    if (pl_in.nlev < 1 || pl_in.nlev > kMaxPackLev) return hipErrorInvalidValue;
+    if (pl_in.lmax && (f64_out || !pl_in.rho_inv)) return hipErrorInvalidValue;
+    PackPlan pl = pl_in;
+    if (pl.lmax) {
+        // the binary16 scale of each level needs its maximum first
+        int64_t nb = 0;
+        for (int i = 0; i < pl.nlev; ++i) {
+            pl.blk0[i] = nb;
+            nb += ((((int64_t)1 << (3 * pl.level[i])) * coef_stride(P)) + kLevelMaxChunk - 1) / kLevelMaxChunk;
+        }
+        pl.blk0[pl.nlev] = nb;
+        k_level_max<<<(unsigned)nb, 256, 0, st>>>(P, pl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const unsigned rows = (unsigned)pl.row0[pl.nlev];
     if (f64_out)
         k_pack<double><<<rows, 256, 0, st>>>(P, pl);

@@ -37,25 +37,33 @@ hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, d
 // far.hip
 // P2M at the leaves; with perm non-NULL it first stores each particle's
 // charge q[perm[i]] (caller dtype q_dtype) into its sorted record i
+// clear (optional): the kLevelSlots per-level maxima of the binary16 M2L
+// encoding, zeroed by P2M's first block
 hipError_t launch_p2m(int P, int L, bool f64, void *src, const uint32_t *start, void *M,
                       double scale, const uint32_t *perm, const void *q, int q_dtype,
-                      hipStream_t st);
+                      uint32_t *clear, hipStream_t st);
 hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *start,
                       const void *Lc, double4 *out, hipStream_t st);
 hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
                            void *out, const void *tab32, const void *tab64, hipStream_t st);
 // M2L operand grids of levels 2..L in one launch; level i of the plan:
 // multipoles in[i] (FP64 when in_f64[i]) -> padded grid out[i] (FP64 when
-// f64_out, else FP32); row0 = first padded row of each level, row0[nlev] =
-// all rows
+// f64_out, else FP32, or with lmax the binary16 parts of the scaled
+// multipoles); row0 = first padded row of each level, row0[nlev] = all rows.
+// With lmax (kLevelSlots words, indexed by level, cleared beforehand) a
+// first kernel takes each level's largest |M_c rho_inv[c]|, from which the
+// level's power-of-two scale follows (level_scale_exp).
 constexpr int kMaxPackLev = FMM_MAX_LEVEL;
 struct PackPlan {
     int nlev;
     int level[kMaxPackLev];
     int in_f64[kMaxPackLev];
     int64_t row0[kMaxPackLev + 1];
+    int64_t blk0[kMaxPackLev + 1];  // filled by launch_pack
     const void *in[kMaxPackLev];
     void *out[kMaxPackLev];
+    uint32_t *lmax;                 // NULL: FP32 / FP64 grids
+    const float *rho_inv;           // [S]: 1 / rho of each coefficient's degree
 };
 hipError_t launch_pack(int P, bool f64_out, const PackPlan &pl, hipStream_t st);
 hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm, const void *q,
@@ -82,8 +90,18 @@ constexpr int kMixedSplit3PMax = 13;  // LDS holds the 3-part operator ring up t
 // within 1e-6 of the FP64 form up to p = 10 only (measured 1.2e-6 at
 // p = 11 and 16).
 constexpr int kMixedSplit2PMax = 10;
+// Binary16 encoding of the mixed form (half != NULL): A = the two binary16
+// parts of a_r T rho_c (same layout as the bf16 parts), B[l] = the pack
+// kernel's binary16 parts of the multipoles times 1/rho_c and the level
+// scale 2^e_l; row r of the result is multiplied by oscale[r] 2^-e_l, with
+// oscale[r] = 1/a_r.
+struct M2LHalf {
+    const uint32_t *lmax;   // per-level maxima (by level) of the scaled multipoles
+    const float *oscale;    // [S]
+};
 hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
-                      const int *out_f64, const void *A, size_t astride, const int2 *cls, double *partial, size_t partial_bytes, int ncu,
+                      const int *out_f64, const void *A, size_t astride, const int2 *cls,
+                      double *partial, size_t partial_bytes, int ncu, const M2LHalf *half,
                       hipStream_t st);
 
 }  // namespace fmm

@@ -75,6 +75,10 @@ struct M2LPlan {
     void *L[kMaxLev];            // local expansions of the level
     int out_f64[kMaxLev];
     int64_t fix0[kMaxLev + 1];   // first fix-up block of each level
+    // binary16 encoding: per-level maxima (by level) from which the operand
+    // scale follows, and the output scale of each row
+    const uint32_t *lmax;
+    const float *oscale;
 };
 
 struct M2LUnit {
@@ -165,7 +169,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // bf16 parts of 8 FP32 values (one MFMA operand piece), hardware
 // v_cvt_pk_bf16_f32 (round to nearest even) on what the previous parts leave
@@ -185,6 +189,31 @@ __device__ __forceinline__ void split8(const float4 lo4, const float4 hi4, bf16x
         }
         out[s] = __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
     }
+}
+
+// Multipole operand parts of one 8-wide piece: the bf16 split of the FP32
+// values, or (binary16 encoding, H) the two parts the pack kernel stored,
+// hi8 in the piece's first 16 bytes and lo8 in the second.
+template <int NSPLIT, bool H>
+__device__ __forceinline__ void b_parts(const float4 a, const float4 b, bf16x8 (&out)[NSPLIT]) {
+    if constexpr (H) {
+        static_assert(NSPLIT == 2, "the binary16 encoding has two parts");
+        out[0] = __builtin_bit_cast(bf16x8, a);
+        out[1] = __builtin_bit_cast(bf16x8, b);
+    } else {
+        split8<NSPLIT>(a, b, out);
+    }
+}
+
+// One 16x16x32 product on the matrix cores, bf16 or binary16 operands
+// (both held as 16-byte fragments), FP32 accumulation.
+template <bool H>
+__device__ __forceinline__ f32x4 mfma32(const bf16x8 a, const bf16x8 b, const f32x4 c) {
+    if constexpr (H)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 template <int I, int N, typename F>
@@ -233,7 +262,7 @@ struct MixCfg {
 // offsets, and one contiguous kilobyte of LDS for the wave's fragment read.
 // All loads are unconditional: pieces past the end read the zero operator
 // and the zero box.
-template <int NSPLIT, int P, int NW>
+template <int NSPLIT, int P, int NW, bool H>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4))) void k_m2l_bf16(
     M2LPlan pl, const uint16_t *__restrict__ A, size_t astride, const int2 *__restrict__ cls,
     double *__restrict__ partial) {
@@ -383,7 +412,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     lds_barrier();
     if constexpr (NW != 8) read_a(stage(std::integral_constant<int, 0>{}), af);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[0][b][0], bv[0][b][1], bf[b]);
+    for (int b = 0; b < NB; ++b) b_parts<NSPLIT, H>(bv[0][b][0], bv[0][b][1], bf[b]);
 
     // A fragments of split part sp of a stage
     auto read_part = [&](const uint4 *st, int sp, bf16x8 (&ap)[RT]) __attribute__((always_inline)) {
@@ -401,7 +430,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
         bf16x8 ap[2][RT], bn[NB][NSPLIT];
         read_part(cur, NSPLIT - 1, ap[0]);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[dn][b][0], bv[dn][b][1], bn[b]);
+        for (int b = 0; b < NB; ++b) b_parts<NSPLIT, H>(bv[dn][b][0], bv[dn][b][1], bn[b]);
         // A parts from the smallest; within a part, the small B parts first
         static_for<0, NSPLIT>([&](auto jc) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value, a = NSPLIT - 1 - j;
@@ -412,7 +441,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
                 for (int r = 0; r < RT; ++r)
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
-                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[j & 1][r], bf[b][t], acc[r][b], 0, 0, 0);
+                        acc[r][b] = mfma32<H>(ap[j & 1][r], bf[b][t], acc[r][b]);
         });
         issue_b(kc + D, bv[d]);
 #pragma unroll
@@ -432,7 +461,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
         bf16x8 an[RT][NSPLIT], bn[NB][NSPLIT];
         read_a(nxt, an);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) split8<NSPLIT>(bv[dn][b][0], bv[dn][b][1], bn[b]);
+        for (int b = 0; b < NB; ++b) b_parts<NSPLIT, H>(bv[dn][b][0], bv[dn][b][1], bn[b]);
         // the small cross products first; consecutive MFMAs update different
         // accumulators (RT * NB independent chains)
 #pragma unroll
@@ -443,7 +472,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
                 for (int r = 0; r < RT; ++r)
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
-                        acc[r][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r][a], bf[b][t - a], acc[r][b], 0, 0, 0);
+                        acc[r][b] = mfma32<H>(af[r][a], bf[b][t - a], acc[r][b]);
         issue_b(kc + D, bv[d]);
 #pragma unroll
         for (int r = 0; r < RT; ++r)
@@ -476,6 +505,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     }
     wait_vm<0>();  // no copy into LDS outlives the block
 
+    if constexpr (H) {
+        // undo the encoding: row r of the result carries the table's row
+        // scale a_r and the level's operand scale 2^e (powers of two)
+        const int sh = -level_scale_exp(pl.lmax[l]);
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * r + 4 * q + i;
+                const double f = row < P2 ? ldexp((double)pl.oscale[row], sh) : 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc64[r][b][i] *= f;
+            }
+    }
     if (nsplit == 1) {
         void *Lout = pick(pl.L, u.li);
         const int out_f64 = pick(pl.out_f64, u.li);
@@ -784,14 +827,14 @@ size_t m2l_partial_bytes(int P, int L, bool f64, int ncu) {
 
 // Eight waves (two per SIMD) wherever their operator ring fits in LDS; four
 // (one per SIMD) otherwise, i.e. for the 3-part split at p = 13.
-template <int NSPLIT, int P>
+template <int NSPLIT, int P, bool H = false>
 static void launch_bf16(unsigned nb, const M2LPlan &pl, const uint16_t *A, size_t astride,
                         const int2 *cls, double *partial, hipStream_t st) {
     constexpr bool fits8 = MixCfg<NSPLIT, P, 8>::NA * MixCfg<NSPLIT, P, 8>::STAGE <= 150;
     if constexpr (fits8)
-        k_m2l_bf16<NSPLIT, P, 8><<<nb, 512, 0, st>>>(pl, A, astride, cls, partial);
+        k_m2l_bf16<NSPLIT, P, 8, H><<<nb, 512, 0, st>>>(pl, A, astride, cls, partial);
     else
-        k_m2l_bf16<NSPLIT, P, 4><<<nb, 256, 0, st>>>(pl, A, astride, cls, partial);
+        k_m2l_bf16<NSPLIT, P, 4, H><<<nb, 256, 0, st>>>(pl, A, astride, cls, partial);
 }
 
 // sum the K parts of the split tiles (after either form's kernel)
@@ -805,9 +848,12 @@ static hipError_t fixup(int P, const M2LPlan &pl, unsigned nfix, const double *p
 
 hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *const *Lc,
                       const int *out_f64, const void *A, size_t astride, const int2 *cls,
-                      double *partial, size_t partial_bytes, int ncu, hipStream_t st) {
+                      double *partial, size_t partial_bytes, int ncu, const M2LHalf *half,
+                      hipStream_t st) {
     if (L < 2) return hipSuccess;
     M2LPlan pl = make_plan(P, L, true, ncu);
+    pl.lmax = half ? half->lmax : nullptr;
+    pl.oscale = half ? half->oscale : nullptr;
     for (int i = 0; i < pl.nlev; ++i) {
         const int l = pl.level[i];
         pl.B[i] = B[l];
@@ -825,6 +871,18 @@ hipError_t launch_m2l(int P, int L, bool f64, int nsplit, void *const *B, void *
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
             CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
+            default: return hipErrorInvalidValue;
+        }
+        return fixup(P, pl, nfix, partial, st);
+    }
+    if (half) {
+        if (!half->lmax || !half->oscale) return hipErrorInvalidValue;
+        switch (P) {
+#define CASEH(PP) \
+    case PP: launch_bf16<2, PP, true>(nb, pl, (const uint16_t *)A, astride, cls, partial, st); break;
+            CASEH(1) CASEH(2) CASEH(3) CASEH(4) CASEH(5) CASEH(6) CASEH(7) CASEH(8)
+            CASEH(9) CASEH(10) CASEH(11) CASEH(12) CASEH(13) CASEH(14) CASEH(15) CASEH(16)
+#undef CASEH
             default: return hipErrorInvalidValue;
         }
         return fixup(P, pl, nfix, partial, st);

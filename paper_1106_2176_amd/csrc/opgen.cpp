@@ -23,6 +23,8 @@
 //   I_{m+1}^m = (2m+1) z/r^2 I_m^m,
 //   r^2 I_n^m = (2n-1) z I_{n-1}^m - (n-m-1)(n+m-1) I_{n-2}^m,
 //   I_n^{-m} = (-1)^m conj(I_n^m).
+#include <algorithm>
+#include <cmath>
 #include <complex>
 #include <cstring>
 #include <vector>
@@ -192,6 +194,48 @@ void split_bf16(double x, int parts, uint16_t *out) {
         out[i] = bf16_bits((float)r);
         r -= (double)bf16_float(out[i]);
     }
+}
+
+uint16_t f16_bits(double x) {
+    const uint16_t sign = std::signbit(x) ? 0x8000u : 0u;
+    const double a = std::fabs(x);
+    if (a == 0.0) return sign;
+    int e = 0;
+    (void)std::frexp(a, &e);       // a in [2^(e-1), 2^e)
+    const int E = std::max(e - 1, -14);  // binary16 exponent (subnormals: -14)
+    const double ulp = std::ldexp(1.0, E - 10);
+    double m = std::nearbyint(a / ulp);  // significand in ulps, ties to even
+    int Eb = E;
+    if (m >= 2048.0) {  // rounded up to the next binade
+        m *= 0.5;
+        Eb += 1;
+    }
+    if (m < 1024.0) return (uint16_t)(sign | (uint16_t)m);  // subnormal (E = -14)
+    return (uint16_t)(sign | (uint16_t)((Eb + 15) << 10) | (uint16_t)(m - 1024.0));
+}
+
+double f16_value(uint16_t h) {
+    const int ex = (h >> 10) & 31, man = h & 1023;
+    const double v = ex == 0 ? std::ldexp((double)man, -24) : std::ldexp(1024.0 + man, ex - 25);
+    return (h & 0x8000u) ? -v : v;
+}
+
+void split_f16(double x, uint16_t out[2]) {
+    out[0] = f16_bits(x);
+    out[1] = f16_bits(x - f16_value(out[0]));
+}
+
+void harmonic_scale(int p, double *rho) {
+    std::vector<double> mx(p, 0.0), v((size_t)p * p);
+    const double r = std::sqrt(3.0) / 2.0, golden = M_PI * (3.0 - std::sqrt(5.0));
+    const int ns = 4096;  // directions on a Fibonacci sphere
+    for (int i = 0; i < ns; ++i) {
+        const double z = 1.0 - (2.0 * i + 1.0) / ns, s = std::sqrt(1.0 - z * z), ph = golden * i;
+        regular_rho(p, r * s * std::cos(ph), r * s * std::sin(ph), r * z, v.data());
+        for (int n = 0; n < p; ++n)
+            for (int c = n * n; c < (n + 1) * (n + 1); ++c) mx[n] = std::max(mx[n], std::fabs(v[c]));
+    }
+    for (int n = 0; n < p; ++n) rho[n] = std::ldexp(1.0, (int)std::lround(std::log2(mx[n])));
 }
 
 }  // namespace fmm

@@ -33,7 +33,7 @@ def test_status_strings_and_defaults():
     c = fmm.Config()
     L.fmm_config_default(ctypes.byref(c))
     assert c.abi_version == fmm.FMM_ABI_VERSION
-    assert (c.p, c.leaf_max, c.max_level, c.precision, c.bf16_splits) == (8, 64, 10, 1, 3)
+    assert (c.p, c.leaf_max, c.max_level, c.precision, c.bf16_splits, c.m2l_fp16) == (8, 64, 10, 1, 3, 1)
     assert c.box_size == 1.0 and list(c.box_lo) == [0.0, 0.0, 0.0]
     # 6 int32 (24) + double[3] (24) + double (8) + 3 pointers (24) + int32[8] (32)
     assert ctypes.sizeof(fmm.Config) == 112

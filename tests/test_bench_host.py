@@ -50,7 +50,41 @@ def test_committed_profiles_name_their_kernel_sources():
     """Each committed counter summary records the hash of a kernel source
     that exists (whether it still matches is checked at bench time)."""
     prof = os.path.join(bench.ROOT, "profiles")
-    for name, src in (("p2p_C2_traffic.txt", "p2p.hip"), ("m2l_bf16_C2_traffic.txt", "m2l.hip")):
+    for name, src in (("p2p_C2_traffic.txt", "p2p.hip"), ("m2l_bf16x3_C2_traffic.txt", "m2l.hip")):
         text = open(os.path.join(prof, name)).read()
         assert "source_sha256:" in text and "copy_fetch_factor:" in text
         assert os.path.exists(os.path.join(bench.ROOT, "paper_1106_2176_amd", "csrc", src))
+
+
+def _fake_result(dom="M2L"):
+    from paper_1106_2176_amd import inputs
+    info = {"n": 1_000_000, "n_leaves": 32768, "levels": 5, "p2p_pairs": 773_617_576,
+            "m2l_pairs": 6_039_504}
+    st = {"gather": 0.0, "P2M": 0.05, "M2M": 0.04, "pack": 0.02, "M2L": 0.5, "L2L": 0.04,
+          "L2P": 0.05, "P2P": 0.45, "combine": 0.04}
+    return inputs.WORKLOADS["C2"], {"info": info, "dom": dom, "dom_ms": st[dom], "stages_ms": st,
+                                    "build_ms": 0.1}
+
+
+def test_rooflines_use_the_algorithmic_work_and_both_fp32_rates():
+    wl, res = _fake_result()
+    roof, other = bench.rooflines(wl, res, "mixed", "fp16x2", False)
+    assert roof["kernel"].startswith("k_m2l_bf16<2,10,8,fp16>") and other["kernel"] == "k_p2p<float>"
+    # 2 p^4 FLOP per M2L pair over the stage time, against the 16-bit MFMA peak
+    assert roof["achieved"] == pytest.approx(2e4 * 6_039_504 / 0.5e-3 / 1e12)
+    assert roof["frac"] == pytest.approx(roof["achieved"] / 2500.0)
+    assert roof["mfma_products_per_term"] == 3
+    # 19 FLOP per P2P pair, against 157.3 and the unpacked 78.6 TFLOP/s
+    assert other["achieved"] == pytest.approx(19 * 773_617_576 / 0.45e-3 / 1e12)
+    assert other["frac_unpacked"] == pytest.approx(2 * other["frac"] * 157.3 / 157.2, rel=1e-3)
+    roof64, _ = bench.rooflines(wl, res, "fp64", None, False)
+    assert roof64["kernel"] == "k_m2l_f64<10>" and roof64["peak"] == 78.6
+
+
+def test_tree_pass_bytes_per_particle():
+    wl, res = _fake_result()
+    tp = bench.tree_pass(wl, res, "mixed")
+    # FP64 inputs, 16-byte records: 92 B build + 32 B P2M + 48 B L2P + 108 B
+    # combine per particle, plus the leaf coefficients written and read once
+    assert tp["bytes"] == 1_000_000 * (92 + 32 + 48 + 108) + 2 * 32768 * 104 * 4
+    assert tp["ms"] == pytest.approx(0.1 + 0.05 + 0.05 + 0.04)

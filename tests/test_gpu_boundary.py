@@ -113,7 +113,8 @@ def test_rebuild_with_other_settings_is_rejected():
         ref = (ref_phi.cpu().numpy(), ref_E.cpu().numpy())
         good = t.cfg
         bad = []
-        for field, value in (("p", 7), ("precision", fmm.PREC_FP64), ("bf16_splits", 2)):
+        for field, value in (("p", 7), ("precision", fmm.PREC_FP64), ("bf16_splits", 2),
+                             ("m2l_fp16", 0)):
             c = fmm.make_config(p=6, leaf_max=32, precision="mixed")
             setattr(c, field, value)
             bad.append(c)

@@ -24,8 +24,8 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def grads(pos, q, w, p, leaf, precision):
-    with fmm.Tree(dev(pos), p=p, leaf_max=leaf, precision=precision) as t:
+def grads(pos, q, w, p, leaf, precision, **kw):
+    with fmm.Tree(dev(pos), p=p, leaf_max=leaf, precision=precision, **kw) as t:
         phi, E = t.evaluate(dev(q))
         gq, gx = t.backward(dev(q), dev(w), E)
         torch.cuda.synchronize()
@@ -75,6 +75,10 @@ def test_c5_mixed_vs_fp64_and_direct(oracle_mod):
     pos, q = inputs.workload("C5")
     w = inputs.weights(wl.n, wl.seed)
     _, _, gq64, gx64 = grads(pos, q, w, wl.p, wl.leaf_max, "fp64")
+    _, _, gqb, gxb = grads(pos, q, w, wl.p, wl.leaf_max, "mixed", m2l_fp16=False)
+    print("C5 mixed (bf16 x3 M2L) vs FP64: dL/dq %.3e, dL/dx %.3e" % (rel_l2(gqb, gq64), rel_l2(gxb, gx64)))
+    assert rel_l2(gqb, gq64) < 1e-6
+    assert rel_l2(gxb, gx64) < 1e-6
     _, _, gqm, gxm = grads(pos, q, w, wl.p, wl.leaf_max, "mixed")
     phi_aw, E_aw, _, _ = grads(pos, np.abs(w), w, wl.p, wl.leaf_max, "fp64")
     _, E_aq, _, _ = grads(pos, np.abs(q), w, wl.p, wl.leaf_max, "fp64")

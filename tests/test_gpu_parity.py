@@ -6,8 +6,8 @@ Tolerances (relative L2 over all checked outputs):
                            basis: spherical harmonics vs Cartesian Taylor)
   FP64 P2P vs oracle near  1e-12
   mixed form vs FP64 form  1e-6 for phi and for F = qE (precision-induced
-                           error only; FP32 P2P, split-bf16 M2L, FP32 fine
-                           levels)
+                           error only; FP32 P2P, binary16- or bf16-split M2L,
+                           FP32 fine levels)
 """
 import numpy as np
 import pytest
@@ -31,6 +31,11 @@ def gpu_eval(pos, q, p, leaf, precision, vec="field", part=None, **kw):
         torch.cuda.synchronize()
         info = t.info()
     return phi.cpu().numpy().astype(np.float64), (None if v is None else v.cpu().numpy().astype(np.float64)), info
+
+
+# mixed-form M2L encodings: binary16 (the default), and bf16 in 3 or 2 parts
+ENCODINGS = {"fp16x2": dict(m2l_fp16=True), "bf16x3": dict(m2l_fp16=False, bf16_splits=3),
+             "bf16x2": dict(m2l_fp16=False, bf16_splits=2)}
 
 
 # ---------------------------------------------------------------- tree
@@ -139,9 +144,10 @@ def test_c1_fp64_and_mixed_vs_oracle(oracle_mod):
     assert info["levels"] == ref["level"] == 3
     assert rel_l2(phi, ref["phi"]) < 1e-10
     assert rel_l2(E, ref["E"]) < 1e-10
-    phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed")
-    assert rel_l2(phm, phi) < 1e-6
-    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+    for enc in ("fp16x2", "bf16x3", "bf16x2"):
+        phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed", **ENCODINGS[enc])
+        assert rel_l2(phm, phi) < 1e-6
+        assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
     # the FMM error itself is that of the oracle (p = 4)
     assert abs(rel_l2(phi, phi_d) - rel_l2(ref["phi"], phi_d)) < 1e-8
 
@@ -167,12 +173,15 @@ def test_c2_sampled_fp64_and_mixed(oracle_mod):
     assert info["levels"] == 5
     assert rel_l2(phi[t], ref["phi"]) < 1e-10
     assert rel_l2(E[t], ref["E"]) < 1e-10
-    phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed")
-    assert rel_l2(phm, phi) < 1e-6
-    assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
-    # accuracy against the exact sum is the FMM truncation error of p = 10
-    assert rel_l2(phm[t], phi_d) < 1e-6
-    assert rel_l2(Em[t], E_d) < 1e-5
+    for enc in ("fp16x2", "bf16x3"):
+        phm, Em, _ = gpu_eval(pos, q, w.p, w.leaf_max, "mixed", **ENCODINGS[enc])
+        e_phi, e_F = rel_l2(phm, phi), rel_l2(q[:, None] * Em, q[:, None] * E)
+        print("C2 mixed (%s) vs FP64 on all N: phi %.3e F %.3e" % (enc, e_phi, e_F))
+        assert e_phi < 1e-6
+        assert e_F < 1e-6
+        # accuracy against the exact sum is the FMM truncation error of p = 10
+        assert rel_l2(phm[t], phi_d) < 1e-6
+        assert rel_l2(Em[t], E_d) < 1e-5
 
 
 def test_c3_sampled_fp64_and_mixed(oracle_mod):
@@ -291,8 +300,8 @@ def test_domain_errors():
 def test_bf16_three_way_split_is_more_accurate():
     pos, q = inputs.particles(60_000, 35)
     ref, Er, _ = gpu_eval(pos, q, 10, 32, "fp64", part="far")
-    a, Ea, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=2)
-    b, Eb, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=3)
+    a, Ea, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=2, m2l_fp16=False)
+    b, Eb, _ = gpu_eval(pos, q, 10, 32, "mixed", part="far", bf16_splits=3, m2l_fp16=False)
     assert rel_l2(b, ref) <= rel_l2(a, ref)
     assert rel_l2(a, ref) < 1e-6
 
@@ -318,8 +327,9 @@ def test_high_order_fp64_vs_oracle_and_mixed(oracle_mod, p):
     """Every order above the workloads' p = 10 that the library accepts: the
     FP64 form against the oracle (level 3, so that the oracle's Cartesian
     M2L of p(p+1)(p+2)/6 terms stays in seconds), and the mixed form in
-    each split it supports (3 parts up to p = 13) against the FP64 form;
-    the splits it does not support are rejected."""
+    each M2L encoding it supports (binary16 at every p, 3 bf16 parts up to
+    p = 13) against the FP64 form; the encodings it does not support (2 bf16
+    parts above p = 10, 3 above 13) are rejected."""
     n, leaf = 4000, 32
     pos, q = inputs.particles(n, 100 + p)
     ref = oracle_mod.fmm(pos, q, p, leaf)
@@ -330,27 +340,31 @@ def test_high_order_fp64_vs_oracle_and_mixed(oracle_mod, p):
     phf, Ef, _ = gpu_eval(pos, q, p, leaf, "fp64", part="far")
     assert rel_l2(phf, ref["phi_far"]) < 1e-10
     assert rel_l2(Ef, ref["E_far"]) < 1e-10
-    for splits in (2, 3):
-        if (splits == 3 and p > 13) or splits == 2:
+    for name, kw in ENCODINGS.items():
+        if (name == "bf16x3" and p > 13) or name == "bf16x2":
             with pytest.raises(fmm.FMMError) as e:
-                gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=splits)
+                gpu_eval(pos, q, p, leaf, "mixed", **kw)
             assert e.value.status == fmm.FMM_EUNSUPPORTED
             continue
-        phm, Em, _ = gpu_eval(pos, q, p, leaf, "mixed", bf16_splits=splits)
+        phm, Em, _ = gpu_eval(pos, q, p, leaf, "mixed", **kw)
         assert rel_l2(phm, phi) < 1e-6
         assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
 
 
-@pytest.mark.parametrize("p,splits", [(13, 3), (11, 3), (12, 3)])
-def test_high_order_mixed_at_level5(p, splits):
+@pytest.mark.parametrize("p,enc", [(13, "bf16x3"), (16, "fp16x2"), (11, "fp16x2"), (4, "fp16x2")])
+def test_high_order_mixed_at_level5(p, enc):
     """Mixed against FP64 on a level-5 tree (whole M2L tiles of 128
-    targets, not only the K-split small levels)."""
+    targets, not only the K-split small levels), far part and whole."""
     pos, q = inputs.particles(300_000, 120 + p)
     phi, E, info = gpu_eval(pos, q, p, 32, "fp64")
     assert info["levels"] == 5
-    phm, Em, _ = gpu_eval(pos, q, p, 32, "mixed", bf16_splits=splits)
+    phm, Em, _ = gpu_eval(pos, q, p, 32, "mixed", **ENCODINGS[enc])
     assert rel_l2(phm, phi) < 1e-6
     assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+    phf, Ef, _ = gpu_eval(pos, q, p, 32, "fp64", part="far")
+    phmf, Emf, _ = gpu_eval(pos, q, p, 32, "mixed", part="far", **ENCODINGS[enc])
+    assert rel_l2(phmf, phf) < 1e-6
+    assert rel_l2(Emf, Ef) < 1e-6
 
 
 # --------------------------------------- graph replay, concurrent near field
