@@ -122,7 +122,16 @@ typedef struct {
                                   that puts the level's largest one just below
                                   2^14; the results are scaled back exactly.
                                   Supports every p <= 16. */
-    int32_t reserved[3];       /* zero */
+    int32_t m2l_rotation;      /* FP64 form only (FMM_EINVAL otherwise), p >= 2:
+                                  nonzero = M2L by rotation: the multipole rotated
+                                  so that the offset lies on the z axis,
+                                  translated along z and rotated back, O(p^3)
+                                  per pair instead of the dense O(p^4) product
+                                  (same results to round-off).  Its tables are
+                                  made on the first build that asks for them (a
+                                  quadrature per offset, about a second of host
+                                  time at p = 16) and kept per device and p. */
+    int32_t reserved[2];       /* zero */
 } fmm_config;
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
@@ -288,6 +297,11 @@ void fmm_tree_destroy(fmm_tree *tree);
  *   kind 1: L2L parent -> child, child octant `index`
  *   kind 2: M2L, offset index `index` = (ox+3) + 7 (oy+3) + 49 (oz+3), target minus source
  *           in box widths, |o|_inf in 2..3
+ *   kind 3: the rotation D of the rotation-based M2L for offset `index` (any nonzero
+ *           offset): rho(Q u) = D rho(u) for the rotation Q that takes the offset's
+ *           direction to +z; block diagonal by degree
+ *   kind 4: the M2L matrix Tz of the offset (0, 0, |o|) for offset `index`; couples
+ *           only coefficients of equal order and kind, and M2L(o) = D^T Tz D
  * Basis: multipole vector mu = sum_j q_j rho(u_j) and potential
  * phi(x) = (1/w) ell . rho(u) with u = (x - c)/w, rho the real and imaginary
  * parts of the regular solid harmonics R_n^m (m >= 0) defined by

@@ -47,7 +47,8 @@ class Config(ctypes.Structure):
         ("overlap_near", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("m2l_fp16", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("m2l_rotation", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -152,13 +153,15 @@ def torch_allocator():
 
 def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
-                graph=False, profile_stages=None, allocator="torch", m2l_fp16=None):
+                graph=False, profile_stages=None, allocator="torch", m2l_fp16=None,
+                m2l_rotation=False):
     """profile_stages: None (all) or an iterable of stage names (STAGES) whose
     boundaries get profiling events.  allocator: "torch" (workspace from
     torch's caching allocator), "library" (the library's own stream-ordered
     hipMallocAsync pool) or an (alloc, free) pair of ctypes callbacks.
     m2l_fp16: None (the library's default), True (the mixed M2L in two
-    binary16 parts) or False (bf16_splits bf16 parts)."""
+    binary16 parts) or False (bf16_splits bf16 parts).  m2l_rotation: the
+    FP64 form's M2L by rotation (O(p^3) per pair)."""
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)
@@ -177,6 +180,7 @@ def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3
         sum(1 << STAGES.index(s) for s in profile_stages)
     if m2l_fp16 is not None:
         c.m2l_fp16 = 1 if m2l_fp16 else 0
+    c.m2l_rotation = 1 if m2l_rotation else 0
     if allocator == "torch":
         c.alloc, c.free = torch_allocator()
     elif allocator != "library":
@@ -239,10 +243,12 @@ class Tree:
 
     def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
                  box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
-                 graph=False, profile_stages=None, allocator="torch", m2l_fp16=None):
+                 graph=False, profile_stages=None, allocator="torch", m2l_fp16=None,
+                 m2l_rotation=False):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,
-                               profile, overlap_near, graph, profile_stages, allocator, m2l_fp16)
+                               profile, overlap_near, graph, profile_stages, allocator, m2l_fp16,
+                               m2l_rotation)
         # the callback objects must outlive every call that can allocate or
         # free (the torch pair is held by the module)
         self._allocator = allocator

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.hpp"
@@ -76,6 +77,9 @@ struct Ops {
     // table (the M2L output's)
     uint16_t *m2lh = nullptr, *am2lh = nullptr;
     float *rho_inv = nullptr, *oscale = nullptr, *aoscale = nullptr;
+    // rotation-based M2L (FP64 form), compact per offset id (made on first
+    // use): forward D of offset -d and Tz, adjoint D of offset d and Tz^T
+    double *rot64 = nullptr, *tz64 = nullptr, *arot64 = nullptr, *atz64 = nullptr;
     int2 *cls = nullptr; // [8][189] (packed source offset, table id)
 };
 
@@ -248,6 +252,74 @@ fmm_status build_ops(int p, Ops **out) {
     return FMM_OK;
 }
 
+// Tables of the rotation-based M2L for p (FP64 form): for every M2L offset
+// id, D and Tz of op_m2l_rotated in the compact layouts of rot_deg_off and
+// tz_off.  The forward pair (target t, source t + d) takes the operator of
+// offset -d; the adjoint takes the transpose of the operator of offset d,
+// D_d^T Tz^T D_d.  Each rotation needs a quadrature over the sphere, so the
+// offsets are spread over host threads.
+fmm_status build_rot_ops(int p, Ops *o) {
+    std::lock_guard<std::mutex> g(g_ops_mu);
+    if (o->rot64) return FMM_OK;
+    const int P2 = p * p, ND = rot_size(p), NZ = tz_size(p);
+    const size_t nid = (size_t)kNumOffsets;
+    std::vector<double> fr(nid * ND), ft(nid * NZ), ar(nid * ND), at(nid * NZ);
+    std::vector<int> todo;
+    for (int i = 0; i < 343; ++i)
+        if (id316_of(i % 7 - 3, (i / 7) % 7 - 3, i / 49 - 3) >= 0) todo.push_back(i);
+    auto compact = [&](const double *D, const double *Tz, bool transpose_tz, double *dr, double *dt) {
+        for (int n = 0; n < p; ++n) {
+            const int w = 2 * n + 1, b = n * n;
+            for (int r = 0; r < w; ++r)
+                for (int c = 0; c < w; ++c) dr[rot_deg_off(n) + r * w + c] = D[(size_t)(b + r) * P2 + b + c];
+        }
+        for (int m = 0; m < p; ++m)
+            for (int kind = 0; kind < (m == 0 ? 1 : 2); ++kind) {
+                const int w = p - m;
+                for (int kk = m; kk < p; ++kk)
+                    for (int nn = m; nn < p; ++nn) {
+                        const int ro = kk * kk + (m == 0 ? 0 : 2 * m - 1 + kind);
+                        const int ci = nn * nn + (m == 0 ? 0 : 2 * m - 1 + kind);
+                        const double v = transpose_tz ? Tz[(size_t)ci * P2 + ro] : Tz[(size_t)ro * P2 + ci];
+                        dt[tz_off(p, m, kind) + (kk - m) * w + (nn - m)] = v;
+                    }
+            }
+    };
+    auto work = [&](size_t first, size_t step) {
+        std::vector<double> D((size_t)P2 * P2), Tz((size_t)P2 * P2);
+        for (size_t j = first; j < todo.size(); j += step) {
+            const int i = todo[j];
+            const int dx = i % 7 - 3, dy = (i / 7) % 7 - 3, dz = i / 49 - 3;
+            const size_t id = (size_t)id316_of(dx, dy, dz);
+            op_m2l_rotated(p, -dx, -dy, -dz, D.data(), Tz.data());
+            compact(D.data(), Tz.data(), false, &fr[id * ND], &ft[id * NZ]);
+            op_m2l_rotated(p, dx, dy, dz, D.data(), Tz.data());
+            compact(D.data(), Tz.data(), true, &ar[id * ND], &at[id * NZ]);
+        }
+    };
+    const size_t nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nth; ++t) th.emplace_back(work, t, nth);
+    work(0, nth);
+    for (auto &x : th) x.join();
+    auto upload = [](double **dst, const std::vector<double> &v) -> hipError_t {
+        hipError_t e = hipMalloc((void **)dst, v.size() * sizeof(double));
+        if (e != hipSuccess) return e;
+        return hipMemcpy(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+    };
+    double *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d4 = nullptr;
+    hipError_t e = upload(&d1, fr);
+    if (e == hipSuccess) e = upload(&d2, ft);
+    if (e == hipSuccess) e = upload(&d3, ar);
+    if (e == hipSuccess) e = upload(&d4, at);
+    if (e != hipSuccess) return fail(FMM_EDEVICE, std::string("rotation table upload: ") + hipGetErrorString(e));
+    o->tz64 = d2;
+    o->arot64 = d3;
+    o->atz64 = d4;
+    o->rot64 = d1;
+    return FMM_OK;
+}
+
 constexpr int kStages = 9;
 constexpr int kTimeRing = 32;  // event sets: stage times of the last 32 profiled calls
 constexpr int kEvents = kStages + 3;  // stage boundaries + start/end of a concurrent P2P
@@ -415,6 +487,9 @@ fmm_status validate_cfg(const fmm_config *c) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->box_lo[a])) return fail(FMM_EINVAL, "box_lo must be finite");
     if (c->graph && c->profile) return fail(FMM_EINVAL, "graph and profile are exclusive");
+    if (c->m2l_rotation && c->precision != FMM_PREC_FP64)
+        return fail(FMM_EINVAL, "the rotation-based M2L is an option of the FP64 form");
+    if (c->m2l_rotation && c->p < 2) return fail(FMM_EINVAL, "the rotation-based M2L needs p >= 2");
     if (c->profile_stages >> kStages) return fail(FMM_EINVAL, "profile_stages has bits past stage 8");
     if ((c->alloc == nullptr) != (c->free == nullptr))
         return fail(FMM_EINVAL, "alloc and free callbacks must be given together");
@@ -603,12 +678,18 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
                 of64[l] = level_f64(t, l);
             }
             const bool half = m2l_half(t->cfg);
-            const void *A = f64    ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
-                            : half ? (const void *)(adjoint ? o->am2lh : o->m2lh)
-                                   : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
-            const M2LHalf hv{w.lmax, adjoint ? o->aoscale : o->oscale};
-            HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, o->bf_part, o->cls, w.m2lpart,
-                              w.m2lpart_bytes, t->ncu, half ? &hv : nullptr, st));
+            if (f64 && t->cfg.m2l_rotation) {  // rotate, translate along z, rotate back
+                if (!o->rot64) return fail(FMM_EDEVICE, "internal: no rotation tables");
+                HIPCHK(launch_m2l_rot(P, L, Bp, Lp, adjoint ? o->arot64 : o->rot64,
+                                      adjoint ? o->atz64 : o->tz64, o->cls, st));
+            } else {  // dense products grouped by offset on the matrix cores
+                const void *A = f64    ? (const void *)(adjoint ? o->am2l64 : o->m2l64)
+                                : half ? (const void *)(adjoint ? o->am2lh : o->m2lh)
+                                       : (const void *)(adjoint ? o->am2lbf : o->m2lbf);
+                const M2LHalf hv{w.lmax, adjoint ? o->aoscale : o->oscale};
+                HIPCHK(launch_m2l(P, L, f64, nsplit, Bp, Lp, of64, A, o->bf_part, o->cls, w.m2lpart,
+                                  w.m2lpart_bytes, t->ncu, half ? &hv : nullptr, st));
+            }
         }
         CHK(rec(t, 5, st));
         // downward sweep (adjoint: M2M^T)
@@ -878,6 +959,9 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     // translation tables of this p (made once per device and p): a tree with
     // a far field has them before its first evaluation
     if (lev >= 2 && !t->ops && (s = build_ops(cfg->p, &t->ops)) != FMM_OK) return bail(s);
+    if (lev >= 2 && cfg->precision == FMM_PREC_FP64 && cfg->m2l_rotation && !t->ops->rot64 &&
+        (s = build_rot_ops(cfg->p, t->ops)) != FMM_OK)
+        return bail(s);
     *out = t;
     return FMM_OK;
 }
@@ -1053,6 +1137,17 @@ fmm_status fmm_operator_host(int32_t p, int32_t kind, int32_t index, double *out
         if (std::max(std::abs(ox), std::max(std::abs(oy), std::abs(oz))) < 2)
             return fail(FMM_EINVAL, "M2L offsets need |o|_inf >= 2");
         op_m2l(p, ox, oy, oz, out);
+        return FMM_OK;
+    }
+    if (kind == 3 || kind == 4) {
+        if (index < 0 || index >= 343) return fail(FMM_EINVAL, "offset index out of range");
+        const int ox = index % 7 - 3, oy = (index / 7) % 7 - 3, oz = index / 49 - 3;
+        if (ox == 0 && oy == 0 && oz == 0) return fail(FMM_EINVAL, "the zero offset has no direction");
+        std::vector<double> other((size_t)p * p * p * p);
+        if (kind == 3)
+            op_m2l_rotated(p, ox, oy, oz, out, other.data());
+        else
+            op_m2l_rotated(p, ox, oy, oz, other.data(), out);
         return FMM_OK;
     }
     return fail(FMM_EINVAL, "unknown operator kind");

@@ -75,6 +75,23 @@ hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const
                                const double4 *farf, double inv_w, const void *q, const void *w,
                                const void *Eq, void *gq, void *gx, hipStream_t st);
 
+// Rotation-based M2L tables (FP64 form), compact per offset id: D by degree
+// blocks, (2n+1)^2 each, the block of degree n first at rot_deg_off(n); Tz by
+// (order m, kind) blocks of (p-m)^2, m = 0 cosine only, then the cosine and
+// sine blocks of m = 1, 2, ..., row = output degree - m, column = input
+// degree - m.
+__host__ __device__ constexpr int rot_deg_off(int n) { return n * (4 * n * n - 1) / 3; }
+__host__ __device__ constexpr int rot_size(int P) { return rot_deg_off(P); }
+__host__ __device__ constexpr int tz_off(int P, int m, int kind) {
+    int o = 0;
+    for (int j = 0; j < m; ++j) o += (j == 0 ? 1 : 2) * (P - j) * (P - j);
+    return o + (kind ? (P - m) * (P - m) : 0);
+}
+__host__ __device__ constexpr int tz_size(int P) { return tz_off(P, P, 0); }
+// every level 2..L in one launch, B[l] = FP64 padded grid, Lc[l] FP64 output
+hipError_t launch_m2l_rot(int P, int L, void *const *B, void *const *Lc, const double *rot,
+                          const double *tz, const int2 *cls, hipStream_t st);
+
 // scratch.hip: device address of the current device's static scratch array
 // (FMM_NOALLOC_SCRATCH_BYTES), looked up on the first call per device
 hipError_t noalloc_scratch(void **ptr);

@@ -735,6 +735,231 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
     }
 }
 
+// ------------------------------------------------ rotation-based M2L (FP64)
+// O(p^3) per pair instead of O(p^4): the multipole of a source box is rotated
+// into the frame whose z axis points along the offset (target minus source),
+// translated along z, and the local expansion rotated back, F = D^T Tz D
+// (the rotations of the paper's GPU code, Fig. 4).  D is block diagonal by
+// degree (sum (2n+1)^2 entries), Tz by order and cosine/sine kind (sum over
+// m of (p-m)^2 entries per kind).  A block takes kRotNT targets of one class
+// at one level and walks the class's 189 offsets; per offset it stages the
+// compact D and Tz and the targets' source multipoles in LDS and runs the
+// three stages, each thread computing a row for kRotTT targets at a time;
+// the rotated-back results accumulate in registers over all offsets.
+constexpr int kRotNT = 16, kRotTT = 4, kRotThreads = 256;
+
+struct RotPlan {
+    int nlev;
+    int level[kMaxLev];
+    int64_t blk0[kMaxLev + 1];  // first block of each level
+    const double *B[kMaxLev];   // FP64 padded multipole grid of the level
+    double *L[kMaxLev];         // local expansions of the level
+};
+
+__device__ __forceinline__ int isqrt_small(int c) {
+    int n = (int)sqrtf((float)c);
+    while (n * n > c) --n;
+    while ((n + 1) * (n + 1) <= c) ++n;
+    return n;
+}
+
+template <int P>
+__global__ __launch_bounds__(kRotThreads) void k_m2l_rot(RotPlan pl, const double *__restrict__ rot,
+                                                        const double *__restrict__ tz,
+                                                        const int2 *__restrict__ cls) {
+    constexpr int P2 = P * P, S = coef_stride(P), ND = rot_size(P), NZ = tz_size(P);
+    constexpr int NT = kRotNT, TT = kRotTT, NG = NT / TT, NI = P2 * NG;
+    // LDS row pitch of the [coefficient][target] buffers: two doubles of
+    // padding against bank conflicts, 16-byte rows kept aligned
+    constexpr int NTP = NT + 2;
+    constexpr int IPT = (NI + kRotThreads - 1) / kRotThreads;
+    __shared__ double sD[ND], sT[NZ];
+    __shared__ __align__(16) double sM[P2 * NTP], sX[P2 * NTP];  // [coefficient][target]
+    __shared__ int64_t sTp[NT];
+    const int tid = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int li = find_level(pl.blk0, pl.nlev, b);
+    const int l = pick(pl.level, li);
+    const double *__restrict__ B = pick(pl.B, li);
+    double *__restrict__ Lout = pick(pl.L, li);
+    const int n = 1 << l, h = n >> 1;
+    const int64_t G = n + 6, npar = (int64_t)h * h * h;
+    const int64_t j = b - pick(pl.blk0, li);
+    const int k = (int)(j & 7);
+    const int64_t pbase = (j >> 3) * NT;
+    if (tid < NT) {
+        int64_t tp, tr;
+        target_of(pbase + tid < npar ? pbase + tid : 0, k, n, G, S, tp, tr);
+        sTp[tid] = tp;
+    }
+    double acc[IPT][TT];
+#pragma unroll
+    for (int it = 0; it < IPT; ++it)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) acc[it][t] = 0.0;
+
+    // The next offset's D, Tz and source multipoles are loaded into registers
+    // while the current offset computes, and stored to LDS at the top of the
+    // next step: the global-memory latency stays off the critical path.
+    constexpr int LD = (ND + kRotThreads - 1) / kRotThreads, LZ = (NZ + kRotThreads - 1) / kRotThreads;
+    constexpr int LM = (P2 * NT + kRotThreads - 1) / kRotThreads;
+    double rD[LD], rZ[LZ], rM[LM];
+    __syncthreads();  // sTp
+    auto fetch = [&](int slot) __attribute__((always_inline)) {
+        const int2 e = cls[k * kOffsetsPerClass + slot];
+        const int64_t shift = unpack_delta(e.x, G) * S;
+        const double *dsrc = rot + (size_t)e.y * ND, *tsrc = tz + (size_t)e.y * NZ;
+#pragma unroll
+        for (int u = 0; u < LD; ++u) {
+            const int i = tid + u * kRotThreads;
+            rD[u] = (ND % kRotThreads == 0 || i < ND) ? dsrc[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LZ; ++u) {
+            const int i = tid + u * kRotThreads;
+            rZ[u] = (NZ % kRotThreads == 0 || i < NZ) ? tsrc[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LM; ++u) {
+            const int i = tid + u * kRotThreads;
+            const int t = i / P2, c = i - t * P2;
+            rM[u] = ((P2 * NT) % kRotThreads == 0 || i < P2 * NT) ? B[sTp[t] + shift + c] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int slot = 0; slot < kOffsetsPerClass; ++slot) {
+        __syncthreads();  // every thread is done with the previous offset's LDS
+#pragma unroll
+        for (int u = 0; u < LD; ++u) {
+            const int i = tid + u * kRotThreads;
+            if (ND % kRotThreads == 0 || i < ND) sD[i] = rD[u];
+        }
+#pragma unroll
+        for (int u = 0; u < LZ; ++u) {
+            const int i = tid + u * kRotThreads;
+            if (NZ % kRotThreads == 0 || i < NZ) sT[i] = rZ[u];
+        }
+#pragma unroll
+        for (int u = 0; u < LM; ++u) {
+            const int i = tid + u * kRotThreads;
+            const int t = i / P2, c = i - t * P2;
+            if ((P2 * NT) % kRotThreads == 0 || i < P2 * NT) sM[c * NTP + t] = rM[u];
+        }
+        __syncthreads();
+        if (slot + 1 < kOffsetsPerClass) fetch(slot + 1);
+        // rotate: X = D M (within each degree block)
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = tid + it * kRotThreads;
+            if (NI % kRotThreads != 0 && item >= NI) break;
+            const int r = item % P2, g = item / P2;
+            const int dn = isqrt_small(r), rb = dn * dn, w = 2 * dn + 1;
+            const double *drow = sD + rot_deg_off(dn) + (r - rb) * w;
+            const double *mc = sM + rb * NTP + g * TT;
+            double a4[TT] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int q = 0; q < w; ++q) {
+                const double d = drow[q];
+                const double2 m01 = *(const double2 *)(mc + q * NTP), m23 = *(const double2 *)(mc + q * NTP + 2);
+                a4[0] += d * m01.x;
+                a4[1] += d * m01.y;
+                a4[2] += d * m23.x;
+                a4[3] += d * m23.y;
+            }
+            double *xo = sX + r * NTP + g * TT;
+            *(double2 *)xo = make_double2(a4[0], a4[1]);
+            *(double2 *)(xo + 2) = make_double2(a4[2], a4[3]);
+        }
+        __syncthreads();
+        // translate along z: Y = Tz X (within each order / kind), into sM
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = tid + it * kRotThreads;
+            if (NI % kRotThreads != 0 && item >= NI) break;
+            const int r = item % P2, g = item / P2;
+            const int kd = isqrt_small(r), rr = r - kd * kd;
+            const int m = (rr + 1) >> 1, kind = (rr > 0 && !(rr & 1)) ? 1 : 0;
+            const double *trow2 = sT + tz_off(P, m, kind) + (kd - m) * (P - m);
+            double a4[TT] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int nn = m; nn < P; ++nn) {
+                const int c = nn * nn + (m == 0 ? 0 : 2 * m - 1 + kind);
+                const double tv = trow2[nn - m];
+                const double *xc = sX + c * NTP + g * TT;
+                const double2 x01 = *(const double2 *)xc, x23 = *(const double2 *)(xc + 2);
+                a4[0] += tv * x01.x;
+                a4[1] += tv * x01.y;
+                a4[2] += tv * x23.x;
+                a4[3] += tv * x23.y;
+            }
+            double *yo = sM + r * NTP + g * TT;
+            *(double2 *)yo = make_double2(a4[0], a4[1]);
+            *(double2 *)(yo + 2) = make_double2(a4[2], a4[3]);
+        }
+        __syncthreads();
+        // rotate back and accumulate: acc += D^T Y
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const int item = tid + it * kRotThreads;
+            if (NI % kRotThreads != 0 && item >= NI) break;
+            const int r = item % P2, g = item / P2;
+            const int dn = isqrt_small(r), rb = dn * dn, w = 2 * dn + 1;
+            const double *dcol = sD + rot_deg_off(dn) + (r - rb);
+            const double *yc = sM + rb * NTP + g * TT;
+#pragma unroll 4
+            for (int q = 0; q < w; ++q) {
+                const double d = dcol[q * w];
+                const double2 y01 = *(const double2 *)(yc + q * NTP), y23 = *(const double2 *)(yc + q * NTP + 2);
+                acc[it][0] += d * y01.x;
+                acc[it][1] += d * y01.y;
+                acc[it][2] += d * y23.x;
+                acc[it][3] += d * y23.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+        const int item = tid + it * kRotThreads;
+        if (NI % kRotThreads != 0 && item >= NI) break;
+        const int r = item % P2, g = item / P2;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+            const int64_t pid = pbase + g * TT + t;
+            if (pid >= npar) continue;
+            int64_t tp, tr;
+            target_of(pid, k, n, G, S, tp, tr);
+            Lout[tr * S + r] = acc[it][t];
+        }
+    }
+}
+
+hipError_t launch_m2l_rot(int P, int L, void *const *B, void *const *Lc, const double *rot,
+                          const double *tz, const int2 *cls, hipStream_t st) {
+    if (L < 2) return hipSuccess;
+    RotPlan pl{};
+    pl.nlev = L - 1;
+    int64_t nb = 0;
+    for (int i = 0; i < pl.nlev; ++i) {
+        const int l = L - i;
+        const int64_t h = (int64_t)1 << (l - 1);
+        pl.level[i] = l;
+        pl.blk0[i] = nb;
+        pl.B[i] = (const double *)B[l];
+        pl.L[i] = (double *)Lc[l];
+        nb += 8 * ((h * h * h + kRotNT - 1) / kRotNT);
+    }
+    pl.blk0[pl.nlev] = nb;
+    switch (P) {
+#define CASE(PP) \
+    case PP: k_m2l_rot<PP><<<(unsigned)nb, kRotThreads, 0, st>>>(pl, rot, tz, cls); break;
+        CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
+        CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
+#undef CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ host side
 static int64_t level_tiles(int l) {
     const int64_t h = (int64_t)1 << (l - 1);

@@ -163,13 +163,86 @@ void op_l2l(int p, int octant, double *out) {
             out);
 }
 
-void op_m2l(int p, int ox, int oy, int oz, double *out) {
-    const Harm I = irregular(2 * p - 1, double(ox), double(oy), double(oz));
+void op_m2l_at(int p, double ox, double oy, double oz, double *out) {
+    const Harm I = irregular(2 * p - 1, ox, oy, oz);
     realify(p, MU, ELL,
             [&](int k, int l, int n, int m) -> cplx {
                 return ((k & 1) ? -1.0 : 1.0) * I.get(n + k, m + l);
             },
             out);
+}
+
+void op_m2l(int p, int ox, int oy, int oz, double *out) { op_m2l_at(p, ox, oy, oz, out); }
+
+namespace {
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton's iteration on the
+// Legendre polynomial from the Chebyshev-like initial guesses).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            if (n == 1) p0 = 1.0, p1 = z;
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+void op_rotation(int p, const double Q[9], double *out) {
+    // Degree-n regular harmonics span a space that rotations map to itself,
+    // so rho(Q u) = D rho(u) with D block diagonal by degree.  On the unit
+    // sphere the real harmonics are orthogonal: with a quadrature exact for
+    // the products (degree <= 2p - 2: Gauss-Legendre in cos(theta) times the
+    // trapezoid rule in phi), D = (sum w rho(Q u) rho(u)^T) G^-1, G the
+    // diagonal Gram matrix sum w rho(u) rho(u)^T.
+    const int P2 = p * p, nt = p, nph = 2 * p;
+    std::vector<double> zt, wt, a(P2), b(P2), G(P2, 0.0), B((size_t)P2 * P2, 0.0);
+    gauss_legendre(nt, zt, wt);
+    for (int i = 0; i < nt; ++i)
+        for (int j = 0; j < nph; ++j) {
+            const double ph = 2.0 * M_PI * j / nph, st = std::sqrt(1.0 - zt[i] * zt[i]);
+            const double u[3] = {st * std::cos(ph), st * std::sin(ph), zt[i]};
+            const double v[3] = {Q[0] * u[0] + Q[1] * u[1] + Q[2] * u[2], Q[3] * u[0] + Q[4] * u[1] + Q[5] * u[2],
+                                 Q[6] * u[0] + Q[7] * u[1] + Q[8] * u[2]};
+            regular_rho(p, u[0], u[1], u[2], a.data());
+            regular_rho(p, v[0], v[1], v[2], b.data());
+            const double wq = wt[i] * (2.0 * M_PI / nph);
+            for (int n = 0; n < p; ++n)
+                for (int r = n * n; r < (n + 1) * (n + 1); ++r) {
+                    G[r] += wq * a[r] * a[r];
+                    for (int c = n * n; c < (n + 1) * (n + 1); ++c) B[(size_t)r * P2 + c] += wq * b[r] * a[c];
+                }
+        }
+    std::memset(out, 0, sizeof(double) * P2 * P2);
+    for (int n = 0; n < p; ++n)
+        for (int r = n * n; r < (n + 1) * (n + 1); ++r)
+            for (int c = n * n; c < (n + 1) * (n + 1); ++c) out[(size_t)r * P2 + c] = B[(size_t)r * P2 + c] / G[c];
+}
+
+void op_m2l_rotated(int p, int ox, int oy, int oz, double *D, double *Tz) {
+    // Q = R_y(-theta) R_z(-phi) takes the direction of o to +z
+    const double r = std::sqrt(double(ox * ox + oy * oy + oz * oz));
+    const double th = std::acos(oz / r), ph = std::atan2(double(oy), double(ox));
+    const double ct = std::cos(th), st = std::sin(th), cp = std::cos(ph), sp = std::sin(ph);
+    // R_z(-phi) = [[cp, sp, 0], [-sp, cp, 0], [0, 0, 1]]; R_y(-theta) = [[ct, 0, -st], [0, 1, 0], [st, 0, ct]]
+    const double Q[9] = {ct * cp, ct * sp, -st, -sp, cp, 0.0, st * cp, st * sp, ct};
+    op_rotation(p, Q, D);
+    op_m2l_at(p, 0.0, 0.0, r, Tz);
 }
 
 // Round to nearest even bfloat16 (the top 16 bits of an IEEE binary32), then

@@ -10,6 +10,15 @@ namespace fmm {
 void op_m2m(int p, int octant, double *out);  // child octant -> parent
 void op_l2l(int p, int octant, double *out);  // parent -> child octant
 void op_m2l(int p, int ox, int oy, int oz, double *out);  // source -> target, o = target - source
+void op_m2l_at(int p, double ox, double oy, double oz, double *out);  // any offset, |o| > 0
+// rho(Q u) = D rho(u) for the rotation Q (row-major 3 x 3): D block diagonal
+// by degree
+void op_rotation(int p, const double Q[9], double *D);
+// M2L of offset o by rotation: the rotation D that takes o's direction to +z
+// and the M2L matrix Tz of the offset (0, 0, |o|), so that
+// op_m2l(o) = D^T Tz D (Tz couples only coefficients of equal order and
+// equal cosine/sine kind)
+void op_m2l_rotated(int p, int ox, int oy, int oz, double *D, double *Tz);
 
 // x = b0 + b1 + ... (+ residual): successive round-to-nearest-even bfloat16
 // parts of x (each the bf16 rounding of the remaining residual).

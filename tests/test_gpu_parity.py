@@ -427,3 +427,49 @@ def test_launch_modes_c2_mixed_vs_fp64_and_oracle(oracle_mod, graph, overlap):
     for phm, Em, gqm, gxm in _modes_run(pos, q, w, wl.p, wl.leaf_max, "mixed", graph, overlap, reps=2):
         assert rel_l2(phm, phi) < 1e-6
         assert rel_l2(q[:, None] * Em, q[:, None] * E) < 1e-6
+
+
+# ------------------------------------------------ rotation-based M2L (FP64)
+
+@pytest.mark.parametrize("p", [2, 4, 10, 12, 16])
+def test_rotation_m2l_fp64_vs_oracle(oracle_mod, p):
+    """M2L by rotation (FP64 form): the same approximation as the dense
+    operators, so the oracle FMM is matched to round-off, whole and far
+    part."""
+    n, leaf = 4000, 32
+    pos, q = inputs.particles(n, 140 + p)
+    ref = oracle_mod.fmm(pos, q, p, leaf)
+    phi, E, info = gpu_eval(pos, q, p, leaf, "fp64", m2l_rotation=True)
+    assert info["levels"] == ref["level"] == 3
+    assert rel_l2(phi, ref["phi"]) < 1e-10
+    assert rel_l2(E, ref["E"]) < 1e-10
+    phf, Ef, _ = gpu_eval(pos, q, p, leaf, "fp64", part="far", m2l_rotation=True)
+    assert rel_l2(phf, ref["phi_far"]) < 1e-10
+    assert rel_l2(Ef, ref["E_far"]) < 1e-10
+
+
+@pytest.mark.parametrize("p", [8, 13])
+def test_rotation_m2l_matches_dense_forward_and_adjoint(p):
+    """On a level-5 tree (every level 2..5, partial and whole target tiles):
+    far field and adjoint gradients of the rotation form against the dense
+    FP64 form."""
+    pos, q = inputs.particles(300_000, 150 + p)
+    w = np.random.default_rng(151).standard_normal(len(q))
+    out = {}
+    for rot in (False, True):
+        with fmm.Tree(dev(pos), p=p, leaf_max=32, precision="fp64", m2l_rotation=rot) as t:
+            assert t.info()["levels"] == 5
+            phi, E = t.evaluate(dev(q), part="far")
+            phi2, E2 = t.evaluate(dev(q))
+            gq, gx = t.backward(dev(q), dev(w), E2)
+            torch.cuda.synchronize()
+            out[rot] = [x.cpu().numpy() for x in (phi, E, gq, gx)]
+    for a, b in zip(out[True], out[False]):
+        assert rel_l2(a, b) < 1e-12
+
+
+def test_rotation_m2l_is_fp64_only():
+    pos, q = inputs.particles(1000, 152)
+    with pytest.raises(fmm.FMMError) as e:
+        gpu_eval(pos, q, 8, 32, "mixed", m2l_rotation=True)
+    assert e.value.status == fmm.FMM_EINVAL

@@ -115,3 +115,76 @@ def test_m2l_translation_invariance_and_symmetry():
             sg[n * n + 2 * m - 1] = (-1) ** (n + m)
             sg[n * n + 2 * m] = (-1) ** (n + m)
     assert np.allclose(np.diag(sg) @ T1 @ np.diag(sg), T2, rtol=1e-13, atol=1e-13 * np.abs(T1).max())
+
+
+# ------------------------------------------------ rotation-based M2L pieces
+
+def _m2l_offsets():
+    for idx in range(343):
+        o = (idx % 7 - 3, (idx // 7) % 7 - 3, idx // 49 - 3)
+        if max(map(abs, o)) >= 2:
+            yield idx, np.array(o, dtype=float)
+
+
+@pytest.mark.parametrize("P", [4, 10, 16])
+def test_rotation_m2l_equals_dense_m2l(P):
+    """Rotate, translate along z, rotate back: D^T Tz D is the dense M2L
+    matrix of every one of the 316 offsets (normwise, to round-off)."""
+    worst = 0.0
+    for idx, _ in _m2l_offsets():
+        T = fmm.operator_host(P, 2, idx)
+        D = fmm.operator_host(P, 3, idx)
+        Tz = fmm.operator_host(P, 4, idx)
+        worst = max(worst, np.linalg.norm(D.T @ Tz @ D - T) / np.linalg.norm(T))
+    assert worst < 1e-11
+
+
+@pytest.mark.parametrize("idx", [(2 + 3) + 7 * (1 + 3) + 49 * (3 + 3), (-3 + 3) + 7 * (3 + 3) + 49 * (-2 + 3),
+                                 (0 + 3) + 7 * (0 + 3) + 49 * (-2 + 3), (3 + 3) + 7 * (3 + 3) + 49 * (3 + 3)])
+def test_rotation_is_a_representation_of_the_offset_rotation(idx):
+    """D is block diagonal by degree; its degree-1 block holds a proper
+    rotation Q (from rho_1 = (z, -x/2, y/2)) that takes the offset's
+    direction to +z; and rho(Q u) = D rho(u) at random points, with rho
+    from the generating function (independent of the library)."""
+    P = 8
+    D = fmm.operator_host(P, 3, idx)
+    deg = np.array([int(np.floor(np.sqrt(c))) for c in range(P * P)])
+    assert np.all(D[deg[:, None] != deg[None, :]] == 0)
+    # degree 1: rho_1(u) = C u with C mapping (x, y, z) to (z, -x/2, y/2)
+    C = np.array([[0, 0, 1], [-0.5, 0, 0], [0, 0.5, 0]])
+    Q = np.linalg.solve(C, D[1:4, 1:4] @ C)
+    assert np.allclose(Q @ Q.T, np.eye(3), atol=1e-13) and abs(np.linalg.det(Q) - 1) < 1e-13
+    o = np.array([idx % 7 - 3, (idx // 7) % 7 - 3, idx // 49 - 3], dtype=float)
+    assert np.allclose(Q @ (o / np.linalg.norm(o)), [0, 0, 1], atol=1e-13)
+    u = np.random.default_rng(idx).uniform(-0.6, 0.6, (10, 3))
+    assert rel_l2(rho(P, u @ Q.T), rho(P, u) @ D.T) < 1e-13
+
+
+@pytest.mark.parametrize("idx", [(2 + 3) + 7 * (1 + 3) + 49 * (3 + 3), (3 + 3) + 7 * (3 + 3) + 49 * (3 + 3)])
+def test_z_translation_structure_and_value(oracle_mod, idx):
+    """Tz couples only coefficients of equal order and equal cosine/sine
+    kind, and it is the M2L of a source box straight below the target at
+    distance |o|: potentials agree with the oracle's Cartesian M2L."""
+    P = 8
+    Tz = fmm.operator_host(P, 4, idx)
+    order = np.zeros(P * P, dtype=int)
+    kind = np.zeros(P * P, dtype=int)
+    for n in range(P):
+        for m in range(1, n + 1):
+            order[n * n + 2 * m - 1] = order[n * n + 2 * m] = m
+            kind[n * n + 2 * m] = 1
+    off = (order[:, None] != order[None, :]) | (kind[:, None] != kind[None, :])
+    assert np.all(Tz[off] == 0)
+    o = np.array([idx % 7 - 3, (idx // 7) % 7 - 3, idx // 49 - 3], dtype=float)
+    w = 0.25
+    cs = np.array([0.5, 0.5, 0.2])
+    ct = cs + w * np.array([0.0, 0.0, np.linalg.norm(o)])
+    rng = np.random.default_rng(idx)
+    src = cs + rng.uniform(-w / 2, w / 2, (15, 3))
+    q = rng.uniform(0, 1, 15)
+    x = ct + rng.uniform(-w / 2, w / 2, (6, 3))
+    mu = (q[:, None] * rho(P, (src - cs) / w)).sum(0)
+    phi_rot = rho(P, (x - ct) / w) @ (Tz @ mu) / w
+    Lc = oracle_mod.m2l(P, oracle_mod.p2m(P, src, q, cs), cs, ct)
+    phi_cart, _ = oracle_mod.l2p(P, Lc, ct, x)
+    assert rel_l2(phi_rot, phi_cart) < 1e-12
