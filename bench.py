@@ -21,7 +21,9 @@ p = 10, leaf <= 64, inputs resident in HBM.  Prints one JSON line.
                dominates), its duration from stages_ms; traffic only on the
                workload the counter summaries were taken on
   tree_pass    the HBM-bound passes (build, P2M with the charge gather, L2P,
-               combine): algorithmic bytes over their time
+               combine): algorithmic bytes over their time; tree_pass_c4_counters
+               the same kernels at N = 1e8 with measured HBM bytes from the
+               committed rocprofv3 counter summary
   overlap      the same step with the near field on a concurrent stream
   c3           N = 1e7, p = 10, leaf <= 128, zero-mean charges: both forms,
                their dominant kernel, errors vs the direct sum and each other
@@ -125,6 +127,34 @@ def traffic_from_profile(kernel_file, summary):
     return (fetch + write) * 1024.0
 
 
+def tree_pass_counters():
+    """The tree passes at N = 1e8 (C4) from the committed counter summary:
+    per kernel the mean duration, measured HBM bytes (FETCH_SIZE + WRITE_SIZE,
+    scaled) and algorithmic bytes, or None when the summary is missing or the
+    kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "tree_passes_C4_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    csrc = os.path.join(ROOT, "paper_1106_2176_amd", "csrc")
+    for name in ("tree.hip", "far.hip"):
+        sha = hashlib.sha256(open(os.path.join(csrc, name), "rb").read()).hexdigest()
+        if "%s %s" % (name, sha) not in text:
+            return None
+    out = {}
+    for line in text.splitlines():
+        f = line.replace("(", " ").replace(")", " ").replace("+", " ").split()
+        if line.startswith("#") or len(f) < 6:
+            continue
+        if f[0] == "total":
+            out["total"] = {"us": float(f[1]), "measured_mb": float(f[2]), "algorithmic_mb": float(f[3]),
+                            "measured_gbs": float(f[4]), "algorithmic_gbs": float(f[5])}
+        else:
+            out[f[0]] = {"us": float(f[1]), "measured_mb": float(f[2]), "algorithmic_mb": float(f[5]),
+                         "measured_gbs": float(f[6]), "algorithmic_gbs": float(f[7])}
+    return out or None
+
+
 def copy_probe():
     import torch
     x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda:0")
@@ -184,7 +214,7 @@ def rooflines(wl, res, precision, enc, on_profiled):
     p2p = {"kernel": "k_p2p<%s>" % ("double" if f64 else "float"), "bound": "alu", "achieved": p2p_tf,
            "peak": PEAK_FP64_TFLOPS if f64 else PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
            "frac": p2p_tf / (PEAK_FP64_TFLOPS if f64 else PEAK_FP32_VECTOR_TFLOPS),
-           "traffic": traffic_from_profile("p2p.hip", "p2p_C2_traffic.txt") if on_profiled and not f64 else None,
+           "traffic": traffic_from_profile("p2p.hip", "p2p_C2_counters.txt") if on_profiled and not f64 else None,
            "ms": p2p_ms, "flop_per_launch": P2P_FLOP_PER_PAIR * pairs}
     if not f64:
         p2p["peak_unpacked"] = PEAK_FP32_UNPACKED_TFLOPS
@@ -199,7 +229,7 @@ def rooflines(wl, res, precision, enc, on_profiled):
         m2l = {"kernel": "k_m2l_bf16<%d,%d,8,%s>" % (nparts, wl.p, "fp16" if opts.get("m2l_fp16") else "bf16"),
                "bound": "mfma", "achieved": m2l_tf, "peak": PEAK_16BIT_MFMA_TFLOPS, "unit": "TFLOP/s",
                "frac": m2l_tf / PEAK_16BIT_MFMA_TFLOPS,
-               "traffic": traffic_from_profile("m2l.hip", "m2l_%s_C2_traffic.txt" % enc) if on_profiled else None,
+               "traffic": traffic_from_profile("m2l.hip", "m2l_%s_C2_counters.txt" % enc) if on_profiled else None,
                "encoding": enc, "mfma_products_per_term": products}
     m2l.update({"ms": m2l_ms, "flop_per_launch": 2.0 * wl.p ** 4 * m2l_pairs})
     return (m2l, p2p) if dom == "M2L" else (p2p, m2l)
@@ -397,6 +427,7 @@ def main():
         "roofline": roof,
         ("roofline_p2p" if mixed["dom"] == "M2L" else "roofline_m2l"): other,
         "tree_pass": tree_pass(wl, mixed, "mixed"),
+        "tree_pass_c4_counters": tree_pass_counters(),
         "rel_l2": rel,
         "overlap": overlap,
         "c3": c3,

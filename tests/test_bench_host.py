@@ -50,7 +50,8 @@ def test_committed_profiles_name_their_kernel_sources():
     """Each committed counter summary records the hash of a kernel source
     that exists (whether it still matches is checked at bench time)."""
     prof = os.path.join(bench.ROOT, "profiles")
-    for name, src in (("p2p_C2_traffic.txt", "p2p.hip"), ("m2l_bf16x3_C2_traffic.txt", "m2l.hip")):
+    for name, src in (("p2p_C2_counters.txt", "p2p.hip"), ("m2l_bf16x3_C2_counters.txt", "m2l.hip"),
+                      ("m2l_fp16x2_C2_counters.txt", "m2l.hip")):
         text = open(os.path.join(prof, name)).read()
         assert "source_sha256:" in text and "copy_fetch_factor:" in text
         assert os.path.exists(os.path.join(bench.ROOT, "paper_1106_2176_amd", "csrc", src))
@@ -88,3 +89,11 @@ def test_tree_pass_bytes_per_particle():
     # combine per particle, plus the leaf coefficients written and read once
     assert tp["bytes"] == 1_000_000 * (92 + 32 + 48 + 108) + 2 * 32768 * 104 * 4
     assert tp["ms"] == pytest.approx(0.1 + 0.05 + 0.05 + 0.04)
+
+
+def test_tree_pass_counters_read_from_the_committed_summary():
+    tp = bench.tree_pass_counters()
+    assert tp is not None, "the tree-pass summary no longer matches tree.hip / far.hip"
+    for k in ("k_keys", "k_place", "k_fixup", "k_p2m", "k_l2p", "k_combine", "total"):
+        assert tp[k]["us"] > 0 and tp[k]["measured_mb"] > 0 and tp[k]["algorithmic_mb"] > 0
+    assert abs(sum(tp[k]["us"] for k in tp if k != "total") - tp["total"]["us"]) < 1.0
