@@ -41,6 +41,12 @@ def _load():
         lib.oracle_l2p.argtypes = [ctypes.c_int, v, v, ctypes.c_int64, v, v, v]
         lib.oracle_m_eval.argtypes = [ctypes.c_int, v, v, ctypes.c_int64, v, v]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_adaptive_sizes.argtypes = [ctypes.c_int64, v, ctypes.c_int, ctypes.c_int, v,
+                                              ctypes.c_double, v]
+        lib.oracle_adaptive_lists.argtypes = [ctypes.c_int64, v, ctypes.c_int, ctypes.c_int, v,
+                                              ctypes.c_double, v, v, v, v]
+        lib.oracle_fmm_adaptive.argtypes = [ctypes.c_int64, v, v, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, v, ctypes.c_double, v, v, v, v, v]
         _lib = lib
     return _lib
 
@@ -228,3 +234,49 @@ def direct_grad(pos, q, w):
     w = _f64(w)
     q = _f64(q)
     return phw, -(w[:, None] * Eq + q[:, None] * Ew)
+
+
+def adaptive_tree(pos, leaf_max, max_level=10, lo=(0.0, 0.0, 0.0), size=1.0):
+    """The adaptive octree and its U/V/W/X lists.
+
+    Returns a dict: boxes [nbox, 8] int64 (level, ix, iy, iz, start, end,
+    parent, leaf; breadth-first, Morton order within a level, box 0 the
+    root), order [n] (sorted position -> input index; every box is the range
+    [start, end) of it), depth, and the lists U, V, W, X, each a Python list
+    of nbox numpy arrays of box ids."""
+    pos = _f64(pos, (-1, 3))
+    lo = _f64(lo, (3,))
+    n = pos.shape[0]
+    sz = np.zeros(6, dtype=np.int64)
+    L = _load()
+    _check(L.oracle_adaptive_sizes(n, _ptr(pos), leaf_max, max_level, _ptr(lo), size, _ptr(sz)))
+    nbox = int(sz[0])
+    boxes = np.zeros((nbox, 8), dtype=np.int64)
+    order = np.zeros(n, dtype=np.int64)
+    starts = np.zeros(4 * (nbox + 1), dtype=np.int64)
+    items = np.zeros(max(1, int(sz[1:5].sum())), dtype=np.int64)
+    _check(L.oracle_adaptive_lists(n, _ptr(pos), leaf_max, max_level, _ptr(lo), size, _ptr(boxes),
+                                   _ptr(order), _ptr(starts), _ptr(items)))
+    out = {"boxes": boxes, "order": order, "depth": int(sz[5])}
+    for w, name in enumerate("UVWX"):
+        st = starts[w * (nbox + 1):(w + 1) * (nbox + 1)]
+        out[name] = [items[st[b]:st[b + 1]].copy() for b in range(nbox)]
+    return out
+
+
+def fmm_adaptive(pos, q, p, leaf_max, max_level=10, lo=(0.0, 0.0, 0.0), size=1.0):
+    """FP64 FMM on the adaptive octree (U/V/W/X lists).  Returns a dict with
+    phi, E (total), the near (P2P) and far parts, and nbox, nleaf, depth."""
+    pos = _f64(pos, (-1, 3))
+    q = _f64(q)
+    lo = _f64(lo, (3,))
+    n = pos.shape[0]
+    pn = np.zeros(n)
+    en = np.zeros((n, 3))
+    pf = np.zeros(n)
+    ef = np.zeros((n, 3))
+    info = np.zeros(3, dtype=np.int64)
+    _check(_load().oracle_fmm_adaptive(n, _ptr(pos), _ptr(q), p, leaf_max, max_level, _ptr(lo), size,
+                                       _ptr(pn), _ptr(en), _ptr(pf), _ptr(ef), _ptr(info)))
+    return {"phi": pn + pf, "E": en + ef, "phi_near": pn, "E_near": en, "phi_far": pf,
+            "E_far": ef, "nbox": int(info[0]), "nleaf": int(info[1]), "depth": int(info[2])}

@@ -789,3 +789,543 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* adaptive tree (the next step named in Sec. 5, future directions:   */
+/* switching between uniform and adaptive tree construction)          */
+/* ------------------------------------------------------------------ */
+/*
+ * The paper names adaptive construction but fixes no rule; this oracle takes
+ * the classic one.  A box holding more than leaf_max particles is split into
+ * its eight children while its level is below max_level; children with no
+ * particles are not created; unsplit boxes are leaves.  Two boxes are
+ * adjacent when their closed cubes intersect and neither contains the other;
+ * a box's colleagues are the adjacent boxes of its own level.  Lists:
+ *   U(b), b a leaf: b and every leaf adjacent to b             -> P2P
+ *   V(b), any box:  children of the colleagues of b's parent
+ *                   that are not adjacent to b                 -> M2L
+ *   W(b), b a leaf: descendants of b's colleagues that are not
+ *                   adjacent to b but whose parent is          -> M2P
+ *   X(b), any box:  the boxes c with b in W(c)                 -> P2L
+ * Every ordered pair of particles is then accounted for exactly once: by
+ * P2P, or by one M2L between ancestors (or the leaves themselves), or by
+ * one M2P / P2L between a leaf and an ancestor of the other leaf.
+ *   M2P  phi(x) = sum_a (-1)^|a| M_a D^a G(x - c),  E = -grad phi (exact
+ *        gradient of the truncated multipole field)
+ *   P2L  L_b(c) = sum_j q_j D^b G(c - x_j) / b!
+ */
+typedef struct {
+    int l;
+    int64_t ix, iy, iz;  /* integer coordinates at level l */
+    int64_t start, end;  /* particle range in the sorted order */
+    int parent;
+    int child[8];        /* -1: no child (empty or unsplit) */
+    int leaf;
+} abox;
+
+typedef struct {
+    int *v;
+    int n, cap;
+} ilist;
+
+static int ilist_push(ilist *a, int x)
+{
+    if (a->n == a->cap) {
+        int nc = a->cap ? 2 * a->cap : 8;
+        int *nv = (int *)realloc(a->v, sizeof(int) * (size_t)nc);
+        if (!nv) return 1;
+        a->v = nv;
+        a->cap = nc;
+    }
+    a->v[a->n++] = x;
+    return 0;
+}
+
+typedef struct {
+    int nbox, cap;
+    abox *box;
+    int depth;
+    int64_t *order;  /* sorted particle order (input indices) */
+    ilist *U, *V, *W, *X;
+    int *lev_first, *lev_count;  /* boxes of each level, contiguous, Morton order */
+} atree;
+
+/* closed-cube intersection of boxes a and b, not nested */
+static int adjacent(const abox *a, const abox *b)
+{
+    const abox *f = a->l >= b->l ? a : b, *c = a->l >= b->l ? b : a;
+    int k = f->l - c->l, ax;
+    int64_t fi[3] = {f->ix, f->iy, f->iz}, ci[3] = {c->ix, c->iy, c->iz};
+    int inside = 1;
+    for (ax = 0; ax < 3; ++ax) {
+        int64_t lo = ci[ax] << k, hi = ((ci[ax] + 1) << k) - 1;  /* c's span at f's level */
+        if (fi[ax] < lo - 1 || fi[ax] > hi + 1) return 0;
+        if (fi[ax] < lo || fi[ax] > hi) inside = 0;
+    }
+    return !inside;
+}
+
+static int find_box(const atree *t, int l, int64_t ix, int64_t iy, int64_t iz)
+{
+    int64_t side = (int64_t)1 << l, key;
+    int lo, hi;
+    if (l > t->depth || ix < 0 || iy < 0 || iz < 0 || ix >= side || iy >= side || iz >= side) return -1;
+    key = (int64_t)morton(ix, iy, iz, l);
+    lo = t->lev_first[l];
+    hi = lo + t->lev_count[l] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        const abox *b = t->box + mid;
+        int64_t k = (int64_t)morton(b->ix, b->iy, b->iz, l);
+        if (k == key) return mid;
+        if (k < key) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+static void atree_free(atree *t)
+{
+    int i;
+    if (t->U)
+        for (i = 0; i < t->nbox; ++i) {
+            free(t->U[i].v);
+            free(t->V[i].v);
+            free(t->W[i].v);
+            free(t->X[i].v);
+        }
+    free(t->U);
+    free(t->V);
+    free(t->W);
+    free(t->X);
+    free(t->box);
+    free(t->order);
+    free(t->lev_first);
+    free(t->lev_count);
+}
+
+typedef struct {
+    uint64_t key;
+    int64_t idx;
+} keyidx;
+
+static int keyidx_cmp(const void *a, const void *b)
+{
+    const keyidx *x = (const keyidx *)a, *y = (const keyidx *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+/* descend from box d (a child of a colleague of leaf b): adjacent leaves go
+ * to U(b), non-adjacent boxes to W(b), adjacent split boxes are opened */
+static int descend_uw(atree *t, int b, int d)
+{
+    const abox *bb = t->box + b, *dd = t->box + d;
+    int c;
+    if (!adjacent(bb, dd)) return ilist_push(&t->W[b], d);
+    if (dd->leaf) return ilist_push(&t->U[b], d);
+    for (c = 0; c < 8; ++c)
+        if (dd->child[c] >= 0 && descend_uw(t, b, dd->child[c])) return 1;
+    return 0;
+}
+
+static int atree_build(int64_t n, const double *pos, int leaf_max, int max_level, const double lo[3],
+                       double size, atree *t)
+{
+    keyidx *ki;
+    int64_t i;
+    int b, l;
+    memset(t, 0, sizeof(*t));
+    ki = (keyidx *)malloc(sizeof(keyidx) * (size_t)n);
+    t->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!ki || !t->order) return ORACLE_ENOMEM;
+    /* particles sorted by their finest-level Morton key (stable): every box
+     * of every level is then one contiguous range */
+    for (i = 0; i < n; ++i) {
+        ki[i].key = morton(box_coord(pos[3 * i], lo[0], size, max_level),
+                           box_coord(pos[3 * i + 1], lo[1], size, max_level),
+                           box_coord(pos[3 * i + 2], lo[2], size, max_level), max_level);
+        ki[i].idx = i;
+    }
+    qsort(ki, (size_t)n, sizeof(keyidx), keyidx_cmp);
+    for (i = 0; i < n; ++i) t->order[i] = ki[i].idx;
+    /* breadth-first construction: level by level, Morton order within a level */
+    t->cap = 64;
+    t->box = (abox *)malloc(sizeof(abox) * (size_t)t->cap);
+    t->lev_first = (int *)calloc((size_t)max_level + 2, sizeof(int));
+    t->lev_count = (int *)calloc((size_t)max_level + 2, sizeof(int));
+    if (!t->box || !t->lev_first || !t->lev_count) return ORACLE_ENOMEM;
+    memset(t->box, 0, sizeof(abox));
+    t->box[0].start = 0;
+    t->box[0].end = n;
+    t->box[0].parent = -1;
+    t->nbox = 1;
+    t->lev_first[0] = 0;
+    t->lev_count[0] = 1;
+    t->depth = 0;
+    for (l = 0; l <= max_level; ++l) {
+        int first = t->lev_first[l], cnt = t->lev_count[l];
+        t->lev_first[l + 1] = t->nbox;
+        for (b = first; b < first + cnt; ++b) {
+            abox *bx = t->box + b;
+            int c;
+            for (c = 0; c < 8; ++c) bx->child[c] = -1;
+            bx->leaf = !(bx->end - bx->start > leaf_max && l < max_level);
+            if (bx->leaf) continue;
+            {
+                int64_t s = bx->start;
+                int sh = 3 * (max_level - l - 1);
+                for (c = 0; c < 8; ++c) {
+                    uint64_t ck = ((uint64_t)morton(bx->ix, bx->iy, bx->iz, l) << 3) | (uint64_t)c;
+                    int64_t e = s;
+                    while (e < bx->end && (ki[e].key >> sh) == ck) ++e;
+                    if (e > s) {
+                        abox *nb;
+                        if (t->nbox == t->cap) {
+                            abox *nbx = (abox *)realloc(t->box, sizeof(abox) * (size_t)t->cap * 2);
+                            if (!nbx) return ORACLE_ENOMEM;
+                            t->box = nbx;
+                            t->cap *= 2;
+                            bx = t->box + b;
+                        }
+                        nb = t->box + t->nbox;
+                        memset(nb, 0, sizeof(abox));
+                        nb->l = l + 1;
+                        nb->ix = 2 * bx->ix + (c & 1);
+                        nb->iy = 2 * bx->iy + ((c >> 1) & 1);
+                        nb->iz = 2 * bx->iz + (c >> 2);
+                        nb->start = s;
+                        nb->end = e;
+                        nb->parent = b;
+                        bx->child[c] = t->nbox++;
+                    }
+                    s = e;
+                }
+            }
+        }
+        t->lev_count[l + 1] = t->nbox - t->lev_first[l + 1];
+        if (t->lev_count[l + 1] == 0) break;
+        t->depth = l + 1;
+    }
+    free(ki);
+    /* lists */
+    t->U = (ilist *)calloc((size_t)t->nbox, sizeof(ilist));
+    t->V = (ilist *)calloc((size_t)t->nbox, sizeof(ilist));
+    t->W = (ilist *)calloc((size_t)t->nbox, sizeof(ilist));
+    t->X = (ilist *)calloc((size_t)t->nbox, sizeof(ilist));
+    if (!t->U || !t->V || !t->W || !t->X) return ORACLE_ENOMEM;
+    for (b = 0; b < t->nbox; ++b) {
+        const abox *bx = t->box + b;
+        int64_t dx, dy, dz;
+        /* V: children of the parent's colleagues, not adjacent to b */
+        if (bx->parent >= 0) {
+            const abox *pa = t->box + bx->parent;
+            for (dz = -1; dz <= 1; ++dz)
+                for (dy = -1; dy <= 1; ++dy)
+                    for (dx = -1; dx <= 1; ++dx) {
+                        int pc = find_box(t, pa->l, pa->ix + dx, pa->iy + dy, pa->iz + dz), c;
+                        if (pc < 0) continue;
+                        for (c = 0; c < 8; ++c) {
+                            int s = t->box[pc].child[c];
+                            if (s < 0 || s == b) continue;
+                            if (!adjacent(bx, t->box + s) && ilist_push(&t->V[b], s)) return ORACLE_ENOMEM;
+                        }
+                    }
+        }
+        if (!bx->leaf) continue;
+        /* U: b itself; coarser adjacent leaves (colleagues of ancestors);
+         * same-level adjacent leaves; finer ones below the colleagues.
+         * W: non-adjacent descendants of colleagues with adjacent parents. */
+        if (ilist_push(&t->U[b], b)) return ORACLE_ENOMEM;
+        {
+            int a = bx->parent;
+            while (a >= 0) {
+                const abox *an = t->box + a;
+                for (dz = -1; dz <= 1; ++dz)
+                    for (dy = -1; dy <= 1; ++dy)
+                        for (dx = -1; dx <= 1; ++dx) {
+                            int c;
+                            if (!dx && !dy && !dz) continue;
+                            c = find_box(t, an->l, an->ix + dx, an->iy + dy, an->iz + dz);
+                            if (c >= 0 && t->box[c].leaf && adjacent(bx, t->box + c) &&
+                                ilist_push(&t->U[b], c))
+                                return ORACLE_ENOMEM;
+                        }
+                a = an->parent;
+            }
+        }
+        for (dz = -1; dz <= 1; ++dz)
+            for (dy = -1; dy <= 1; ++dy)
+                for (dx = -1; dx <= 1; ++dx) {
+                    int c, k;
+                    if (!dx && !dy && !dz) continue;
+                    c = find_box(t, bx->l, bx->ix + dx, bx->iy + dy, bx->iz + dz);
+                    if (c < 0) continue;
+                    if (t->box[c].leaf) {
+                        if (ilist_push(&t->U[b], c)) return ORACLE_ENOMEM;
+                        continue;
+                    }
+                    for (k = 0; k < 8; ++k)
+                        if (t->box[c].child[k] >= 0 && descend_uw(t, b, t->box[c].child[k])) return ORACLE_ENOMEM;
+                }
+    }
+    /* X: the dual of W */
+    for (b = 0; b < t->nbox; ++b) {
+        int k;
+        for (k = 0; k < t->W[b].n; ++k)
+            if (ilist_push(&t->X[t->W[b].v[k]], b)) return ORACLE_ENOMEM;
+    }
+    return ORACLE_OK;
+}
+
+static void abox_centre(const abox *b, const double lo[3], double size, double c[3])
+{
+    double w = size / (double)((int64_t)1 << b->l);
+    centre(lo, w, b->ix, b->iy, b->iz, c);
+}
+
+/*
+ * Tree and lists of the adaptive FMM, for tests.  Boxes in breadth-first,
+ * Morton order (box 0 is the root).  box_out[b*8 + 0..7] = level, ix, iy,
+ * iz, start, end, parent, leaf.  Lists as CSR: *_start[nbox+1], *_items;
+ * the caller sizes the outputs from oracle_adaptive_sizes.
+ */
+int oracle_adaptive_sizes(int64_t n, const double *pos, int leaf_max, int max_level, const double *lo,
+                          double size, int64_t *sizes_out /* nbox, nU, nV, nW, nX, depth */)
+{
+    atree t;
+    int rc, b;
+    int64_t s[4] = {0, 0, 0, 0};
+    if (n < 1 || leaf_max < 1 || max_level < 0 || max_level > 10 || !(size > 0)) return ORACLE_EINVAL;
+    if (check_domain(n, pos, lo, size)) return ORACLE_EDOMAIN;
+    rc = atree_build(n, pos, leaf_max, max_level, lo, size, &t);
+    if (rc) {
+        atree_free(&t);
+        return rc;
+    }
+    for (b = 0; b < t.nbox; ++b) {
+        s[0] += t.U[b].n;
+        s[1] += t.V[b].n;
+        s[2] += t.W[b].n;
+        s[3] += t.X[b].n;
+    }
+    sizes_out[0] = t.nbox;
+    sizes_out[1] = s[0];
+    sizes_out[2] = s[1];
+    sizes_out[3] = s[2];
+    sizes_out[4] = s[3];
+    sizes_out[5] = t.depth;
+    atree_free(&t);
+    return ORACLE_OK;
+}
+
+int oracle_adaptive_lists(int64_t n, const double *pos, int leaf_max, int max_level, const double *lo,
+                          double size, int64_t *box_out, int64_t *order_out, int64_t *lst_start,
+                          int64_t *lst_items /* U, V, W, X: each [nbox+1] starts, items concatenated */)
+{
+    atree t;
+    int rc, b, w, k;
+    int64_t at = 0;
+    ilist *L[4];
+    rc = atree_build(n, pos, leaf_max, max_level, lo, size, &t);
+    if (rc) {
+        atree_free(&t);
+        return rc;
+    }
+    for (b = 0; b < t.nbox; ++b) {
+        const abox *x = t.box + b;
+        int64_t *o = box_out + 8 * (int64_t)b;
+        o[0] = x->l;
+        o[1] = x->ix;
+        o[2] = x->iy;
+        o[3] = x->iz;
+        o[4] = x->start;
+        o[5] = x->end;
+        o[6] = x->parent;
+        o[7] = x->leaf;
+    }
+    memcpy(order_out, t.order, sizeof(int64_t) * (size_t)n);
+    L[0] = t.U;
+    L[1] = t.V;
+    L[2] = t.W;
+    L[3] = t.X;
+    for (w = 0; w < 4; ++w)
+        for (b = 0; b < t.nbox; ++b) {
+            lst_start[(int64_t)w * (t.nbox + 1) + b] = at;
+            for (k = 0; k < L[w][b].n; ++k) lst_items[at++] = L[w][b].v[k];
+            lst_start[(int64_t)w * (t.nbox + 1) + b + 1] = at;
+        }
+    atree_free(&t);
+    return ORACLE_OK;
+}
+
+/* The adaptive FMM: P2M at the leaves, M2M upward, M2L over V and P2L over X
+ * into every box, L2L downward, L2P and M2P over W at the leaves, P2P over U.
+ * Outputs per particle in input order; near = P2P, far = everything else. */
+int oracle_fmm_adaptive(int64_t n, const double *pos, const double *q, int p, int leaf_max,
+                        int max_level, const double *lo, double size, double *phi_near,
+                        double *E_near, double *phi_far, double *E_far, int64_t *info_out)
+{
+    atree t;
+    mindex mp, md, mg;
+    int rc, b, l;
+    double *M = NULL, *Lc = NULL;
+    int *sumidx = NULL;
+    int64_t i;
+    if (n < 1 || p < 1 || p > 30 || leaf_max < 1 || max_level < 0 || max_level > 10 || !(size > 0))
+        return ORACLE_EINVAL;
+    if (check_domain(n, pos, lo, size)) return ORACLE_EDOMAIN;
+    rc = atree_build(n, pos, leaf_max, max_level, lo, size, &t);
+    if (rc) {
+        atree_free(&t);
+        return rc;
+    }
+    if (mindex_init(&mp, p - 1) || mindex_init(&md, 2 * p - 2) || mindex_init(&mg, p)) return ORACLE_ENOMEM;
+    M = (double *)calloc((size_t)t.nbox * mp.n, sizeof(double));
+    Lc = (double *)calloc((size_t)t.nbox * mp.n, sizeof(double));
+    sumidx = m2l_sum_table(&mp, &md);
+    if (!M || !Lc || !sumidx) return ORACLE_ENOMEM;
+    for (i = 0; i < n; ++i) {
+        phi_near[i] = phi_far[i] = 0.0;
+        E_near[3 * i] = E_near[3 * i + 1] = E_near[3 * i + 2] = 0.0;
+        E_far[3 * i] = E_far[3 * i + 1] = E_far[3 * i + 2] = 0.0;
+    }
+    /* P2M at the leaves, M2M from the deepest level up */
+    for (l = t.depth; l >= 0; --l) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (b = t.lev_first[l]; b < t.lev_first[l] + t.lev_count[l]; ++b) {
+            const abox *x = t.box + b;
+            double c[3];
+            int k;
+            abox_centre(x, lo, size, c);
+            if (x->leaf) {
+                p2m(&mp, x->end - x->start, t.order + x->start, pos, q, c, M + (size_t)b * mp.n);
+                continue;
+            }
+            for (k = 0; k < 8; ++k) {
+                double c1[3];
+                if (x->child[k] < 0) continue;
+                abox_centre(t.box + x->child[k], lo, size, c1);
+                m2m(&mp, M + (size_t)x->child[k] * mp.n, c1, c, M + (size_t)b * mp.n);
+            }
+        }
+    }
+    /* M2L over V and P2L over X into every box */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (b = 0; b < t.nbox; ++b) {
+        const abox *x = t.box + b;
+        double ct[3], *dG = (double *)malloc(sizeof(double) * md.n);
+        int k;
+        int64_t j;
+        abox_centre(x, lo, size, ct);
+        for (k = 0; k < t.V[b].n; ++k) {
+            double cs[3], d[3];
+            abox_centre(t.box + t.V[b].v[k], lo, size, cs);
+            d[0] = ct[0] - cs[0];
+            d[1] = ct[1] - cs[1];
+            d[2] = ct[2] - cs[2];
+            derivs(&md, d, dG);
+            m2l(&mp, sumidx, M + (size_t)t.V[b].v[k] * mp.n, dG, Lc + (size_t)b * mp.n);
+        }
+        for (k = 0; k < t.X[b].n; ++k) {
+            const abox *s = t.box + t.X[b].v[k];
+            for (j = s->start; j < s->end; ++j) {
+                int64_t jp = t.order[j];
+                double d[3] = {ct[0] - pos[3 * jp], ct[1] - pos[3 * jp + 1], ct[2] - pos[3 * jp + 2]};
+                int a;
+                derivs(&mp, d, dG);
+                for (a = 0; a < mp.n; ++a) {
+                    const int *bb = mp.k + 3 * a;
+                    Lc[(size_t)b * mp.n + a] += q[jp] * dG[a] / (fact(bb[0]) * fact(bb[1]) * fact(bb[2]));
+                }
+            }
+        }
+        free(dG);
+    }
+    /* L2L from the root down */
+    for (l = 1; l <= t.depth; ++l) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (b = t.lev_first[l]; b < t.lev_first[l] + t.lev_count[l]; ++b) {
+            double c1[3], c2[3];
+            abox_centre(t.box + t.box[b].parent, lo, size, c1);
+            abox_centre(t.box + b, lo, size, c2);
+            l2l(&mp, Lc + (size_t)t.box[b].parent * mp.n, c1, c2, Lc + (size_t)b * mp.n);
+        }
+    }
+    /* at the leaves: L2P, M2P over W, P2P over U */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (b = 0; b < t.nbox; ++b) {
+        const abox *x = t.box + b;
+        double c[3], *dG;
+        int64_t ii;
+        if (!x->leaf) continue;
+        abox_centre(x, lo, size, c);
+        dG = (double *)malloc(sizeof(double) * mg.n);
+        for (ii = x->start; ii < x->end; ++ii) {
+            int64_t ip = t.order[ii], j;
+            double f, E[3];
+            int k, a;
+            l2p(&mp, Lc + (size_t)b * mp.n, c, pos + 3 * ip, &f, E);
+            for (k = 0; k < t.W[b].n; ++k) {
+                const double *Mw = M + (size_t)t.W[b].v[k] * mp.n;
+                double cw[3], d[3];
+                abox_centre(t.box + t.W[b].v[k], lo, size, cw);
+                d[0] = pos[3 * ip] - cw[0];
+                d[1] = pos[3 * ip + 1] - cw[1];
+                d[2] = pos[3 * ip + 2] - cw[2];
+                derivs(&mg, d, dG);
+                for (a = 0; a < mp.n; ++a) {
+                    const int *al = mp.k + 3 * a;
+                    double sg = (mp.deg[a] & 1) ? -1.0 : 1.0;
+                    f += sg * Mw[a] * dG[mi(&mg, al[0], al[1], al[2])];
+                    E[0] -= sg * Mw[a] * dG[mi(&mg, al[0] + 1, al[1], al[2])];
+                    E[1] -= sg * Mw[a] * dG[mi(&mg, al[0], al[1] + 1, al[2])];
+                    E[2] -= sg * Mw[a] * dG[mi(&mg, al[0], al[1], al[2] + 1)];
+                }
+            }
+            phi_far[ip] = f;
+            E_far[3 * ip] = E[0];
+            E_far[3 * ip + 1] = E[1];
+            E_far[3 * ip + 2] = E[2];
+            f = E[0] = E[1] = E[2] = 0.0;
+            for (k = 0; k < t.U[b].n; ++k) {
+                const abox *s = t.box + t.U[b].v[k];
+                for (j = s->start; j < s->end; ++j) {
+                    int64_t jp = t.order[j];
+                    double d0, d1, d2, r2, r;
+                    if (jp == ip) continue;
+                    d0 = pos[3 * ip] - pos[3 * jp];
+                    d1 = pos[3 * ip + 1] - pos[3 * jp + 1];
+                    d2 = pos[3 * ip + 2] - pos[3 * jp + 2];
+                    r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                    if (r2 == 0.0) continue;
+                    r = sqrt(r2);
+                    f += q[jp] / r;
+                    E[0] += q[jp] * d0 / (r2 * r);
+                    E[1] += q[jp] * d1 / (r2 * r);
+                    E[2] += q[jp] * d2 / (r2 * r);
+                }
+            }
+            phi_near[ip] = f;
+            E_near[3 * ip] = E[0];
+            E_near[3 * ip + 1] = E[1];
+            E_near[3 * ip + 2] = E[2];
+        }
+        free(dG);
+    }
+    if (info_out) {
+        int nleaf = 0;
+        for (b = 0; b < t.nbox; ++b) nleaf += t.box[b].leaf;
+        info_out[0] = t.nbox;
+        info_out[1] = nleaf;
+        info_out[2] = t.depth;
+    }
+    free(M);
+    free(Lc);
+    free(sumidx);
+    mindex_free(&mp);
+    mindex_free(&md);
+    mindex_free(&mg);
+    atree_free(&t);
+    return ORACLE_OK;
+}

@@ -10,7 +10,8 @@ Generator: numpy PCG64 (``numpy.random.default_rng(seed)``).
              workload is FP32;
   charges    U[0,1), or U[-1,1) for the zero-mean workload;
   targets    ``default_rng(seed + 100).choice(N, n_targets, replace=False)``;
-  weights    ``default_rng(seed + 200).standard_normal(N)`` (loss weights).
+  weights    ``default_rng(seed + 200).standard_normal(N)`` (loss weights);
+  clustered  Gaussian blobs for the adaptive tree (``clustered``).
 """
 from dataclasses import dataclass
 
@@ -73,3 +74,18 @@ def targets(n: int, seed: int, n_targets: int = 1000) -> np.ndarray:
 def weights(n: int, seed: int) -> np.ndarray:
     """Loss weights w ~ N(0,1) for the weighted-potential loss."""
     return np.random.default_rng(seed + 200).standard_normal(n)
+
+
+def clustered(n: int, seed: int, blobs: int = 6, dtype: str = "f64"):
+    """Positions [n,3] in Gaussian blobs and charges U[0,1) (inputs of the
+    adaptive tree).  Blob centres U[0.2,0.8)^3, widths U[0.005,0.06), each
+    particle in a uniformly chosen blob; coordinates clipped into [0,1)."""
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform(0.2, 0.8, (blobs, 3))
+    width = rng.uniform(0.005, 0.06, blobs)
+    lab = rng.integers(0, blobs, n)
+    pos = np.clip(cen[lab] + rng.normal(size=(n, 3)) * width[lab, None], 0.0, np.nextafter(1.0, 0.0))
+    q = rng.random(n)
+    if dtype == "f32":
+        return pos.astype(np.float32), q.astype(np.float32)
+    return pos, q
