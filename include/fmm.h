@@ -131,8 +131,38 @@ typedef struct {
                                   made on the first build that asks for them (a
                                   quadrature per offset, about a second of host
                                   time at p = 16) and kept per device and p. */
-    int32_t reserved[2];       /* zero */
+    int32_t adaptive;          /* FP64 form only (FMM_EUNSUPPORTED otherwise),
+                                  not with m2l_rotation (FMM_EUNSUPPORTED):
+                                  nonzero = the adaptive octree of the
+                                  construction Sec. 5 names beside the uniform
+                                  one.  A box is split while it holds more than
+                                  leaf_max particles and its level is below
+                                  max_level, which is at most
+                                  FMM_ADAPTIVE_MAX_LEVEL (FMM_EINVAL above);
+                                  empty children are dropped, so leaves sit at
+                                  many levels.  The interactions follow the
+                                  U/V/W/X lists of the adaptive FMM: U(b), b a
+                                  leaf: b and the leaves touching it (P2P); V(b):
+                                  the children of the colleagues of b's parent
+                                  not touching b (M2L, the dense FP64 product
+                                  on the matrix cores); W(b), b a leaf: the
+                                  descendants of b's colleagues that do not
+                                  touch b but whose parent does (the multipole
+                                  evaluated at b's particles, M2P); X(b): the
+                                  leaves c with b in W(c) (each particle of c
+                                  expanded about b's centre, P2L).  Two boxes
+                                  touch when their closed cubes intersect and
+                                  neither contains the other.  fmm_backward
+                                  and overlap_near are not available on such a
+                                  tree (FMM_EUNSUPPORTED / ignored); the build
+                                  blocks once per tree level and once more at
+                                  the end, until a few counts have reached the
+                                  host. */
+    int32_t reserved[1];       /* zero */
 } fmm_config;
+
+/* Deepest level of an adaptive tree (the finest Morton sort has 8^8 bins). */
+#define FMM_ADAPTIVE_MAX_LEVEL 8
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
  * precision with the binary16 M2L encoding (m2l_fp16 = 1; bf16_splits = 3
@@ -143,15 +173,23 @@ void fmm_config_default(fmm_config *cfg);
 typedef struct fmm_tree fmm_tree; /* opaque, library-owned */
 
 typedef struct {
-    int32_t levels;            /* leaf level L (the tree has levels 0..L) */
+    int32_t levels;            /* leaf level L (the tree has levels 0..L); adaptive
+                                  tree: its deepest level */
     int32_t p;
     int64_t n;
-    int64_t n_leaves;          /* 8^L */
+    int64_t n_leaves;          /* 8^L; adaptive tree: its (non-empty) leaves */
     int64_t max_leaf_count;    /* fullest leaf */
     int64_t p2p_pairs;         /* ordered pairs (i, j), i != j, in each other's near field
-                                  (27-leaf neighbourhood), i.e. P2P interactions evaluated */
-    int64_t m2l_pairs;         /* (target box, source box) M2L translations over all levels */
+                                  (27-leaf neighbourhood; adaptive tree: the U lists),
+                                  i.e. P2P interactions evaluated */
+    int64_t m2l_pairs;         /* (target box, source box) M2L translations over all levels
+                                  (adaptive tree: the V lists) */
     size_t workspace_bytes;    /* device memory held by the tree */
+    int64_t n_boxes;           /* boxes of all levels (uniform tree: sum of 8^l) */
+    int64_t m2p_evals;         /* adaptive tree: (particle, box) pairs of the W
+                                  lists, i.e. multipole evaluations; 0 otherwise */
+    int64_t p2l_evals;         /* adaptive tree: (particle, box) pairs of the X
+                                  lists, i.e. particle-to-local expansions */
 } fmm_tree_info_t;
 
 /*
@@ -286,6 +324,26 @@ fmm_status fmm_stage_times_reset(fmm_tree *tree);
  * perm[n] (sorted position -> input index, uint32), leaf_start[8^L + 1]
  * (uint32, Morton leaf order).  Synchronous. */
 fmm_status fmm_tree_export(const fmm_tree *tree, uint32_t *perm, uint32_t *leaf_start);
+
+/* The boxes and interaction lists of an adaptive tree (cfg.adaptive), copied
+ * to host memory; synchronous.  FMM_EINVAL on a uniform tree.
+ *   sizes   host int64[6] out: boxes, then the item counts of the U, V, W
+ *           and X lists, then the deepest level.  Call with the other
+ *           pointers NULL to size the arrays.
+ *   boxes   host int32 [boxes][8] or NULL: level, ix, iy, iz (integer box
+ *           coordinates at that level), start, end (the box's particles are
+ *           sorted positions [start, end)), parent (-1 for the root), leaf
+ *           (0/1).  Boxes are numbered breadth first, Morton order within a
+ *           level, box 0 the root.
+ *   perm    host uint32 [n] or NULL: sorted position -> input index.
+ *   list_start  host int64 [4][boxes + 1] or NULL: list k (U, V, W, X) of
+ *           box b is items[off_k + list_start[k][b], off_k +
+ *           list_start[k][b + 1]), off_k the item counts of the lists
+ *           before k (list_start[k][0] = 0).
+ *   items   host int32 [sum of the four counts] or NULL: box ids; the order
+ *           within a list is unspecified. */
+fmm_status fmm_tree_export_adaptive(const fmm_tree *tree, int64_t *sizes, int32_t *boxes, uint32_t *perm,
+                                    int64_t *list_start, int32_t *items);
 
 /* Release all device memory of the tree (stream ordered on the build stream).
  * NULL is ignored. */

@@ -23,6 +23,7 @@ FMM_F32, FMM_F64 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 VEC_NONE, VEC_FIELD, VEC_FORCE = 0, 1, 2
 PART_NEAR_ONLY, PART_FAR_ONLY = 4, 8
+ADAPTIVE_MAX_LEVEL = 8
 STAGES = ("gather", "P2M", "M2M", "pack", "M2L", "L2L", "L2P", "P2P", "combine")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -48,7 +49,8 @@ class Config(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("m2l_fp16", ctypes.c_int32),
         ("m2l_rotation", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("adaptive", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -62,6 +64,9 @@ class TreeInfo(ctypes.Structure):
         ("p2p_pairs", ctypes.c_int64),
         ("m2l_pairs", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_size_t),
+        ("n_boxes", ctypes.c_int64),
+        ("m2p_evals", ctypes.c_int64),
+        ("p2l_evals", ctypes.c_int64),
     ]
 
 
@@ -87,6 +92,7 @@ _SIGS = {
     "fmm_stage_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "fmm_stage_times_reset": (ctypes.c_int, [_vp]),
     "fmm_tree_export": (ctypes.c_int, [_vp, _vp, _vp]),
+    "fmm_tree_export_adaptive": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "fmm_tree_destroy": (None, [_vp]),
     "fmm_operator_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp]),
     "fmm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -151,22 +157,27 @@ def torch_allocator():
     return _ALLOC_CB
 
 
-def make_config(p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
+def make_config(p=8, leaf_max=64, precision="mixed", max_level=None, bf16_splits=3,
                 box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
                 graph=False, profile_stages=None, allocator="torch", m2l_fp16=None,
-                m2l_rotation=False):
+                m2l_rotation=False, adaptive=False):
     """profile_stages: None (all) or an iterable of stage names (STAGES) whose
     boundaries get profiling events.  allocator: "torch" (workspace from
     torch's caching allocator), "library" (the library's own stream-ordered
     hipMallocAsync pool) or an (alloc, free) pair of ctypes callbacks.
     m2l_fp16: None (the library's default), True (the mixed M2L in two
     binary16 parts) or False (bf16_splits bf16 parts).  m2l_rotation: the
-    FP64 form's M2L by rotation (O(p^3) per pair)."""
+    FP64 form's M2L by rotation (O(p^3) per pair).  adaptive: the adaptive
+    octree with U/V/W/X lists (FP64 form); max_level None selects 10 for
+    the uniform tree and ADAPTIVE_MAX_LEVEL for the adaptive one."""
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)
     c.leaf_max = int(leaf_max)
+    if max_level is None:
+        max_level = ADAPTIVE_MAX_LEVEL if adaptive else 10
     c.max_level = int(max_level)
+    c.adaptive = 1 if adaptive else 0
     c.precision = {"fp64": PREC_FP64, "mixed": PREC_MIXED}[precision] if isinstance(precision, str) \
         else int(precision)
     c.bf16_splits = int(bf16_splits)
@@ -241,14 +252,14 @@ class Tree:
     while the output tensors passed in (phi, out_vec, gradients) and the
     tree's memory stay the same, so pass preallocated outputs."""
 
-    def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=10, bf16_splits=3,
+    def __init__(self, pos, p=8, leaf_max=64, precision="mixed", max_level=None, bf16_splits=3,
                  box_lo=(0.0, 0.0, 0.0), box_size=1.0, profile=False, overlap_near=False,
                  graph=False, profile_stages=None, allocator="torch", m2l_fp16=None,
-                 m2l_rotation=False):
+                 m2l_rotation=False, adaptive=False):
         self._h = ctypes.c_void_p(None)
         self.cfg = make_config(p, leaf_max, precision, max_level, bf16_splits, box_lo, box_size,
                                profile, overlap_near, graph, profile_stages, allocator, m2l_fp16,
-                               m2l_rotation)
+                               m2l_rotation, adaptive)
         # the callback objects must outlive every call that can allocate or
         # free (the torch pair is held by the module)
         self._allocator = allocator
@@ -316,12 +327,38 @@ class Tree:
         _check(lib().fmm_stage_times_reset(self._h))
 
     def export(self):
-        """(perm [n], leaf_start [8^L+1]) as numpy uint32 (synchronous)."""
-        L = self.info()["levels"]
+        """(perm [n], leaf_start [n_leaves + 1]) as numpy uint32 (synchronous);
+        uniform tree: n_leaves = 8^L in Morton order; adaptive tree: its
+        leaves in particle order."""
+        nl = self.info()["n_leaves"]
         perm = np.zeros(self.n, dtype=np.uint32)
-        start = np.zeros(8 ** L + 1, dtype=np.uint32)
+        start = np.zeros(nl + 1, dtype=np.uint32)
         _check(lib().fmm_tree_export(self._h, perm.ctypes.data_as(_vp), start.ctypes.data_as(_vp)))
         return perm, start
+
+    def export_adaptive(self):
+        """An adaptive tree's boxes and lists (synchronous): a dict with
+        boxes [nbox, 8] int64 (level, ix, iy, iz, start, end, parent, leaf),
+        order [n] (sorted position -> input index), depth, and U, V, W, X,
+        each a list of nbox numpy arrays of box ids."""
+        L = lib()
+        sz = np.zeros(6, dtype=np.int64)
+        _check(L.fmm_tree_export_adaptive(self._h, sz.ctypes.data_as(_vp), None, None, None, None))
+        nbox = int(sz[0])
+        boxes = np.zeros((nbox, 8), dtype=np.int32)
+        perm = np.zeros(self.n, dtype=np.uint32)
+        starts = np.zeros(4 * (nbox + 1), dtype=np.int64)
+        items = np.zeros(max(1, int(sz[1:5].sum())), dtype=np.int32)
+        _check(L.fmm_tree_export_adaptive(self._h, sz.ctypes.data_as(_vp), boxes.ctypes.data_as(_vp),
+                                          perm.ctypes.data_as(_vp), starts.ctypes.data_as(_vp),
+                                          items.ctypes.data_as(_vp)))
+        out = {"boxes": boxes.astype(np.int64), "order": perm.astype(np.int64), "depth": int(sz[5])}
+        at = 0
+        for k, name in enumerate("UVWX"):
+            st = starts[k * (nbox + 1):(k + 1) * (nbox + 1)] + at
+            out[name] = [items[st[b]:st[b + 1]].astype(np.int64) for b in range(nbox)]
+            at += int(sz[1 + k])
+        return out
 
     def close(self):
         if self._h:

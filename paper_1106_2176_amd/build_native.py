@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libfmm.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "opgen.cpp", "tree.hip", "p2p.hip", "far.hip", "m2l.hip", "scratch.hip"]
+SOURCES = ["api.cpp", "opgen.cpp", "tree.hip", "p2p.hip", "far.hip", "m2l.hip", "scratch.hip", "adaptive.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           "-I" + os.path.join(HERE, "..", "include")]
 HIPFLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

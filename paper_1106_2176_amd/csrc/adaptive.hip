@@ -1,0 +1,1041 @@
+// adaptive.hip -- the adaptive octree on the GPU (the adaptive construction
+// that Sec. 5, future directions, names next to the uniform one), FP64 form.
+//
+// Tree.  Particles are counting-sorted by their Morton key at the finest
+// level Lf (stable, ties in input order), so every box of every level is one
+// contiguous range of the sorted order.  Level by level, a box holding more
+// than leaf_max particles (below Lf) is split and its non-empty children are
+// appended to the next level in Morton order; the rest are leaves.  Box ids
+// are global (levels concatenated, breadth first), box 0 is the root.
+//
+// Lists, for box b (colleagues: the adjacent boxes of b's own level; two boxes
+// are adjacent when their closed cubes touch and neither contains the other):
+//   U(b), b a leaf: b and every leaf adjacent to b                    (P2P)
+//   V(b): the children of the colleagues of b's parent not adjacent to b
+//         (M2L; the 189 offsets of b's child class, absent sources empty)
+//   W(b), b a leaf: descendants of b's colleagues not adjacent to b whose
+//         parent is                                                   (M2P)
+//   X(b): the leaves c with b in W(c)                                 (P2L)
+// Each list is built by one thread per box walking the tree in a fixed
+// order, so the lists, and the sums over them, are the same on every run.
+//
+// Coefficients live in box-id-indexed arrays [nbox + 1][S] (FP64); row nbox
+// is all zero (the source of an absent M2L slot).  Multipoles are in units of
+// their own box (mu = sum q rho(u)), locals ell with phi = (1/w) ell . rho(u),
+// as in the uniform tree, so the same translation tables serve.  Potentials
+// and fields leave the kernels in root units (phi * size, E * size^2).
+#include <algorithm>
+
+#include "harmonics.hpp"
+#include "kernels.hpp"
+
+namespace fmm {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ tree build
+__device__ __forceinline__ void box_coords(uint32_t code, int64_t &x, int64_t &y, int64_t &z) {
+    x = compact3(code);
+    y = compact3(code >> 1);
+    z = compact3(code >> 2);
+}
+
+// closed cubes of boxes (la, a) and (lb, b) touch and neither contains the other
+__device__ inline bool ad_adjacent(int la, uint32_t ca, int lb, uint32_t cb) {
+    const bool af = la >= lb;  // a is the finer (or equal)
+    const int k = af ? la - lb : lb - la;
+    int64_t f[3], c[3];
+    box_coords(af ? ca : cb, f[0], f[1], f[2]);
+    box_coords(af ? cb : ca, c[0], c[1], c[2]);
+    bool inside = true;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int64_t lo = c[ax] << k, hi = ((c[ax] + 1) << k) - 1;
+        if (f[ax] < lo - 1 || f[ax] > hi + 1) return false;
+        if (f[ax] < lo || f[ax] > hi) inside = false;
+    }
+    return !inside;
+}
+
+__global__ void k_ad_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe, int *parent) {
+    code[0] = 0;
+    ps[0] = 0;
+    pe[0] = n;
+    parent[0] = -1;
+}
+
+// Split decision and the non-empty children of the level's boxes [b0, b0+nb).
+__global__ void k_ad_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, const uint32_t *__restrict__ code,
+                           const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
+                           const uint32_t *__restrict__ fstart, uint8_t *__restrict__ leaf,
+                           uint32_t *__restrict__ nchild, uint8_t *__restrict__ cmask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t g = b0 + i;
+    const bool split = pe[g] - ps[g] > (uint32_t)leaf_max && l < Lf;
+    uint32_t k = 0, mask = 0;
+    if (split) {
+        const int sh = 3 * (Lf - l - 1);
+        for (uint32_t c = 0; c < 8; ++c) {
+            const uint64_t m = ((uint64_t)code[g] << 3) | c;
+            if (fstart[(m + 1) << sh] > fstart[m << sh]) {
+                mask |= 1u << c;
+                ++k;
+            }
+        }
+    }
+    leaf[g] = split ? 0 : 1;
+    nchild[i] = k;
+    cmask[g] = (uint8_t)mask;
+}
+
+// Append the children of level l's boxes at global ids next0 + coff[i] ...
+__global__ void k_ad_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0,
+                              const uint32_t *__restrict__ fstart, const uint32_t *__restrict__ coff,
+                              const uint8_t *__restrict__ cmask, uint32_t *__restrict__ code,
+                              uint32_t *__restrict__ ps, uint32_t *__restrict__ pe, int *__restrict__ parent,
+                              int *__restrict__ child) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t g = b0 + i;
+    const uint32_t mask = cmask[g];
+    int64_t j = next0 + coff[i];
+    const int sh = 3 * (Lf - l - 1);
+    for (uint32_t c = 0; c < 8; ++c) {
+        if (!((mask >> c) & 1u)) {
+            child[8 * g + c] = -1;
+            continue;
+        }
+        const uint64_t m = ((uint64_t)code[g] << 3) | c;
+        code[j] = (uint32_t)m;
+        ps[j] = fstart[m << sh];
+        pe[j] = fstart[(m + 1) << sh];
+        parent[j] = (int)g;
+        child[8 * g + c] = (int)j;
+        ++j;
+    }
+}
+
+// Colleagues (the 27 same-level boxes at offsets -1..1, -1 if absent) of the
+// level's boxes, by binary search in the level's Morton-sorted codes.
+__global__ void k_ad_colleagues(int64_t b0, int64_t nb, int l, const uint32_t *__restrict__ code,
+                                int *__restrict__ col) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t g = b0 + i;
+    int64_t x, y, z;
+    box_coords(code[g], x, y, z);
+    const int64_t side = (int64_t)1 << l;
+    for (int o = 0; o < 27; ++o) {
+        const int64_t sx = x + o % 3 - 1, sy = y + (o / 3) % 3 - 1, sz = z + o / 9 - 1;
+        int r = -1;
+        if (sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side) {
+            const uint32_t key = morton3((uint32_t)sx, (uint32_t)sy, (uint32_t)sz);
+            int64_t lo = b0, hi = b0 + nb - 1;
+            while (lo <= hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const uint32_t k = code[mid];
+                if (k == key) {
+                    r = (int)mid;
+                    break;
+                }
+                if (k < key) lo = mid + 1;
+                else hi = mid - 1;
+            }
+        }
+        col[27 * g + o] = r;
+    }
+}
+
+// V as slots: for box g of level l >= 2 and class k (its coordinate parities),
+// slot s of the class's 189 offsets holds the source box t + d if it exists
+// (a child of one of the parent's colleagues), else -1.
+__global__ void k_ad_vslots(int64_t b0, int64_t nb, const uint32_t *__restrict__ code,
+                            const int *__restrict__ parent, const int *__restrict__ col,
+                            const int *__restrict__ child, const int2 *__restrict__ cls,
+                            int *__restrict__ vidx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t g = b0 + i;
+    int64_t tx, ty, tz;
+    box_coords(code[g], tx, ty, tz);
+    const int k = (int)((tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2));
+    const int P = parent[g];
+    for (int s = 0; s < kOffsetsPerClass; ++s) {
+        const int e = cls[k * kOffsetsPerClass + s].x;
+        const int64_t sx = tx + (e & 15) - 4, sy = ty + ((e >> 4) & 15) - 4, sz = tz + ((e >> 8) & 15) - 4;
+        int r = -1;
+        if (sx >= 0 && sy >= 0 && sz >= 0) {
+            const int64_t ox = (sx >> 1) - (tx >> 1), oy = (sy >> 1) - (ty >> 1), oz = (sz >> 1) - (tz >> 1);
+            const int pc = col[27 * (int64_t)P + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+            if (pc >= 0) r = child[8 * (int64_t)pc + ((sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2))];
+        }
+        vidx[189 * i + s] = r;
+    }
+}
+
+// U and W of leaf g (count only when items are NULL).  Order: g; the leaf
+// colleagues of its ancestors (coarser leaves) that touch g, from the parent
+// up; its own colleagues (leaves to U, split ones opened depth first: touching
+// leaves to U, touching split boxes opened, the rest to W).
+__device__ void ad_uw(int g, const int *lev, const uint32_t *code, const int *parent, const int *col,
+                      const int *child, const uint8_t *leaf, int *u, int &nu, int *w, int &nw) {
+    nu = nw = 0;
+    if (u) u[nu] = g;
+    ++nu;
+    const int lg = lev[g];
+    const uint32_t cg = code[g];
+    for (int a = parent[g]; a >= 0; a = parent[a])
+        for (int o = 0; o < 27; ++o) {
+            const int c = col[27 * (int64_t)a + o];
+            if (o == 13 || c < 0 || !leaf[c] || !ad_adjacent(lg, cg, lev[c], code[c])) continue;
+            if (u) u[nu] = c;
+            ++nu;
+        }
+    int stack[8 * (FMM_MAX_LEVEL + 1)];
+    for (int o = 0; o < 27; ++o) {
+        const int c = col[27 * (int64_t)g + o];
+        if (o == 13 || c < 0) continue;
+        if (leaf[c]) {
+            if (u) u[nu] = c;
+            ++nu;
+            continue;
+        }
+        int sp = 0;
+        for (int ch = 7; ch >= 0; --ch)
+            if (child[8 * (int64_t)c + ch] >= 0) stack[sp++] = child[8 * (int64_t)c + ch];
+        while (sp > 0) {
+            const int d = stack[--sp];
+            if (!ad_adjacent(lg, cg, lev[d], code[d])) {
+                if (w) w[nw] = d;
+                ++nw;
+            } else if (leaf[d]) {
+                if (u) u[nu] = d;
+                ++nu;
+            } else {
+                for (int ch = 7; ch >= 0; --ch)
+                    if (child[8 * (int64_t)d + ch] >= 0) stack[sp++] = child[8 * (int64_t)d + ch];
+            }
+        }
+    }
+}
+
+// X of box g: the leaf colleagues c of its proper ancestors (from the parent
+// up) that touch g's parent but not g.
+__device__ int ad_x(int g, const int *lev, const uint32_t *code, const int *parent, const int *col,
+                    const uint8_t *leaf, int *x) {
+    int nx = 0;
+    const int p = parent[g];
+    if (p < 0) return 0;
+    for (int a = p; a >= 0; a = parent[a])
+        for (int o = 0; o < 27; ++o) {
+            const int c = col[27 * (int64_t)a + o];
+            if (o == 13 || c < 0 || !leaf[c]) continue;
+            if (ad_adjacent(lev[p], code[p], lev[c], code[c]) && !ad_adjacent(lev[g], code[g], lev[c], code[c])) {
+                if (x) x[nx] = c;
+                ++nx;
+            }
+        }
+    return nx;
+}
+
+// pass 0: counts of U, W (leaves) and X (all boxes); pass 1: the items
+__global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                           const int *__restrict__ parent, const int *__restrict__ col,
+                           const int *__restrict__ child, const uint8_t *__restrict__ leaf,
+                           uint32_t *__restrict__ nu, uint32_t *__restrict__ nw, uint32_t *__restrict__ nx,
+                           const uint32_t *__restrict__ ou, const uint32_t *__restrict__ ow,
+                           const uint32_t *__restrict__ ox, int *__restrict__ iu, int *__restrict__ iw,
+                           int *__restrict__ ix) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    int a = 0, b = 0;
+    if (pass == 0) {
+        if (leaf[g]) ad_uw((int)g, lev, code, parent, col, child, leaf, nullptr, a, nullptr, b);
+        nu[g] = a;
+        nw[g] = b;
+        nx[g] = ad_x((int)g, lev, code, parent, col, leaf, nullptr);
+    } else {
+        if (leaf[g]) ad_uw((int)g, lev, code, parent, col, child, leaf, iu + ou[g], a, iw + ow[g], b);
+        (void)ad_x((int)g, lev, code, parent, col, leaf, ix + ox[g]);
+    }
+}
+
+// level of every box from the level offsets
+__global__ void k_ad_levels(int64_t nbox, const int64_t *__restrict__ off, int nlev, int *__restrict__ lev) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    int l = 0;
+    for (int j = 1; j < nlev; ++j)
+        if (g >= off[j]) l = j;
+    lev[g] = l;
+}
+
+// Leaves in particle order: head[ps] = leaf id, compacted by a scan
+__global__ void k_ad_heads(int64_t nbox, const uint8_t *__restrict__ leaf, const uint32_t *__restrict__ ps,
+                           const uint32_t *__restrict__ pe, uint32_t *__restrict__ is_head,
+                           int *__restrict__ head) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nbox || !leaf[g]) return;
+    is_head[ps[g]] = 1u;
+    head[ps[g]] = (int)g;
+}
+__global__ void k_ad_leaflist(int64_t n, const uint32_t *__restrict__ is_head, const uint32_t *__restrict__ hoff,
+                              const int *__restrict__ head, const uint32_t *__restrict__ ps,
+                              int *__restrict__ lbox, uint32_t *__restrict__ lstart, uint8_t *__restrict__ llev,
+                              const int *__restrict__ lev, const uint32_t *__restrict__ pe,
+                              unsigned int *__restrict__ mx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (is_head[i]) {
+        const uint32_t j = hoff[i];
+        const int g = head[i];
+        lbox[j] = g;
+        lstart[j] = ps[g];
+        llev[j] = (uint8_t)lev[g];
+        atomicMax(mx, pe[g] - ps[g]);
+    }
+    if (i == n - 1) lstart[hoff[n]] = (uint32_t)n;
+}
+
+// Work counts: [0] ordered P2P pairs (self pairs included), [1] V entries,
+// [2] (particle, box) pairs of W, [3] of X.
+__global__ void k_ad_counts(int64_t nbox, int64_t box2, const uint8_t *__restrict__ leaf,
+                            const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
+                            const uint32_t *__restrict__ ou, const int *__restrict__ iu,
+                            const uint32_t *__restrict__ ow, const uint32_t *__restrict__ ox,
+                            const int *__restrict__ ix, const int *__restrict__ vidx,
+                            unsigned long long *__restrict__ out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nbox) return;
+    const unsigned long long ng = pe[g] - ps[g];
+    unsigned long long u = 0, v = 0, xs = 0;
+    if (leaf[g])
+        for (uint32_t e = ou[g]; e < ou[g + 1]; ++e) u += pe[iu[e]] - ps[iu[e]];
+    if (g >= box2)
+        for (int s = 0; s < kOffsetsPerClass; ++s) v += vidx[kOffsetsPerClass * (g - box2) + s] >= 0;
+    for (uint32_t e = ox[g]; e < ox[g + 1]; ++e) xs += pe[ix[e]] - ps[ix[e]];
+    if (u) atomicAdd(out, u * ng);
+    if (v) atomicAdd(out + 1, v);
+    if (ow[g + 1] > ow[g]) atomicAdd(out + 2, ng * (ow[g + 1] - ow[g]));
+    if (xs) atomicAdd(out + 3, xs);
+}
+
+// Sorted records relative to each particle's leaf (leaf units, FP64); the
+// leaf of sorted position i is the last leaf head at or before i.
+template <typename Tin>
+__global__ void k_ad_records(int64_t n, const uint32_t *__restrict__ hoff, const int *__restrict__ lbox,
+                             const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                             const uint32_t *__restrict__ perm, const Tin *__restrict__ pos, double lo0,
+                             double lo1, double lo2, double inv_size, double4 *__restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int g = lbox[hoff[i + 1] - 1];
+    const int l = lev[g];
+    int64_t bx, by, bz;
+    box_coords(code[g], bx, by, bz);
+    const double sc = (double)((int64_t)1 << l) * inv_size;
+    const uint32_t o = perm[i];
+    double4 r;
+    r.x = ((double)pos[3 * (size_t)o] - lo0) * sc - ((double)bx + 0.5);
+    r.y = ((double)pos[3 * (size_t)o + 1] - lo1) * sc - ((double)by + 0.5);
+    r.z = ((double)pos[3 * (size_t)o + 2] - lo2) * sc - ((double)bz + 0.5);
+    r.w = 0.0;
+    rec[i] = r;
+}
+
+// --------------------------------------------------------------- evaluate
+// centre of box (l1, c1) minus centre of box (l2, c2), in units of the
+// width of level lu (exact in FP64: dyadic rationals)
+__device__ inline void ad_centre_diff(int l1, uint32_t c1, int l2, uint32_t c2, int lu, double &dx, double &dy,
+                                      double &dz) {
+    int64_t a[3], b[3];
+    box_coords(c1, a[0], a[1], a[2]);
+    box_coords(c2, b[0], b[1], b[2]);
+    const double s1 = ldexp(1.0, lu - l1), s2 = ldexp(1.0, lu - l2);
+    dx = ((double)a[0] + 0.5) * s1 - ((double)b[0] + 0.5) * s2;
+    dy = ((double)a[1] + 0.5) * s1 - ((double)b[1] + 0.5) * s2;
+    dz = ((double)a[2] + 0.5) * s1 - ((double)b[2] + 0.5) * s2;
+}
+
+// P2M at the leaves: mu(g) = sum_j q_j rho(u_j), leaf units; one block of 64
+// per leaf, 16 particles' harmonics at a time in LDS.  Rows are written whole
+// (zero past p^2).
+template <int P>
+__global__ __launch_bounds__(64) void k_ad_p2m(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+                                               const double4 *__restrict__ rec, double *__restrict__ M) {
+    constexpr int P2 = P * P, S = coef_stride(P), B = 16, NC = (S + 63) / 64;
+    __shared__ double rows[B][P2 + 1];
+    const int j = blockIdx.x, t = threadIdx.x;
+    const uint32_t s0 = lstart[j], s1 = lstart[j + 1];
+    double acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = 0.0;
+    for (uint32_t b0 = s0; b0 < s1; b0 += B) {
+        __syncthreads();
+        if (t < B) {
+            if (b0 + t < s1) {
+                const double4 r = rec[b0 + t];
+                regular_rho<double>(P, r.x, r.y, r.z, rows[t]);
+                for (int c = 0; c < P2; ++c) rows[t][c] *= r.w;
+            } else {
+                for (int c = 0; c < P2; ++c) rows[t][c] = 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+            const int c = t + 64 * a;
+            if (c < P2)
+                for (int k = 0; k < B; ++k) acc[a] += rows[k][c];
+        }
+    }
+    const int g = lbox[j];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+        const int c = t + 64 * a;
+        if (c < S) M[(size_t)g * S + c] = c < P2 ? acc[a] : 0.0;
+    }
+}
+
+// M2M for the split boxes of one level: mu(g) = sum_c A_c mu(child c)
+// (tab [8][p^2][p^2] input-major, [c][in][out])
+template <int P>
+__global__ __launch_bounds__(256) void k_ad_m2m(int64_t b0, const uint8_t *__restrict__ leaf,
+                                                const int *__restrict__ child, const double *__restrict__ tab,
+                                                double *__restrict__ M) {
+    constexpr int P2 = P * P, S = coef_stride(P);
+    __shared__ double in[8][P2];
+    __shared__ int has[8];
+    const int64_t g = b0 + blockIdx.x;
+    if (leaf[g]) return;
+    for (int i = threadIdx.x; i < 8 * P2; i += 256) {
+        const int c = i / P2, k = i - c * P2;
+        const int ch = child[8 * g + c];
+        in[c][k] = ch >= 0 ? M[(size_t)ch * S + k] : 0.0;
+    }
+    if (threadIdx.x < 8) has[threadIdx.x] = child[8 * g + threadIdx.x] >= 0;
+    __syncthreads();
+    for (int o = threadIdx.x; o < S; o += 256) {
+        double v = 0.0;
+        if (o < P2)
+            for (int c = 0; c < 8; ++c) {
+                if (!has[c]) continue;
+                const double *tc = tab + (size_t)c * P2 * P2 + o;
+                for (int k = 0; k < P2; ++k) v += tc[(size_t)k * P2] * in[c][k];
+            }
+        M[(size_t)g * S + o] = v;
+    }
+}
+
+// L2L into the boxes of one level (>= 3): ell(g) += B_c ell(parent)
+template <int P>
+__global__ __launch_bounds__(256) void k_ad_l2l(int64_t b0, const uint32_t *__restrict__ code,
+                                                const int *__restrict__ parent, const double *__restrict__ tab,
+                                                double *__restrict__ Lc) {
+    constexpr int P2 = P * P, S = coef_stride(P);
+    __shared__ double in[P2];
+    const int64_t g = b0 + blockIdx.x;
+    const int pa = parent[g];
+    for (int k = threadIdx.x; k < P2; k += 256) in[k] = Lc[(size_t)pa * S + k];
+    __syncthreads();
+    const uint32_t cd = code[g];
+    const int c = (int)(cd & 7u);  // the child octant: bit 0 x, 1 y, 2 z of the Morton code
+    for (int o = threadIdx.x; o < P2; o += 256) {
+        double v = 0.0;
+        const double *tc = tab + (size_t)c * P2 * P2 + o;
+        for (int k = 0; k < P2; ++k) v += tc[(size_t)k * P2] * in[k];
+        Lc[(size_t)g * S + o] += v;
+    }
+}
+
+// L2P at the leaves, outputs in root units (phi * 2^l, E * 4^l)
+template <int P>
+__global__ __launch_bounds__(64) void k_ad_l2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+                                               const uint8_t *__restrict__ llev, const double4 *__restrict__ rec,
+                                               const double *__restrict__ Lc, double4 *__restrict__ out) {
+    constexpr int P2 = P * P, S = coef_stride(P);
+    __shared__ double ell[P2];
+    __shared__ double4 coef[P2];
+    const int j = blockIdx.x;
+    const int g = lbox[j];
+    for (int c = threadIdx.x; c < P2; c += 64) ell[c] = Lc[(size_t)g * S + c];
+    __syncthreads();
+    for (int c = threadIdx.x; c < P2; c += 64) coef[c] = l2p_coef<double, double4>(ell, P, c);
+    __syncthreads();
+    const double s1 = ldexp(1.0, (int)llev[j]), s2 = s1 * s1;
+    for (uint32_t i = lstart[j] + threadIdx.x; i < lstart[j + 1]; i += 64) {
+        __asm__ volatile("" ::: "memory");
+        const double4 r = rec[i];
+        double phi, gx, gy, gz;
+        l2p_point<P, double, double4>(coef, r.x, r.y, r.z, phi, gx, gy, gz);
+        out[i] = make_double4(phi * s1, -gx * s2, -gy * s2, -gz * s2);
+    }
+}
+
+// Irregular solid harmonics I_n^m(y) for 0 <= m <= n <= N (complex, as in
+// the translation operators: I_0^0 = 1/r, I_m^m = -(2m-1) (x+iy)/r^2
+// I_{m-1}^{m-1}, I_{m+1}^m = (2m+1) z/r^2 I_m^m, r^2 I_n^m = (2n-1) z
+// I_{n-1}^m - (n-m-1)(n+m-1) I_{n-2}^m), visited column by column: f(n, m,
+// re, im) for every pair.
+template <int N, typename F>
+__device__ __forceinline__ void irregular_each(double x, double y, double z, F &&f) {
+    const double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
+    double dr = sqrt(ir2), di = 0.0;  // I_m^m
+#pragma unroll
+    for (int m = 0; m <= N; ++m) {
+        if (m > 0) {
+            const double k = -(2.0 * m - 1.0) * ir2;
+            const double nr = k * (x * dr - y * di), ni = k * (x * di + y * dr);
+            dr = nr;
+            di = ni;
+        }
+        double ar = dr, ai = di, br = 0.0, bi = 0.0;
+#pragma unroll
+        for (int n = m; n <= N; ++n) {
+            double cr = ar, ci = ai;
+            if (n == m + 1) {
+                cr = (2.0 * m + 1.0) * z * ir2 * ar;
+                ci = (2.0 * m + 1.0) * z * ir2 * ai;
+            } else if (n > m + 1) {
+                const double a = (2.0 * n - 1.0) * z, b = (double)((n - m - 1) * (n + m - 1));
+                cr = (a * ar - b * br) * ir2;
+                ci = (a * ai - b * bi) * ir2;
+            }
+            if (n > m) {
+                br = ar;
+                bi = ai;
+                ar = cr;
+                ai = ci;
+            }
+            f(n, m, cr, ci);
+        }
+    }
+}
+
+// P2L over X: for every box g, ell(g) += sum over the leaves c of X(g) of the
+// local expansion of each particle of c: the complex local coefficient of a
+// charge q at y (g units) is q I_n^m(y), i.e. ell_c = 2 q Re, ell_s = -2 q Im.
+template <int P>
+__global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, const int *__restrict__ ix,
+                                               const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                                               const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
+                                               const double4 *__restrict__ rec, double *__restrict__ Lc) {
+    constexpr int P2 = P * P, S = coef_stride(P), B = 16, NC = (P2 + 63) / 64;
+    __shared__ double rows[B][P2 + 1];
+    const int g = blockIdx.x, t = threadIdx.x;
+    const uint32_t x0 = ox[g], x1 = ox[g + 1];
+    if (x0 == x1) return;
+    const int lg = lev[g];
+    double acc[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) acc[a] = 0.0;
+    for (uint32_t e = x0; e < x1; ++e) {
+        const int c = ix[e];
+        const int lc = lev[c];
+        double cx, cy, cz;
+        ad_centre_diff(lc, code[c], lg, code[g], lg, cx, cy, cz);
+        const double sc = ldexp(1.0, lg - lc);
+        for (uint32_t b0 = ps[c]; b0 < pe[c]; b0 += B) {
+            __syncthreads();
+            if (t < B) {
+                double *row = rows[t];
+                if (b0 + t < pe[c]) {
+                    const double4 r = rec[b0 + t];
+                    const double q = r.w;
+                    irregular_each<P - 1>(cx + sc * r.x, cy + sc * r.y, cz + sc * r.z,
+                                          [&](int n, int m, double re, double im) {
+                                              if (m == 0) {
+                                                  row[n * n] = q * re;
+                                              } else {
+                                                  row[n * n + 2 * m - 1] = 2.0 * q * re;
+                                                  row[n * n + 2 * m] = -2.0 * q * im;
+                                              }
+                                          });
+                } else {
+                    for (int k = 0; k < P2; ++k) row[k] = 0.0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                const int k = t + 64 * a;
+                if (k < P2)
+                    for (int r = 0; r < B; ++r) acc[a] += rows[r][k];
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+        const int k = t + 64 * a;
+        if (k < P2) Lc[(size_t)g * S + k] += acc[a];
+    }
+}
+
+// M2P over W at the leaves: the field of the truncated multipole of each w in
+// W(g) at g's particles.  With M_n^m = mu_c + i mu_s (M_n^{-m} = (-1)^m
+// conj) and y the particle relative to w's centre (w units), the degree-0
+// and degree-1 coefficients of the local expansion at the particle are
+//   L_0^0 = sum M_n^m I_n^m,  L_1^l = -sum M_n^m I_{n+1}^{m+l},
+// and phi = L_0^0 / w, grad = (-Re L_1^1, -Im L_1^1, L_1^0) / w^2.
+// Accumulated into out (root units: phi * 2^l_w, E * 4^l_w).
+template <int P>
+__global__ __launch_bounds__(64) void k_ad_m2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+                                               const uint32_t *__restrict__ ow, const int *__restrict__ iw,
+                                               const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                                               const double4 *__restrict__ rec, const double *__restrict__ M,
+                                               double4 *__restrict__ out) {
+    constexpr int P2 = P * P, S = coef_stride(P);
+    __shared__ double mu[P2];
+    const int j = blockIdx.x;
+    const int g = lbox[j];
+    const uint32_t w0 = ow[g], w1 = ow[g + 1];
+    if (w0 == w1) return;
+    const int lg = lev[g];
+    for (uint32_t i0 = lstart[j]; i0 < lstart[j + 1]; i0 += 64) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool live = i < lstart[j + 1];
+        double4 r = live ? rec[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+        double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (uint32_t e = w0; e < w1; ++e) {
+            const int w = iw[e];
+            const int lw = lev[w];
+            __syncthreads();
+            for (int c = threadIdx.x; c < P2; c += 64) mu[c] = M[(size_t)w * S + c];
+            __syncthreads();
+            double cx, cy, cz;
+            ad_centre_diff(lg, code[g], lw, code[w], lw, cx, cy, cz);
+            const double sc = ldexp(1.0, lw - lg);
+            double l00 = 0.0, l10 = 0.0, l11r = 0.0, l11i = 0.0;
+            irregular_each<P>(cx + sc * r.x, cy + sc * r.y, cz + sc * r.z, [&](int n, int m, double ir, double ii) {
+                // M_{n'}^{m'} of the multipole (0 outside n' < P, |m'| <= n')
+                auto Mc = [&](int nn, int mm, double &mr, double &mi) {
+                    mr = mi = 0.0;
+                    if (nn < 0 || nn >= P || mm > nn || mm < 0) return;
+                    if (mm == 0) {
+                        mr = mu[nn * nn];
+                    } else {
+                        mr = mu[nn * nn + 2 * mm - 1];
+                        mi = mu[nn * nn + 2 * mm];
+                    }
+                };
+                double mr, mi;
+                if (n < P) {  // L_0^0: M_n^m I_n^m and its conjugate partner
+                    Mc(n, m, mr, mi);
+                    const double re = mr * ir - mi * ii;
+                    l00 += m == 0 ? re : 2.0 * re;
+                }
+                if (n >= 1) {
+                    // L_1^0: -M_{n-1}^m I_n^m, with the partner -m
+                    Mc(n - 1, m, mr, mi);
+                    const double re = mr * ir - mi * ii;
+                    l10 -= m == 0 ? re : 2.0 * re;
+                    // L_1^1: -M_{n-1}^{m-1} I_n^m (m >= 1) and
+                    //        +conj(M_{n-1}^{m+1} I_n^m) (the terms of order -(m+1))
+                    if (m >= 1) {
+                        Mc(n - 1, m - 1, mr, mi);
+                        l11r -= mr * ir - mi * ii;
+                        l11i -= mr * ii + mi * ir;
+                    }
+                    Mc(n - 1, m + 1, mr, mi);
+                    l11r += mr * ir - mi * ii;
+                    l11i -= mr * ii + mi * ir;
+                }
+            });
+            const double s1 = ldexp(1.0, lw), s2 = s1 * s1;
+            phi += l00 * s1;
+            ex += l11r * s2;
+            ey += l11i * s2;
+            ez -= l10 * s2;
+        }
+        if (live) {
+            double4 o = out[i];
+            o.x += phi;
+            o.y += ex;
+            o.z += ey;
+            o.w += ez;
+            out[i] = o;
+        }
+    }
+}
+
+// P2P over U at the leaves (FP64): sources of each leaf c in U(g) brought
+// into g's frame and units, (c_c - c_g)/w_g + u 2^(l_g - l_c), in LDS tiles of
+// 64; j = i and coincident points excluded.  Root units out.
+__global__ __launch_bounds__(64) void k_ad_p2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+                                               const uint32_t *__restrict__ ou, const int *__restrict__ iu,
+                                               const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                                               const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
+                                               const double4 *__restrict__ rec, double4 *__restrict__ out) {
+    __shared__ double4 tile[64];
+    const int j = blockIdx.x;
+    const int g = lbox[j];
+    const int lg = lev[g];
+    const uint32_t u0 = ou[g], u1 = ou[g + 1];
+    for (uint32_t i0 = lstart[j]; i0 < lstart[j + 1]; i0 += 64) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool live = i < lstart[j + 1];
+        const double4 r = live ? rec[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+        double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (uint32_t e = u0; e < u1; ++e) {
+            const int c = iu[e];
+            const int lc = lev[c];
+            double cx, cy, cz;
+            ad_centre_diff(lc, code[c], lg, code[g], lg, cx, cy, cz);
+            const double sc = ldexp(1.0, lg - lc);
+            for (uint32_t s0 = ps[c]; s0 < pe[c]; s0 += 64) {
+                __syncthreads();
+                if (s0 + threadIdx.x < pe[c]) {
+                    const double4 v = rec[s0 + threadIdx.x];
+                    tile[threadIdx.x] = make_double4(cx + sc * v.x, cy + sc * v.y, cz + sc * v.z, v.w);
+                }
+                __syncthreads();
+                const int cnt = (int)min(64u, pe[c] - s0);
+                for (int k = 0; k < cnt; ++k) {
+                    const double4 v = tile[k];
+                    const double dx = r.x - v.x, dy = r.y - v.y, dz = r.z - v.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (s0 + k == i || r2 == 0.0) continue;
+                    const double rinv = 1.0 / sqrt(r2);
+                    const double qr = v.w * rinv, qr3 = qr * rinv * rinv;
+                    phi += qr;
+                    ex += qr3 * dx;
+                    ey += qr3 * dy;
+                    ez += qr3 * dz;
+                }
+            }
+        }
+        if (live) {
+            const double s1 = ldexp(1.0, lg), s2 = s1 * s1;
+            out[i] = make_double4(phi * s1, ex * s2, ey * s2, ez * s2);
+        }
+    }
+}
+
+// Gathered M2L (FP64 MFMA): the targets of each (level, class) group, in
+// tiles of 128 columns (4 waves x 2 x 16), against the K range of the class's
+// 189 slots x S coefficients in chunks of 8; a column's source row for a slot
+// comes from its V slots (an absent source reads the zero row).  A chunk's
+// operator (R x 8, uniform over the block) is staged in LDS one chunk ahead;
+// lane group q takes K index 4 j + q of a chunk (v_mfma_f64_16x16x4_f64).
+template <int P>
+__global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__restrict__ A,
+                                                const int2 *__restrict__ cls, const double *__restrict__ M,
+                                                const int *__restrict__ vidx, int64_t box2,
+                                                const int *__restrict__ tgt, int64_t zero_row,
+                                                double *__restrict__ Lc) {
+    constexpr int P2 = P * P, S = coef_stride(P), RT = m2l_rows(P) / 16, R = RT * 16;
+    constexpr int NB = 2, KC = 8, ROWP = KC + 1, CPO = S / KC;
+    constexpr int NEL = R * KC, EPT = (NEL + 255) / 256;
+    constexpr int NCH = kOffsetsPerClass * CPO;
+    __shared__ double As[2][R * ROWP];
+    __shared__ int sA[kOffsetsPerClass];
+    const int64_t b = blockIdx.x;
+    int gi = 0;
+    for (int j = 1; j < pl.ngroups; ++j)
+        if (b >= pl.grp[j].unit0) gi = j;
+    const AdM2LGroup gr = pl.grp[gi];
+    const int64_t tile = b - gr.unit0;
+    const int k = gr.cls;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    for (int i = tid; i < kOffsetsPerClass; i += 256) sA[i] = cls[k * kOffsetsPerClass + i].y * R * S;
+    int64_t tbox[NB];
+    const int *vrow[NB];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+        const int64_t c = tile * 128 + wave * NB * 16 + bb * 16 + col;
+        tbox[bb] = c < gr.count ? tgt[gr.toff + c] : -1;
+        vrow[bb] = tbox[bb] >= 0 ? vidx + (tbox[bb] - box2) * kOffsetsPerClass : nullptr;
+    }
+    __syncthreads();
+    auto load_a = [&](int kc, double (&dst)[EPT]) __attribute__((always_inline)) {
+        const int slot = kc / CPO, c0 = KC * (kc - slot * CPO);
+        const double *a = A + sA[slot] + c0;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + 256 * i;
+            dst[i] = (NEL % 256 == 0 || e < NEL) ? a[(e / KC) * S + e % KC] : 0.0;
+        }
+    };
+    auto store_a = [&](int buf, const double (&src)[EPT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + 256 * i;
+            if (NEL % 256 == 0 || e < NEL) As[buf][(e / KC) * ROWP + e % KC] = src[i];
+        }
+    };
+    auto load_b = [&](int kc, double (&dst)[2][NB]) __attribute__((always_inline)) {
+        const int slot = kc / CPO, c0 = KC * (kc - slot * CPO);
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            const int s = vrow[bb] ? vrow[bb][slot] : -1;
+            const double *src = M + (s >= 0 ? (int64_t)s : zero_row) * S + c0 + q;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) dst[j][bb] = src[4 * j];
+        }
+    };
+    f64x4 acc[RT][NB];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) acc[r][bb] = f64x4{0, 0, 0, 0};
+    double ar[2][EPT], br[2][2][NB], bc[2][NB];
+    load_a(0, ar[0]);
+    store_a(0, ar[0]);
+    load_b(0, bc);
+    load_a(min(1, NCH - 1), ar[0]);
+    load_b(min(1, NCH - 1), br[0]);
+    load_a(min(2, NCH - 1), ar[1]);
+    load_b(min(2, NCH - 1), br[1]);
+    __syncthreads();
+    auto chunk = [&](int kc, auto pc) __attribute__((always_inline)) {
+        constexpr int ph = decltype(pc)::value;
+        const double *as = As[ph];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const double av = as[(16 * r + col) * ROWP + 4 * j + q];
+#pragma unroll
+                for (int bb = 0; bb < NB; ++bb)
+                    acc[r][bb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bc[j][bb], acc[r][bb], 0, 0, 0);
+            }
+        store_a(ph ^ 1, ar[ph]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) bc[j][bb] = br[ph][j][bb];
+        load_a(min(kc + 3, NCH - 1), ar[ph]);
+        load_b(min(kc + 3, NCH - 1), br[ph]);
+        __syncthreads();
+    };
+    int kc = 0;
+    for (; kc + 1 < NCH; kc += 2) {
+        chunk(kc, std::integral_constant<int, 0>{});
+        chunk(kc + 1, std::integral_constant<int, 1>{});
+    }
+    if (kc < NCH) chunk(kc, std::integral_constant<int, 0>{});
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+        if (tbox[bb] < 0) continue;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * r + q + 4 * i;
+                if (row < P2) Lc[tbox[bb] * S + row] = acc[r][bb][i];
+            }
+    }
+}
+
+// targets of levels >= 2 grouped by (level, class): per-group counts, then
+// the fill (a target's position within its group does not change its sums)
+__global__ void k_ad_class_count(int64_t box2, int64_t nb, const int *__restrict__ lev,
+                                 const uint32_t *__restrict__ code, unsigned int *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t g = box2 + i;
+    int64_t x, y, z;
+    box_coords(code[g], x, y, z);
+    const int k = (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+    atomicAdd(cnt + 8 * (lev[g] - 2) + k, 1u);
+}
+__global__ void k_ad_class_fill(int64_t box2, int64_t nb, const int *__restrict__ lev,
+                                const uint32_t *__restrict__ code, const int64_t *__restrict__ goff,
+                                unsigned int *__restrict__ fill, int *__restrict__ tgt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t g = box2 + i;
+    int64_t x, y, z;
+    box_coords(code[g], x, y, z);
+    const int grp = 8 * (lev[g] - 2) + (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+    tgt[goff[grp] + atomicAdd(fill + grp, 1u)] = (int)g;
+}
+
+// ---------------------------------------------------------- host helpers
+static inline unsigned ad_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t ad_launch_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe, int *parent, hipStream_t st) {
+    k_ad_root<<<1, 1, 0, st>>>(n, code, ps, pe, parent);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, const uint32_t *code,
+                           const uint32_t *ps, const uint32_t *pe, const uint32_t *fstart, uint8_t *leaf,
+                           uint32_t *nchild, uint8_t *cmask, hipStream_t st) {
+    k_ad_count<<<ad_blocks(nb, 256), 256, 0, st>>>(b0, nb, l, Lf, leaf_max, code, ps, pe, fstart, leaf, nchild, cmask);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const uint32_t *fstart,
+                              const uint32_t *coff, const uint8_t *cmask, uint32_t *code, uint32_t *ps,
+                              uint32_t *pe, int *parent, int *child, hipStream_t st) {
+    k_ad_children<<<ad_blocks(nb, 256), 256, 0, st>>>(b0, nb, l, Lf, next0, fstart, coff, cmask, code, ps, pe,
+                                                       parent, child);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_structure(int64_t nbox, int nlev, const int64_t *off_host, const int64_t *off_dev,
+                               const uint32_t *code, const int *parent, const int *child, int *lev, int *col,
+                               const int2 *cls, int *vidx, hipStream_t st) {
+    k_ad_levels<<<ad_blocks(nbox, 256), 256, 0, st>>>(nbox, off_dev, nlev, lev);
+    for (int l = 0; l < nlev; ++l) {
+        const int64_t nb = off_host[l + 1] - off_host[l];
+        if (nb > 0) k_ad_colleagues<<<ad_blocks(nb, 256), 256, 0, st>>>(off_host[l], nb, l, code, col);
+    }
+    for (int l = 2; l < nlev; ++l) {
+        const int64_t nb = off_host[l + 1] - off_host[l];
+        if (nb > 0)
+            k_ad_vslots<<<ad_blocks(nb, 256), 256, 0, st>>>(off_host[l], nb, code, parent, col, child, cls,
+                                                             vidx + 189 * (off_host[l] - off_host[2]));
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_lists(int64_t nbox, int pass, const int *lev, const uint32_t *code, const int *parent,
+                           const int *col, const int *child, const uint8_t *leaf, uint32_t *nu, uint32_t *nw,
+                           uint32_t *nx, const uint32_t *ou, const uint32_t *ow, const uint32_t *ox, int *iu,
+                           int *iw, int *ix, hipStream_t st) {
+    k_ad_lists<<<ad_blocks(nbox, 128), 128, 0, st>>>(nbox, pass, lev, code, parent, col, child, leaf, nu, nw, nx,
+                                                      ou, ow, ox, iu, iw, ix);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_heads(int64_t nbox, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,
+                           uint32_t *is_head, int *head, hipStream_t st) {
+    k_ad_heads<<<ad_blocks(nbox, 256), 256, 0, st>>>(nbox, leaf, ps, pe, is_head, head);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_leaflist(int64_t n, const uint32_t *is_head, const uint32_t *hoff, const int *head,
+                              const uint32_t *ps, const uint32_t *pe, int *lbox, uint32_t *lstart, uint8_t *llev,
+                              const int *lev, unsigned int *mx, hipStream_t st) {
+    k_ad_leaflist<<<ad_blocks(n, 256), 256, 0, st>>>(n, is_head, hoff, head, ps, lbox, lstart, llev, lev, pe, mx);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_counts(int64_t nbox, int64_t box2, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,
+                            const uint32_t *ou, const int *iu, const uint32_t *ow, const uint32_t *ox, const int *ix,
+                            const int *vidx, unsigned long long *out, hipStream_t st) {
+    k_ad_counts<<<ad_blocks(nbox, 256), 256, 0, st>>>(nbox, box2, leaf, ps, pe, ou, iu, ow, ox, ix, vidx, out);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_records(int64_t n, int dtype, const uint32_t *hoff, const int *lbox, const int *lev,
+                             const uint32_t *code, const uint32_t *perm, const void *pos, const double lo[3],
+                             double size, double4 *rec, hipStream_t st) {
+    if (dtype == FMM_F64)
+        k_ad_records<double><<<ad_blocks(n, 256), 256, 0, st>>>(n, hoff, lbox, lev, code, perm, (const double *)pos,
+                                                                lo[0], lo[1], lo[2], 1.0 / size, rec);
+    else
+        k_ad_records<float><<<ad_blocks(n, 256), 256, 0, st>>>(n, hoff, lbox, lev, code, perm, (const float *)pos,
+                                                               lo[0], lo[1], lo[2], 1.0 / size, rec);
+    return hipGetLastError();
+}
+
+#define AD_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const double4 *rec,
+                         double *M, hipStream_t st) {
+    if (nleaf == 0) return hipSuccess;
+    switch (P) {
+#define X(PP) case PP: k_ad_p2m<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, rec, M); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
+                         double *M, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    switch (P) {
+#define X(PP) case PP: k_ad_m2m<PP><<<(unsigned)nb, 256, 0, st>>>(b0, leaf, child, tab, M); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_l2l(int P, int64_t b0, int64_t nb, const uint32_t *code, const int *parent, const double *tab,
+                         double *Lc, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    switch (P) {
+#define X(PP) case PP: k_ad_l2l<PP><<<(unsigned)nb, 256, 0, st>>>(b0, code, parent, tab, Lc); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, int64_t nunits, const double *A, const int2 *cls,
+                         const double *M, const int *vidx, int64_t box2, const int *tgt, int64_t zero_row,
+                         double *Lc, hipStream_t st) {
+    if (nunits == 0) return hipSuccess;
+    switch (P) {
+#define X(PP) \
+    case PP: k_ad_m2l<PP><<<(unsigned)nunits, 256, 0, st>>>(pl, A, cls, M, vidx, box2, tgt, zero_row, Lc); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_class(int64_t box2, int64_t nb, const int *lev, const uint32_t *code, unsigned int *cnt,
+                           const int64_t *goff, unsigned int *fill, int *tgt, hipStream_t st) {
+    if (nb == 0) return hipSuccess;
+    if (!goff)
+        k_ad_class_count<<<ad_blocks(nb, 256), 256, 0, st>>>(box2, nb, lev, code, cnt);
+    else
+        k_ad_class_fill<<<ad_blocks(nb, 256), 256, 0, st>>>(box2, nb, lev, code, goff, fill, tgt);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
+                         const uint32_t *code, const uint32_t *ps, const uint32_t *pe, const double4 *rec,
+                         double *Lc, hipStream_t st) {
+    switch (P) {
+#define X(PP) case PP: k_ad_p2l<PP><<<(unsigned)nbox, 64, 0, st>>>(ox, ix, lev, code, ps, pe, rec, Lc); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
+                         const double4 *rec, const double *Lc, double4 *out, hipStream_t st) {
+    switch (P) {
+#define X(PP) case PP: k_ad_l2p<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, rec, Lc, out); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_m2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ow,
+                         const int *iw, const int *lev, const uint32_t *code, const double4 *rec, const double *M,
+                         double4 *out, hipStream_t st) {
+    switch (P) {
+#define X(PP) \
+    case PP: k_ad_m2p<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, ow, iw, lev, code, rec, M, out); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_p2p(int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ou, const int *iu,
+                         const int *lev, const uint32_t *code, const uint32_t *ps, const uint32_t *pe,
+                         const double4 *rec, double4 *out, hipStream_t st) {
+    k_ad_p2p<<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, ou, iu, lev, code, ps, pe, rec, out);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

@@ -337,6 +337,29 @@ struct GraphSlot {
     int32_t flags = 0;
 };
 
+// Adaptive tree (cfg.adaptive): box arrays indexed by global box id (levels
+// concatenated breadth first), the U/W/X lists in CSR form, the V lists as
+// 189 slots per box of level >= 2, the leaves in particle order, and host
+// copies of the level offsets and of the M2L target groups.
+constexpr int kAdHostWords = 64;
+struct AdTree {
+    int depth = 0;
+    int64_t nbox = 0, nleaf = 0, nvbox = 0;  // nvbox: boxes of levels >= 2
+    int64_t off[FMM_MAX_LEVEL + 2] = {};      // first box of each level, off[depth + 1] = nbox
+    int64_t nlist[3] = {};                    // items of U, W, X
+    int64_t goff[8 * FMM_MAX_LEVEL + 1] = {}; // first target of each (level, class) group
+    AdM2LPlan plan{};
+    int64_t m2l_units = 0;
+    uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
+    Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
+        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts;
+    std::vector<Buf *> bufs() {
+        return {&code, &ps, &pe, &parent, &child, &leaf, &cmask, &nchild, &coff, &lev, &col, &vidx, &cnts,
+                &offs, &iu, &iw, &ix, &is_head, &head, &hoff, &lbox, &lstart, &llev, &tgt, &ccnt, &goffd,
+                &offd, &counts};
+    }
+};
+
 }  // namespace
 
 struct fmm_tree {
@@ -368,6 +391,7 @@ struct fmm_tree {
     bool capturing = false;
     GraphSlot gfwd, gbwd;       // graphs of fmm_evaluate and fmm_backward
     bool quiet = false;         // a call that records no profiling events
+    AdTree *ad = nullptr;       // the adaptive tree (cfg.adaptive), else NULL
 };
 
 namespace {
@@ -414,6 +438,11 @@ WorkSizes work_sizes(const fmm_tree *t, bool far) {
     const bool f64 = is_f64_form(t);
     z.nearf = sizeof(double4) * (size_t)t->n;
     if (!far || L < 2) return z;
+    if (t->ad) {  // FP64 coefficients by box id, plus the zero row
+        z.farf = sizeof(double4) * (size_t)t->n;
+        z.M[0] = z.Lc[0] = sizeof(double) * (size_t)(t->ad->nbox + 1) * S;
+        return z;
+    }
     z.farf = sizeof(double4) * (size_t)t->n;
     for (int l = 2; l <= L; ++l) {
         const size_t nb = (size_t)1 << (3 * l);
@@ -490,6 +519,12 @@ fmm_status validate_cfg(const fmm_config *c) {
     if (c->m2l_rotation && c->precision != FMM_PREC_FP64)
         return fail(FMM_EINVAL, "the rotation-based M2L is an option of the FP64 form");
     if (c->m2l_rotation && c->p < 2) return fail(FMM_EINVAL, "the rotation-based M2L needs p >= 2");
+    if (c->adaptive && c->max_level > FMM_ADAPTIVE_MAX_LEVEL)
+        return fail(FMM_EINVAL, "an adaptive tree needs max_level <= 8");
+    if (c->adaptive && c->precision != FMM_PREC_FP64)
+        return fail(FMM_EUNSUPPORTED, "the adaptive tree is evaluated in the FP64 form only");
+    if (c->adaptive && c->m2l_rotation)
+        return fail(FMM_EUNSUPPORTED, "the adaptive tree uses the dense M2L only");
     if (c->profile_stages >> kStages) return fail(FMM_EINVAL, "profile_stages has bits past stage 8");
     if ((c->alloc == nullptr) != (c->free == nullptr))
         return fail(FMM_EINVAL, "alloc and free callbacks must be given together");
@@ -532,13 +567,17 @@ fmm_status work_from_tree(fmm_tree *t, bool far, hipStream_t st, Work &w) {
     if (!z.farf) return FMM_OK;
     CHK(ensure(t, t->farf, z.farf, st));
     w.farf = (double4 *)t->farf.p;
-    for (int l = 2; l <= t->L; ++l) {
-        CHK(ensure(t, t->M[l], z.M[l], st));
-        CHK(ensure(t, t->Lc[l], z.Lc[l], st));
-        CHK(ensure(t, t->pack[l], z.pack[l], st));
-        w.M[l] = t->M[l].p;
-        w.Lc[l] = t->Lc[l].p;
-        w.pack[l] = t->pack[l].p;
+    for (int l = 0; l <= FMM_MAX_LEVEL; ++l) {
+        if (z.M[l]) {
+            CHK(ensure(t, t->M[l], z.M[l], st));
+            CHK(ensure(t, t->Lc[l], z.Lc[l], st));
+            w.M[l] = t->M[l].p;
+            w.Lc[l] = t->Lc[l].p;
+        }
+        if (z.pack[l]) {
+            CHK(ensure(t, t->pack[l], z.pack[l], st));
+            w.pack[l] = t->pack[l].p;
+        }
     }
     if (z.m2lpart) {
         CHK(ensure(t, t->m2lpart, z.m2lpart, st));
@@ -566,10 +605,12 @@ fmm_status work_from_scratch(fmm_tree *t, bool far, Work &w) {
     const size_t o_near = take(z.nearf), o_far = take(z.farf), o_part = take(z.m2lpart),
                  o_lmax = take(z.lmax);
     size_t oM[FMM_MAX_LEVEL + 1] = {}, oL[FMM_MAX_LEVEL + 1] = {}, oP[FMM_MAX_LEVEL + 1] = {};
-    for (int l = 2; l <= t->L && z.farf; ++l) {
-        oM[l] = take(z.M[l]);
-        oL[l] = take(z.Lc[l]);
-        oP[l] = take(z.pack[l]);
+    for (int l = 0; l <= FMM_MAX_LEVEL && z.farf; ++l) {
+        if (z.M[l]) {
+            oM[l] = take(z.M[l]);
+            oL[l] = take(z.Lc[l]);
+        }
+        if (z.pack[l]) oP[l] = take(z.pack[l]);
     }
     if (off > (size_t)FMM_NOALLOC_SCRATCH_BYTES)
         return fail(FMM_EINVAL, "this tree's evaluation needs " + std::to_string(off) +
@@ -585,10 +626,12 @@ fmm_status work_from_scratch(fmm_tree *t, bool far, Work &w) {
         w.m2lpart_bytes = z.m2lpart;
     }
     if (z.lmax) w.lmax = (uint32_t *)(base + o_lmax);
-    for (int l = 2; l <= t->L; ++l) {
-        w.M[l] = base + oM[l];
-        w.Lc[l] = base + oL[l];
-        w.pack[l] = base + oP[l];
+    for (int l = 0; l <= FMM_MAX_LEVEL; ++l) {
+        if (z.M[l]) {
+            w.M[l] = base + oM[l];
+            w.Lc[l] = base + oL[l];
+        }
+        if (z.pack[l]) w.pack[l] = base + oP[l];
     }
     return FMM_OK;
 }
@@ -712,6 +755,233 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
     return FMM_OK;
 }
 
+// ------------------------------------------------------------ adaptive tree
+template <typename T>
+T *bp(const Buf &b) { return (T *)b.p; }
+
+// Build of an adaptive tree: keys and the counting sort at the finest level
+// Lf = max_level; the boxes level by level (a box over leaf_max below Lf is
+// split, its non-empty children appended in Morton order; one host read of
+// the child count per level); then the levels, colleagues and V slots, the
+// U/W/X counts and the leaf heads, one host read of their totals and of the
+// M2L group sizes, and the lists, the leaf list, the leaf-relative records
+// and the grouped M2L targets.
+fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos, hipStream_t st) {
+    const fmm_config &c = t->cfg;
+    const int Lf = c.max_level;
+    if (!t->ad && !(t->ad = new (std::nothrow) AdTree())) return fail(FMM_ENOMEM, "host allocation failed");
+    AdTree *a = t->ad;
+    if (!a->hbuf) HIPCHK(hipHostMalloc((void **)&a->hbuf, kAdHostWords * sizeof(uint32_t)));
+    const int64_t nf = (int64_t)1 << (3 * Lf);
+    // the boxes of a level l >= 1 are non-empty children of split boxes of
+    // level l - 1, which are disjoint and hold more than leaf_max each
+    int64_t bound = 0;
+    for (int l = 0; l <= Lf; ++l) {
+        int64_t b = std::min<int64_t>((int64_t)1 << (3 * l), n);
+        if (l > 0) b = std::min<int64_t>(b, 8 * (n / ((int64_t)c.leaf_max + 1)));
+        bound += b;
+    }
+    const size_t u4 = sizeof(uint32_t);
+    CHK(ensure(t, t->key10, u4 * n, st));
+    CHK(ensure(t, t->rank, u4 * n, st));
+    CHK(ensure(t, t->counters, 4 * u4, st));
+    CHK(ensure(t, t->tmp, u4 * n, st));
+    CHK(ensure(t, t->perm, u4 * n, st));
+    CHK(ensure(t, t->xyz64, sizeof(double4) * n, st));
+    CHK(ensure(t, t->cnt, u4 * nf, st));
+    CHK(ensure(t, t->start, u4 * (nf + 1), st));
+    CHK(ensure(t, t->scan, u4 * scan_scratch_words(std::max(std::max(nf, n), bound) + 1), st));
+    CHK(ensure(t, a->code, u4 * bound, st));
+    CHK(ensure(t, a->ps, u4 * bound, st));
+    CHK(ensure(t, a->pe, u4 * bound, st));
+    CHK(ensure(t, a->parent, u4 * bound, st));
+    CHK(ensure(t, a->child, 8 * u4 * bound, st));
+    CHK(ensure(t, a->leaf, bound + 4, st));  // read back as whole words by the export
+    CHK(ensure(t, a->cmask, bound, st));
+    CHK(ensure(t, a->nchild, u4 * bound, st));
+    CHK(ensure(t, a->coff, u4 * (bound + 1), st));
+    unsigned int *dc = bp<unsigned int>(t->counters);
+    uint32_t *code = bp<uint32_t>(a->code), *ps = bp<uint32_t>(a->ps), *pe = bp<uint32_t>(a->pe);
+    int *parent = bp<int>(a->parent), *child = bp<int>(a->child);
+    uint8_t *leaf = bp<uint8_t>(a->leaf);
+    uint32_t *fstart = bp<uint32_t>(t->start), *scan = bp<uint32_t>(t->scan);
+    auto host_read = [&]() -> fmm_status {
+        HIPCHK(hipEventRecord(t->ev_counters, st));
+        HIPCHK(hipEventSynchronize(t->ev_counters));
+        return FMM_OK;
+    };
+    HIPCHK(launch_keys(n, dtype, pos, c.box_lo, c.box_size, Lf, bp<uint32_t>(t->key10), bp<uint32_t>(t->cnt),
+                       bp<uint32_t>(t->rank), dc, st));
+    HIPCHK(launch_scan_max(nf, bp<uint32_t>(t->cnt), fstart, scan, dc + 1, st));
+    HIPCHK(launch_sort(n, Lf, bp<uint32_t>(t->key10), bp<uint32_t>(t->rank), fstart, bp<uint32_t>(t->tmp), dtype,
+                       pos, c.box_lo, c.box_size, bp<uint32_t>(t->perm), nullptr, bp<double4>(t->xyz64), st));
+    a->off[0] = 0;
+    a->off[1] = 1;
+    HIPCHK(ad_launch_root((uint32_t)n, code, ps, pe, parent, st));
+    int l = 0;
+    for (;; ++l) {
+        const int64_t b0 = a->off[l], nb = a->off[l + 1] - a->off[l];
+        HIPCHK(ad_launch_count(b0, nb, l, Lf, c.leaf_max, code, ps, pe, fstart, leaf, bp<uint32_t>(a->nchild),
+                               bp<uint8_t>(a->cmask), st));
+        HIPCHK(launch_scan(nb, bp<uint32_t>(a->nchild), bp<uint32_t>(a->coff), scan, st));
+        HIPCHK(ad_launch_children(b0, nb, l, Lf, a->off[l + 1], fstart, bp<uint32_t>(a->coff),
+                                  bp<uint8_t>(a->cmask), code, ps, pe, parent, child, st));
+        HIPCHK(hipMemcpyAsync(a->hbuf, bp<uint32_t>(a->coff) + nb, u4, hipMemcpyDeviceToHost, st));
+        if (l == 0) HIPCHK(hipMemcpyAsync(a->hbuf + 1, dc, u4, hipMemcpyDeviceToHost, st));
+        CHK(host_read());
+        if (l == 0 && a->hbuf[1] != 0)
+            return fail(FMM_EDOMAIN, std::to_string(a->hbuf[1]) + " positions outside the root cube or not finite");
+        const int64_t kids = a->hbuf[0];
+        if (kids == 0) break;
+        if (a->off[l + 1] + kids > bound) return fail(FMM_EDEVICE, "internal: box count over its bound");
+        a->off[l + 2] = a->off[l + 1] + kids;
+    }
+    const int nlev = l + 1;
+    const int64_t nbox = a->off[nlev];
+    a->depth = l;
+    a->nbox = nbox;
+    a->nvbox = nlev > 2 ? nbox - a->off[2] : 0;
+    if (!t->ops) CHK(build_ops(c.p, &t->ops));
+    CHK(ensure(t, a->lev, u4 * nbox, st));
+    CHK(ensure(t, a->col, 27 * u4 * nbox, st));
+    CHK(ensure(t, a->vidx, (size_t)kOffsetsPerClass * u4 * std::max<int64_t>(a->nvbox, 1), st));
+    CHK(ensure(t, a->offd, sizeof(int64_t) * (nlev + 1), st));
+    CHK(ensure(t, a->cnts, 3 * u4 * nbox, st));
+    CHK(ensure(t, a->offs, 3 * u4 * (nbox + 1), st));
+    CHK(ensure(t, a->is_head, u4 * n, st));
+    CHK(ensure(t, a->head, u4 * n, st));
+    CHK(ensure(t, a->hoff, u4 * (n + 1), st));
+    const int ngrp = 8 * std::max(nlev - 2, 0);
+    CHK(ensure(t, a->ccnt, u4 * std::max(ngrp, 1), st));
+    int *lev = bp<int>(a->lev), *col = bp<int>(a->col), *vidx = bp<int>(a->vidx);
+    uint32_t *nu = bp<uint32_t>(a->cnts), *nw = nu + nbox, *nx = nw + nbox;
+    uint32_t *ou = bp<uint32_t>(a->offs), *ow = ou + nbox + 1, *ox = ow + nbox + 1;
+    HIPCHK(hipMemcpyAsync(a->offd.p, a->off, sizeof(int64_t) * (nlev + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(ad_launch_structure(nbox, nlev, a->off, bp<int64_t>(a->offd), code, parent, child, lev, col,
+                               t->ops->cls, vidx, st));
+    HIPCHK(ad_launch_lists(nbox, 0, lev, code, parent, col, child, leaf, nu, nw, nx, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, st));
+    HIPCHK(launch_scan(nbox, nu, ou, scan, st));
+    HIPCHK(launch_scan(nbox, nw, ow, scan, st));
+    HIPCHK(launch_scan(nbox, nx, ox, scan, st));
+    HIPCHK(launch_zero(bp<uint32_t>(a->is_head), n, st));
+    HIPCHK(ad_launch_heads(nbox, leaf, ps, pe, bp<uint32_t>(a->is_head), bp<int>(a->head), st));
+    HIPCHK(launch_scan(n, bp<uint32_t>(a->is_head), bp<uint32_t>(a->hoff), scan, st));
+    if (ngrp) {
+        HIPCHK(launch_zero(bp<uint32_t>(a->ccnt), ngrp, st));
+        HIPCHK(ad_launch_class(a->off[2], a->nvbox, lev, code, bp<unsigned int>(a->ccnt), nullptr, nullptr,
+                               nullptr, st));
+        HIPCHK(hipMemcpyAsync(a->hbuf + 4, a->ccnt.p, u4 * ngrp, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(a->hbuf, ou + nbox, u4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(a->hbuf + 1, ow + nbox, u4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(a->hbuf + 2, ox + nbox, u4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(a->hbuf + 3, bp<uint32_t>(a->hoff) + n, u4, hipMemcpyDeviceToHost, st));
+    CHK(host_read());
+    for (int k = 0; k < 3; ++k) a->nlist[k] = a->hbuf[k];
+    a->nleaf = a->hbuf[3];
+    CHK(ensure(t, a->iu, u4 * std::max<int64_t>(a->nlist[0], 1), st));
+    CHK(ensure(t, a->iw, u4 * std::max<int64_t>(a->nlist[1], 1), st));
+    CHK(ensure(t, a->ix, u4 * std::max<int64_t>(a->nlist[2], 1), st));
+    HIPCHK(ad_launch_lists(nbox, 1, lev, code, parent, col, child, leaf, nu, nw, nx, ou, ow, ox, bp<int>(a->iu),
+                           bp<int>(a->iw), bp<int>(a->ix), st));
+    CHK(ensure(t, a->lbox, u4 * a->nleaf, st));
+    CHK(ensure(t, a->lstart, u4 * (a->nleaf + 1), st));
+    CHK(ensure(t, a->llev, a->nleaf, st));
+    HIPCHK(launch_zero(dc + 3, 1, st));
+    HIPCHK(ad_launch_leaflist(n, bp<uint32_t>(a->is_head), bp<uint32_t>(a->hoff), bp<int>(a->head), ps, pe,
+                              bp<int>(a->lbox), bp<uint32_t>(a->lstart), bp<uint8_t>(a->llev), lev, dc + 3, st));
+    HIPCHK(ad_launch_records(n, dtype, bp<uint32_t>(a->hoff), bp<int>(a->lbox), lev, code, bp<uint32_t>(t->perm),
+                             pos, c.box_lo, c.box_size, bp<double4>(t->xyz64), st));
+    // M2L targets grouped by (level, class), tiles of 128 targets per block
+    a->plan = AdM2LPlan{};
+    a->m2l_units = 0;
+    int64_t at = 0;
+    for (int g = 0; g < ngrp; ++g) {
+        a->goff[g] = at;
+        const int64_t cnt = a->hbuf[4 + g];
+        if (cnt) {
+            AdM2LGroup &e = a->plan.grp[a->plan.ngroups++];
+            e.unit0 = a->m2l_units;
+            e.toff = at;
+            e.count = cnt;
+            e.cls = g % 8;
+            a->m2l_units += (cnt + 127) / 128;
+        }
+        at += cnt;
+    }
+    a->goff[ngrp] = at;
+    if (at != a->nvbox) return fail(FMM_EDEVICE, "internal: M2L groups do not cover the boxes");
+    if (ngrp) {
+        CHK(ensure(t, a->tgt, u4 * a->nvbox, st));
+        CHK(ensure(t, a->goffd, sizeof(int64_t) * (ngrp + 1), st));
+        HIPCHK(hipMemcpyAsync(a->goffd.p, a->goff, sizeof(int64_t) * (ngrp + 1), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_zero(bp<uint32_t>(a->ccnt), ngrp, st));
+        HIPCHK(ad_launch_class(a->off[2], a->nvbox, lev, code, nullptr, bp<int64_t>(a->goffd),
+                               bp<unsigned int>(a->ccnt), bp<int>(a->tgt), st));
+    }
+    t->L = a->depth;
+    t->nleaf = a->nleaf;
+    t->max_count = -1;  // read by fmm_tree_info
+    ++t->gen;           // a captured graph holds this tree's launch shapes
+    return FMM_OK;
+}
+
+// Evaluation on an adaptive tree (FP64): gather, P2M at the leaves, M2M up
+// to level 2, M2L over the V slots and P2L over X into the locals, L2L down,
+// L2P and M2P over W at the leaves, P2P over U.  The stage events keep the
+// uniform chain's numbering: stage 3 is the clearing of the level 0-1
+// locals, stage 4 M2L and P2L, stage 6 L2P and M2P.
+fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do_far, bool do_near,
+                        hipStream_t st) {
+    const AdTree *a = t->ad;
+    const int P = t->cfg.p, S = coef_stride(P);
+    const Ops *o = t->ops;
+    t->cur = (int)(t->ncalls % kTimeRing);
+    if (t->xyz64.cap < sizeof(double4) * (size_t)t->n || a->lbox.cap < sizeof(int) * (size_t)a->nleaf)
+        return fail(FMM_EDEVICE, "internal: adaptive tree buffers do not match");
+    double4 *recs = bp<double4>(t->xyz64);
+    const int *lbox = bp<int>(a->lbox), *lev = bp<int>(a->lev);
+    const uint32_t *lstart = bp<uint32_t>(a->lstart), *code = bp<uint32_t>(a->code);
+    const uint32_t *ps = bp<uint32_t>(a->ps), *pe = bp<uint32_t>(a->pe);
+    const uint32_t *ou = bp<uint32_t>(a->offs), *ow = ou + a->nbox + 1, *ox = ow + a->nbox + 1;
+    CHK(rec(t, 0, st));
+    HIPCHK(launch_gather_q(t->n, t->dtype, true, bp<uint32_t>(t->perm), charges, recs, st));
+    CHK(rec(t, 1, st));
+    if (do_far && a->depth >= 2) {
+        if (!o || !w.farf || !w.M[0] || !w.Lc[0]) return fail(FMM_EDEVICE, "internal: no far-field buffers");
+        double *M = (double *)w.M[0], *Lc = (double *)w.Lc[0];
+        HIPCHK(launch_zero((uint32_t *)(M + (size_t)a->nbox * S), 2 * S, st));  // the zero row
+        HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, recs, M, st));
+        CHK(rec(t, 2, st));
+        for (int l = a->depth - 1; l >= 2; --l)
+            HIPCHK(ad_launch_m2m(P, a->off[l], a->off[l + 1] - a->off[l], bp<uint8_t>(a->leaf), bp<int>(a->child),
+                                 o->up64, M, st));
+        CHK(rec(t, 3, st));
+        HIPCHK(launch_zero((uint32_t *)Lc, 2 * S * a->off[2], st));
+        CHK(rec(t, 4, st));
+        HIPCHK(ad_launch_m2l(P, a->plan, a->m2l_units, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2],
+                             bp<int>(a->tgt), a->nbox, Lc, st));
+        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, recs, Lc, st));
+        CHK(rec(t, 5, st));
+        for (int l = 3; l <= a->depth; ++l)
+            HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent), o->down64, Lc,
+                                 st));
+        CHK(rec(t, 6, st));
+        HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, bp<uint8_t>(a->llev), recs, Lc, w.farf, st));
+        HIPCHK(ad_launch_m2p(P, a->nleaf, lbox, lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, st));
+    } else {
+        for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
+    }
+    CHK(rec(t, 7, st));
+    if (do_near)
+        HIPCHK(ad_launch_p2p(a->nleaf, lbox, lstart, ou, bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, st));
+    else
+        HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
+    CHK(rec(t, 8, st));
+    return FMM_OK;
+}
+
 // ---------------------------------------------------------------- graphs
 bool slot_matches(const fmm_tree *t, const GraphSlot &g, const void *const arg[5], int32_t flags) {
     if (!g.exec || g.gen != t->gen || g.L != t->L || g.n != t->n || g.flags != flags) return false;
@@ -776,8 +1046,9 @@ fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int3
     const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
     Work w;
     CHK(noalloc ? work_from_scratch(t, do_far, w) : work_from_tree(t, do_far, st, w));
-    CHK(run_chain(t, w, q, false, do_far, do_near, st));
-    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
+    CHK(t->ad ? run_adaptive(t, w, q, do_far, do_near, st) : run_chain(t, w, q, false, do_far, do_near, st));
+    // the adaptive kernels leave their results in units of the root box
+    const double inv_w = (t->ad ? 1.0 : (double)((int64_t)1 << t->L)) / t->cfg.box_size;
     HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, w.nearf,
                           (t->L >= 2 && do_far) ? w.farf : nullptr, inv_w, q, phi, vec, kind, st));
     CHK(rec(t, kStages, st));
@@ -796,6 +1067,31 @@ fmm_status backward_chain(fmm_tree *t, const void *q, const void *w, const void 
                                grad_pos, st));
     CHK(rec(t, kStages, st));
     if (t->cfg.profile) ++t->ncalls;
+    return FMM_OK;
+}
+
+// P2P and M2L pair counts of a uniform tree
+fmm_status uniform_counts(fmm_tree *t, fmm_tree_info_t *info) {
+    CHK(ensure(t, t->pairs, sizeof(unsigned long long), t->stream));
+    HIPCHK(launch_pair_count(t->L, (const uint32_t *)t->start.p, (unsigned long long *)t->pairs.p, t->stream));
+    unsigned long long pairs = 0;
+    HIPCHK(hipMemcpyAsync(&pairs, t->pairs.p, sizeof(pairs), hipMemcpyDeviceToHost, t->stream));
+    HIPCHK(hipStreamSynchronize(t->stream));
+    info->p2p_pairs = (int64_t)pairs - t->n;
+    // M2L pairs: per axis the count factorises; sum over targets of
+    // (children of in-domain parent neighbours) - (in-domain near boxes)
+    int64_t m2l = 0;
+    for (int l = 2; l <= t->L; ++l) {
+        const int64_t n = (int64_t)1 << l, h = n / 2;
+        int64_t sc = 0, sm = 0;
+        for (int64_t x = 0; x < n; ++x) {
+            const int64_t pp = x / 2;
+            sc += 2 * ((pp - 1 >= 0) + 1 + (pp + 1 < h));
+            sm += (x - 1 >= 0) + 1 + (x + 1 < n);
+        }
+        m2l += sc * sc * sc - sm * sm * sm;
+    }
+    info->m2l_pairs = m2l;
     return FMM_OK;
 }
 
@@ -848,9 +1144,10 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
         const fmm_config &o = t->cfg;
         const bool mixed = cfg->precision == FMM_PREC_MIXED;
         if (o.p != cfg->p || o.precision != cfg->precision || t->dtype != dtype ||
-            (mixed && (split_parts(o) != split_parts(*cfg) || !o.m2l_fp16 != !cfg->m2l_fp16)))
+            (mixed && (split_parts(o) != split_parts(*cfg) || !o.m2l_fp16 != !cfg->m2l_fp16)) ||
+            !o.adaptive != !cfg->adaptive)
             return fail(FMM_EINVAL, "a tree is rebuilt only with the p, precision, M2L encoding "
-                                    "(bf16_splits, m2l_fp16) and dtype it was created with");
+                                    "(bf16_splits, m2l_fp16), tree kind and dtype it was created with");
         if (o.alloc != cfg->alloc || o.free != cfg->free || o.alloc_ctx != cfg->alloc_ctx)
             return fail(FMM_EINVAL, "a tree is rebuilt only with the allocator it was created with");
     }
@@ -893,6 +1190,11 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     while (lev < cfg->max_level && ((int64_t)1 << (3 * lev)) * (int64_t)cfg->leaf_max < n) ++lev;
     if (!t->ev_counters && hipEventCreateWithFlags(&t->ev_counters, hipEventDisableTiming) != hipSuccess)
         return bail(fail(FMM_EDEVICE, "hipEventCreate failed"));
+    if (cfg->adaptive) {
+        if ((s = build_adaptive(t, n, dtype, pos, st)) != FMM_OK) return bail(s);
+        *out = t;
+        return FMM_OK;
+    }
     const bool f64 = is_f64_form(t);
     if ((s = ensure(t, t->key10, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
     if ((s = ensure(t, t->rank, sizeof(uint32_t) * n, st)) != FMM_OK) return bail(s);
@@ -1003,6 +1305,7 @@ fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *f
                         void *grad_q, void *grad_pos, void *stream) {
     if (!t || !q || !w) return fail(FMM_EINVAL, "tree, q and w are required");
     if (grad_pos && !field_fwd) return fail(FMM_EINVAL, "field_fwd is required for grad_pos");
+    if (t->ad) return fail(FMM_EUNSUPPORTED, "fmm_backward is not available on an adaptive tree");
     if (!grad_q && !grad_pos) return FMM_OK;
     hipStream_t st = (hipStream_t)stream;
     if (!t->cfg.graph) return backward_chain(t, q, w, field_fwd, grad_q, grad_pos, st);
@@ -1023,34 +1326,42 @@ fmm_status fmm_tree_info(const fmm_tree *tc, fmm_tree_info_t *info) {
     info->n = t->n;
     info->n_leaves = t->nleaf;
     info->max_leaf_count = t->max_count;
-    CHK(ensure(t, t->pairs, sizeof(unsigned long long), t->stream));
-    HIPCHK(launch_pair_count(t->L, (const uint32_t *)t->start.p, (unsigned long long *)t->pairs.p, t->stream));
-    unsigned long long pairs = 0;
-    HIPCHK(hipMemcpyAsync(&pairs, t->pairs.p, sizeof(pairs), hipMemcpyDeviceToHost, t->stream));
-    HIPCHK(hipStreamSynchronize(t->stream));
-    info->p2p_pairs = (int64_t)pairs - t->n;
-    // M2L pairs: per axis the count factorises; sum over targets of
-    // (children of in-domain parent neighbours) - (in-domain near boxes)
-    int64_t m2l = 0;
-    for (int l = 2; l <= t->L; ++l) {
-        const int64_t n = (int64_t)1 << l, h = n / 2;
-        int64_t sc = 0, sm = 0;
-        for (int64_t x = 0; x < n; ++x) {
-            const int64_t pp = x / 2;
-            sc += 2 * ((pp - 1 >= 0) + 1 + (pp + 1 < h));
-            sm += (x - 1 >= 0) + 1 + (x + 1 < n);
-        }
-        m2l += sc * sc * sc - sm * sm * sm;
+    if (t->ad) {
+        const AdTree *a = t->ad;
+        CHK(ensure(t, t->pairs, 4 * sizeof(unsigned long long), t->stream));
+        HIPCHK(launch_zero((uint32_t *)t->pairs.p, 8, t->stream));
+        const uint32_t *ou = bp<uint32_t>(a->offs), *ow = ou + a->nbox + 1, *ox = ow + a->nbox + 1;
+        HIPCHK(ad_launch_counts(a->nbox, a->off[std::min(a->depth + 1, 2)], bp<uint8_t>(a->leaf),
+                                bp<uint32_t>(a->ps), bp<uint32_t>(a->pe), ou, bp<int>(a->iu), ow, ox,
+                                bp<int>(a->ix), bp<int>(a->vidx), (unsigned long long *)t->pairs.p, t->stream));
+        unsigned long long c[4] = {};
+        unsigned int mx = 0;
+        HIPCHK(hipMemcpyAsync(c, t->pairs.p, sizeof(c), hipMemcpyDeviceToHost, t->stream));
+        HIPCHK(hipMemcpyAsync(&mx, (unsigned int *)t->counters.p + 3, sizeof(mx), hipMemcpyDeviceToHost,
+                              t->stream));
+        HIPCHK(hipStreamSynchronize(t->stream));
+        info->max_leaf_count = mx;
+        info->p2p_pairs = (int64_t)c[0] - t->n;
+        info->m2l_pairs = (int64_t)c[1];
+        info->m2p_evals = (int64_t)c[2];
+        info->p2l_evals = (int64_t)c[3];
+        info->n_boxes = a->nbox;
+    } else {
+        info->n_boxes = 0;
+        for (int l = 0; l <= t->L; ++l) info->n_boxes += (int64_t)1 << (3 * l);
+        CHK(uniform_counts(t, info));
     }
-    info->m2l_pairs = m2l;
     size_t ws = 0;
     const Buf *bufs[] = {&t->key10, &t->rank, &t->cnt, &t->start, &t->tmp, &t->perm, &t->scan,
                          &t->counters, &t->xyz32, &t->xyz64, &t->nearf, &t->farf, &t->pairs, &t->m2lpart, &t->lmax};
     for (const Buf *b : bufs) ws += b->cap;
     for (int l = 0; l <= FMM_MAX_LEVEL; ++l) ws += t->M[l].cap + t->Lc[l].cap + t->pack[l].cap;
+    if (t->ad)
+        for (const Buf *b : t->ad->bufs()) ws += b->cap;
     info->workspace_bytes = ws;
     return FMM_OK;
 }
+
 
 fmm_status fmm_stage_times(const fmm_tree *t, double *ms, int32_t n_stages) {
     if (!t || !ms) return fail(FMM_EINVAL, "tree and ms are required");
@@ -1087,9 +1398,103 @@ fmm_status fmm_tree_export(const fmm_tree *t, uint32_t *perm, uint32_t *leaf_sta
     if (!t) return fail(FMM_EINVAL, "tree is NULL");
     if (perm) HIPCHK(hipMemcpyAsync(perm, t->perm.p, sizeof(uint32_t) * t->n, hipMemcpyDeviceToHost, t->stream));
     if (leaf_start)
-        HIPCHK(hipMemcpyAsync(leaf_start, t->start.p, sizeof(uint32_t) * (t->nleaf + 1),
+        HIPCHK(hipMemcpyAsync(leaf_start, t->ad ? t->ad->lstart.p : t->start.p, sizeof(uint32_t) * (t->nleaf + 1),
                               hipMemcpyDeviceToHost, t->stream));
     HIPCHK(hipStreamSynchronize(t->stream));
+    return FMM_OK;
+}
+
+fmm_status fmm_tree_export_adaptive(const fmm_tree *t, int64_t *sizes, int32_t *boxes, uint32_t *perm,
+                                    int64_t *list_start, int32_t *items) {
+    if (!t || !sizes) return fail(FMM_EINVAL, "tree and sizes are required");
+    if (!t->ad) return fail(FMM_EINVAL, "not an adaptive tree");
+    const AdTree *a = t->ad;
+    const int64_t nbox = a->nbox;
+    hipStream_t st = t->stream;
+    auto get = [&](std::vector<uint32_t> &v, const void *src, size_t words) -> fmm_status {
+        v.resize(std::max<size_t>(words, 1));
+        if (words) HIPCHK(hipMemcpyAsync(v.data(), src, 4 * words, hipMemcpyDeviceToHost, st));
+        return FMM_OK;
+    };
+    std::vector<uint32_t> vid;
+    CHK(get(vid, a->vidx.p, (size_t)kOffsetsPerClass * a->nvbox));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t nv = 0;
+    for (int64_t i = 0; i < kOffsetsPerClass * a->nvbox; ++i) nv += (int32_t)vid[i] >= 0;
+    const int64_t box2 = nbox - a->nvbox;
+    sizes[0] = nbox;
+    sizes[1] = a->nlist[0];
+    sizes[2] = nv;
+    sizes[3] = a->nlist[1];
+    sizes[4] = a->nlist[2];
+    sizes[5] = a->depth;
+    if (boxes) {
+        std::vector<uint32_t> code, ps, pe, parent, lev, leaf;
+        CHK(get(code, a->code.p, nbox));
+        CHK(get(ps, a->ps.p, nbox));
+        CHK(get(pe, a->pe.p, nbox));
+        CHK(get(parent, a->parent.p, nbox));
+        CHK(get(lev, a->lev.p, nbox));
+        CHK(get(leaf, a->leaf.p, (nbox + 3) / 4));
+        HIPCHK(hipStreamSynchronize(st));
+        const uint8_t *lf = (const uint8_t *)leaf.data();
+        for (int64_t b = 0; b < nbox; ++b) {
+            int32_t *o = boxes + 8 * b;
+            uint32_t xyz[3] = {0, 0, 0};
+            for (int bit = 0; bit < 10; ++bit)
+                for (int ax = 0; ax < 3; ++ax) xyz[ax] |= ((code[b] >> (3 * bit + ax)) & 1u) << bit;
+            o[0] = (int32_t)lev[b];
+            o[1] = (int32_t)xyz[0];
+            o[2] = (int32_t)xyz[1];
+            o[3] = (int32_t)xyz[2];
+            o[4] = (int32_t)ps[b];
+            o[5] = (int32_t)pe[b];
+            o[6] = (int32_t)parent[b];
+            o[7] = lf[b];
+        }
+    }
+    if (perm) {
+        HIPCHK(hipMemcpyAsync(perm, t->perm.p, sizeof(uint32_t) * t->n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (list_start || items) {
+        std::vector<uint32_t> offs, iu, iw, ix;
+        CHK(get(offs, a->offs.p, 3 * (nbox + 1)));
+        CHK(get(iu, a->iu.p, a->nlist[0]));
+        CHK(get(iw, a->iw.p, a->nlist[1]));
+        CHK(get(ix, a->ix.p, a->nlist[2]));
+        HIPCHK(hipStreamSynchronize(st));
+        const uint32_t *ou = offs.data(), *ow = ou + nbox + 1, *ox = ow + nbox + 1;
+        int64_t *su = list_start, *sv = su ? su + (nbox + 1) : nullptr, *sw = sv ? sv + (nbox + 1) : nullptr,
+                *sx = sw ? sw + (nbox + 1) : nullptr;
+        int32_t *it = items;
+        for (int64_t b = 0; b <= nbox; ++b) {
+            if (su) {
+                su[b] = ou[b];
+                sw[b] = ow[b];
+                sx[b] = ox[b];
+            }
+        }
+        if (it) {
+            for (int64_t e = 0; e < a->nlist[0]; ++e) *it++ = (int32_t)iu[e];
+        }
+        int64_t at = 0;
+        for (int64_t b = 0; b < nbox; ++b) {
+            if (sv) sv[b] = at;
+            if (b >= box2)
+                for (int k = 0; k < kOffsetsPerClass; ++k) {
+                    const int32_t v = (int32_t)vid[kOffsetsPerClass * (b - box2) + k];
+                    if (v < 0) continue;
+                    if (it) *it++ = v;
+                    ++at;
+                }
+        }
+        if (sv) sv[nbox] = at;
+        if (it) {
+            for (int64_t e = 0; e < a->nlist[1]; ++e) *it++ = (int32_t)iw[e];
+            for (int64_t e = 0; e < a->nlist[2]; ++e) *it++ = (int32_t)ix[e];
+        }
+    }
     return FMM_OK;
 }
 
@@ -1106,6 +1511,11 @@ void fmm_tree_destroy(fmm_tree *t) {
         release(t, t->M[l], st);
         release(t, t->Lc[l], st);
         release(t, t->pack[l], st);
+    }
+    if (t->ad) {
+        for (Buf *b : t->ad->bufs()) release(t, *b, st);
+        if (t->ad->hbuf) (void)hipHostFree(t->ad->hbuf);
+        delete t->ad;
     }
     if (t->ev_ready)
         for (int j = 0; j < kTimeRing; ++j)

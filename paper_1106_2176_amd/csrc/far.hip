@@ -7,6 +7,7 @@
 // (the sorted particle order) and mapped to their row.
 #include <type_traits>
 
+#include "harmonics.hpp"
 #include "kernels.hpp"
 
 namespace fmm {
@@ -188,27 +189,6 @@ __global__ __launch_bounds__(64) void k_p2m(int L, typename V4T<T>::type *__rest
 //   d/dz R_n^m = R_{n-1}^m,  d/dx R_n^m = (R_{n-1}^{m+1} - R_{n-1}^{m-1})/2,
 //   d/dy R_n^m = i (R_{n-1}^{m+1} + R_{n-1}^{m-1})/2.
 // The same kernel evaluates an adjoint multipole vector at its particles.
-template <typename T>
-__device__ inline void getL(const T *ell, int P, int n, int m, T &re, T &im) {
-    // complex L_n^m of an ell-type vector (m may be negative)
-    re = T(0);
-    im = T(0);
-    if (n < 0 || n >= P) return;
-    const int am = m < 0 ? -m : m;
-    if (am > n) return;
-    if (am == 0) {
-        re = ell[n * n];
-        return;
-    }
-    re = ell[n * n + 2 * am - 1] * T(0.5);
-    im = -ell[n * n + 2 * am] * T(0.5);
-    if (m < 0) {  // L^{-m} = (-1)^m conj(L^m)
-        const T sg = (am & 1) ? T(-1) : T(1);
-        re *= sg;
-        im = -im * sg;
-    }
-}
-
 // Two Morton-consecutive leaves per 64-lane block, 32 lanes each (a leaf
 // holds a few tens of particles).  The harmonic loops are fully unrolled, so
 // that every recurrence coefficient is a compile-time constant.
@@ -233,41 +213,7 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
                        (size_t)side * (compact3(leaf >> 1) + (size_t)side * compact3(leaf >> 2));
     for (int c = hl; c < P2; c += HL) ell[c] = live ? Lc[row * S + c] : T(0);
     __syncthreads();
-    for (int c = hl; c < P2; c += HL) {
-        // slot c -> (j, v, part)
-        int j = 0;
-        while ((j + 1) * (j + 1) <= c) ++j;
-        const int o = c - j * j;  // 0 .. 2j
-        const int v = (o + 1) >> 1;
-        const bool sine = o > 0 && (o & 1) == 0;
-        V w;
-        w.x = ell[c];
-        w.y = w.z = w.w = T(0);
-        if (j + 1 < P) {
-            T r1, i1, r2, i2;
-            getL(ell, P, j + 1, v - 1, r1, i1);
-            getL(ell, P, j + 1, v + 1, r2, i2);
-            // Gx = (L^{v-1} - L^{v+1})/2, Gy = i (L^{v-1} + L^{v+1})/2, Gz = L^v
-            const T gxr = (r1 - r2) * T(0.5), gxi = (i1 - i2) * T(0.5);
-            const T gyr = -(i1 + i2) * T(0.5), gyi = (r1 + r2) * T(0.5);
-            T gzr, gzi;
-            getL(ell, P, j + 1, v, gzr, gzi);
-            if (v == 0) {
-                w.y = gxr;
-                w.z = gyr;
-                w.w = gzr;
-            } else if (!sine) {
-                w.y = T(2) * gxr;
-                w.z = T(2) * gyr;
-                w.w = T(2) * gzr;
-            } else {
-                w.y = T(-2) * gxi;
-                w.z = T(-2) * gyi;
-                w.w = T(-2) * gzi;
-            }
-        }
-        coef[c] = w;
-    }
+    for (int c = hl; c < P2; c += HL) coef[c] = l2p_coef<T, V>(ell, P, c);
     __syncthreads();
     for (uint32_t j0 = hl; j0 < cnt; j0 += HL) {
         // keep the coefficient reads in the loop: hoisted, all p^2 of them
@@ -275,51 +221,8 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
         __asm__ volatile("" ::: "memory");
         T x, y, z, qq;
         unpack_rec(src[s0 + j0], x, y, z, qq);
-        const T r2 = x * x + y * y + z * z;
-        T phi = T(0), gx = T(0), gy = T(0), gz = T(0);
-        T dr = T(1), di = T(0);
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            if (m > 0) {
-                const T inv = T(-1) / T(2 * m);
-                const T nr = (dr * x + di * y) * inv;
-                const T ni = (di * x - dr * y) * inv;
-                dr = nr;
-                di = ni;
-            }
-            T ar = dr, ai = di, br = T(0), bi = T(0);
-#pragma unroll
-            for (int n = m; n < P; ++n) {
-                T cr = ar, ci = ai;
-                if (n == m + 1) {
-                    cr = z * ar;
-                    ci = z * ai;
-                } else if (n > m + 1) {
-                    const T inv = T(1) / T((n - m) * (n + m));
-                    cr = (T(2 * n - 1) * z * ar - r2 * br) * inv;
-                    ci = (T(2 * n - 1) * z * ai - r2 * bi) * inv;
-                }
-                if (n > m) {
-                    br = ar;
-                    bi = ai;
-                    ar = cr;
-                    ai = ci;
-                }
-                if (m == 0) {
-                    const V w = coef[n * n];
-                    phi += w.x * cr;
-                    gx += w.y * cr;
-                    gy += w.z * cr;
-                    gz += w.w * cr;
-                } else {
-                    const V w1 = coef[n * n + 2 * m - 1], w2 = coef[n * n + 2 * m];
-                    phi += w1.x * cr + w2.x * ci;
-                    gx += w1.y * cr + w2.y * ci;
-                    gy += w1.z * cr + w2.z * ci;
-                    gz += w1.w * cr + w2.w * ci;
-                }
-            }
-        }
+        T phi, gx, gy, gz;
+        l2p_point<P, T, V>(coef, x, y, z, phi, gx, gy, gz);
         out[s0 + j0] = make_double4((double)phi, -(double)gx, -(double)gy, -(double)gz);
     }
 }

@@ -92,6 +92,72 @@ __host__ __device__ constexpr int tz_size(int P) { return tz_off(P, P, 0); }
 hipError_t launch_m2l_rot(int P, int L, void *const *B, void *const *Lc, const double *rot,
                           const double *tz, const int2 *cls, hipStream_t st);
 
+// adaptive.hip: the adaptive octree (FP64 form); see the file's header for
+// the layout.  Build steps (per level, host-driven) and list construction:
+hipError_t ad_launch_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe, int *parent, hipStream_t st);
+hipError_t ad_launch_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, const uint32_t *code,
+                           const uint32_t *ps, const uint32_t *pe, const uint32_t *fstart, uint8_t *leaf,
+                           uint32_t *nchild, uint8_t *cmask, hipStream_t st);
+hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const uint32_t *fstart,
+                              const uint32_t *coff, const uint8_t *cmask, uint32_t *code, uint32_t *ps,
+                              uint32_t *pe, int *parent, int *child, hipStream_t st);
+hipError_t ad_launch_structure(int64_t nbox, int nlev, const int64_t *off_host, const int64_t *off_dev,
+                               const uint32_t *code, const int *parent, const int *child, int *lev, int *col,
+                               const int2 *cls, int *vidx, hipStream_t st);
+hipError_t ad_launch_lists(int64_t nbox, int pass, const int *lev, const uint32_t *code, const int *parent,
+                           const int *col, const int *child, const uint8_t *leaf, uint32_t *nu, uint32_t *nw,
+                           uint32_t *nx, const uint32_t *ou, const uint32_t *ow, const uint32_t *ox, int *iu,
+                           int *iw, int *ix, hipStream_t st);
+hipError_t ad_launch_heads(int64_t nbox, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,
+                           uint32_t *is_head, int *head, hipStream_t st);
+// leaves in particle order, and the fullest leaf's count into *mx
+hipError_t ad_launch_leaflist(int64_t n, const uint32_t *is_head, const uint32_t *hoff, const int *head,
+                              const uint32_t *ps, const uint32_t *pe, int *lbox, uint32_t *lstart, uint8_t *llev,
+                              const int *lev, unsigned int *mx, hipStream_t st);
+// out[4] (zeroed): ordered P2P pairs incl. self, V entries, W and X (particle, box) pairs
+hipError_t ad_launch_counts(int64_t nbox, int64_t box2, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,
+                            const uint32_t *ou, const int *iu, const uint32_t *ow, const uint32_t *ox, const int *ix,
+                            const int *vidx, unsigned long long *out, hipStream_t st);
+hipError_t ad_launch_records(int64_t n, int dtype, const uint32_t *hoff, const int *lbox, const int *lev,
+                             const uint32_t *code, const uint32_t *perm, const void *pos, const double lo[3],
+                             double size, double4 *rec, hipStream_t st);
+hipError_t ad_launch_class(int64_t box2, int64_t nb, const int *lev, const uint32_t *code, unsigned int *cnt,
+                           const int64_t *goff, unsigned int *fill, int *tgt, hipStream_t st);
+// M2L targets: groups (level >= 2, class) of the target list, tiles of 128
+struct AdM2LGroup {
+    int64_t unit0;  // first block of the group
+    int64_t toff;   // first target of the group in the target list
+    int64_t count;  // targets in the group
+    int cls;        // child class of the group's targets
+    int pad;
+};
+constexpr int kAdMaxGroups = 8 * (FMM_MAX_LEVEL - 1);
+struct AdM2LPlan {
+    int ngroups;
+    AdM2LGroup grp[kAdMaxGroups];
+};
+// evaluation (FP64, box-id-indexed coefficient rows of stride coef_stride(P))
+hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const double4 *rec,
+                         double *M, hipStream_t st);
+hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
+                         double *M, hipStream_t st);
+hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, int64_t nunits, const double *A, const int2 *cls,
+                         const double *M, const int *vidx, int64_t box2, const int *tgt, int64_t zero_row,
+                         double *Lc, hipStream_t st);
+hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
+                         const uint32_t *code, const uint32_t *ps, const uint32_t *pe, const double4 *rec,
+                         double *Lc, hipStream_t st);
+hipError_t ad_launch_l2l(int P, int64_t b0, int64_t nb, const uint32_t *code, const int *parent, const double *tab,
+                         double *Lc, hipStream_t st);
+hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
+                         const double4 *rec, const double *Lc, double4 *out, hipStream_t st);
+hipError_t ad_launch_m2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ow,
+                         const int *iw, const int *lev, const uint32_t *code, const double4 *rec, const double *M,
+                         double4 *out, hipStream_t st);
+hipError_t ad_launch_p2p(int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ou, const int *iu,
+                         const int *lev, const uint32_t *code, const uint32_t *ps, const uint32_t *pe,
+                         const double4 *rec, double4 *out, hipStream_t st);
+
 // scratch.hip: device address of the current device's static scratch array
 // (FMM_NOALLOC_SCRATCH_BYTES), looked up on the first call per device
 hipError_t noalloc_scratch(void **ptr);

@@ -59,6 +59,20 @@ def test_build_rejects_bad_config(field, value):
     assert fmm.lib().fmm_last_error_message()
 
 
+@pytest.mark.parametrize("changes,status", [
+    (dict(precision=1), fmm.FMM_EUNSUPPORTED),          # adaptive trees are FP64-form only
+    (dict(m2l_rotation=1), fmm.FMM_EUNSUPPORTED),       # and use the dense M2L
+    (dict(max_level=9), fmm.FMM_EINVAL),                # finest sort at level <= 8
+])
+def test_adaptive_config_checks(changes, status):
+    cfg = fmm.make_config(precision="fp64", adaptive=True)
+    assert cfg.adaptive == 1 and cfg.max_level == fmm.ADAPTIVE_MAX_LEVEL
+    for k, v in changes.items():
+        setattr(cfg, k, v)
+    rc, h = _build(cfg)
+    assert rc == status and not h.value
+
+
 def test_profile_stages_past_the_last_stage_rejected():
     cfg = fmm.make_config(profile=True)
     cfg.profile_stages = 1 << 9
@@ -92,6 +106,7 @@ def test_other_entry_points_reject_null():
     assert L.fmm_tree_info(None, None) == fmm.FMM_EINVAL
     assert L.fmm_stage_times(None, None, 0) == fmm.FMM_EINVAL
     assert L.fmm_tree_export(None, None, None) == fmm.FMM_EINVAL
+    assert L.fmm_tree_export_adaptive(None, None, None, None, None, None) == fmm.FMM_EINVAL
     L.fmm_tree_destroy(None)
     assert L.fmm_operator_host(0, 0, 0, None) == fmm.FMM_EINVAL
     with pytest.raises(fmm.FMMError):
