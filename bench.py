@@ -58,6 +58,9 @@ PEAK_16BIT_MFMA_TFLOPS = 2500.0  # bf16 and fp16 dense
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 P2P_FLOP_PER_PAIR = 19
+# stage names of fmm_stage_times, and their meaning on an adaptive tree
+STAGE_NAMES = ("gather", "P2M", "M2M", "pack", "M2L", "L2L", "L2P", "P2P", "combine")
+ADAPTIVE_STAGE_NAMES = ("gather", "P2M", "M2M", "P2L", "M2L", "L2L", "L2P+M2P", "P2P", "combine")
 COPY_PROBE_BYTES = 1 << 30
 
 # mixed-form M2L encodings: tree options and MFMA products per term
@@ -78,12 +81,18 @@ def parse():
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-overlap", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="particles for the CPU oracle baseline (0: the whole workload)")
     ap.add_argument("--m2l", default="fp16x2", choices=sorted(ENCODINGS),
                     help="M2L operand encoding of the mixed form")
     ap.add_argument("--copy-probe", action="store_true")
     return ap.parse_args()
+
+
+def log(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def timed_steps(step, steps, warmup, sync):
@@ -235,6 +244,76 @@ def rooflines(wl, res, precision, enc, on_profiled):
     return (m2l, p2p) if dom == "M2L" else (p2p, m2l)
 
 
+# The adaptive-tree record: Gaussian blobs (inputs.clustered), FP64 form,
+# beside the uniform FP64 tree on the same input with its level capped at 7
+# and at 8 (uncapped, the uniform level of these blobs would exceed 8).
+ADAPTIVE = {"n": 1_000_000, "seed": 6, "blobs": 6, "p": 8, "leaf_max": 64, "max_level": 8,
+            "uniform_levels": (7, 8)}
+
+
+def sampled_errors(res, q_np, t_idx, phi_d, E_d):
+    """Relative L2 of phi and F = qE on sampled targets against the direct sum."""
+    ph = res["phi"].cpu().numpy().astype(np.float64)[t_idx]
+    Ef = res["E"].cpu().numpy().astype(np.float64)[t_idx]
+    qq = q_np.astype(np.float64)[t_idx][:, None]
+    return {"phi": float(np.linalg.norm(ph - phi_d) / np.linalg.norm(phi_d)),
+            "F": float(np.linalg.norm(qq * (Ef - E_d)) / np.linalg.norm(qq * E_d))}
+
+
+def adaptive_rooflines(p, res):
+    """(dominant, other) rooflines of the adaptive tree's M2L (gathered FP64
+    MFMA, 2 p^4 FLOP per V entry) and P2P (FP64, 19 FLOP per pair)."""
+    info, st = res["info"], res["stages_ms"]
+    m2l_ms = res["dom_ms"] if res["dom"] == "M2L" else st["M2L"]
+    p2p_ms = res["dom_ms"] if res["dom"] == "P2P" else st["P2P"]
+    m2l_tf = 2.0 * p ** 4 * info["m2l_pairs"] / (m2l_ms * 1e-3) / 1e12
+    p2p_tf = P2P_FLOP_PER_PAIR * info["p2p_pairs"] / (p2p_ms * 1e-3) / 1e12
+    m2l = {"kernel": "k_ad_m2l<%d>" % p, "bound": "mfma", "achieved": m2l_tf, "peak": PEAK_FP64_TFLOPS,
+           "unit": "TFLOP/s", "frac": m2l_tf / PEAK_FP64_TFLOPS, "traffic": None, "ms": m2l_ms,
+           "flop_per_launch": 2.0 * p ** 4 * info["m2l_pairs"]}
+    p2p = {"kernel": "k_ad_p2p", "bound": "alu", "achieved": p2p_tf, "peak": PEAK_FP64_TFLOPS,
+           "unit": "TFLOP/s", "frac": p2p_tf / PEAK_FP64_TFLOPS, "traffic": None, "ms": p2p_ms,
+           "flop_per_launch": P2P_FLOP_PER_PAIR * info["p2p_pairs"]}
+    return (m2l, p2p) if res["dom"] == "M2L" else (p2p, m2l)
+
+
+def adaptive_record(fmm, oracle, inputs, steps, warmup, sync, dev):
+    import torch
+    a = ADAPTIVE
+    n = a["n"]
+    pos_np, q_np = inputs.clustered(n, a["seed"], a["blobs"])
+    P, Q = torch.from_numpy(pos_np).to(dev), torch.from_numpy(q_np).to(dev)
+    wl = inputs.Workload("clustered", a["seed"], n, a["p"], a["leaf_max"], "u01", "f64")
+    t_idx = inputs.targets(n, a["seed"])
+    phi_d, E_d = oracle.direct(pos_np, q_np, t_idx)
+    res = measure(fmm, wl, P, Q, "fp64", steps, warmup, sync, adaptive=True, max_level=a["max_level"])
+    log("adaptive tree: adaptive form measured")
+    info = res["info"]
+    roof, other = adaptive_rooflines(a["p"], res)
+    names = dict(zip(STAGE_NAMES, ADAPTIVE_STAGE_NAMES))
+    out = {"workload": "N=%g Gaussian blobs (%d blobs, widths U[0.005,0.06)), charges U[0,1), p=%d, "
+                       "leaf<=%d, max level %d, f64 positions/charges, FP64 form"
+                       % (n, a["blobs"], a["p"], a["leaf_max"], a["max_level"]),
+           "ms_per_step": res["sec"] * 1e3, "particles_per_s": n / res["sec"],
+           "build_ms": res["build_ms"],
+           "stages_ms": {names[k]: v for k, v in res["stages_ms"].items()},
+           "tree": {k: info[k] for k in ("levels", "n_boxes", "n_leaves", "max_leaf_count", "p2p_pairs",
+                                         "m2l_pairs", "m2p_evals", "p2l_evals")},
+           "p2p_gint_s": info["p2p_pairs"] / (res["stages_ms"]["P2P"] * 1e-3) / 1e9,
+           "roofline": roof, ("roofline_p2p" if res["dom"] == "M2L" else "roofline_m2l"): other,
+           "rel_l2_vs_direct": sampled_errors(res, q_np, t_idx, phi_d, E_d), "uniform": {}}
+    del res
+    for ml in a["uniform_levels"]:
+        u = measure(fmm, wl, P, Q, "fp64", 2, 1, sync, max_level=ml)
+        log("adaptive tree: uniform tree at max level %d measured" % ml)
+        out["uniform"]["max_level_%d" % ml] = {
+            "levels": u["info"]["levels"], "ms_per_step": u["sec"] * 1e3, "particles_per_s": n / u["sec"],
+            "p2p_pairs": u["info"]["p2p_pairs"], "m2l_pairs": u["info"]["m2l_pairs"],
+            "stages_ms": u["stages_ms"], "rel_l2_vs_direct": sampled_errors(u, q_np, t_idx, phi_d, E_d)}
+        del u
+    return out
+
+
 def tree_pass(wl, res, precision):
     """Algorithmic HBM bytes of the build, P2M (with the charge gather), L2P
     and the combine, over their measured time (build: wall time of the
@@ -282,6 +361,7 @@ def main():
     enc_kw = ENCODINGS[args.m2l][0]
 
     mixed = measure(fmm, wl, pos, q, "mixed", args.steps, args.warmup, sync, **enc_kw)
+    log("%s mixed form measured" % args.workload)
     info = mixed["info"]
     n = wl.n
     value = n / mixed["sec"]
@@ -292,11 +372,7 @@ def main():
     p2p_ms = roof["ms"] if mixed["dom"] == "P2P" else other["ms"]
 
     def errs(res, pos_np, q_np, t_idx, phi_d, E_d):
-        ph = res["phi"].cpu().numpy().astype(np.float64)[t_idx]
-        Ef = res["E"].cpu().numpy().astype(np.float64)[t_idx]
-        qq = q_np.astype(np.float64)[t_idx][:, None]
-        return {"phi": float(np.linalg.norm(ph - phi_d) / np.linalg.norm(phi_d)),
-                "F": float(np.linalg.norm(qq * (Ef - E_d)) / np.linalg.norm(qq * E_d))}
+        return sampled_errors(res, q_np, t_idx, phi_d, E_d)
 
     def mixed_vs_fp64(a_res, b_res, q_np):
         a, b = a_res["phi"].cpu().numpy(), b_res["phi"].cpu().numpy()
@@ -312,6 +388,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         fp64 = measure(fmm, wl, pos, q, "fp64", max(3, args.steps // 4), 1, sync)
+        log("%s FP64 form measured" % args.workload)
         rel["fp64_vs_direct"] = errs(fp64, pos_np, q_np, t_idx, phi_d, E_d)
         rel["mixed_vs_fp64_all"] = mixed_vs_fp64(mixed, fp64, q_np)
 
@@ -322,6 +399,7 @@ def main():
                    "serial_ms_per_step": mixed["sec"] * 1e3,
                    "p2p_ms_side_stream": ov["stages_ms"]["P2P"], "m2l_ms": ov["stages_ms"]["M2L"]}
         del ov
+        log("overlapped near field measured")
 
     c3 = None
     if not args.no_c3 and args.workload != "C3":
@@ -329,6 +407,7 @@ def main():
         p3, q3 = inputs.workload("C3")
         P3, Q3 = torch.from_numpy(p3).to(dev), torch.from_numpy(q3).to(dev)
         m3 = measure(fmm, w3, P3, Q3, "mixed", max(5, args.steps // 2), 2, sync, **enc_kw)
+        log("C3 mixed form measured")
         r3, o3 = rooflines(w3, m3, "mixed", args.m2l, False)
         t3 = inputs.targets(w3.n, w3.seed)
         pd3, Ed3 = oracle.direct(p3, q3, t3)
@@ -341,6 +420,7 @@ def main():
               "rel_l2": {"mixed_vs_direct": errs(m3, p3, q3, t3, pd3, Ed3)}}
         if not args.no_fp64:
             f3 = measure(fmm, w3, P3, Q3, "fp64", 3, 1, sync)
+            log("C3 FP64 form measured")
             r3f, o3f = rooflines(w3, f3, "fp64", None, False)
             c3["fp64"] = {"ms_per_step": f3["sec"] * 1e3, "particles_per_s": w3.n / f3["sec"],
                           "p2p_gint_s": f3["info"]["p2p_pairs"] / (f3["stages_ms"]["P2P"] * 1e-3) / 1e9,
@@ -367,6 +447,7 @@ def main():
 
         s5 = timed_steps(fb, max(3, args.steps // 2), 2, sync)
         tree5.close()
+        log("C5 forward + backward measured")
         adj = {"workload": w5.describe() + ", loss sum w_i phi_i, w ~ N(0,1)",
                "fwd_bwd_particles_per_s": w5.n / s5, "ms_per_step": s5 * 1e3}
 
@@ -392,6 +473,12 @@ def main():
             small[name] = {"evaluate_us": 1e6 * timed_steps(ev, 200, 10, sync),
                            "step_us": 1e6 * timed_steps(st, 100, 5, sync)}
             t1.close()
+        log("C1 launch modes measured")
+
+    adaptive = None
+    if not args.no_adaptive:
+        adaptive = adaptive_record(fmm, oracle, inputs, max(5, args.steps // 2), 2, sync, dev)
+        log("adaptive tree measured")
 
     cpu = None
     if not args.no_cpu:
@@ -400,6 +487,7 @@ def main():
         t0 = time.perf_counter()
         oracle.fmm(ps.astype(np.float64), qs.astype(np.float64), wl.p, wl.leaf_max)
         tc = time.perf_counter() - t0
+        log("CPU oracle timed")
         what = "the whole workload" if ns == n else "a sample of N=%d particles" % ns
         cpu = {"value": ns / tc, "unit": "particles/s", "cores": oracle.num_threads(),
                "kind": "oracle",
@@ -434,6 +522,7 @@ def main():
         "cpu_baseline": cpu,
         "adjoint": adj,
         "small": small,
+        "adaptive": adaptive,
     }
     if fp64 is not None:
         r64, o64 = rooflines(wl, fp64, "fp64", None, False)

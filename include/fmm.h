@@ -311,6 +311,8 @@ fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
  * Stages, in order:
  *   0 gather   1 P2M   2 M2M   3 pack (M2L operand)   4 M2L   5 L2L
  *   6 L2P      7 P2P   8 combine
+ * On an adaptive tree stage 3 is P2L (the X lists) and stage 6 holds L2P
+ * and M2P (the W lists).
  * `ms` receives min(n_stages, 9) values; stages outside cfg.profile_stages
  * (when it is nonzero) receive NaN.  FMM_EINVAL if profiling is off or no
  * call was recorded. */

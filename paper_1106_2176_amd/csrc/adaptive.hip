@@ -297,6 +297,21 @@ __global__ void k_ad_leaflist(int64_t n, const uint32_t *__restrict__ is_head, c
     if (i == n - 1) lstart[hoff[n]] = (uint32_t)n;
 }
 
+// P2P work units: ceil(count / 64) per leaf (pass 0), then each unit's
+// (leaf, first target) from the scanned counts (pass 1).
+__global__ void k_ad_units(int64_t nleaf, int pass, const uint32_t *__restrict__ lstart,
+                           uint32_t *__restrict__ cnt, const uint32_t *__restrict__ uoff,
+                           int2 *__restrict__ units) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nleaf) return;
+    const uint32_t m = (lstart[j + 1] - lstart[j] + 63) / 64;
+    if (pass == 0) {
+        cnt[j] = m;
+        return;
+    }
+    for (uint32_t k = 0; k < m; ++k) units[uoff[j] + k] = make_int2((int)j, (int)(64 * k));
+}
+
 // Work counts: [0] ordered P2P pairs (self pairs included), [1] V entries,
 // [2] (particle, box) pairs of W, [3] of X.
 __global__ void k_ad_counts(int64_t nbox, int64_t box2, const uint8_t *__restrict__ leaf,
@@ -512,9 +527,11 @@ __device__ __forceinline__ void irregular_each(double x, double y, double z, F &
     }
 }
 
-// P2L over X: for every box g, ell(g) += sum over the leaves c of X(g) of the
+// P2L over X: for every box g, ell(g) = sum over the leaves c of X(g) of the
 // local expansion of each particle of c: the complex local coefficient of a
 // charge q at y (g units) is q I_n^m(y), i.e. ell_c = 2 q Re, ell_s = -2 q Im.
+// Every box's row is written (zero for an empty X), so this pass also clears
+// the locals before M2L and L2L add to them.
 template <int P>
 __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, const int *__restrict__ ix,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
@@ -524,7 +541,6 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
     __shared__ double rows[B][P2 + 1];
     const int g = blockIdx.x, t = threadIdx.x;
     const uint32_t x0 = ox[g], x1 = ox[g + 1];
-    if (x0 == x1) return;
     const int lg = lev[g];
     double acc[NC];
 #pragma unroll
@@ -567,7 +583,7 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         const int k = t + 64 * a;
-        if (k < P2) Lc[(size_t)g * S + k] += acc[a];
+        if (k < P2) Lc[(size_t)g * S + k] = acc[a];
     }
 }
 
@@ -658,63 +674,156 @@ __global__ __launch_bounds__(64) void k_ad_m2p(const int *__restrict__ lbox, con
     }
 }
 
-// P2P over U at the leaves (FP64): sources of each leaf c in U(g) brought
-// into g's frame and units, (c_c - c_g)/w_g + u 2^(l_g - l_c), in LDS tiles of
-// 64; j = i and coincident points excluded.  Root units out.
-__global__ __launch_bounds__(64) void k_ad_p2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
-                                               const uint32_t *__restrict__ ou, const int *__restrict__ iu,
-                                               const int *__restrict__ lev, const uint32_t *__restrict__ code,
-                                               const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
-                                               const double4 *__restrict__ rec, double4 *__restrict__ out) {
-    __shared__ double4 tile[64];
-    const int j = blockIdx.x;
-    const int g = lbox[j];
-    const int lg = lev[g];
-    const uint32_t u0 = ou[g], u1 = ou[g + 1];
-    for (uint32_t i0 = lstart[j]; i0 < lstart[j + 1]; i0 += 64) {
-        const uint32_t i = i0 + threadIdx.x;
-        const bool live = i < lstart[j + 1];
-        const double4 r = live ? rec[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+// One pair of the FP64 near field: rsqrt by the hardware estimate and one
+// Newton step (relative error near 2^-52); a coincident source (r = 0,
+// which includes the target itself) adds nothing when SELF.
+template <bool SELF>
+__device__ __forceinline__ void ad_pair(double xi, double yi, double zi, const double4 s, double &phi,
+                                        double &ex, double &ey, double &ez) {
+    const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+    double r2 = dx * dx;
+    r2 = __builtin_fma(dy, dy, r2);
+    r2 = __builtin_fma(dz, dz, r2);
+    double y = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2 * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    if (SELF) y = r2 > 0.0 ? y : 0.0;
+    const double qr = s.w * y;
+    phi += qr;
+    const double qr3 = qr * (y * y);
+    ex = __builtin_fma(qr3, dx, ex);
+    ey = __builtin_fma(qr3, dy, ey);
+    ez = __builtin_fma(qr3, dz, ez);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// P2P over U at the leaves (FP64), one wave per unit of up to 64 targets of
+// one leaf (a leaf of more than 64 particles gives several units, so that
+// the work of the fullest leaves spreads over several waves).  The unit's
+// targets take T = 2^LT lanes (the power of two >= its count) and the 64 / T
+// lane groups split every source tile, their sums joined by shuffles at the
+// end.  The sources of U(g) are taken as one sequence, up to
+// 64 list entries at a time: each lane holds one entry's particle range and
+// its frame change (c_c - c_g)/w_g + u 2^(l_g - l_c) (exact scaling, one
+// rounding), a wave scan of the counts gives the entries' offsets, and the
+// sequence is staged in tiles of 64 in the wave's LDS (the last one padded
+// with far, uncharged points), each lane finding its entry by bisection.  A
+// coincident source, the target itself included, adds nothing.  Root units
+// out.
+constexpr int kAdP2PWaves = 4;
+struct AdP2PShared {
+    double4 tile[64];
+    double4 frame[64];    // (cx, cy, cz, scale) of a batch's entries
+    uint32_t first[64];   // first particle of each entry
+    uint32_t off[65];     // exclusive offsets of the entries, total last
+};
+
+template <int LT>
+__device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, int lg, uint32_t cg, uint32_t t0,
+                                            uint32_t nt, uint32_t u0, uint32_t u1, const int *__restrict__ iu,
+                                            const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                                            const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
+                                            const double4 *__restrict__ rec, double4 *__restrict__ out) {
+    constexpr int T = 1 << LT, G = 64 >> LT;
+    const int slot = lane & (T - 1), grp = lane >> LT;
+    const double s1 = ldexp(1.0, lg), s2 = s1 * s1;
+    {
+        const uint32_t ti = slot;
+        const bool live = ti < nt;
+        const double4 r = live ? rec[t0 + ti] : make_double4(0.0, 0.0, 0.0, 0.0);
         double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        for (uint32_t e = u0; e < u1; ++e) {
-            const int c = iu[e];
-            const int lc = lev[c];
-            double cx, cy, cz;
-            ad_centre_diff(lc, code[c], lg, code[g], lg, cx, cy, cz);
-            const double sc = ldexp(1.0, lg - lc);
-            for (uint32_t s0 = ps[c]; s0 < pe[c]; s0 += 64) {
-                __syncthreads();
-                if (s0 + threadIdx.x < pe[c]) {
-                    const double4 v = rec[s0 + threadIdx.x];
-                    tile[threadIdx.x] = make_double4(cx + sc * v.x, cy + sc * v.y, cz + sc * v.z, v.w);
+        for (uint32_t e0 = u0; e0 < u1; e0 += 64) {
+            const int nb = (int)min(64u, u1 - e0);
+            uint32_t cnt = 0;
+            wave_sync();  // the previous batch's tables have been read
+            if (lane < nb) {
+                const int c = iu[e0 + lane];
+                const int lc = lev[c];
+                double cx, cy, cz;
+                ad_centre_diff(lc, code[c], lg, cg, lg, cx, cy, cz);
+                sh.frame[lane] = make_double4(cx, cy, cz, ldexp(1.0, lg - lc));
+                sh.first[lane] = ps[c];
+                cnt = pe[c] - ps[c];
+            }
+            uint32_t incl = cnt;  // inclusive scan over the lanes
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t v = __shfl_up(incl, d);
+                if (lane >= d) incl += v;
+            }
+            sh.off[lane + 1] = incl;
+            if (lane == 0) sh.off[0] = 0;
+            const uint32_t total = __shfl(incl, 63);
+            wave_sync();
+            for (uint32_t f0 = 0; f0 < total; f0 += 64) {
+                const uint32_t f = f0 + lane;
+                double4 src = make_double4(1e3, 1e3, 1e3, 0.0);
+                if (f < total) {
+                    int lo = 0, hi = nb - 1;  // the entry k with off[k] <= f < off[k + 1]
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sh.off[mid] <= f) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const double4 fr = sh.frame[lo];
+                    const double4 v = rec[sh.first[lo] + (f - sh.off[lo])];
+                    src = make_double4(fr.x + fr.w * v.x, fr.y + fr.w * v.y, fr.z + fr.w * v.z, v.w);
                 }
-                __syncthreads();
-                const int cnt = (int)min(64u, pe[c] - s0);
-                for (int k = 0; k < cnt; ++k) {
-                    const double4 v = tile[k];
-                    const double dx = r.x - v.x, dy = r.y - v.y, dz = r.z - v.z;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (s0 + k == i || r2 == 0.0) continue;
-                    const double rinv = 1.0 / sqrt(r2);
-                    const double qr = v.w * rinv, qr3 = qr * rinv * rinv;
-                    phi += qr;
-                    ex += qr3 * dx;
-                    ey += qr3 * dy;
-                    ez += qr3 * dz;
-                }
+                wave_sync();  // the previous tile has been read
+                sh.tile[lane] = src;
+                wave_sync();
+#pragma unroll
+                for (int k = 0; k < 64; k += G) ad_pair<true>(r.x, r.y, r.z, sh.tile[k + grp], phi, ex, ey, ez);
             }
         }
-        if (live) {
-            const double s1 = ldexp(1.0, lg), s2 = s1 * s1;
-            out[i] = make_double4(phi * s1, ex * s2, ey * s2, ez * s2);
+#pragma unroll
+        for (int d = 32; d >= T; d >>= 1) {
+            phi += __shfl_xor(phi, d);
+            ex += __shfl_xor(ex, d);
+            ey += __shfl_xor(ey, d);
+            ez += __shfl_xor(ez, d);
         }
+        if (live && grp == 0) out[t0 + ti] = make_double4(phi * s1, ex * s2, ey * s2, ez * s2);
     }
 }
 
-// Gathered M2L (FP64 MFMA): the targets of each (level, class) group, in
-// tiles of 128 columns (4 waves x 2 x 16), against the K range of the class's
-// 189 slots x S coefficients in chunks of 8; a column's source row for a slot
-// comes from its V slots (an absent source reads the zero row).  A chunk's
+__global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
+    const uint32_t *__restrict__ nunits, const int2 *__restrict__ units, const int *__restrict__ lbox,
+    const uint32_t *__restrict__ lstart, const uint32_t *__restrict__ ou, const int *__restrict__ iu,
+    const int *__restrict__ lev, const uint32_t *__restrict__ code, const uint32_t *__restrict__ ps,
+    const uint32_t *__restrict__ pe, const double4 *__restrict__ rec, double4 *__restrict__ out) {
+    __shared__ AdP2PShared shm[kAdP2PWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * kAdP2PWaves + wave;
+    if (w >= (int64_t)*nunits) return;  // waves work alone: no block barrier below
+    const int2 un = units[w];
+    const int j = un.x;
+    const int g = lbox[j];
+    const uint32_t t0 = lstart[j] + (uint32_t)un.y, nt = min(64u, lstart[j + 1] - t0);
+    int lt = 0;  // log2 T
+    while ((1u << lt) < nt && lt < 6) ++lt;
+#define AD_P2P_CASE(K)                                                                                       \
+    case K:                                                                                                  \
+        ad_p2p_unit<K>(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, \
+                       rec, out);                                                                            \
+        break;
+    switch (lt) {
+        AD_P2P_CASE(0) AD_P2P_CASE(1) AD_P2P_CASE(2) AD_P2P_CASE(3) AD_P2P_CASE(4) AD_P2P_CASE(5)
+        AD_P2P_CASE(6)
+    }
+#undef AD_P2P_CASE
+}
+
+// Gathered M2L (FP64 MFMA), added to the locals: the targets of each (level,
+// class) group, in tiles of 128 columns (4 waves x 2 x 16), against the K
+// range of the class's 189 slots x S coefficients in chunks of 8; a column's
+// source row for a slot comes from its V slots (an absent source reads the
+// zero row).  A chunk's
 // operator (R x 8, uniform over the block) is staged in LDS one chunk ahead;
 // lane group q takes K index 4 j + q of a chunk (v_mfma_f64_16x16x4_f64).
 template <int P>
@@ -823,7 +932,7 @@ __global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__re
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * r + q + 4 * i;
-                if (row < P2) Lc[tbox[bb] * S + row] = acc[r][bb][i];
+                if (row < P2) Lc[tbox[bb] * S + row] += acc[r][bb][i];
             }
     }
 }
@@ -1031,10 +1140,17 @@ hipError_t ad_launch_m2p(int P, int64_t nleaf, const int *lbox, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t ad_launch_p2p(int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ou, const int *iu,
-                         const int *lev, const uint32_t *code, const uint32_t *ps, const uint32_t *pe,
-                         const double4 *rec, double4 *out, hipStream_t st) {
-    k_ad_p2p<<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, ou, iu, lev, code, ps, pe, rec, out);
+hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint32_t *cnt, const uint32_t *uoff,
+                           int2 *units, hipStream_t st) {
+    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, lstart, cnt, uoff, units);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_p2p(int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
+                         const uint32_t *lstart, const uint32_t *ou, const int *iu, const int *lev, const uint32_t *code,
+                         const uint32_t *ps, const uint32_t *pe, const double4 *rec, double4 *out, hipStream_t st) {
+    k_ad_p2p<<<ad_blocks(max_units, kAdP2PWaves), 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu,
+                                                                            lev, code, ps, pe, rec, out);
     return hipGetLastError();
 }
 

@@ -352,11 +352,12 @@ struct AdTree {
     int64_t m2l_units = 0;
     uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
     Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
-        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts;
+        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts, ucnt, uoff, units;
+    int64_t max_units = 0;  // bound of the P2P work units (their count stays on the device)
     std::vector<Buf *> bufs() {
         return {&code, &ps, &pe, &parent, &child, &leaf, &cmask, &nchild, &coff, &lev, &col, &vidx, &cnts,
                 &offs, &iu, &iw, &ix, &is_head, &head, &hoff, &lbox, &lstart, &llev, &tgt, &ccnt, &goffd,
-                &offd, &counts};
+                &offd, &counts, &ucnt, &uoff, &units};
     }
 };
 
@@ -813,7 +814,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     HIPCHK(launch_keys(n, dtype, pos, c.box_lo, c.box_size, Lf, bp<uint32_t>(t->key10), bp<uint32_t>(t->cnt),
                        bp<uint32_t>(t->rank), dc, st));
     HIPCHK(launch_scan_max(nf, bp<uint32_t>(t->cnt), fstart, scan, dc + 1, st));
-    HIPCHK(launch_sort(n, Lf, bp<uint32_t>(t->key10), bp<uint32_t>(t->rank), fstart, bp<uint32_t>(t->tmp), dtype,
+    HIPCHK(launch_sort(n, Lf, UINT32_MAX, bp<uint32_t>(t->key10), bp<uint32_t>(t->rank), fstart, bp<uint32_t>(t->tmp), dtype,
                        pos, c.box_lo, c.box_size, bp<uint32_t>(t->perm), nullptr, bp<double4>(t->xyz64), st));
     a->off[0] = 0;
     a->off[1] = 1;
@@ -893,6 +894,15 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
                               bp<int>(a->lbox), bp<uint32_t>(a->lstart), bp<uint8_t>(a->llev), lev, dc + 3, st));
     HIPCHK(ad_launch_records(n, dtype, bp<uint32_t>(a->hoff), bp<int>(a->lbox), lev, code, bp<uint32_t>(t->perm),
                              pos, c.box_lo, c.box_size, bp<double4>(t->xyz64), st));
+    // P2P work units: at most one per leaf plus one per 64 particles
+    a->max_units = a->nleaf + n / 64;
+    CHK(ensure(t, a->ucnt, u4 * a->nleaf, st));
+    CHK(ensure(t, a->uoff, u4 * (a->nleaf + 1), st));
+    CHK(ensure(t, a->units, sizeof(int2) * a->max_units, st));
+    HIPCHK(ad_launch_units(a->nleaf, 0, bp<uint32_t>(a->lstart), bp<uint32_t>(a->ucnt), nullptr, nullptr, st));
+    HIPCHK(launch_scan(a->nleaf, bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), scan, st));
+    HIPCHK(ad_launch_units(a->nleaf, 1, bp<uint32_t>(a->lstart), nullptr, bp<uint32_t>(a->uoff), bp<int2>(a->units),
+                           st));
     // M2L targets grouped by (level, class), tiles of 128 targets per block
     a->plan = AdM2LPlan{};
     a->m2l_units = 0;
@@ -928,10 +938,10 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
 }
 
 // Evaluation on an adaptive tree (FP64): gather, P2M at the leaves, M2M up
-// to level 2, M2L over the V slots and P2L over X into the locals, L2L down,
-// L2P and M2P over W at the leaves, P2P over U.  The stage events keep the
-// uniform chain's numbering: stage 3 is the clearing of the level 0-1
-// locals, stage 4 M2L and P2L, stage 6 L2P and M2P.
+// to level 2, P2L over X (which writes every box's locals) and M2L over the V
+// slots (added), L2L down, L2P and M2P over W at the leaves, P2P over U.  The
+// stage events keep the uniform chain's numbering, with P2L in the place of
+// the operand pack (stage 3) and M2P with L2P (stage 6).
 fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do_far, bool do_near,
                         hipStream_t st) {
     const AdTree *a = t->ad;
@@ -958,11 +968,10 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
             HIPCHK(ad_launch_m2m(P, a->off[l], a->off[l + 1] - a->off[l], bp<uint8_t>(a->leaf), bp<int>(a->child),
                                  o->up64, M, st));
         CHK(rec(t, 3, st));
-        HIPCHK(launch_zero((uint32_t *)Lc, 2 * S * a->off[2], st));
+        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, recs, Lc, st));
         CHK(rec(t, 4, st));
         HIPCHK(ad_launch_m2l(P, a->plan, a->m2l_units, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2],
                              bp<int>(a->tgt), a->nbox, Lc, st));
-        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, recs, Lc, st));
         CHK(rec(t, 5, st));
         for (int l = 3; l <= a->depth; ++l)
             HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent), o->down64, Lc,
@@ -975,7 +984,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
     }
     CHK(rec(t, 7, st));
     if (do_near)
-        HIPCHK(ad_launch_p2p(a->nleaf, lbox, lstart, ou, bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, st));
+        HIPCHK(ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
+                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, st));
     else
         HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
     CHK(rec(t, 8, st));
@@ -1226,7 +1236,8 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
     };
     // placement and the in-leaf ordering (after read_counters at level l)
     auto sort_at = [&](int l) -> hipError_t {
-        return launch_sort(n, l, (const uint32_t *)t->key10.p, (const uint32_t *)t->rank.p,
+        const uint32_t skip = l < cfg->max_level ? (uint32_t)cfg->leaf_max : UINT32_MAX;
+        return launch_sort(n, l, skip, (const uint32_t *)t->key10.p, (const uint32_t *)t->rank.p,
                            (const uint32_t *)t->start.p, (uint32_t *)t->tmp.p, dtype, pos, cfg->box_lo,
                            cfg->box_size, (uint32_t *)t->perm.p, f64 ? nullptr : (int4 *)t->xyz32.p,
                            f64 ? (double4 *)t->xyz64.p : nullptr, st);

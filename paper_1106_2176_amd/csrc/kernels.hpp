@@ -23,7 +23,9 @@ hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *
 // *mx (one kernel up to 32768 counts; *mx must be zero before a larger scan)
 hipError_t launch_scan_max(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
                            unsigned int *mx, hipStream_t st);
-hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *rank,
+// placement and in-leaf input order; leaves over `skip` particles are left
+// unordered and without records (a sort that the build repeats finer)
+hipError_t launch_sort(int64_t n, int level, uint32_t skip, const uint32_t *key10, const uint32_t *rank,
                        const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st);
@@ -154,9 +156,14 @@ hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *
 hipError_t ad_launch_m2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ow,
                          const int *iw, const int *lev, const uint32_t *code, const double4 *rec, const double *M,
                          double4 *out, hipStream_t st);
-hipError_t ad_launch_p2p(int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ou, const int *iu,
-                         const int *lev, const uint32_t *code, const uint32_t *ps, const uint32_t *pe,
-                         const double4 *rec, double4 *out, hipStream_t st);
+// P2P work units of up to 64 targets: pass 0 counts per leaf into cnt,
+// pass 1 fills units (leaf, first target) from uoff, the scan of the counts
+hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint32_t *cnt, const uint32_t *uoff,
+                           int2 *units, hipStream_t st);
+// one wave per unit; max_units bounds *nunits (the grid's size)
+hipError_t ad_launch_p2p(int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
+                         const uint32_t *lstart, const uint32_t *ou, const int *iu, const int *lev, const uint32_t *code,
+                         const uint32_t *ps, const uint32_t *pe, const double4 *rec, double4 *out, hipStream_t st);
 
 // scratch.hip: device address of the current device's static scratch array
 // (FMM_NOALLOC_SCRATCH_BYTES), looked up on the first call per device

@@ -197,8 +197,11 @@ __global__ void k_place(int64_t n, const uint32_t *__restrict__ key10, int shift
 // (possible only at the deepest level) ranks from global memory.
 constexpr int kFixupCache = 512;
 
+// A leaf of more than `skip` particles is left as it is: the host sorts at
+// a finer level when a leaf is over the cap below the deepest level, so the
+// quadratic ranking of such a leaf would be wasted.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict__ start,
+__global__ __launch_bounds__(256) void k_fixup(int L, uint32_t skip, const uint32_t *__restrict__ start,
                                                const uint32_t *__restrict__ tmp,
                                                const T *__restrict__ pos, double lo0, double lo1,
                                                double lo2, double size, uint32_t *__restrict__ perm,
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(256) void k_fixup(int L, const uint32_t *__restrict
     if (leaf >= (1u << (3 * L))) return;  // no block barrier below
     uint32_t *const idx = idxs[wave];
     const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
-    if (cnt == 0) return;
+    if (cnt == 0 || cnt > skip) return;
     const bool cached = cnt <= (uint32_t)kFixupCache;
     if (cached)
         for (uint32_t j = lane; j < cnt; j += 64) idx[j] = tmp[s0 + j];
@@ -342,17 +345,17 @@ hipError_t launch_scan_max(int64_t nb, const uint32_t *in, uint32_t *out, uint32
     return launch_scan(nb, in, out, scratch, st);
 }
 
-hipError_t launch_sort(int64_t n, int level, const uint32_t *key10, const uint32_t *rank,
+hipError_t launch_sort(int64_t n, int level, uint32_t skip, const uint32_t *key10, const uint32_t *rank,
                        const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st) {
     const int64_t nb = (int64_t)1 << (3 * level);
     k_place<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), rank, start, tmp);
     if (dtype == FMM_F64)
-        k_fixup<double><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, start, tmp, (const double *)pos, lo[0],
+        k_fixup<double><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, skip, start, tmp, (const double *)pos, lo[0],
                                                        lo[1], lo[2], size, perm, xyz32, xyz64);
     else
-        k_fixup<float><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, start, tmp, (const float *)pos, lo[0],
+        k_fixup<float><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, skip, start, tmp, (const float *)pos, lo[0],
                                                       lo[1], lo[2], size, perm, xyz32, xyz64);
     return hipGetLastError();
 }

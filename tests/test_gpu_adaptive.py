@@ -222,3 +222,25 @@ def test_unsupported_requests():
         phi2, _ = t.evaluate(Q)  # the tree is untouched
         torch.cuda.synchronize()
         assert bool(torch.isfinite(phi2).all())
+
+
+def test_million_blobs_sampled_against_the_direct_sum(oracle_mod):
+    """The benchmark's adaptive workload (N = 1e6 Gaussian blobs, p = 8,
+    leaf <= 64, max level 8) on 1000 sampled targets against the FP64 direct
+    sum.  The bound is the truncation error the oracle's adaptive FMM shows
+    on smaller inputs of the same distribution at p = 8 (phi about 3e-6,
+    E about 5e-5 at N = 1e5), with a factor of 3 to 4 of room."""
+    import bench
+    a = bench.ADAPTIVE
+    pos, q = inputs.clustered(a["n"], a["seed"], a["blobs"])
+    t_idx = inputs.targets(a["n"], a["seed"])
+    phi_d, E_d = oracle_mod.direct(pos, q, t_idx)
+    with fmm.Tree(dev(pos), p=a["p"], leaf_max=a["leaf_max"], max_level=a["max_level"], precision="fp64",
+                  adaptive=True) as t:
+        phi, E = gpu_eval(t, q)
+        info = t.info()
+    print("1e6 blobs: depth %d, %d leaves, phi %.2e, E %.2e" % (
+        info["levels"], info["n_leaves"], rel_l2(phi[t_idx], phi_d), rel_l2(E[t_idx], E_d)))
+    assert info["levels"] == a["max_level"]
+    assert rel_l2(phi[t_idx], phi_d) < 1e-5
+    assert rel_l2(E[t_idx], E_d) < 2e-4
