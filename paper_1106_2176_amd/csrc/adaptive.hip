@@ -116,129 +116,132 @@ __global__ void k_ad_children(int64_t b0, int64_t nb, int l, int Lf, int64_t nex
 }
 
 // Colleagues (the 27 same-level boxes at offsets -1..1, -1 if absent) of the
-// level's boxes, by binary search in the level's Morton-sorted codes.
+// level's boxes, by binary search in the level's Morton-sorted codes; one
+// thread per (box, offset).
 __global__ void k_ad_colleagues(int64_t b0, int64_t nb, int l, const uint32_t *__restrict__ code,
                                 int *__restrict__ col) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int64_t g = b0 + i;
+    if (i >= 27 * nb) return;
+    const int64_t g = b0 + i / 27;
+    const int o = (int)(i % 27);
     int64_t x, y, z;
     box_coords(code[g], x, y, z);
     const int64_t side = (int64_t)1 << l;
-    for (int o = 0; o < 27; ++o) {
-        const int64_t sx = x + o % 3 - 1, sy = y + (o / 3) % 3 - 1, sz = z + o / 9 - 1;
-        int r = -1;
-        if (sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side) {
-            const uint32_t key = morton3((uint32_t)sx, (uint32_t)sy, (uint32_t)sz);
-            int64_t lo = b0, hi = b0 + nb - 1;
-            while (lo <= hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                const uint32_t k = code[mid];
-                if (k == key) {
-                    r = (int)mid;
-                    break;
-                }
-                if (k < key) lo = mid + 1;
-                else hi = mid - 1;
+    const int64_t sx = x + o % 3 - 1, sy = y + (o / 3) % 3 - 1, sz = z + o / 9 - 1;
+    int r = -1;
+    if (sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side) {
+        const uint32_t key = morton3((uint32_t)sx, (uint32_t)sy, (uint32_t)sz);
+        int64_t lo = b0, hi = b0 + nb - 1;
+        while (lo <= hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            const uint32_t k = code[mid];
+            if (k == key) {
+                r = (int)mid;
+                break;
             }
+            if (k < key) lo = mid + 1;
+            else hi = mid - 1;
         }
-        col[27 * g + o] = r;
     }
+    col[27 * g + o] = r;
 }
 
 // V as slots: for box g of level l >= 2 and class k (its coordinate parities),
 // slot s of the class's 189 offsets holds the source box t + d if it exists
-// (a child of one of the parent's colleagues), else -1.
+// (a child of one of the parent's colleagues), else -1; one thread per
+// (box, slot).
 __global__ void k_ad_vslots(int64_t b0, int64_t nb, const uint32_t *__restrict__ code,
                             const int *__restrict__ parent, const int *__restrict__ col,
                             const int *__restrict__ child, const int2 *__restrict__ cls,
                             int *__restrict__ vidx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int64_t g = b0 + i;
+    if (i >= (int64_t)kOffsetsPerClass * nb) return;
+    const int64_t bi = i / kOffsetsPerClass;
+    const int s = (int)(i - bi * kOffsetsPerClass);
+    const int64_t g = b0 + bi;
     int64_t tx, ty, tz;
     box_coords(code[g], tx, ty, tz);
     const int k = (int)((tx & 1) | ((ty & 1) << 1) | ((tz & 1) << 2));
-    const int P = parent[g];
-    for (int s = 0; s < kOffsetsPerClass; ++s) {
-        const int e = cls[k * kOffsetsPerClass + s].x;
-        const int64_t sx = tx + (e & 15) - 4, sy = ty + ((e >> 4) & 15) - 4, sz = tz + ((e >> 8) & 15) - 4;
-        int r = -1;
-        if (sx >= 0 && sy >= 0 && sz >= 0) {
-            const int64_t ox = (sx >> 1) - (tx >> 1), oy = (sy >> 1) - (ty >> 1), oz = (sz >> 1) - (tz >> 1);
-            const int pc = col[27 * (int64_t)P + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
-            if (pc >= 0) r = child[8 * (int64_t)pc + ((sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2))];
-        }
-        vidx[189 * i + s] = r;
+    const int e = cls[k * kOffsetsPerClass + s].x;
+    const int64_t sx = tx + (e & 15) - 4, sy = ty + ((e >> 4) & 15) - 4, sz = tz + ((e >> 8) & 15) - 4;
+    int r = -1;
+    if (sx >= 0 && sy >= 0 && sz >= 0) {
+        const int64_t ox = (sx >> 1) - (tx >> 1), oy = (sy >> 1) - (ty >> 1), oz = (sz >> 1) - (tz >> 1);
+        const int pc = col[27 * (int64_t)parent[g] + (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+        if (pc >= 0) r = child[8 * (int64_t)pc + ((sx & 1) | ((sy & 1) << 1) | ((sz & 1) << 2))];
     }
+    vidx[i] = r;
 }
 
-// U and W of leaf g (count only when items are NULL).  Order: g; the leaf
-// colleagues of its ancestors (coarser leaves) that touch g, from the parent
-// up; its own colleagues (leaves to U, split ones opened depth first: touching
-// leaves to U, touching split boxes opened, the rest to W).
-__device__ void ad_uw(int g, const int *lev, const uint32_t *code, const int *parent, const int *col,
+// The part of U and W of leaf g that comes through colleague direction o
+// (count only when the item pointers are NULL).  o = 13 (the box itself):
+// g.  Otherwise: the colleague o of each proper ancestor (from the parent
+// up) when it is a leaf touching g; then g's own colleague o: a leaf goes to
+// U, a split one is opened depth first (touching leaves to U, touching split
+// boxes opened, the rest to W).
+__device__ void ad_uw(int g, int o, const int *lev, const uint32_t *code, const int *parent, const int *col,
                       const int *child, const uint8_t *leaf, int *u, int &nu, int *w, int &nw) {
     nu = nw = 0;
-    if (u) u[nu] = g;
-    ++nu;
+    if (o == 13) {
+        if (u) u[0] = g;
+        nu = 1;
+        return;
+    }
     const int lg = lev[g];
     const uint32_t cg = code[g];
-    for (int a = parent[g]; a >= 0; a = parent[a])
-        for (int o = 0; o < 27; ++o) {
-            const int c = col[27 * (int64_t)a + o];
-            if (o == 13 || c < 0 || !leaf[c] || !ad_adjacent(lg, cg, lev[c], code[c])) continue;
-            if (u) u[nu] = c;
-            ++nu;
-        }
+    for (int a = parent[g]; a >= 0; a = parent[a]) {
+        const int c = col[27 * (int64_t)a + o];
+        if (c < 0 || !leaf[c] || !ad_adjacent(lg, cg, lev[c], code[c])) continue;
+        if (u) u[nu] = c;
+        ++nu;
+    }
+    const int c = col[27 * (int64_t)g + o];
+    if (c < 0) return;
+    if (leaf[c]) {
+        if (u) u[nu] = c;
+        ++nu;
+        return;
+    }
     int stack[8 * (FMM_MAX_LEVEL + 1)];
-    for (int o = 0; o < 27; ++o) {
-        const int c = col[27 * (int64_t)g + o];
-        if (o == 13 || c < 0) continue;
-        if (leaf[c]) {
-            if (u) u[nu] = c;
+    int sp = 0;
+    for (int ch = 7; ch >= 0; --ch)
+        if (child[8 * (int64_t)c + ch] >= 0) stack[sp++] = child[8 * (int64_t)c + ch];
+    while (sp > 0) {
+        const int d = stack[--sp];
+        if (!ad_adjacent(lg, cg, lev[d], code[d])) {
+            if (w) w[nw] = d;
+            ++nw;
+        } else if (leaf[d]) {
+            if (u) u[nu] = d;
             ++nu;
-            continue;
-        }
-        int sp = 0;
-        for (int ch = 7; ch >= 0; --ch)
-            if (child[8 * (int64_t)c + ch] >= 0) stack[sp++] = child[8 * (int64_t)c + ch];
-        while (sp > 0) {
-            const int d = stack[--sp];
-            if (!ad_adjacent(lg, cg, lev[d], code[d])) {
-                if (w) w[nw] = d;
-                ++nw;
-            } else if (leaf[d]) {
-                if (u) u[nu] = d;
-                ++nu;
-            } else {
-                for (int ch = 7; ch >= 0; --ch)
-                    if (child[8 * (int64_t)d + ch] >= 0) stack[sp++] = child[8 * (int64_t)d + ch];
-            }
+        } else {
+            for (int ch = 7; ch >= 0; --ch)
+                if (child[8 * (int64_t)d + ch] >= 0) stack[sp++] = child[8 * (int64_t)d + ch];
         }
     }
 }
 
-// X of box g: the leaf colleagues c of its proper ancestors (from the parent
-// up) that touch g's parent but not g.
-__device__ int ad_x(int g, const int *lev, const uint32_t *code, const int *parent, const int *col,
+// The part of X of box g through direction o: the colleague o of each
+// proper ancestor (from the parent up) when it is a leaf that touches g's
+// parent but not g.
+__device__ int ad_x(int g, int o, const int *lev, const uint32_t *code, const int *parent, const int *col,
                     const uint8_t *leaf, int *x) {
     int nx = 0;
     const int p = parent[g];
-    if (p < 0) return 0;
-    for (int a = p; a >= 0; a = parent[a])
-        for (int o = 0; o < 27; ++o) {
-            const int c = col[27 * (int64_t)a + o];
-            if (o == 13 || c < 0 || !leaf[c]) continue;
-            if (ad_adjacent(lev[p], code[p], lev[c], code[c]) && !ad_adjacent(lev[g], code[g], lev[c], code[c])) {
-                if (x) x[nx] = c;
-                ++nx;
-            }
+    if (p < 0 || o == 13) return 0;
+    for (int a = p; a >= 0; a = parent[a]) {
+        const int c = col[27 * (int64_t)a + o];
+        if (c < 0 || !leaf[c]) continue;
+        if (ad_adjacent(lev[p], code[p], lev[c], code[c]) && !ad_adjacent(lev[g], code[g], lev[c], code[c])) {
+            if (x) x[nx] = c;
+            ++nx;
         }
+    }
     return nx;
 }
 
-// pass 0: counts of U, W (leaves) and X (all boxes); pass 1: the items
+// One thread per (box, direction), i = 27 g + o.  pass 0: counts of U, W
+// (leaves) and X (all boxes); pass 1: the items, at the scanned offsets.
 __global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, const uint32_t *__restrict__ code,
                            const int *__restrict__ parent, const int *__restrict__ col,
                            const int *__restrict__ child, const uint8_t *__restrict__ leaf,
@@ -246,18 +249,31 @@ __global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, 
                            const uint32_t *__restrict__ ou, const uint32_t *__restrict__ ow,
                            const uint32_t *__restrict__ ox, int *__restrict__ iu, int *__restrict__ iw,
                            int *__restrict__ ix) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nbox) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 27 * nbox) return;
+    const int g = (int)(i / 27), o = (int)(i % 27);
     int a = 0, b = 0;
     if (pass == 0) {
-        if (leaf[g]) ad_uw((int)g, lev, code, parent, col, child, leaf, nullptr, a, nullptr, b);
-        nu[g] = a;
-        nw[g] = b;
-        nx[g] = ad_x((int)g, lev, code, parent, col, leaf, nullptr);
+        if (leaf[g]) ad_uw(g, o, lev, code, parent, col, child, leaf, nullptr, a, nullptr, b);
+        nu[i] = a;
+        nw[i] = b;
+        nx[i] = ad_x(g, o, lev, code, parent, col, leaf, nullptr);
     } else {
-        if (leaf[g]) ad_uw((int)g, lev, code, parent, col, child, leaf, iu + ou[g], a, iw + ow[g], b);
-        (void)ad_x((int)g, lev, code, parent, col, leaf, ix + ox[g]);
+        if (leaf[g]) ad_uw(g, o, lev, code, parent, col, child, leaf, iu + ou[i], a, iw + ow[i], b);
+        (void)ad_x(g, o, lev, code, parent, col, leaf, ix + ox[i]);
     }
+}
+
+// Per-box list offsets from the per-(box, direction) scans: box g starts at
+// its direction 0 (g = nbox: the totals).
+__global__ void k_ad_box_offsets(int64_t nbox, const uint32_t *__restrict__ s27, uint32_t *__restrict__ ou,
+                                 uint32_t *__restrict__ ow, uint32_t *__restrict__ ox) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > nbox) return;
+    const int64_t m = 27 * nbox + 1;
+    ou[g] = s27[27 * g];
+    ow[g] = s27[m + 27 * g];
+    ox[g] = s27[2 * m + 27 * g];
 }
 
 // level of every box from the level offsets
@@ -285,16 +301,21 @@ __global__ void k_ad_leaflist(int64_t n, const uint32_t *__restrict__ is_head, c
                               const int *__restrict__ lev, const uint32_t *__restrict__ pe,
                               unsigned int *__restrict__ mx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (is_head[i]) {
+    uint32_t m = 0;
+    if (i < n && is_head[i]) {
         const uint32_t j = hoff[i];
         const int g = head[i];
         lbox[j] = g;
         lstart[j] = ps[g];
         llev[j] = (uint8_t)lev[g];
-        atomicMax(mx, pe[g] - ps[g]);
+        m = pe[g] - ps[g];
     }
     if (i == n - 1) lstart[hoff[n]] = (uint32_t)n;
+    // the fullest leaf: a wave maximum, one atomic per wave (every lane of
+    // the wave reaches this point)
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(mx, m);
 }
 
 // P2P work units: ceil(count / 64) per leaf (pass 0), then each unit's
@@ -937,28 +958,33 @@ __global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__re
     }
 }
 
-// targets of levels >= 2 grouped by (level, class): per-group counts, then
-// the fill (a target's position within its group does not change its sums)
-__global__ void k_ad_class_count(int64_t box2, int64_t nb, const int *__restrict__ lev,
-                                 const uint32_t *__restrict__ code, unsigned int *__restrict__ cnt) {
+// Targets of levels >= 2 grouped by (level, class): block histograms in LDS
+// and one global atomic per (block, group): counts (fill == NULL), or the
+// fill, where each group's block range is reserved by that atomic and the
+// LDS rank places the target in it (the order within a group does not
+// change any result).
+__global__ __launch_bounds__(256) void k_ad_class(int64_t box2, int64_t nb, const int *__restrict__ lev,
+                                                  const uint32_t *__restrict__ code, unsigned int *__restrict__ cnt,
+                                                  const int64_t *__restrict__ goff, unsigned int *__restrict__ fill,
+                                                  int *__restrict__ tgt) {
+    __shared__ unsigned int h[kAdMaxGroups], base[kAdMaxGroups];
+    for (int k = threadIdx.x; k < kAdMaxGroups; k += 256) h[k] = 0;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int64_t g = box2 + i;
-    int64_t x, y, z;
-    box_coords(code[g], x, y, z);
-    const int k = (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
-    atomicAdd(cnt + 8 * (lev[g] - 2) + k, 1u);
-}
-__global__ void k_ad_class_fill(int64_t box2, int64_t nb, const int *__restrict__ lev,
-                                const uint32_t *__restrict__ code, const int64_t *__restrict__ goff,
-                                unsigned int *__restrict__ fill, int *__restrict__ tgt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int64_t g = box2 + i;
-    int64_t x, y, z;
-    box_coords(code[g], x, y, z);
-    const int grp = 8 * (lev[g] - 2) + (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
-    tgt[goff[grp] + atomicAdd(fill + grp, 1u)] = (int)g;
+    int grp = -1;
+    unsigned int rank = 0;
+    if (i < nb) {
+        const int64_t g = box2 + i;
+        int64_t x, y, z;
+        box_coords(code[g], x, y, z);
+        grp = 8 * (lev[g] - 2) + (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+        rank = atomicAdd(&h[grp], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kAdMaxGroups; k += 256)
+        if (h[k]) base[k] = atomicAdd(fill ? fill + k : cnt + k, h[k]);
+    __syncthreads();
+    if (fill && grp >= 0) tgt[goff[grp] + base[grp] + rank] = (int)(box2 + i);
 }
 
 // ---------------------------------------------------------- host helpers
@@ -990,12 +1016,13 @@ hipError_t ad_launch_structure(int64_t nbox, int nlev, const int64_t *off_host, 
     k_ad_levels<<<ad_blocks(nbox, 256), 256, 0, st>>>(nbox, off_dev, nlev, lev);
     for (int l = 0; l < nlev; ++l) {
         const int64_t nb = off_host[l + 1] - off_host[l];
-        if (nb > 0) k_ad_colleagues<<<ad_blocks(nb, 256), 256, 0, st>>>(off_host[l], nb, l, code, col);
+        if (nb > 0) k_ad_colleagues<<<ad_blocks(27 * nb, 256), 256, 0, st>>>(off_host[l], nb, l, code, col);
     }
     for (int l = 2; l < nlev; ++l) {
         const int64_t nb = off_host[l + 1] - off_host[l];
         if (nb > 0)
-            k_ad_vslots<<<ad_blocks(nb, 256), 256, 0, st>>>(off_host[l], nb, code, parent, col, child, cls,
+            k_ad_vslots<<<ad_blocks(kOffsetsPerClass * nb, 256), 256, 0, st>>>(off_host[l], nb, code, parent, col,
+                                                                                child, cls,
                                                              vidx + 189 * (off_host[l] - off_host[2]));
     }
     return hipGetLastError();
@@ -1005,8 +1032,14 @@ hipError_t ad_launch_lists(int64_t nbox, int pass, const int *lev, const uint32_
                            const int *col, const int *child, const uint8_t *leaf, uint32_t *nu, uint32_t *nw,
                            uint32_t *nx, const uint32_t *ou, const uint32_t *ow, const uint32_t *ox, int *iu,
                            int *iw, int *ix, hipStream_t st) {
-    k_ad_lists<<<ad_blocks(nbox, 128), 128, 0, st>>>(nbox, pass, lev, code, parent, col, child, leaf, nu, nw, nx,
+    k_ad_lists<<<ad_blocks(27 * nbox, 128), 128, 0, st>>>(nbox, pass, lev, code, parent, col, child, leaf, nu, nw, nx,
                                                       ou, ow, ox, iu, iw, ix);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_box_offsets(int64_t nbox, const uint32_t *s27, uint32_t *ou, uint32_t *ow, uint32_t *ox,
+                                 hipStream_t st) {
+    k_ad_box_offsets<<<ad_blocks(nbox + 1, 256), 256, 0, st>>>(nbox, s27, ou, ow, ox);
     return hipGetLastError();
 }
 
@@ -1097,10 +1130,7 @@ hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, int64_t nunits, const doubl
 hipError_t ad_launch_class(int64_t box2, int64_t nb, const int *lev, const uint32_t *code, unsigned int *cnt,
                            const int64_t *goff, unsigned int *fill, int *tgt, hipStream_t st) {
     if (nb == 0) return hipSuccess;
-    if (!goff)
-        k_ad_class_count<<<ad_blocks(nb, 256), 256, 0, st>>>(box2, nb, lev, code, cnt);
-    else
-        k_ad_class_fill<<<ad_blocks(nb, 256), 256, 0, st>>>(box2, nb, lev, code, goff, fill, tgt);
+    k_ad_class<<<ad_blocks(nb, 256), 256, 0, st>>>(box2, nb, lev, code, cnt, goff, fill, tgt);
     return hipGetLastError();
 }
 

@@ -352,12 +352,12 @@ struct AdTree {
     int64_t m2l_units = 0;
     uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
     Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
-        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts, ucnt, uoff, units;
+        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts, ucnt, uoff, units, s27;
     int64_t max_units = 0;  // bound of the P2P work units (their count stays on the device)
     std::vector<Buf *> bufs() {
         return {&code, &ps, &pe, &parent, &child, &leaf, &cmask, &nchild, &coff, &lev, &col, &vidx, &cnts,
                 &offs, &iu, &iw, &ix, &is_head, &head, &hoff, &lbox, &lstart, &llev, &tgt, &ccnt, &goffd,
-                &offd, &counts, &ucnt, &uoff, &units};
+                &offd, &counts, &ucnt, &uoff, &units, &s27};
     }
 };
 
@@ -847,24 +847,30 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     CHK(ensure(t, a->col, 27 * u4 * nbox, st));
     CHK(ensure(t, a->vidx, (size_t)kOffsetsPerClass * u4 * std::max<int64_t>(a->nvbox, 1), st));
     CHK(ensure(t, a->offd, sizeof(int64_t) * (nlev + 1), st));
-    CHK(ensure(t, a->cnts, 3 * u4 * nbox, st));
+    const int64_t n27 = 27 * nbox;  // (box, direction) pairs of the list passes
+    CHK(ensure(t, a->cnts, 3 * u4 * n27, st));
+    CHK(ensure(t, a->s27, 3 * u4 * (n27 + 1), st));
     CHK(ensure(t, a->offs, 3 * u4 * (nbox + 1), st));
+    CHK(ensure(t, t->scan, u4 * scan_scratch_words(std::max(n27, n) + 1), st));
+    scan = bp<uint32_t>(t->scan);
     CHK(ensure(t, a->is_head, u4 * n, st));
     CHK(ensure(t, a->head, u4 * n, st));
     CHK(ensure(t, a->hoff, u4 * (n + 1), st));
     const int ngrp = 8 * std::max(nlev - 2, 0);
     CHK(ensure(t, a->ccnt, u4 * std::max(ngrp, 1), st));
     int *lev = bp<int>(a->lev), *col = bp<int>(a->col), *vidx = bp<int>(a->vidx);
-    uint32_t *nu = bp<uint32_t>(a->cnts), *nw = nu + nbox, *nx = nw + nbox;
+    uint32_t *nu = bp<uint32_t>(a->cnts), *nw = nu + n27, *nx = nw + n27;
+    uint32_t *su = bp<uint32_t>(a->s27), *sw = su + n27 + 1, *sx = sw + n27 + 1;
     uint32_t *ou = bp<uint32_t>(a->offs), *ow = ou + nbox + 1, *ox = ow + nbox + 1;
     HIPCHK(hipMemcpyAsync(a->offd.p, a->off, sizeof(int64_t) * (nlev + 1), hipMemcpyHostToDevice, st));
     HIPCHK(ad_launch_structure(nbox, nlev, a->off, bp<int64_t>(a->offd), code, parent, child, lev, col,
                                t->ops->cls, vidx, st));
     HIPCHK(ad_launch_lists(nbox, 0, lev, code, parent, col, child, leaf, nu, nw, nx, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, st));
-    HIPCHK(launch_scan(nbox, nu, ou, scan, st));
-    HIPCHK(launch_scan(nbox, nw, ow, scan, st));
-    HIPCHK(launch_scan(nbox, nx, ox, scan, st));
+    HIPCHK(launch_scan(n27, nu, su, scan, st));
+    HIPCHK(launch_scan(n27, nw, sw, scan, st));
+    HIPCHK(launch_scan(n27, nx, sx, scan, st));
+    HIPCHK(ad_launch_box_offsets(nbox, su, ou, ow, ox, st));
     HIPCHK(launch_zero(bp<uint32_t>(a->is_head), n, st));
     HIPCHK(ad_launch_heads(nbox, leaf, ps, pe, bp<uint32_t>(a->is_head), bp<int>(a->head), st));
     HIPCHK(launch_scan(n, bp<uint32_t>(a->is_head), bp<uint32_t>(a->hoff), scan, st));
@@ -884,7 +890,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     CHK(ensure(t, a->iu, u4 * std::max<int64_t>(a->nlist[0], 1), st));
     CHK(ensure(t, a->iw, u4 * std::max<int64_t>(a->nlist[1], 1), st));
     CHK(ensure(t, a->ix, u4 * std::max<int64_t>(a->nlist[2], 1), st));
-    HIPCHK(ad_launch_lists(nbox, 1, lev, code, parent, col, child, leaf, nu, nw, nx, ou, ow, ox, bp<int>(a->iu),
+    HIPCHK(ad_launch_lists(nbox, 1, lev, code, parent, col, child, leaf, nu, nw, nx, su, sw, sx, bp<int>(a->iu),
                            bp<int>(a->iw), bp<int>(a->ix), st));
     CHK(ensure(t, a->lbox, u4 * a->nleaf, st));
     CHK(ensure(t, a->lstart, u4 * (a->nleaf + 1), st));

@@ -106,10 +106,16 @@ hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t nex
 hipError_t ad_launch_structure(int64_t nbox, int nlev, const int64_t *off_host, const int64_t *off_dev,
                                const uint32_t *code, const int *parent, const int *child, int *lev, int *col,
                                const int2 *cls, int *vidx, hipStream_t st);
+// one thread per (box, direction): pass 0 counts [27 nbox] each, pass 1
+// fills at the scanned per-(box, direction) offsets
 hipError_t ad_launch_lists(int64_t nbox, int pass, const int *lev, const uint32_t *code, const int *parent,
                            const int *col, const int *child, const uint8_t *leaf, uint32_t *nu, uint32_t *nw,
                            uint32_t *nx, const uint32_t *ou, const uint32_t *ow, const uint32_t *ox, int *iu,
                            int *iw, int *ix, hipStream_t st);
+// per-box list offsets ou/ow/ox [nbox + 1] from the three per-(box,
+// direction) scans stored one after another, each 27 nbox + 1 long
+hipError_t ad_launch_box_offsets(int64_t nbox, const uint32_t *s27, uint32_t *ou, uint32_t *ow, uint32_t *ox,
+                                 hipStream_t st);
 hipError_t ad_launch_heads(int64_t nbox, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,
                            uint32_t *is_head, int *head, hipStream_t st);
 // leaves in particle order, and the fullest leaf's count into *mx

@@ -196,6 +196,7 @@ __global__ void k_place(int64_t n, const uint32_t *__restrict__ key10, int shift
 // 32-bit fixed point (mixed form).  A leaf of more than kFixupCache particles
 // (possible only at the deepest level) ranks from global memory.
 constexpr int kFixupCache = 512;
+constexpr int64_t kFixupBlocks = 16384;
 
 // A leaf of more than `skip` particles is left as it is: the host sorts at
 // a finer level when a leaf is over the cap below the deepest level, so the
@@ -208,42 +209,47 @@ __global__ __launch_bounds__(256) void k_fixup(int L, uint32_t skip, const uint3
                                                int4 *__restrict__ xyz32, double4 *__restrict__ xyz64) {
     __shared__ uint32_t idxs[4][kFixupCache];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint32_t leaf = 4 * blockIdx.x + wave;
-    if (leaf >= (1u << (3 * L))) return;  // no block barrier below
+    const uint32_t nleaf = 1u << (3 * L);
     uint32_t *const idx = idxs[wave];
-    const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
-    if (cnt == 0 || cnt > skip) return;
-    const bool cached = cnt <= (uint32_t)kFixupCache;
-    if (cached)
-        for (uint32_t j = lane; j < cnt; j += 64) idx[j] = tmp[s0 + j];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double scale = (double)(1u << L);
-    const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
-                 bz = (double)compact3(leaf >> 2) + 0.5;
-    for (uint32_t j = lane; j < cnt; j += 64) {
-        const uint32_t me = cached ? idx[j] : tmp[s0 + j];
-        uint32_t rank = 0;
-        if (cached) {
-            for (uint32_t k = 0; k < cnt; ++k) rank += idx[k] < me;
-        } else {
-            for (uint32_t k = 0; k < cnt; ++k) rank += tmp[s0 + k] < me;
+    // one wave per leaf, the grid striding over the leaves (no block barrier)
+    for (uint32_t leaf = 4 * blockIdx.x + wave; leaf < nleaf; leaf += 4 * gridDim.x) {
+        const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
+        if (cnt == 0 || cnt > skip) continue;
+        const bool cached = cnt <= (uint32_t)kFixupCache;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // the previous leaf's reads of idx
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (cached)
+            for (uint32_t j = lane; j < cnt; j += 64) idx[j] = tmp[s0 + j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
+                     bz = (double)compact3(leaf >> 2) + 0.5;
+        for (uint32_t j = lane; j < cnt; j += 64) {
+            const uint32_t me = cached ? idx[j] : tmp[s0 + j];
+            uint32_t rank = 0;
+            if (cached) {
+                for (uint32_t k = 0; k < cnt; ++k) rank += idx[k] < me;
+            } else {
+                for (uint32_t k = 0; k < cnt; ++k) rank += tmp[s0 + k] < me;
+            }
+            const uint32_t d = s0 + rank;
+            perm[d] = me;
+            const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
+            const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
+            const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
+            if (xyz32) {
+                // fixed point in [-2^29, 2^29 - 1]: u = +1/2 (a point on the upper
+                // face of the root cube) moves by 2^-30 leaf widths
+                const int top = (1 << 29) - 1;
+                xyz32[d] = make_int4(min(__double2int_rn(ux * kFixScale), top),
+                                     min(__double2int_rn(uy * kFixScale), top),
+                                     min(__double2int_rn(uz * kFixScale), top), 0);
+            }
+            if (xyz64) xyz64[d] = make_double4(ux, uy, uz, 0.0);
         }
-        const uint32_t d = s0 + rank;
-        perm[d] = me;
-        const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
-        const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
-        const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
-        if (xyz32) {
-            // fixed point in [-2^29, 2^29 - 1]: u = +1/2 (a point on the upper
-            // face of the root cube) moves by 2^-30 leaf widths
-            const int top = (1 << 29) - 1;
-            xyz32[d] = make_int4(min(__double2int_rn(ux * kFixScale), top),
-                                 min(__double2int_rn(uy * kFixScale), top),
-                                 min(__double2int_rn(uz * kFixScale), top), 0);
-        }
-        if (xyz64) xyz64[d] = make_double4(ux, uy, uz, 0.0);
     }
 }
 
@@ -351,11 +357,13 @@ hipError_t launch_sort(int64_t n, int level, uint32_t skip, const uint32_t *key1
                        double4 *xyz64, hipStream_t st) {
     const int64_t nb = (int64_t)1 << (3 * level);
     k_place<<<nblk(n, 256), 256, 0, st>>>(n, key10, 3 * (10 - level), rank, start, tmp);
+    // four leaves per block, at most kFixupBlocks blocks striding over the rest
+    const unsigned fix_blocks = (unsigned)std::min<int64_t>((nb + 3) / 4, kFixupBlocks);
     if (dtype == FMM_F64)
-        k_fixup<double><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, skip, start, tmp, (const double *)pos, lo[0],
+        k_fixup<double><<<fix_blocks, 256, 0, st>>>(level, skip, start, tmp, (const double *)pos, lo[0],
                                                        lo[1], lo[2], size, perm, xyz32, xyz64);
     else
-        k_fixup<float><<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(level, skip, start, tmp, (const float *)pos, lo[0],
+        k_fixup<float><<<fix_blocks, 256, 0, st>>>(level, skip, start, tmp, (const float *)pos, lo[0],
                                                       lo[1], lo[2], size, perm, xyz32, xyz64);
     return hipGetLastError();
 }
