@@ -852,14 +852,16 @@ __global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__re
                                                 const int2 *__restrict__ cls, const double *__restrict__ M,
                                                 const int *__restrict__ vidx, int64_t box2,
                                                 const int *__restrict__ tgt, int64_t zero_row,
-                                                double *__restrict__ Lc) {
+                                                double *__restrict__ Lc, double *__restrict__ partial) {
     constexpr int P2 = P * P, S = coef_stride(P), RT = m2l_rows(P) / 16, R = RT * 16;
     constexpr int NB = 2, KC = 8, ROWP = KC + 1, CPO = S / KC;
     constexpr int NEL = R * KC, EPT = (NEL + 255) / 256;
     constexpr int NCH = kOffsetsPerClass * CPO;
     __shared__ double As[2][R * ROWP];
     __shared__ int sA[kOffsetsPerClass];
-    const int64_t b = blockIdx.x;
+    // block = part * units + tile: part takes chunks [kbeg, kend) of the K range
+    const int64_t part = blockIdx.x / pl.units, b = blockIdx.x - part * pl.units;
+    const int kbeg = (int)(part * NCH / pl.nsplit), kend = (int)((part + 1) * NCH / pl.nsplit);
     int gi = 0;
     for (int j = 1; j < pl.ngroups; ++j)
         if (b >= pl.grp[j].unit0) gi = j;
@@ -894,12 +896,28 @@ __global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__re
             if (NEL % 256 == 0 || e < NEL) As[buf][(e / KC) * ROWP + e % KC] = src[i];
         }
     };
+    // source rows of the slot being fetched and of the next slot (its vidx
+    // load is issued a slot ahead, so that no fetch waits on it); load_b is
+    // called with a chunk index that never decreases and grows by at most one
+    int srow[NB], snext[NB], pslot = kbeg / CPO;
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+        srow[bb] = vrow[bb] ? vrow[bb][pslot] : -1;
+        snext[bb] = (vrow[bb] && pslot + 1 < kOffsetsPerClass) ? vrow[bb][pslot + 1] : -1;
+    }
     auto load_b = [&](int kc, double (&dst)[2][NB]) __attribute__((always_inline)) {
         const int slot = kc / CPO, c0 = KC * (kc - slot * CPO);
+        if (slot != pslot) {
+            pslot = slot;
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) {
+                srow[bb] = snext[bb];
+                snext[bb] = (vrow[bb] && slot + 1 < kOffsetsPerClass) ? vrow[bb][slot + 1] : -1;
+            }
+        }
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) {
-            const int s = vrow[bb] ? vrow[bb][slot] : -1;
-            const double *src = M + (s >= 0 ? (int64_t)s : zero_row) * S + c0 + q;
+            const double *src = M + (srow[bb] >= 0 ? (int64_t)srow[bb] : zero_row) * S + c0 + q;
 #pragma unroll
             for (int j = 0; j < 2; ++j) dst[j][bb] = src[4 * j];
         }
@@ -910,13 +928,13 @@ __global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__re
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb) acc[r][bb] = f64x4{0, 0, 0, 0};
     double ar[2][EPT], br[2][2][NB], bc[2][NB];
-    load_a(0, ar[0]);
+    load_a(kbeg, ar[0]);
     store_a(0, ar[0]);
-    load_b(0, bc);
-    load_a(min(1, NCH - 1), ar[0]);
-    load_b(min(1, NCH - 1), br[0]);
-    load_a(min(2, NCH - 1), ar[1]);
-    load_b(min(2, NCH - 1), br[1]);
+    load_b(kbeg, bc);
+    load_a(min(kbeg + 1, kend - 1), ar[0]);
+    load_b(min(kbeg + 1, kend - 1), br[0]);
+    load_a(min(kbeg + 2, kend - 1), ar[1]);
+    load_b(min(kbeg + 2, kend - 1), br[1]);
     __syncthreads();
     auto chunk = [&](int kc, auto pc) __attribute__((always_inline)) {
         constexpr int ph = decltype(pc)::value;
@@ -935,27 +953,60 @@ __global__ __launch_bounds__(256) void k_ad_m2l(AdM2LPlan pl, const double *__re
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int bb = 0; bb < NB; ++bb) bc[j][bb] = br[ph][j][bb];
-        load_a(min(kc + 3, NCH - 1), ar[ph]);
-        load_b(min(kc + 3, NCH - 1), br[ph]);
+        load_a(min(kc + 3, kend - 1), ar[ph]);
+        load_b(min(kc + 3, kend - 1), br[ph]);
         __syncthreads();
     };
-    int kc = 0;
-    for (; kc + 1 < NCH; kc += 2) {
+    int kc = kbeg;
+    for (; kc + 1 < kend; kc += 2) {
         chunk(kc, std::integral_constant<int, 0>{});
         chunk(kc + 1, std::integral_constant<int, 1>{});
     }
-    if (kc < NCH) chunk(kc, std::integral_constant<int, 0>{});
+    if (kc < kend) chunk(kc, std::integral_constant<int, 0>{});
+    if (pl.nsplit == 1) {
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) {
-        if (tbox[bb] < 0) continue;
+        for (int bb = 0; bb < NB; ++bb) {
+            if (tbox[bb] < 0) continue;
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+            for (int r = 0; r < RT; ++r)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * r + q + 4 * i;
-                if (row < P2) Lc[tbox[bb] * S + row] += acc[r][bb][i];
-            }
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + q + 4 * i;
+                    if (row < P2) Lc[tbox[bb] * S + row] += acc[r][bb][i];
+                }
+        }
+    } else {  // this part's sums of the tile's 128 columns, summed by k_ad_m2l_sum
+        double *dst = partial + (part * pl.units + b) * 128 * P2;
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + q + 4 * i;
+                    if (row < P2) dst[(wave * NB * 16 + bb * 16 + col) * P2 + row] = acc[r][bb][i];
+                }
     }
+}
+
+// The K-split parts of the gathered M2L added into the locals in part order
+// (one thread per (tile, column, row)).
+__global__ void k_ad_m2l_sum(AdM2LPlan pl, int P2, int S, const int *__restrict__ tgt,
+                             const double *__restrict__ partial, double *__restrict__ Lc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)128 * P2;
+    if (i >= pl.units * per) return;
+    const int64_t b = i / per;
+    const int e = (int)(i - b * per), c = e / P2, row = e - c * P2;
+    int gi = 0;
+    for (int j = 1; j < pl.ngroups; ++j)
+        if (b >= pl.grp[j].unit0) gi = j;
+    const AdM2LGroup gr = pl.grp[gi];
+    const int64_t t = (b - gr.unit0) * 128 + c;
+    if (t >= gr.count) return;
+    double v = 0.0;
+    for (int k = 0; k < pl.nsplit; ++k) v += partial[((int64_t)k * pl.units + b) * per + e];
+    Lc[(int64_t)tgt[gr.toff + t] * S + row] += v;
 }
 
 // Targets of levels >= 2 grouped by (level, class): block histograms in LDS
@@ -1113,17 +1164,22 @@ hipError_t ad_launch_l2l(int P, int64_t b0, int64_t nb, const uint32_t *code, co
     return hipGetLastError();
 }
 
-hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, int64_t nunits, const double *A, const int2 *cls,
-                         const double *M, const int *vidx, int64_t box2, const int *tgt, int64_t zero_row,
-                         double *Lc, hipStream_t st) {
-    if (nunits == 0) return hipSuccess;
+hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, const double *A, const int2 *cls, const double *M,
+                         const int *vidx, int64_t box2, const int *tgt, int64_t zero_row, double *Lc, double *partial,
+                         hipStream_t st) {
+    if (pl.units == 0) return hipSuccess;
+    if (pl.nsplit < 1 || (pl.nsplit > 1 && !partial)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)(pl.units * pl.nsplit);
     switch (P) {
 #define X(PP) \
-    case PP: k_ad_m2l<PP><<<(unsigned)nunits, 256, 0, st>>>(pl, A, cls, M, vidx, box2, tgt, zero_row, Lc); break;
+    case PP: k_ad_m2l<PP><<<nb, 256, 0, st>>>(pl, A, cls, M, vidx, box2, tgt, zero_row, Lc, partial); break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
     }
+    if (pl.nsplit > 1)
+        k_ad_m2l_sum<<<ad_blocks(pl.units * 128 * P * P, 256), 256, 0, st>>>(pl, P * P, coef_stride(P), tgt, partial,
+                                                                             Lc);
     return hipGetLastError();
 }
 

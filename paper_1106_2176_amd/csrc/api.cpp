@@ -349,7 +349,6 @@ struct AdTree {
     int64_t nlist[3] = {};                    // items of U, W, X
     int64_t goff[8 * FMM_MAX_LEVEL + 1] = {}; // first target of each (level, class) group
     AdM2LPlan plan{};
-    int64_t m2l_units = 0;
     uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
     Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
         is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts, ucnt, uoff, units, s27;
@@ -442,6 +441,7 @@ WorkSizes work_sizes(const fmm_tree *t, bool far) {
     if (t->ad) {  // FP64 coefficients by box id, plus the zero row
         z.farf = sizeof(double4) * (size_t)t->n;
         z.M[0] = z.Lc[0] = sizeof(double) * (size_t)(t->ad->nbox + 1) * S;
+        z.m2lpart = ad_m2l_partial_bytes(t->ad->plan, P);
         return z;
     }
     z.farf = sizeof(double4) * (size_t)t->n;
@@ -911,22 +911,25 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
                            st));
     // M2L targets grouped by (level, class), tiles of 128 targets per block
     a->plan = AdM2LPlan{};
-    a->m2l_units = 0;
     int64_t at = 0;
     for (int g = 0; g < ngrp; ++g) {
         a->goff[g] = at;
         const int64_t cnt = a->hbuf[4 + g];
         if (cnt) {
             AdM2LGroup &e = a->plan.grp[a->plan.ngroups++];
-            e.unit0 = a->m2l_units;
+            e.unit0 = a->plan.units;
             e.toff = at;
             e.count = cnt;
             e.cls = g % 8;
-            a->m2l_units += (cnt + 127) / 128;
+            a->plan.units += (cnt + 127) / 128;
         }
         at += cnt;
     }
     a->goff[ngrp] = at;
+    // K-split so that the launch has about four blocks per compute unit
+    a->plan.nsplit = a->plan.units ? (int)std::min<int64_t>(8, std::max<int64_t>(1, (4 * t->ncu + a->plan.units - 1) /
+                                                                                         a->plan.units))
+                                   : 1;
     if (at != a->nvbox) return fail(FMM_EDEVICE, "internal: M2L groups do not cover the boxes");
     if (ngrp) {
         CHK(ensure(t, a->tgt, u4 * a->nvbox, st));
@@ -965,7 +968,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
     HIPCHK(launch_gather_q(t->n, t->dtype, true, bp<uint32_t>(t->perm), charges, recs, st));
     CHK(rec(t, 1, st));
     if (do_far && a->depth >= 2) {
-        if (!o || !w.farf || !w.M[0] || !w.Lc[0]) return fail(FMM_EDEVICE, "internal: no far-field buffers");
+        if (!o || !w.farf || !w.M[0] || !w.Lc[0] || w.m2lpart_bytes < ad_m2l_partial_bytes(a->plan, P))
+            return fail(FMM_EDEVICE, "internal: no far-field buffers");
         double *M = (double *)w.M[0], *Lc = (double *)w.Lc[0];
         HIPCHK(launch_zero((uint32_t *)(M + (size_t)a->nbox * S), 2 * S, st));  // the zero row
         HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, recs, M, st));
@@ -976,8 +980,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
         CHK(rec(t, 3, st));
         HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, recs, Lc, st));
         CHK(rec(t, 4, st));
-        HIPCHK(ad_launch_m2l(P, a->plan, a->m2l_units, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2],
-                             bp<int>(a->tgt), a->nbox, Lc, st));
+        HIPCHK(ad_launch_m2l(P, a->plan, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2], bp<int>(a->tgt), a->nbox,
+                             Lc, w.m2lpart, st));
         CHK(rec(t, 5, st));
         for (int l = 3; l <= a->depth; ++l)
             HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent), o->down64, Lc,

@@ -142,16 +142,24 @@ struct AdM2LGroup {
 constexpr int kAdMaxGroups = 8 * (FMM_MAX_LEVEL - 1);
 struct AdM2LPlan {
     int ngroups;
+    int nsplit;      // K-split parts (1: the blocks add straight into the locals)
+    int64_t units;   // tiles of 128 targets over all groups
     AdM2LGroup grp[kAdMaxGroups];
 };
+// bytes of the K-split partial sums of a plan
+inline size_t ad_m2l_partial_bytes(const AdM2LPlan &pl, int P) {
+    return pl.nsplit > 1 ? sizeof(double) * (size_t)pl.nsplit * pl.units * 128 * P * P : 0;
+}
 // evaluation (FP64, box-id-indexed coefficient rows of stride coef_stride(P))
 hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const double4 *rec,
                          double *M, hipStream_t st);
 hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
                          double *M, hipStream_t st);
-hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, int64_t nunits, const double *A, const int2 *cls,
-                         const double *M, const int *vidx, int64_t box2, const int *tgt, int64_t zero_row,
-                         double *Lc, hipStream_t st);
+// adds M2L over the V slots into Lc; with pl.nsplit > 1 through `partial`
+// (ad_m2l_partial_bytes) and a summing kernel, in a fixed order
+hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, const double *A, const int2 *cls, const double *M,
+                         const int *vidx, int64_t box2, const int *tgt, int64_t zero_row, double *Lc, double *partial,
+                         hipStream_t st);
 hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
                          const uint32_t *code, const uint32_t *ps, const uint32_t *pe, const double4 *rec,
                          double *Lc, hipStream_t st);
