@@ -33,6 +33,14 @@ namespace fmm {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// LDS written by some lanes of a wave and read by others: the wave's own
+// barrier with the fences that order its LDS accesses
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------ tree build
 __device__ __forceinline__ void box_coords(uint32_t code, int64_t &x, int64_t &y, int64_t &z) {
     x = compact3(code);
@@ -552,34 +560,67 @@ __device__ __forceinline__ void irregular_each(double x, double y, double z, F &
 // local expansion of each particle of c: the complex local coefficient of a
 // charge q at y (g units) is q I_n^m(y), i.e. ell_c = 2 q Re, ell_s = -2 q Im.
 // Every box's row is written (zero for an empty X), so this pass also clears
-// the locals before M2L and L2L add to them.
+// the locals before M2L and L2L add to them.  One wave per box: the
+// particles of X(g) are taken as one sequence (up to 64 list entries at a
+// time, offsets by a wave scan, each lane finding its entry by bisection),
+// B of them at a time each expanded by one lane into an LDS row, and the
+// rows summed coefficient by coefficient.
 template <int P>
 __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, const int *__restrict__ ix,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                                const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
                                                const double4 *__restrict__ rec, double *__restrict__ Lc) {
-    constexpr int P2 = P * P, S = coef_stride(P), B = 16, NC = (P2 + 63) / 64;
+    constexpr int P2 = P * P, S = coef_stride(P), NC = (P2 + 63) / 64;
+    constexpr int B = P <= 8 ? 32 : (P <= 11 ? 16 : 8);  // rows of at most ~17 KB (2 waves per SIMD)
     __shared__ double rows[B][P2 + 1];
+    __shared__ double4 frame[64];
+    __shared__ uint32_t first[64], off[65];
     const int g = blockIdx.x, t = threadIdx.x;
     const uint32_t x0 = ox[g], x1 = ox[g + 1];
     const int lg = lev[g];
+    const uint32_t cg = code[g];
     double acc[NC];
 #pragma unroll
     for (int a = 0; a < NC; ++a) acc[a] = 0.0;
-    for (uint32_t e = x0; e < x1; ++e) {
-        const int c = ix[e];
-        const int lc = lev[c];
-        double cx, cy, cz;
-        ad_centre_diff(lc, code[c], lg, code[g], lg, cx, cy, cz);
-        const double sc = ldexp(1.0, lg - lc);
-        for (uint32_t b0 = ps[c]; b0 < pe[c]; b0 += B) {
-            __syncthreads();
+    for (uint32_t e0 = x0; e0 < x1; e0 += 64) {
+        const int nb = (int)min(64u, x1 - e0);
+        uint32_t cnt = 0;
+        __syncthreads();  // the previous batch's tables have been read
+        if (t < nb) {
+            const int c = ix[e0 + t];
+            const int lc = lev[c];
+            double cx, cy, cz;
+            ad_centre_diff(lc, code[c], lg, cg, lg, cx, cy, cz);
+            frame[t] = make_double4(cx, cy, cz, ldexp(1.0, lg - lc));
+            first[t] = ps[c];
+            cnt = pe[c] - ps[c];
+        }
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(incl, d);
+            if (t >= d) incl += v;
+        }
+        off[t + 1] = incl;
+        if (t == 0) off[0] = 0;
+        const uint32_t total = __shfl(incl, 63);
+        __syncthreads();
+        for (uint32_t f0 = 0; f0 < total; f0 += B) {
+            __syncthreads();  // the previous rows have been summed
             if (t < B) {
                 double *row = rows[t];
-                if (b0 + t < pe[c]) {
-                    const double4 r = rec[b0 + t];
-                    const double q = r.w;
-                    irregular_each<P - 1>(cx + sc * r.x, cy + sc * r.y, cz + sc * r.z,
+                const uint32_t f = f0 + t;
+                if (f < total) {
+                    int lo = 0, hi = nb - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (off[mid] <= f) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const double4 fr = frame[lo];
+                    const double4 v = rec[first[lo] + (f - off[lo])];
+                    const double q = v.w;
+                    irregular_each<P - 1>(fr.x + fr.w * v.x, fr.y + fr.w * v.y, fr.z + fr.w * v.z,
                                           [&](int n, int m, double re, double im) {
                                               if (m == 0) {
                                                   row[n * n] = q * re;
@@ -614,85 +655,120 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
 // and degree-1 coefficients of the local expansion at the particle are
 //   L_0^0 = sum M_n^m I_n^m,  L_1^l = -sum M_n^m I_{n+1}^{m+l},
 // and phi = L_0^0 / w, grad = (-Re L_1^1, -Im L_1^1, L_1^0) / w^2.
-// Accumulated into out (root units: phi * 2^l_w, E * 4^l_w).
+// Added into out (root units: phi * 2^l_w, E * 4^l_w).  One wave per unit
+// of up to 64 targets (the P2P units): the targets take T = 2^LT lanes, and
+// the 64 / T lane groups take the boxes of W(g) in turn, each staging its
+// box's multipole in LDS; the groups' sums are joined by shuffles.
+template <int P, int LT>
+__device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int g, int lg, uint32_t cg, uint32_t t0,
+                                            uint32_t nt, uint32_t w0, uint32_t w1, const int *__restrict__ iw,
+                                            const int *__restrict__ lev, const uint32_t *__restrict__ code,
+                                            const double4 *__restrict__ rec, const double *__restrict__ M,
+                                            double4 *__restrict__ out) {
+    constexpr int P2 = P * P, S = coef_stride(P), T = 1 << LT, G = 64 >> LT;
+    const int slot = lane & (T - 1), grp = lane >> LT;
+    const bool live = (uint32_t)slot < nt;
+    const double4 r = live ? rec[t0 + slot] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+    double *const mu = mus[grp];
+    for (uint32_t e0 = w0; e0 < w1; e0 += G) {
+        const uint32_t e = e0 + grp;
+        const bool has = e < w1;
+        const int w = has ? iw[e] : 0;
+        wave_sync();  // the previous round's multipoles have been read
+        if (has)
+            for (int c = slot; c < P2; c += T) mu[c] = M[(size_t)w * S + c];
+        wave_sync();
+        if (!has) continue;
+        const int lw = lev[w];
+        double cx, cy, cz;
+        ad_centre_diff(lg, cg, lw, code[w], lw, cx, cy, cz);
+        const double sc = ldexp(1.0, lw - lg);
+        double l00 = 0.0, l10 = 0.0, l11r = 0.0, l11i = 0.0;
+        irregular_each<P>(cx + sc * r.x, cy + sc * r.y, cz + sc * r.z, [&](int n, int m, double ir, double ii) {
+            // M_{n'}^{m'} of the multipole (0 outside n' < P, 0 <= m' <= n')
+            auto Mc = [&](int nn, int mm, double &mr, double &mi) {
+                mr = mi = 0.0;
+                if (nn < 0 || nn >= P || mm > nn || mm < 0) return;
+                if (mm == 0) {
+                    mr = mu[nn * nn];
+                } else {
+                    mr = mu[nn * nn + 2 * mm - 1];
+                    mi = mu[nn * nn + 2 * mm];
+                }
+            };
+            double mr, mi;
+            if (n < P) {  // L_0^0: M_n^m I_n^m and its conjugate partner
+                Mc(n, m, mr, mi);
+                const double re = mr * ir - mi * ii;
+                l00 += m == 0 ? re : 2.0 * re;
+            }
+            if (n >= 1) {
+                // L_1^0: -M_{n-1}^m I_n^m, with the partner -m
+                Mc(n - 1, m, mr, mi);
+                const double re = mr * ir - mi * ii;
+                l10 -= m == 0 ? re : 2.0 * re;
+                // L_1^1: -M_{n-1}^{m-1} I_n^m (m >= 1) and
+                //        +conj(M_{n-1}^{m+1} I_n^m) (the terms of order -(m+1))
+                if (m >= 1) {
+                    Mc(n - 1, m - 1, mr, mi);
+                    l11r -= mr * ir - mi * ii;
+                    l11i -= mr * ii + mi * ir;
+                }
+                Mc(n - 1, m + 1, mr, mi);
+                l11r += mr * ir - mi * ii;
+                l11i -= mr * ii + mi * ir;
+            }
+        });
+        const double s1 = ldexp(1.0, lw), s2 = s1 * s1;
+        phi += l00 * s1;
+        ex += l11r * s2;
+        ey += l11i * s2;
+        ez -= l10 * s2;
+    }
+#pragma unroll
+    for (int d = 32; d >= T; d >>= 1) {
+        phi += __shfl_xor(phi, d);
+        ex += __shfl_xor(ex, d);
+        ey += __shfl_xor(ey, d);
+        ez += __shfl_xor(ez, d);
+    }
+    if (live && grp == 0) {
+        double4 o = out[t0 + slot];
+        o.x += phi;
+        o.y += ex;
+        o.z += ey;
+        o.w += ez;
+        out[t0 + slot] = o;
+    }
+}
+
+// at most 16 lane groups (4 lanes per unit target at least), so that the
+// staged multipoles stay within 32 KB at p = 16
 template <int P>
-__global__ __launch_bounds__(64) void k_ad_m2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+__global__ __launch_bounds__(64) void k_ad_m2p(const uint32_t *__restrict__ nunits, const int2 *__restrict__ units,
+                                               const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
                                                const uint32_t *__restrict__ ow, const int *__restrict__ iw,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                                const double4 *__restrict__ rec, const double *__restrict__ M,
                                                double4 *__restrict__ out) {
-    constexpr int P2 = P * P, S = coef_stride(P);
-    __shared__ double mu[P2];
-    const int j = blockIdx.x;
+    __shared__ double mus[16][P * P];
+    if (blockIdx.x >= *nunits) return;
+    const int2 un = units[blockIdx.x];
+    const int j = un.x;
     const int g = lbox[j];
     const uint32_t w0 = ow[g], w1 = ow[g + 1];
     if (w0 == w1) return;
-    const int lg = lev[g];
-    for (uint32_t i0 = lstart[j]; i0 < lstart[j + 1]; i0 += 64) {
-        const uint32_t i = i0 + threadIdx.x;
-        const bool live = i < lstart[j + 1];
-        double4 r = live ? rec[i] : make_double4(0.0, 0.0, 0.0, 0.0);
-        double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        for (uint32_t e = w0; e < w1; ++e) {
-            const int w = iw[e];
-            const int lw = lev[w];
-            __syncthreads();
-            for (int c = threadIdx.x; c < P2; c += 64) mu[c] = M[(size_t)w * S + c];
-            __syncthreads();
-            double cx, cy, cz;
-            ad_centre_diff(lg, code[g], lw, code[w], lw, cx, cy, cz);
-            const double sc = ldexp(1.0, lw - lg);
-            double l00 = 0.0, l10 = 0.0, l11r = 0.0, l11i = 0.0;
-            irregular_each<P>(cx + sc * r.x, cy + sc * r.y, cz + sc * r.z, [&](int n, int m, double ir, double ii) {
-                // M_{n'}^{m'} of the multipole (0 outside n' < P, |m'| <= n')
-                auto Mc = [&](int nn, int mm, double &mr, double &mi) {
-                    mr = mi = 0.0;
-                    if (nn < 0 || nn >= P || mm > nn || mm < 0) return;
-                    if (mm == 0) {
-                        mr = mu[nn * nn];
-                    } else {
-                        mr = mu[nn * nn + 2 * mm - 1];
-                        mi = mu[nn * nn + 2 * mm];
-                    }
-                };
-                double mr, mi;
-                if (n < P) {  // L_0^0: M_n^m I_n^m and its conjugate partner
-                    Mc(n, m, mr, mi);
-                    const double re = mr * ir - mi * ii;
-                    l00 += m == 0 ? re : 2.0 * re;
-                }
-                if (n >= 1) {
-                    // L_1^0: -M_{n-1}^m I_n^m, with the partner -m
-                    Mc(n - 1, m, mr, mi);
-                    const double re = mr * ir - mi * ii;
-                    l10 -= m == 0 ? re : 2.0 * re;
-                    // L_1^1: -M_{n-1}^{m-1} I_n^m (m >= 1) and
-                    //        +conj(M_{n-1}^{m+1} I_n^m) (the terms of order -(m+1))
-                    if (m >= 1) {
-                        Mc(n - 1, m - 1, mr, mi);
-                        l11r -= mr * ir - mi * ii;
-                        l11i -= mr * ii + mi * ir;
-                    }
-                    Mc(n - 1, m + 1, mr, mi);
-                    l11r += mr * ir - mi * ii;
-                    l11i -= mr * ii + mi * ir;
-                }
-            });
-            const double s1 = ldexp(1.0, lw), s2 = s1 * s1;
-            phi += l00 * s1;
-            ex += l11r * s2;
-            ey += l11i * s2;
-            ez -= l10 * s2;
-        }
-        if (live) {
-            double4 o = out[i];
-            o.x += phi;
-            o.y += ex;
-            o.z += ey;
-            o.w += ez;
-            out[i] = o;
-        }
-    }
+    const int lane = threadIdx.x;
+    const uint32_t t0 = lstart[j] + (uint32_t)un.y, nt = min(64u, lstart[j + 1] - t0);
+    int lt = 2;  // log2 T, at least 2
+    while ((1u << lt) < nt && lt < 6) ++lt;
+#define AD_M2P_CASE(K)                                                                                          \
+    case K:                                                                                                     \
+        ad_m2p_unit<P, K>(mus, lane, g, lev[g], code[g], t0, nt, w0, w1, iw, lev, code, rec, M, out);          \
+        break;
+    switch (lt) { AD_M2P_CASE(2) AD_M2P_CASE(3) AD_M2P_CASE(4) AD_M2P_CASE(5) AD_M2P_CASE(6) }
+#undef AD_M2P_CASE
 }
 
 // One pair of the FP64 near field: rsqrt by the hardware estimate and one
@@ -715,12 +791,6 @@ __device__ __forceinline__ void ad_pair(double xi, double yi, double zi, const d
     ex = __builtin_fma(qr3, dx, ex);
     ey = __builtin_fma(qr3, dy, ey);
     ez = __builtin_fma(qr3, dz, ez);
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // P2P over U at the leaves (FP64), one wave per unit of up to 64 targets of
@@ -1213,12 +1283,14 @@ hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t ad_launch_m2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint32_t *ow,
-                         const int *iw, const int *lev, const uint32_t *code, const double4 *rec, const double *M,
-                         double4 *out, hipStream_t st) {
+hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
+                         const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
+                         const uint32_t *code, const double4 *rec, const double *M, double4 *out, hipStream_t st) {
     switch (P) {
-#define X(PP) \
-    case PP: k_ad_m2p<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, ow, iw, lev, code, rec, M, out); break;
+#define X(PP)                                                                                                      \
+    case PP:                                                                                                       \
+        k_ad_m2p<PP><<<(unsigned)max_units, 64, 0, st>>>(nunits, units, lbox, lstart, ow, iw, lev, code, rec, M, out); \
+        break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;

@@ -988,7 +988,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
                                  st));
         CHK(rec(t, 6, st));
         HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, bp<uint8_t>(a->llev), recs, Lc, w.farf, st));
-        HIPCHK(ad_launch_m2p(P, a->nleaf, lbox, lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, st));
+        HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ow,
+                             bp<int>(a->iw), lev, code, recs, M, w.farf, st));
     } else {
         for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
     }
