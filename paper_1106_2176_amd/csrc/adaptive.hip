@@ -306,24 +306,33 @@ __global__ void k_ad_heads(int64_t nbox, const uint8_t *__restrict__ leaf, const
 __global__ void k_ad_leaflist(int64_t n, const uint32_t *__restrict__ is_head, const uint32_t *__restrict__ hoff,
                               const int *__restrict__ head, const uint32_t *__restrict__ ps,
                               int *__restrict__ lbox, uint32_t *__restrict__ lstart, uint8_t *__restrict__ llev,
-                              const int *__restrict__ lev, const uint32_t *__restrict__ pe,
-                              unsigned int *__restrict__ mx) {
+                              const int *__restrict__ lev) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t m = 0;
-    if (i < n && is_head[i]) {
+    if (i >= n) return;
+    if (is_head[i]) {
         const uint32_t j = hoff[i];
         const int g = head[i];
         lbox[j] = g;
         lstart[j] = ps[g];
         llev[j] = (uint8_t)lev[g];
-        m = pe[g] - ps[g];
     }
     if (i == n - 1) lstart[hoff[n]] = (uint32_t)n;
-    // the fullest leaf: a wave maximum, one atomic per wave (every lane of
-    // the wave reaches this point)
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d));
-    if ((threadIdx.x & 63) == 0 && m) atomicMax(mx, m);
+}
+
+// The fullest leaf: a block maximum over a grid stride, one atomic per block.
+__global__ __launch_bounds__(256) void k_ad_leafmax(int64_t nleaf, const uint32_t *__restrict__ lstart,
+                                                    unsigned int *__restrict__ mx) {
+    __shared__ unsigned int red[256];
+    unsigned int m = 0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < nleaf; j += (int64_t)gridDim.x * 256)
+        m = max(m, lstart[j + 1] - lstart[j]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(mx, red[0]);
 }
 
 // P2P work units: ceil(count / 64) per leaf (pass 0), then each unit's
@@ -1170,10 +1179,11 @@ hipError_t ad_launch_heads(int64_t nbox, const uint8_t *leaf, const uint32_t *ps
     return hipGetLastError();
 }
 
-hipError_t ad_launch_leaflist(int64_t n, const uint32_t *is_head, const uint32_t *hoff, const int *head,
-                              const uint32_t *ps, const uint32_t *pe, int *lbox, uint32_t *lstart, uint8_t *llev,
+hipError_t ad_launch_leaflist(int64_t n, int64_t nleaf, const uint32_t *is_head, const uint32_t *hoff,
+                              const int *head, const uint32_t *ps, int *lbox, uint32_t *lstart, uint8_t *llev,
                               const int *lev, unsigned int *mx, hipStream_t st) {
-    k_ad_leaflist<<<ad_blocks(n, 256), 256, 0, st>>>(n, is_head, hoff, head, ps, lbox, lstart, llev, lev, pe, mx);
+    k_ad_leaflist<<<ad_blocks(n, 256), 256, 0, st>>>(n, is_head, hoff, head, ps, lbox, lstart, llev, lev);
+    k_ad_leafmax<<<(unsigned)std::min<int64_t>(256, (nleaf + 255) / 256), 256, 0, st>>>(nleaf, lstart, mx);
     return hipGetLastError();
 }
 

@@ -896,7 +896,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     CHK(ensure(t, a->lstart, u4 * (a->nleaf + 1), st));
     CHK(ensure(t, a->llev, a->nleaf, st));
     HIPCHK(launch_zero(dc + 3, 1, st));
-    HIPCHK(ad_launch_leaflist(n, bp<uint32_t>(a->is_head), bp<uint32_t>(a->hoff), bp<int>(a->head), ps, pe,
+    HIPCHK(ad_launch_leaflist(n, a->nleaf, bp<uint32_t>(a->is_head), bp<uint32_t>(a->hoff), bp<int>(a->head), ps,
                               bp<int>(a->lbox), bp<uint32_t>(a->lstart), bp<uint8_t>(a->llev), lev, dc + 3, st));
     HIPCHK(ad_launch_records(n, dtype, bp<uint32_t>(a->hoff), bp<int>(a->lbox), lev, code, bp<uint32_t>(t->perm),
                              pos, c.box_lo, c.box_size, bp<double4>(t->xyz64), st));

@@ -119,8 +119,8 @@ hipError_t ad_launch_box_offsets(int64_t nbox, const uint32_t *s27, uint32_t *ou
 hipError_t ad_launch_heads(int64_t nbox, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,
                            uint32_t *is_head, int *head, hipStream_t st);
 // leaves in particle order, and the fullest leaf's count into *mx
-hipError_t ad_launch_leaflist(int64_t n, const uint32_t *is_head, const uint32_t *hoff, const int *head,
-                              const uint32_t *ps, const uint32_t *pe, int *lbox, uint32_t *lstart, uint8_t *llev,
+hipError_t ad_launch_leaflist(int64_t n, int64_t nleaf, const uint32_t *is_head, const uint32_t *hoff,
+                              const int *head, const uint32_t *ps, int *lbox, uint32_t *lstart, uint8_t *llev,
                               const int *lev, unsigned int *mx, hipStream_t st);
 // out[4] (zeroed): ordered P2P pairs incl. self, V entries, W and X (particle, box) pairs
 hipError_t ad_launch_counts(int64_t nbox, int64_t box2, const uint8_t *leaf, const uint32_t *ps, const uint32_t *pe,

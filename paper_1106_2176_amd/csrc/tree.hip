@@ -212,43 +212,55 @@ __global__ __launch_bounds__(256) void k_fixup(int L, uint32_t skip, const uint3
     const uint32_t nleaf = 1u << (3 * L);
     uint32_t *const idx = idxs[wave];
     const double scale = (double)(1u << L);
-    // one wave per leaf, the grid striding over the leaves (no block barrier)
-    for (uint32_t leaf = 4 * blockIdx.x + wave; leaf < nleaf; leaf += 4 * gridDim.x) {
-        const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
-        if (cnt == 0 || cnt > skip) continue;
-        const bool cached = cnt <= (uint32_t)kFixupCache;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // the previous leaf's reads of idx
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (cached)
-            for (uint32_t j = lane; j < cnt; j += 64) idx[j] = tmp[s0 + j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
-                     bz = (double)compact3(leaf >> 2) + 0.5;
-        for (uint32_t j = lane; j < cnt; j += 64) {
-            const uint32_t me = cached ? idx[j] : tmp[s0 + j];
-            uint32_t rank = 0;
-            if (cached) {
-                for (uint32_t k = 0; k < cnt; ++k) rank += idx[k] < me;
-            } else {
-                for (uint32_t k = 0; k < cnt; ++k) rank += tmp[s0 + k] < me;
+    // Wave w of the W in the grid takes the leaves w, w + W, w + 2W, ... (no
+    // block barrier), 64 at a time: the lanes read 64 counts at once and the
+    // wave then works through the leaves that need it.  A tree of mostly
+    // empty bins costs one load per 64 of them, and a wave's leaves lie far
+    // apart, so that a dense region of the input is spread over many waves.
+    const uint32_t W = 4 * gridDim.x, w = 4 * blockIdx.x + wave;
+    for (uint32_t base = w; base < nleaf; base += 64 * W) {
+        const uint32_t mine = base + lane * W;
+        const uint32_t c_l = mine < nleaf ? start[mine + 1] - start[mine] : 0;
+        uint64_t todo = __ballot(c_l != 0 && c_l <= skip);
+        while (todo) {
+            const int b = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const uint32_t leaf = base + (uint32_t)b * W;
+            const uint32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
+            const bool cached = cnt <= (uint32_t)kFixupCache;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");  // the previous leaf's reads of idx
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (cached)
+                for (uint32_t j = lane; j < cnt; j += 64) idx[j] = tmp[s0 + j];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
+                         bz = (double)compact3(leaf >> 2) + 0.5;
+            for (uint32_t j = lane; j < cnt; j += 64) {
+                const uint32_t me = cached ? idx[j] : tmp[s0 + j];
+                uint32_t rank = 0;
+                if (cached) {
+                    for (uint32_t k = 0; k < cnt; ++k) rank += idx[k] < me;
+                } else {
+                    for (uint32_t k = 0; k < cnt; ++k) rank += tmp[s0 + k] < me;
+                }
+                const uint32_t d = s0 + rank;
+                perm[d] = me;
+                const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
+                const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
+                const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
+                if (xyz32) {
+                    // fixed point in [-2^29, 2^29 - 1]: u = +1/2 (a point on the upper
+                    // face of the root cube) moves by 2^-30 leaf widths
+                    const int top = (1 << 29) - 1;
+                    xyz32[d] = make_int4(min(__double2int_rn(ux * kFixScale), top),
+                                         min(__double2int_rn(uy * kFixScale), top),
+                                         min(__double2int_rn(uz * kFixScale), top), 0);
+                }
+                if (xyz64) xyz64[d] = make_double4(ux, uy, uz, 0.0);
             }
-            const uint32_t d = s0 + rank;
-            perm[d] = me;
-            const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
-            const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
-            const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
-            if (xyz32) {
-                // fixed point in [-2^29, 2^29 - 1]: u = +1/2 (a point on the upper
-                // face of the root cube) moves by 2^-30 leaf widths
-                const int top = (1 << 29) - 1;
-                xyz32[d] = make_int4(min(__double2int_rn(ux * kFixScale), top),
-                                     min(__double2int_rn(uy * kFixScale), top),
-                                     min(__double2int_rn(uz * kFixScale), top), 0);
-            }
-            if (xyz64) xyz64[d] = make_double4(ux, uy, uz, 0.0);
         }
     }
 }
