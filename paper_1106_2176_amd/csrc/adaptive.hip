@@ -805,9 +805,9 @@ __device__ __forceinline__ void ad_pair(double xi, double yi, double zi, const d
 // P2P over U at the leaves (FP64), one wave per unit of up to 64 targets of
 // one leaf (a leaf of more than 64 particles gives several units, so that
 // the work of the fullest leaves spreads over several waves).  The unit's
-// targets take T = 2^LT lanes (the power of two >= its count) and the 64 / T
-// lane groups split every source tile, their sums joined by shuffles at the
-// end.  The sources of U(g) are taken as one sequence, up to
+// targets take T = 2^LT lanes, two per lane (T the power of two >= half its
+// count), and the 64 / T lane groups split every source tile, their sums
+// joined by shuffles at the end.  The sources of U(g) are taken as one sequence, up to
 // 64 list entries at a time: each lane holds one entry's particle range and
 // its frame change (c_c - c_g)/w_g + u 2^(l_g - l_c) (exact scaling, one
 // rounding), a wave scan of the counts gives the entries' offsets, and the
@@ -832,63 +832,73 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
     constexpr int T = 1 << LT, G = 64 >> LT;
     const int slot = lane & (T - 1), grp = lane >> LT;
     const double s1 = ldexp(1.0, lg), s2 = s1 * s1;
-    {
-        const uint32_t ti = slot;
-        const bool live = ti < nt;
-        const double4 r = live ? rec[t0 + ti] : make_double4(0.0, 0.0, 0.0, 0.0);
-        double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        for (uint32_t e0 = u0; e0 < u1; e0 += 64) {
-            const int nb = (int)min(64u, u1 - e0);
-            uint32_t cnt = 0;
-            wave_sync();  // the previous batch's tables have been read
-            if (lane < nb) {
-                const int c = iu[e0 + lane];
-                const int lc = lev[c];
-                double cx, cy, cz;
-                ad_centre_diff(lc, code[c], lg, cg, lg, cx, cy, cz);
-                sh.frame[lane] = make_double4(cx, cy, cz, ldexp(1.0, lg - lc));
-                sh.first[lane] = ps[c];
-                cnt = pe[c] - ps[c];
-            }
-            uint32_t incl = cnt;  // inclusive scan over the lanes
+    // two targets per lane, slot and slot + T: each source read feeds both
+    const bool live0 = (uint32_t)slot < nt, live1 = (uint32_t)(slot + T) < nt;
+    const double4 r0 = live0 ? rec[t0 + slot] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double4 r1 = live1 ? rec[t0 + slot + T] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double phi0 = 0.0, ex0 = 0.0, ey0 = 0.0, ez0 = 0.0, phi1 = 0.0, ex1 = 0.0, ey1 = 0.0, ez1 = 0.0;
+    for (uint32_t e0 = u0; e0 < u1; e0 += 64) {
+        const int nb = (int)min(64u, u1 - e0);
+        uint32_t cnt = 0;
+        wave_sync();  // the previous batch's tables have been read
+        if (lane < nb) {
+            const int c = iu[e0 + lane];
+            const int lc = lev[c];
+            double cx, cy, cz;
+            ad_centre_diff(lc, code[c], lg, cg, lg, cx, cy, cz);
+            sh.frame[lane] = make_double4(cx, cy, cz, ldexp(1.0, lg - lc));
+            sh.first[lane] = ps[c];
+            cnt = pe[c] - ps[c];
+        }
+        uint32_t incl = cnt;  // inclusive scan over the lanes
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t v = __shfl_up(incl, d);
-                if (lane >= d) incl += v;
-            }
-            sh.off[lane + 1] = incl;
-            if (lane == 0) sh.off[0] = 0;
-            const uint32_t total = __shfl(incl, 63);
-            wave_sync();
-            for (uint32_t f0 = 0; f0 < total; f0 += 64) {
-                const uint32_t f = f0 + lane;
-                double4 src = make_double4(1e3, 1e3, 1e3, 0.0);
-                if (f < total) {
-                    int lo = 0, hi = nb - 1;  // the entry k with off[k] <= f < off[k + 1]
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (sh.off[mid] <= f) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    const double4 fr = sh.frame[lo];
-                    const double4 v = rec[sh.first[lo] + (f - sh.off[lo])];
-                    src = make_double4(fr.x + fr.w * v.x, fr.y + fr.w * v.y, fr.z + fr.w * v.z, v.w);
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        sh.off[lane + 1] = incl;
+        if (lane == 0) sh.off[0] = 0;
+        const uint32_t total = __shfl(incl, 63);
+        wave_sync();
+        for (uint32_t f0 = 0; f0 < total; f0 += 64) {
+            const uint32_t f = f0 + lane;
+            double4 src = make_double4(1e3, 1e3, 1e3, 0.0);
+            if (f < total) {
+                int lo = 0, hi = nb - 1;  // the entry k with off[k] <= f < off[k + 1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sh.off[mid] <= f) lo = mid;
+                    else hi = mid - 1;
                 }
-                wave_sync();  // the previous tile has been read
-                sh.tile[lane] = src;
-                wave_sync();
+                const double4 fr = sh.frame[lo];
+                const double4 v = rec[sh.first[lo] + (f - sh.off[lo])];
+                src = make_double4(fr.x + fr.w * v.x, fr.y + fr.w * v.y, fr.z + fr.w * v.z, v.w);
+            }
+            wave_sync();  // the previous tile has been read
+            sh.tile[lane] = src;
+            wave_sync();
 #pragma unroll
-                for (int k = 0; k < 64; k += G) ad_pair<true>(r.x, r.y, r.z, sh.tile[k + grp], phi, ex, ey, ez);
+            for (int k = 0; k < 64; k += G) {
+                const double4 sk = sh.tile[k + grp];
+                ad_pair<true>(r0.x, r0.y, r0.z, sk, phi0, ex0, ey0, ez0);
+                ad_pair<true>(r1.x, r1.y, r1.z, sk, phi1, ex1, ey1, ez1);
             }
         }
+    }
 #pragma unroll
-        for (int d = 32; d >= T; d >>= 1) {
-            phi += __shfl_xor(phi, d);
-            ex += __shfl_xor(ex, d);
-            ey += __shfl_xor(ey, d);
-            ez += __shfl_xor(ez, d);
-        }
-        if (live && grp == 0) out[t0 + ti] = make_double4(phi * s1, ex * s2, ey * s2, ez * s2);
+    for (int d = 32; d >= T; d >>= 1) {
+        phi0 += __shfl_xor(phi0, d);
+        ex0 += __shfl_xor(ex0, d);
+        ey0 += __shfl_xor(ey0, d);
+        ez0 += __shfl_xor(ez0, d);
+        phi1 += __shfl_xor(phi1, d);
+        ex1 += __shfl_xor(ex1, d);
+        ey1 += __shfl_xor(ey1, d);
+        ez1 += __shfl_xor(ez1, d);
+    }
+    if (grp == 0) {
+        if (live0) out[t0 + slot] = make_double4(phi0 * s1, ex0 * s2, ey0 * s2, ez0 * s2);
+        if (live1) out[t0 + slot + T] = make_double4(phi1 * s1, ex1 * s2, ey1 * s2, ez1 * s2);
     }
 }
 
@@ -905,8 +915,8 @@ __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
     const int j = un.x;
     const int g = lbox[j];
     const uint32_t t0 = lstart[j] + (uint32_t)un.y, nt = min(64u, lstart[j + 1] - t0);
-    int lt = 0;  // log2 T
-    while ((1u << lt) < nt && lt < 6) ++lt;
+    int lt = 0;  // log2 T, T >= half the unit's targets
+    while (2u * (1u << lt) < nt && lt < 5) ++lt;
 #define AD_P2P_CASE(K)                                                                                       \
     case K:                                                                                                  \
         ad_p2p_unit<K>(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, \
@@ -914,7 +924,6 @@ __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
         break;
     switch (lt) {
         AD_P2P_CASE(0) AD_P2P_CASE(1) AD_P2P_CASE(2) AD_P2P_CASE(3) AD_P2P_CASE(4) AD_P2P_CASE(5)
-        AD_P2P_CASE(6)
     }
 #undef AD_P2P_CASE
 }
