@@ -131,8 +131,9 @@ typedef struct {
                                   made on the first build that asks for them (a
                                   quadrature per offset, about a second of host
                                   time at p = 16) and kept per device and p. */
-    int32_t adaptive;          /* FP64 form only (FMM_EUNSUPPORTED otherwise),
-                                  not with m2l_rotation (FMM_EUNSUPPORTED):
+    int32_t adaptive;          /* not with m2l_rotation, nor with the bf16
+                                  encodings (m2l_fp16 = 0) of the mixed form
+                                  (FMM_EUNSUPPORTED):
                                   nonzero = the adaptive octree of the
                                   construction Sec. 5 names beside the uniform
                                   one.  A box is split while it holds more than
@@ -152,7 +153,10 @@ typedef struct {
                                   leaves c with b in W(c) (each particle of c
                                   expanded about b's centre, P2L).  Two boxes
                                   touch when their closed cubes intersect and
-                                  neither contains the other.  fmm_backward
+                                  neither contains the other.  Every step is
+                                  FP64 except, in the mixed form, the M2L (the
+                                  binary16 encoding described at m2l_fp16,
+                                  with one operand scale per level).  fmm_backward
                                   and overlap_near are not available on such a
                                   tree (FMM_EUNSUPPORTED / ignored); the build
                                   blocks once per tree level and once more at

@@ -1126,6 +1126,278 @@ __global__ __launch_bounds__(256) void k_ad_class(int64_t box2, int64_t nb, cons
     if (fill && grp >= 0) tgt[goff[grp] + base[grp] + rank] = (int)(box2 + i);
 }
 
+// ------------------------------------------------ M2L, binary16 encoding
+// The mixed form's M2L on the adaptive tree: the uniform tree's binary16
+// encoding (operators scaled per row and by the harmonic size of each
+// column's degree, split hi + lo; multipoles scaled by the same column
+// factors and by a power of two per level, split likewise; three products
+// hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_f16, FP32 accumulation
+// merged into FP64 every 256 K terms), with the multipole operand gathered
+// through the V slots as in the FP64 kernel.
+
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// Per-level maxima of |M_c rho_inv[c]|: one thread per (box, coefficient),
+// an LDS maximum per level in the block, one global atomic per level and
+// block (non-negative floats order like their bit patterns).
+__global__ __launch_bounds__(256) void k_ad_level_max(int P, int64_t box2, int64_t nb, const int *__restrict__ lev,
+                                                      const double *__restrict__ M, const float *__restrict__ rho_inv,
+                                                      uint32_t *__restrict__ lmax) {
+    __shared__ unsigned int lm[kLevelSlots];
+    const int P2 = P * P, S = coef_stride(P);
+    if (threadIdx.x < kLevelSlots) lm[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb * P2) {
+        const int64_t g = box2 + i / P2;
+        const int c = (int)(i % P2);
+        const float v = (float)fabs(M[g * S + c]) * rho_inv[c];
+        if (v > 0.0f) atomicMax(&lm[lev[g]], __float_as_uint(v));
+    }
+    __syncthreads();
+    if (threadIdx.x < kLevelSlots && lm[threadIdx.x]) atomicMax(lmax + threadIdx.x, lm[threadIdx.x]);
+}
+
+// One thread per 8-coefficient piece of rows box2 .. nbox (the last the zero
+// row): scaled by rho_inv[c] 2^e(level) and split into binary16 hi and lo,
+// stored hi8 then lo8 (32 bytes).
+__global__ __launch_bounds__(256) void k_ad_pack_h(int P, int64_t box2, int64_t nbox, const int *__restrict__ lev,
+                                                   const double *__restrict__ M, const float *__restrict__ rho_inv,
+                                                   const uint32_t *__restrict__ lmax, uint4 *__restrict__ Bh) {
+    const int S = coef_stride(P), PPO = S / 8;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (nbox + 1 - box2) * PPO) return;
+    const int64_t g = box2 + i / PPO;
+    const int pc = (int)(i % PPO);
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g < nbox) {
+        const float sc = ldexpf(1.0f, level_scale_exp(lmax[lev[g]]));
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = 8 * pc + k;
+            const float r = rho_inv[c];  // 0 past p^2 (padding, never written)
+            v[k] = r != 0.0f ? (float)M[g * S + c] * (r * sc) : 0.0f;
+        }
+    }
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const f32x2_t a = {v[2 * k], v[2 * k + 1]};
+        const f16x2_t h = __builtin_convertvector(a, f16x2_t);
+        const f16x2_t lo = __builtin_convertvector(a - __builtin_convertvector(h, f32x2_t), f16x2_t);
+        hw[k] = __builtin_bit_cast(uint32_t, h);
+        lw[k] = __builtin_bit_cast(uint32_t, lo);
+    }
+    Bh[2 * (g * PPO + pc)] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    Bh[2 * (g * PPO + pc) + 1] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+}
+
+// Tiles of 128 targets of one (level, class) group, 4 waves x 2 blocks of 16
+// columns; K in steps of 32 (4 pieces of 8; lane group q takes piece
+// 4 kc + q, which belongs to slot (4 kc + q) / (S/8) of the class).  A step's
+// operator fragments (2 parts x RT row tiles, 1 KB each) are copied into LDS
+// one step ahead through registers; each lane's multipole fragments come
+// from the row its column's V slot names (the zero row when absent), the
+// slot table read a slot ahead and the fragments three steps ahead.
+template <int P>
+__global__ __launch_bounds__(256) void k_ad_m2l_h(AdM2LPlan pl, const uint16_t *__restrict__ Ah, size_t astride,
+                                                  const int2 *__restrict__ cls, const uint4 *__restrict__ Bh,
+                                                  const int *__restrict__ vidx, int64_t box2,
+                                                  const int *__restrict__ tgt, int64_t zero_row,
+                                                  const uint32_t *__restrict__ lmax,
+                                                  const float *__restrict__ oscale, double *__restrict__ Lc,
+                                                  double *__restrict__ partial) {
+    constexpr int P2 = P * P, S = coef_stride(P), PPO = S / 8, RT = m2l_rows(P) / 16, R = RT * 16, NB = 2;
+    constexpr int NPC = kOffsetsPerClass * PPO;  // pieces of a class
+    constexpr int NCH = (NPC + 3) / 4;           // K steps
+    constexpr int NFR = 2 * RT;                  // operator fragments per step
+    constexpr int EPT = (NFR * 64 + 255) / 256;  // of them per thread
+    constexpr int D = 3;                         // multipole steps in flight
+    __shared__ uint4 As[2][NFR * 64];
+    __shared__ int sA[kOffsetsPerClass + 1];
+    const int64_t part = blockIdx.x / pl.units, b = blockIdx.x - part * pl.units;
+    const int kbeg = (int)(part * NCH / pl.nsplit), kend = (int)((part + 1) * NCH / pl.nsplit);
+    int gi = 0;
+    for (int j = 1; j < pl.ngroups; ++j)
+        if (b >= pl.grp[j].unit0) gi = j;
+    const AdM2LGroup gr = pl.grp[gi];
+    const int64_t tile = b - gr.unit0;
+    const int k = gr.cls;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = lane >> 4, col = lane & 15;
+    for (int i = tid; i <= kOffsetsPerClass; i += 256)
+        sA[i] = (i < kOffsetsPerClass ? cls[k * kOffsetsPerClass + i].y : kNumOffsets) * R * S;
+    int64_t tbox[NB];
+    const int *vrow[NB];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+        const int64_t c = tile * 128 + wave * NB * 16 + bb * 16 + col;
+        tbox[bb] = c < gr.count ? tgt[gr.toff + c] : -1;
+        vrow[bb] = tbox[bb] >= 0 ? vidx + (tbox[bb] - box2) * kOffsetsPerClass : nullptr;
+    }
+    __syncthreads();
+    auto load_a = [&](int kc, uint4 (&dst)[EPT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + 256 * i;
+            if (NFR * 64 % 256 == 0 || e < NFR * 64) {
+                const int fr = e >> 6, L = e & 63, sp = fr / RT, r = fr - sp * RT;
+                const int g = 4 * kc + (L >> 4);
+                const int slot = g < NPC ? g / PPO : kOffsetsPerClass, pc = g < NPC ? g - (g / PPO) * PPO : 0;
+                dst[i] = *(const uint4 *)(Ah + sp * astride + sA[slot] + (r * PPO + pc) * 128 + (L & 15) * 8);
+            }
+        }
+    };
+    auto store_a = [&](int buf, const uint4 (&src)[EPT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + 256 * i;
+            if (NFR * 64 % 256 == 0 || e < NFR * 64) As[buf][e] = src[i];
+        }
+    };
+    // this lane's source rows: srow for the slot of the piece being fetched,
+    // snext for the slot after it (loaded a slot ahead when a slot spans at
+    // least one step, else read when needed)
+    int pslot = -2, srow[NB], snext[NB];  // -2: no slot fetched yet
+    auto row_of = [&](int bb, int slot) __attribute__((always_inline)) -> int {
+        return (vrow[bb] && slot < kOffsetsPerClass) ? vrow[bb][slot] : -1;
+    };
+    auto load_b = [&](int kc, uint4 (&hi)[NB], uint4 (&lo)[NB]) __attribute__((always_inline)) {
+        const int g = 4 * kc + q;
+        const int slot = g < NPC ? g / PPO : kOffsetsPerClass, pc = g < NPC ? g - (g / PPO) * PPO : 0;
+        if (slot != pslot) {
+            if constexpr (PPO >= 4) {
+                if (slot == pslot + 1) {
+#pragma unroll
+                    for (int bb = 0; bb < NB; ++bb) {
+                        srow[bb] = snext[bb];
+                        snext[bb] = row_of(bb, slot + 1);
+                    }
+                } else {
+#pragma unroll
+                    for (int bb = 0; bb < NB; ++bb) {
+                        srow[bb] = row_of(bb, slot);
+                        snext[bb] = row_of(bb, slot + 1);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int bb = 0; bb < NB; ++bb) srow[bb] = row_of(bb, slot);
+            }
+            pslot = slot;
+        }
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            const uint4 *src = Bh + 2 * ((srow[bb] >= 0 ? (int64_t)srow[bb] : zero_row) * PPO + pc);
+            hi[bb] = src[0];
+            lo[bb] = src[1];
+        }
+    };
+    f32x4_t acc[RT][NB];
+    f64x4 acc64[RT][NB];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            acc[r][bb] = f32x4_t{0, 0, 0, 0};
+            acc64[r][bb] = f64x4{0, 0, 0, 0};
+        }
+    uint4 ar[EPT], bhi[D][NB], blo[D][NB];
+    load_a(kbeg, ar);
+    store_a(0, ar);
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_b(min(kbeg + d, kend - 1), bhi[d], blo[d]);
+    load_a(min(kbeg + 1, kend - 1), ar);
+    __syncthreads();
+    auto step = [&](int kc, auto dc) __attribute__((always_inline)) {
+        constexpr int d = decltype(dc)::value % D, ph = decltype(dc)::value & 1;
+        const uint4 *as = As[ph];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const f16x8_t ah = __builtin_bit_cast(f16x8_t, as[r * 64 + lane]);
+            const f16x8_t al = __builtin_bit_cast(f16x8_t, as[(RT + r) * 64 + lane]);
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) {
+                const f16x8_t bh = __builtin_bit_cast(f16x8_t, bhi[d][bb]);
+                const f16x8_t bl = __builtin_bit_cast(f16x8_t, blo[d][bb]);
+                acc[r][bb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, acc[r][bb], 0, 0, 0);
+                acc[r][bb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, acc[r][bb], 0, 0, 0);
+                acc[r][bb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, acc[r][bb], 0, 0, 0);
+            }
+        }
+        store_a(ph ^ 1, ar);  // step kc + 1, read by every wave after the barrier below
+        load_a(min(kc + 2, kend - 1), ar);
+        load_b(min(kc + D, kend - 1), bhi[d], blo[d]);
+        __syncthreads();
+    };
+    auto merge = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc64[r][bb][i] += (double)acc[r][bb][i];
+                acc[r][bb] = f32x4_t{0, 0, 0, 0};
+            }
+    };
+    // six steps per pass keep both the LDS parity and the multipole ring
+    // position compile-time constants; merges every 6 steps (192 K terms)
+    int kc = kbeg;
+    for (; kc + 5 < kend; kc += 6) {
+        step(kc, std::integral_constant<int, 0>{});
+        step(kc + 1, std::integral_constant<int, 1>{});
+        step(kc + 2, std::integral_constant<int, 2>{});
+        step(kc + 3, std::integral_constant<int, 3>{});
+        step(kc + 4, std::integral_constant<int, 4>{});
+        step(kc + 5, std::integral_constant<int, 5>{});
+        merge();
+    }
+    // the remaining steps, with the ring positions they would have had
+    if (kc < kend) step(kc, std::integral_constant<int, 0>{});
+    if (kc + 1 < kend) step(kc + 1, std::integral_constant<int, 1>{});
+    if (kc + 2 < kend) step(kc + 2, std::integral_constant<int, 2>{});
+    if (kc + 3 < kend) step(kc + 3, std::integral_constant<int, 3>{});
+    if (kc + 4 < kend) step(kc + 4, std::integral_constant<int, 4>{});
+    merge();
+    // undo the encoding: row r carries the table's row scale and the level's
+    // operand scale (powers of two)
+    const int sh = -level_scale_exp(lmax[gr.lev]);
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * r + 4 * q + i;
+            const double f = row < P2 ? ldexp((double)oscale[row], sh) : 0.0;
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) acc64[r][bb][i] *= f;
+        }
+    if (pl.nsplit == 1) {
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb) {
+            if (tbox[bb] < 0) continue;
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + 4 * q + i;
+                    if (row < P2) Lc[tbox[bb] * S + row] += acc64[r][bb][i];
+                }
+        }
+    } else {  // this part's sums of the tile's 128 columns, summed by k_ad_m2l_sum
+        double *dst = partial + (part * pl.units + b) * 128 * P2;
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * r + 4 * q + i;
+                    if (row < P2) dst[(wave * NB * 16 + bb * 16 + col) * P2 + row] = acc64[r][bb][i];
+                }
+    }
+}
+
 // ---------------------------------------------------------- host helpers
 static inline unsigned ad_blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -1262,6 +1534,38 @@ hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, const double *A, const int2
     switch (P) {
 #define X(PP) \
     case PP: k_ad_m2l<PP><<<nb, 256, 0, st>>>(pl, A, cls, M, vidx, box2, tgt, zero_row, Lc, partial); break;
+        AD_CASES(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    if (pl.nsplit > 1)
+        k_ad_m2l_sum<<<ad_blocks(pl.units * 128 * P * P, 256), 256, 0, st>>>(pl, P * P, coef_stride(P), tgt, partial,
+                                                                             Lc);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_pack_h(int P, int64_t box2, int64_t nbox, const int *lev, const double *M,
+                            const float *rho_inv, uint32_t *lmax, void *Bh, hipStream_t st) {
+    const int64_t nb = nbox - box2;
+    if (nb > 0)
+        k_ad_level_max<<<ad_blocks(nb * P * P, 256), 256, 0, st>>>(P, box2, nb, lev, M, rho_inv, lmax);
+    k_ad_pack_h<<<ad_blocks((nb + 1) * (coef_stride(P) / 8), 256), 256, 0, st>>>(P, box2, nbox, lev, M, rho_inv,
+                                                                                 lmax, (uint4 *)Bh);
+    return hipGetLastError();
+}
+
+hipError_t ad_launch_m2l_h(int P, const AdM2LPlan &pl, const uint16_t *Ah, size_t astride, const int2 *cls,
+                           const void *Bh, const int *vidx, int64_t box2, const int *tgt, int64_t zero_row,
+                           const uint32_t *lmax, const float *oscale, double *Lc, double *partial, hipStream_t st) {
+    if (pl.units == 0) return hipSuccess;
+    if (pl.nsplit < 1 || (pl.nsplit > 1 && !partial)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)(pl.units * pl.nsplit);
+    switch (P) {
+#define X(PP)                                                                                             \
+    case PP:                                                                                              \
+        k_ad_m2l_h<PP><<<nb, 256, 0, st>>>(pl, Ah, astride, cls, (const uint4 *)Bh, vidx, box2, tgt, zero_row, \
+                                           lmax, oscale, Lc, partial);                                     \
+        break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;

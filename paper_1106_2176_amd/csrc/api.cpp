@@ -442,6 +442,10 @@ WorkSizes work_sizes(const fmm_tree *t, bool far) {
         z.farf = sizeof(double4) * (size_t)t->n;
         z.M[0] = z.Lc[0] = sizeof(double) * (size_t)(t->ad->nbox + 1) * S;
         z.m2lpart = ad_m2l_partial_bytes(t->ad->plan, P);
+        if (m2l_half(t->cfg)) {  // the binary16 parts of the multipoles, and the level maxima
+            z.pack[0] = sizeof(float) * (size_t)(t->ad->nbox + 1) * S;
+            z.lmax = sizeof(uint32_t) * kLevelSlots;
+        }
         return z;
     }
     z.farf = sizeof(double4) * (size_t)t->n;
@@ -522,8 +526,8 @@ fmm_status validate_cfg(const fmm_config *c) {
     if (c->m2l_rotation && c->p < 2) return fail(FMM_EINVAL, "the rotation-based M2L needs p >= 2");
     if (c->adaptive && c->max_level > FMM_ADAPTIVE_MAX_LEVEL)
         return fail(FMM_EINVAL, "an adaptive tree needs max_level <= 8");
-    if (c->adaptive && c->precision != FMM_PREC_FP64)
-        return fail(FMM_EUNSUPPORTED, "the adaptive tree is evaluated in the FP64 form only");
+    if (c->adaptive && c->precision == FMM_PREC_MIXED && !c->m2l_fp16)
+        return fail(FMM_EUNSUPPORTED, "the adaptive tree's mixed form uses the binary16 M2L (m2l_fp16 = 1)");
     if (c->adaptive && c->m2l_rotation)
         return fail(FMM_EUNSUPPORTED, "the adaptive tree uses the dense M2L only");
     if (c->profile_stages >> kStages) return fail(FMM_EINVAL, "profile_stages has bits past stage 8");
@@ -921,6 +925,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
             e.toff = at;
             e.count = cnt;
             e.cls = g % 8;
+            e.lev = 2 + g / 8;
             a->plan.units += (cnt + 127) / 128;
         }
         at += cnt;
@@ -946,11 +951,13 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     return FMM_OK;
 }
 
-// Evaluation on an adaptive tree (FP64): gather, P2M at the leaves, M2M up
-// to level 2, P2L over X (which writes every box's locals) and M2L over the V
-// slots (added), L2L down, L2P and M2P over W at the leaves, P2P over U.  The
-// stage events keep the uniform chain's numbering, with P2L in the place of
-// the operand pack (stage 3) and M2P with L2P (stage 6).
+// Evaluation on an adaptive tree: gather, P2M at the leaves, M2M up to level
+// 2, P2L over X (which writes every box's locals) and M2L over the V slots
+// (added), L2L down, L2P and M2P over W at the leaves, P2P over U, all in
+// FP64 except the mixed form's M2L (binary16 parts on the 16-bit matrix
+// cores, its operands packed after P2L).  The stage events keep the uniform
+// chain's numbering, with P2L and the operand pack in the place of the pack
+// (stage 3) and M2P with L2P (stage 6).
 fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do_far, bool do_near,
                         hipStream_t st) {
     const AdTree *a = t->ad;
@@ -971,6 +978,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
         if (!o || !w.farf || !w.M[0] || !w.Lc[0] || w.m2lpart_bytes < ad_m2l_partial_bytes(a->plan, P))
             return fail(FMM_EDEVICE, "internal: no far-field buffers");
         double *M = (double *)w.M[0], *Lc = (double *)w.Lc[0];
+        const bool half = m2l_half(t->cfg);
+        if (half && (!w.pack[0] || !w.lmax)) return fail(FMM_EDEVICE, "internal: no binary16 operand buffers");
         HIPCHK(launch_zero((uint32_t *)(M + (size_t)a->nbox * S), 2 * S, st));  // the zero row
         HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, recs, M, st));
         CHK(rec(t, 2, st));
@@ -979,9 +988,17 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
                                  o->up64, M, st));
         CHK(rec(t, 3, st));
         HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, recs, Lc, st));
+        if (half) {  // the mixed form's operands: level maxima, scaled binary16 parts
+            HIPCHK(launch_zero(w.lmax, kLevelSlots, st));
+            HIPCHK(ad_launch_pack_h(P, a->off[2], a->nbox, lev, M, o->rho_inv, w.lmax, w.pack[0], st));
+        }
         CHK(rec(t, 4, st));
-        HIPCHK(ad_launch_m2l(P, a->plan, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2], bp<int>(a->tgt), a->nbox,
-                             Lc, w.m2lpart, st));
+        if (half)
+            HIPCHK(ad_launch_m2l_h(P, a->plan, o->m2lh, o->bf_part, o->cls, w.pack[0], bp<int>(a->vidx), a->off[2],
+                                   bp<int>(a->tgt), a->nbox, w.lmax, o->oscale, Lc, w.m2lpart, st));
+        else
+            HIPCHK(ad_launch_m2l(P, a->plan, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2], bp<int>(a->tgt),
+                                 a->nbox, Lc, w.m2lpart, st));
         CHK(rec(t, 5, st));
         for (int l = 3; l <= a->depth; ++l)
             HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent), o->down64, Lc,

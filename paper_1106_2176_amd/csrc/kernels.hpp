@@ -137,7 +137,7 @@ struct AdM2LGroup {
     int64_t toff;   // first target of the group in the target list
     int64_t count;  // targets in the group
     int cls;        // child class of the group's targets
-    int pad;
+    int lev;        // level of the group's targets
 };
 constexpr int kAdMaxGroups = 8 * (FMM_MAX_LEVEL - 1);
 struct AdM2LPlan {
@@ -155,6 +155,17 @@ hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *
                          double *M, hipStream_t st);
 hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
                          double *M, hipStream_t st);
+// mixed form: the per-level maxima of |M_c rho_inv[c]| over the boxes of
+// levels >= 2 (lmax, kLevelSlots words, zeroed beforehand), then the scaled
+// multipoles split into binary16 parts Bh [nbox + 1][S/8][hi8, lo8] (rows
+// box2 .. nbox, the last all zero)
+hipError_t ad_launch_pack_h(int P, int64_t box2, int64_t nbox, const int *lev, const double *M,
+                            const float *rho_inv, uint32_t *lmax, void *Bh, hipStream_t st);
+// M2L over the V slots in the binary16 encoding (3 products on the 16-bit
+// matrix cores, FP32 accumulation merged into FP64), added into Lc
+hipError_t ad_launch_m2l_h(int P, const AdM2LPlan &pl, const uint16_t *Ah, size_t astride, const int2 *cls,
+                           const void *Bh, const int *vidx, int64_t box2, const int *tgt, int64_t zero_row,
+                           const uint32_t *lmax, const float *oscale, double *Lc, double *partial, hipStream_t st);
 // adds M2L over the V slots into Lc; with pl.nsplit > 1 through `partial`
 // (ad_m2l_partial_bytes) and a summing kernel, in a fixed order
 hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, const double *A, const int2 *cls, const double *M,

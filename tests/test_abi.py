@@ -60,7 +60,7 @@ def test_build_rejects_bad_config(field, value):
 
 
 @pytest.mark.parametrize("changes,status", [
-    (dict(precision=1), fmm.FMM_EUNSUPPORTED),          # adaptive trees are FP64-form only
+    (dict(precision=1, m2l_fp16=0), fmm.FMM_EUNSUPPORTED),  # the adaptive mixed form is binary16 only
     (dict(m2l_rotation=1), fmm.FMM_EUNSUPPORTED),       # and use the dense M2L
     (dict(max_level=9), fmm.FMM_EINVAL),                # finest sort at level <= 8
 ])

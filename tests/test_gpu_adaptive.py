@@ -1,13 +1,15 @@
-"""GPU parity of the adaptive octree (cfg.adaptive, FP64 form) against the
-oracle's adaptive FMM, through the C ABI.
+"""GPU parity of the adaptive octree (cfg.adaptive) against the oracle's
+adaptive FMM, through the C ABI.
 
   boxes and particle order  bit-exact (levels, coordinates, ranges, parents,
                             leaf flags; the stable finest-level sort)
   U, V, W, X lists          equal as sets per box (their order is free)
   work counts               exact (pairs and evaluations implied by the lists)
-  phi and E                 relative L2 <= 1e-10 against the oracle (same lists
+  phi and E, FP64 form      relative L2 <= 1e-10 against the oracle (same lists
                             and truncation; the two differ by rounding only),
                             near and far parts separately as well
+  phi and E, mixed form     relative L2 <= 1e-6 against the FP64 form on the
+                            same tree (all N) and against the oracle
 The inputs are Gaussian blobs (inputs.clustered), which put leaves on many
 levels, plus uniform and degenerate cases."""
 import ctypes
@@ -202,11 +204,61 @@ def test_noalloc_matches_evaluate():
     np.testing.assert_array_equal(outs[1][1], outs[0][1])
 
 
+@pytest.mark.parametrize("kind,n,leaf,ml,p,seed", [
+    ("clustered", 20_000, 32, 8, 8, 81),
+    ("clustered", 50_000, 64, 7, 10, 82),
+    ("uniform", 30_000, 16, 8, 6, 83),
+    ("clustered", 6_000, 24, 8, 13, 84),
+    ("clustered", 3_000, 8, 6, 16, 85),
+    ("clustered", 8_000, 20, 8, 1, 86),
+])
+def test_mixed_form_vs_fp64_and_oracle(oracle_mod, kind, n, leaf, ml, p, seed):
+    """The mixed form (binary16 M2L, the rest FP64) against the FP64 form on
+    the same tree, all N, within the mixed form's 1e-6 budget, and against
+    the oracle."""
+    pos, q = _input(kind, n, seed)
+    q = q - 0.5
+    ref = oracle_mod.fmm_adaptive(pos, q, p, leaf, ml)
+    print("adaptive mixed", kind, n, leaf, ml, p, seed, flush=True)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        with fmm.Tree(dev(pos), p=p, leaf_max=leaf, max_level=ml, precision=prec, adaptive=True) as t:
+            out[prec] = gpu_eval(t, q)
+            out[prec + "_far"] = gpu_eval(t, q, part="far")
+    (p64, E64), (pm, Em) = out["fp64"], out["mixed"]
+    e_phi, e_E = rel_l2(pm, p64), rel_l2(Em, E64)
+    print("  mixed vs FP64: phi %.2e, E %.2e" % (e_phi, e_E))
+    assert e_phi < 1e-6 and e_E < 1e-6
+    assert rel_l2(pm, ref["phi"]) < 1e-6 and rel_l2(Em, ref["E"]) < 1e-6
+    # the far field alone: the encoding's own error, against the far field's size
+    assert rel_l2(out["mixed_far"][0], out["fp64_far"][0]) < 1e-6
+    assert rel_l2(out["mixed_far"][1], out["fp64_far"][1]) < 1e-6
+
+
+def test_mixed_noalloc_matches_evaluate():
+    pos, q = inputs.clustered(20_000, 62)
+    with fmm.Tree(dev(pos), p=8, leaf_max=32, precision="mixed", adaptive=True) as t:
+        Q = dev(q)
+        outs = []
+        L = fmm.lib()
+        for fn in (L.fmm_evaluate, L.fmm_evaluate_noalloc):
+            phi = torch.full((len(q),), float("nan"), dtype=torch.float64, device="cuda")
+            vec = torch.full((len(q), 3), float("nan"), dtype=torch.float64, device="cuda")
+            rc = fn(t._h, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(phi.data_ptr()),
+                    ctypes.c_void_p(vec.data_ptr()), fmm.VEC_FIELD,
+                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            assert rc == fmm.FMM_OK, L.fmm_last_error_message()
+            torch.cuda.synchronize()
+            outs.append((phi.cpu().numpy(), vec.cpu().numpy()))
+    np.testing.assert_array_equal(outs[1][0], outs[0][0])
+    np.testing.assert_array_equal(outs[1][1], outs[0][1])
+
+
 def test_unsupported_requests():
     pos, q = inputs.clustered(5_000, 71)
     P = dev(pos)
     with pytest.raises(fmm.FMMError) as e:
-        fmm.Tree(P, precision="mixed", adaptive=True)
+        fmm.Tree(P, precision="mixed", m2l_fp16=False, adaptive=True)
     assert e.value.status == fmm.FMM_EUNSUPPORTED
     with fmm.Tree(P, p=4, precision="fp64", adaptive=True) as t:
         Q = dev(q)
