@@ -156,9 +156,11 @@ typedef struct {
                                   neither contains the other.  Every step is
                                   FP64 except, in the mixed form, the M2L (the
                                   binary16 encoding described at m2l_fp16,
-                                  with one operand scale per level).  fmm_backward
-                                  and overlap_near are not available on such a
-                                  tree (FMM_EUNSUPPORTED / ignored); the build
+                                  with one operand scale per level).
+                                  fmm_backward runs the transposed chain over
+                                  the same lists; overlap_near is ignored on
+                                  such a tree (the near field runs after the
+                                  far field); the build
                                   blocks once per tree level and once more at
                                   the end, until a few counts have reached the
                                   host. */

@@ -412,9 +412,11 @@ __device__ inline void ad_centre_diff(int l1, uint32_t c1, int l2, uint32_t c2, 
 
 // P2M at the leaves: mu(g) = sum_j q_j rho(u_j), leaf units; one block of 64
 // per leaf, 16 particles' harmonics at a time in LDS.  Rows are written whole
-// (zero past p^2).
+// (zero past p^2).  adj = 1: the transpose of L2P (the weights' sum times
+// 2^l, the leaf's root-unit factor).
 template <int P>
 __global__ __launch_bounds__(64) void k_ad_p2m(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+                                               const uint8_t *__restrict__ llev, int adj,
                                                const double4 *__restrict__ rec, double *__restrict__ M) {
     constexpr int P2 = P * P, S = coef_stride(P), B = 16, NC = (S + 63) / 64;
     __shared__ double rows[B][P2 + 1];
@@ -443,10 +445,11 @@ __global__ __launch_bounds__(64) void k_ad_p2m(const int *__restrict__ lbox, con
         }
     }
     const int g = lbox[j];
+    const double f = adj ? ldexp(1.0, (int)llev[j]) : 1.0;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         const int c = t + 64 * a;
-        if (c < S) M[(size_t)g * S + c] = c < P2 ? acc[a] : 0.0;
+        if (c < S) M[(size_t)g * S + c] = c < P2 ? acc[a] * f : 0.0;
     }
 }
 
@@ -501,11 +504,13 @@ __global__ __launch_bounds__(256) void k_ad_l2l(int64_t b0, const uint32_t *__re
     }
 }
 
-// L2P at the leaves, outputs in root units (phi * 2^l, E * 4^l)
+// L2P at the leaves, outputs in root units (phi * 2^l, E * 4^l).  adj = 1:
+// the transpose of P2M and its position derivative (phi, E * 2^l).
 template <int P>
 __global__ __launch_bounds__(64) void k_ad_l2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
-                                               const uint8_t *__restrict__ llev, const double4 *__restrict__ rec,
-                                               const double *__restrict__ Lc, double4 *__restrict__ out) {
+                                               const uint8_t *__restrict__ llev, int adj,
+                                               const double4 *__restrict__ rec, const double *__restrict__ Lc,
+                                               double4 *__restrict__ out) {
     constexpr int P2 = P * P, S = coef_stride(P);
     __shared__ double ell[P2];
     __shared__ double4 coef[P2];
@@ -515,7 +520,7 @@ __global__ __launch_bounds__(64) void k_ad_l2p(const int *__restrict__ lbox, con
     __syncthreads();
     for (int c = threadIdx.x; c < P2; c += 64) coef[c] = l2p_coef<double, double4>(ell, P, c);
     __syncthreads();
-    const double s1 = ldexp(1.0, (int)llev[j]), s2 = s1 * s1;
+    const double s1 = ldexp(1.0, (1 - adj) * (int)llev[j]), s2 = ldexp(1.0, (2 - adj) * (int)llev[j]);
     for (uint32_t i = lstart[j] + threadIdx.x; i < lstart[j + 1]; i += 64) {
         __asm__ volatile("" ::: "memory");
         const double4 r = rec[i];
@@ -578,7 +583,7 @@ template <int P>
 __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, const int *__restrict__ ix,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                                const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
-                                               const double4 *__restrict__ rec, double *__restrict__ Lc) {
+                                               int adj, const double4 *__restrict__ rec, double *__restrict__ Lc) {
     constexpr int P2 = P * P, S = coef_stride(P), NC = (P2 + 63) / 64;
     constexpr int B = P <= 8 ? 32 : (P <= 11 ? 16 : 8);  // rows of at most ~17 KB (2 waves per SIMD)
     __shared__ double rows[B][P2 + 1];
@@ -651,10 +656,11 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
             }
         }
     }
+    const double f = adj ? ldexp(1.0, lg) : 1.0;  // adj = 1: the transpose of M2P
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
         const int k = t + 64 * a;
-        if (k < P2) Lc[(size_t)g * S + k] = acc[a];
+        if (k < P2) Lc[(size_t)g * S + k] = acc[a] * f;
     }
 }
 
@@ -664,13 +670,15 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
 // and degree-1 coefficients of the local expansion at the particle are
 //   L_0^0 = sum M_n^m I_n^m,  L_1^l = -sum M_n^m I_{n+1}^{m+l},
 // and phi = L_0^0 / w, grad = (-Re L_1^1, -Im L_1^1, L_1^0) / w^2.
-// Added into out (root units: phi * 2^l_w, E * 4^l_w).  One wave per unit
+// Added into out (root units: phi * 2^l_w, E * 4^l_w; adj = 1, the
+// transpose of P2L and its position derivative: phi, E * 2^l_w).  One wave per unit
 // of up to 64 targets (the P2P units): the targets take T = 2^LT lanes, and
 // the 64 / T lane groups take the boxes of W(g) in turn, each staging its
 // box's multipole in LDS; the groups' sums are joined by shuffles.
 template <int P, int LT>
-__device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int g, int lg, uint32_t cg, uint32_t t0,
-                                            uint32_t nt, uint32_t w0, uint32_t w1, const int *__restrict__ iw,
+__device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int adj, int g, int lg, uint32_t cg,
+                                            uint32_t t0, uint32_t nt, uint32_t w0, uint32_t w1,
+                                            const int *__restrict__ iw,
                                             const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                             const double4 *__restrict__ rec, const double *__restrict__ M,
                                             double4 *__restrict__ out) {
@@ -729,7 +737,7 @@ __device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int 
                 l11i -= mr * ii + mi * ir;
             }
         });
-        const double s1 = ldexp(1.0, lw), s2 = s1 * s1;
+        const double s1 = ldexp(1.0, (1 - adj) * lw), s2 = ldexp(1.0, (2 - adj) * lw);
         phi += l00 * s1;
         ex += l11r * s2;
         ey += l11i * s2;
@@ -756,7 +764,7 @@ __device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int 
 // staged multipoles stay within 32 KB at p = 16
 template <int P>
 __global__ __launch_bounds__(64) void k_ad_m2p(const uint32_t *__restrict__ nunits, const int2 *__restrict__ units,
-                                               const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
+                                               int adj, const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
                                                const uint32_t *__restrict__ ow, const int *__restrict__ iw,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                                const double4 *__restrict__ rec, const double *__restrict__ M,
@@ -774,7 +782,7 @@ __global__ __launch_bounds__(64) void k_ad_m2p(const uint32_t *__restrict__ nuni
     while ((1u << lt) < nt && lt < 6) ++lt;
 #define AD_M2P_CASE(K)                                                                                          \
     case K:                                                                                                     \
-        ad_m2p_unit<P, K>(mus, lane, g, lev[g], code[g], t0, nt, w0, w1, iw, lev, code, rec, M, out);          \
+        ad_m2p_unit<P, K>(mus, lane, adj, g, lev[g], code[g], t0, nt, w0, w1, iw, lev, code, rec, M, out);     \
         break;
     switch (lt) { AD_M2P_CASE(2) AD_M2P_CASE(3) AD_M2P_CASE(4) AD_M2P_CASE(5) AD_M2P_CASE(6) }
 #undef AD_M2P_CASE
@@ -1489,11 +1497,11 @@ hipError_t ad_launch_records(int64_t n, int dtype, const uint32_t *hoff, const i
 
 #define AD_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const double4 *rec,
-                         double *M, hipStream_t st) {
+hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev, int adj,
+                         const double4 *rec, double *M, hipStream_t st) {
     if (nleaf == 0) return hipSuccess;
     switch (P) {
-#define X(PP) case PP: k_ad_p2m<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, rec, M); break;
+#define X(PP) case PP: k_ad_p2m<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, M); break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -1584,10 +1592,10 @@ hipError_t ad_launch_class(int64_t box2, int64_t nb, const int *lev, const uint3
 }
 
 hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
-                         const uint32_t *code, const uint32_t *ps, const uint32_t *pe, const double4 *rec,
+                         const uint32_t *code, const uint32_t *ps, const uint32_t *pe, int adj, const double4 *rec,
                          double *Lc, hipStream_t st) {
     switch (P) {
-#define X(PP) case PP: k_ad_p2l<PP><<<(unsigned)nbox, 64, 0, st>>>(ox, ix, lev, code, ps, pe, rec, Lc); break;
+#define X(PP) case PP: k_ad_p2l<PP><<<(unsigned)nbox, 64, 0, st>>>(ox, ix, lev, code, ps, pe, adj, rec, Lc); break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -1596,9 +1604,9 @@ hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix,
 }
 
 hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
-                         const double4 *rec, const double *Lc, double4 *out, hipStream_t st) {
+                         int adj, const double4 *rec, const double *Lc, double4 *out, hipStream_t st) {
     switch (P) {
-#define X(PP) case PP: k_ad_l2p<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, rec, Lc, out); break;
+#define X(PP) case PP: k_ad_l2p<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, Lc, out); break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -1606,13 +1614,14 @@ hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *
     return hipGetLastError();
 }
 
-hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
-                         const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
+hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, int adj,
+                         const int *lbox, const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
                          const uint32_t *code, const double4 *rec, const double *M, double4 *out, hipStream_t st) {
     switch (P) {
-#define X(PP)                                                                                                      \
-    case PP:                                                                                                       \
-        k_ad_m2p<PP><<<(unsigned)max_units, 64, 0, st>>>(nunits, units, lbox, lstart, ow, iw, lev, code, rec, M, out); \
+#define X(PP)                                                                                                   \
+    case PP:                                                                                                    \
+        k_ad_m2p<PP><<<(unsigned)max_units, 64, 0, st>>>(nunits, units, adj, lbox, lstart, ow, iw, lev, code, rec, \
+                                                         M, out);                                               \
         break;
         AD_CASES(X)
 #undef X

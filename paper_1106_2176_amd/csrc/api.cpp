@@ -958,7 +958,13 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
 // cores, its operands packed after P2L).  The stage events keep the uniform
 // chain's numbering, with P2L and the operand pack in the place of the pack
 // (stage 3) and M2P with L2P (stage 6).
-fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do_far, bool do_near,
+// The adjoint runs the same launches on the weights with the transposed
+// operators: P2M as L2P^T and the upward pass with L2L^T (the M buffer then
+// holds the local adjoints), P2L as M2P^T and M2L^T over the same V slots
+// (V is symmetric) into the L buffer, the downward pass with M2M^T, then
+// L2P and M2P as P2M^T and P2L^T with their position derivatives (X and W
+// are each other's transposes), and P2P on the weights (U is symmetric).
+fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool adjoint, bool do_far, bool do_near,
                         hipStream_t st) {
     const AdTree *a = t->ad;
     const int P = t->cfg.p, S = coef_stride(P);
@@ -981,32 +987,35 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool do
         const bool half = m2l_half(t->cfg);
         if (half && (!w.pack[0] || !w.lmax)) return fail(FMM_EDEVICE, "internal: no binary16 operand buffers");
         HIPCHK(launch_zero((uint32_t *)(M + (size_t)a->nbox * S), 2 * S, st));  // the zero row
-        HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, recs, M, st));
+        const int adj = adjoint ? 1 : 0;
+        const uint8_t *llev = bp<uint8_t>(a->llev);
+        HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, llev, adj, recs, M, st));
         CHK(rec(t, 2, st));
         for (int l = a->depth - 1; l >= 2; --l)
             HIPCHK(ad_launch_m2m(P, a->off[l], a->off[l + 1] - a->off[l], bp<uint8_t>(a->leaf), bp<int>(a->child),
-                                 o->up64, M, st));
+                                 adjoint ? o->aup64 : o->up64, M, st));
         CHK(rec(t, 3, st));
-        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, recs, Lc, st));
+        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, adj, recs, Lc, st));
         if (half) {  // the mixed form's operands: level maxima, scaled binary16 parts
             HIPCHK(launch_zero(w.lmax, kLevelSlots, st));
             HIPCHK(ad_launch_pack_h(P, a->off[2], a->nbox, lev, M, o->rho_inv, w.lmax, w.pack[0], st));
         }
         CHK(rec(t, 4, st));
         if (half)
-            HIPCHK(ad_launch_m2l_h(P, a->plan, o->m2lh, o->bf_part, o->cls, w.pack[0], bp<int>(a->vidx), a->off[2],
-                                   bp<int>(a->tgt), a->nbox, w.lmax, o->oscale, Lc, w.m2lpart, st));
+            HIPCHK(ad_launch_m2l_h(P, a->plan, adjoint ? o->am2lh : o->m2lh, o->bf_part, o->cls, w.pack[0],
+                                   bp<int>(a->vidx), a->off[2], bp<int>(a->tgt), a->nbox, w.lmax,
+                                   adjoint ? o->aoscale : o->oscale, Lc, w.m2lpart, st));
         else
-            HIPCHK(ad_launch_m2l(P, a->plan, o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2], bp<int>(a->tgt),
-                                 a->nbox, Lc, w.m2lpart, st));
+            HIPCHK(ad_launch_m2l(P, a->plan, adjoint ? o->am2l64 : o->m2l64, o->cls, M, bp<int>(a->vidx), a->off[2],
+                                 bp<int>(a->tgt), a->nbox, Lc, w.m2lpart, st));
         CHK(rec(t, 5, st));
         for (int l = 3; l <= a->depth; ++l)
-            HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent), o->down64, Lc,
-                                 st));
+            HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent),
+                                 adjoint ? o->adown64 : o->down64, Lc, st));
         CHK(rec(t, 6, st));
-        HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, bp<uint8_t>(a->llev), recs, Lc, w.farf, st));
-        HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ow,
-                             bp<int>(a->iw), lev, code, recs, M, w.farf, st));
+        HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, llev, adj, recs, Lc, w.farf, st));
+        HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), adj, lbox,
+                             lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, st));
     } else {
         for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
     }
@@ -1084,7 +1093,7 @@ fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int3
     const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
     Work w;
     CHK(noalloc ? work_from_scratch(t, do_far, w) : work_from_tree(t, do_far, st, w));
-    CHK(t->ad ? run_adaptive(t, w, q, do_far, do_near, st) : run_chain(t, w, q, false, do_far, do_near, st));
+    CHK(t->ad ? run_adaptive(t, w, q, false, do_far, do_near, st) : run_chain(t, w, q, false, do_far, do_near, st));
     // the adaptive kernels leave their results in units of the root box
     const double inv_w = (t->ad ? 1.0 : (double)((int64_t)1 << t->L)) / t->cfg.box_size;
     HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, w.nearf,
@@ -1098,8 +1107,8 @@ fmm_status backward_chain(fmm_tree *t, const void *q, const void *w, const void 
                           void *grad_q, void *grad_pos, hipStream_t st) {
     Work wk;
     CHK(work_from_tree(t, true, st, wk));
-    CHK(run_chain(t, wk, w, true, true, true, st));
-    const double inv_w = (double)((int64_t)1 << t->L) / t->cfg.box_size;
+    CHK(t->ad ? run_adaptive(t, wk, w, true, true, true, st) : run_chain(t, wk, w, true, true, true, st));
+    const double inv_w = (t->ad ? 1.0 : (double)((int64_t)1 << t->L)) / t->cfg.box_size;
     HIPCHK(launch_combine_grad(t->n, t->dtype, (const uint32_t *)t->perm.p, wk.nearf,
                                t->L >= 2 ? wk.farf : nullptr, inv_w, q, w, field_fwd, grad_q,
                                grad_pos, st));
@@ -1344,7 +1353,6 @@ fmm_status fmm_backward(fmm_tree *t, const void *q, const void *w, const void *f
                         void *grad_q, void *grad_pos, void *stream) {
     if (!t || !q || !w) return fail(FMM_EINVAL, "tree, q and w are required");
     if (grad_pos && !field_fwd) return fail(FMM_EINVAL, "field_fwd is required for grad_pos");
-    if (t->ad) return fail(FMM_EUNSUPPORTED, "fmm_backward is not available on an adaptive tree");
     if (!grad_q && !grad_pos) return FMM_OK;
     hipStream_t st = (hipStream_t)stream;
     if (!t->cfg.graph) return backward_chain(t, q, w, field_fwd, grad_q, grad_pos, st);

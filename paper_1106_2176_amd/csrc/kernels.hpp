@@ -151,8 +151,11 @@ inline size_t ad_m2l_partial_bytes(const AdM2LPlan &pl, int P) {
     return pl.nsplit > 1 ? sizeof(double) * (size_t)pl.nsplit * pl.units * 128 * P * P : 0;
 }
 // evaluation (FP64, box-id-indexed coefficient rows of stride coef_stride(P))
-hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const double4 *rec,
-                         double *M, hipStream_t st);
+// adj = 1 in the transposed chain: P2M as the transpose of L2P (times 2^l),
+// P2L as that of M2P (times 2^l of the box), L2P and M2P as those of P2M
+// and P2L with their position derivatives (outputs times 2^-l)
+hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev, int adj,
+                         const double4 *rec, double *M, hipStream_t st);
 hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
                          double *M, hipStream_t st);
 // mixed form: the per-level maxima of |M_c rho_inv[c]| over the boxes of
@@ -172,15 +175,15 @@ hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, const double *A, const int2
                          const int *vidx, int64_t box2, const int *tgt, int64_t zero_row, double *Lc, double *partial,
                          hipStream_t st);
 hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
-                         const uint32_t *code, const uint32_t *ps, const uint32_t *pe, const double4 *rec,
+                         const uint32_t *code, const uint32_t *ps, const uint32_t *pe, int adj, const double4 *rec,
                          double *Lc, hipStream_t st);
 hipError_t ad_launch_l2l(int P, int64_t b0, int64_t nb, const uint32_t *code, const int *parent, const double *tab,
                          double *Lc, hipStream_t st);
 hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
-                         const double4 *rec, const double *Lc, double4 *out, hipStream_t st);
+                         int adj, const double4 *rec, const double *Lc, double4 *out, hipStream_t st);
 // one wave per P2P work unit (see ad_launch_units)
-hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
-                         const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
+hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, int adj,
+                         const int *lbox, const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
                          const uint32_t *code, const double4 *rec, const double *M, double4 *out, hipStream_t st);
 // P2P work units of up to 64 targets: pass 0 counts per leaf into cnt,
 // pass 1 fills units (leaf, first target) from uoff, the scan of the counts

@@ -262,10 +262,6 @@ def test_unsupported_requests():
     assert e.value.status == fmm.FMM_EUNSUPPORTED
     with fmm.Tree(P, p=4, precision="fp64", adaptive=True) as t:
         Q = dev(q)
-        _, E = t.evaluate(Q)
-        with pytest.raises(fmm.FMMError) as e:
-            t.backward(Q, Q, E)
-        assert e.value.status == fmm.FMM_EUNSUPPORTED
         # a rebuild keeps the tree kind
         cfg = fmm.make_config(p=4, precision="fp64")
         rc = fmm.lib().fmm_build_tree(ctypes.byref(cfg), len(q), fmm.FMM_F64, ctypes.c_void_p(P.data_ptr()),
@@ -296,3 +292,68 @@ def test_million_blobs_sampled_against_the_direct_sum(oracle_mod):
     assert info["levels"] == a["max_level"]
     assert rel_l2(phi[t_idx], phi_d) < 1e-5
     assert rel_l2(E[t_idx], E_d) < 2e-4
+
+
+@pytest.mark.parametrize("kind,n,leaf,ml,p,seed", [
+    ("clustered", 20_000, 32, 8, 8, 91),
+    ("uniform", 20_000, 16, 8, 5, 92),
+    ("clustered", 4_000, 16, 6, 12, 93),
+])
+def test_adjoint_fp64_matches_the_oracle(oracle_mod, kind, n, leaf, ml, p, seed):
+    """Gradient of Loss = sum w phi on the adaptive tree (FP64 form).  The
+    FMM operator A (q -> phi) is symmetric for fixed leaf assignments (V and
+    U are symmetric, X and W are each other's transposes, and each
+    translation of one direction is the transpose of the other's), so
+    dL/dq = A w is the oracle's potential for the charges w, and
+    dL/dx = -(w E_q + q E_w) with the oracle's fields for q and for w."""
+    pos, q = _input(kind, n, seed)
+    q = q - 0.5
+    w = inputs.weights(n, seed)
+    rq = oracle_mod.fmm_adaptive(pos, q, p, leaf, ml)
+    rw = oracle_mod.fmm_adaptive(pos, w, p, leaf, ml)
+    print("adaptive adjoint", kind, n, leaf, ml, p, seed, flush=True)
+    with fmm.Tree(dev(pos), p=p, leaf_max=leaf, max_level=ml, precision="fp64", adaptive=True) as t:
+        Q, W = dev(q), dev(w)
+        _, E = t.evaluate(Q)
+        gq, gx = t.backward(Q, W, E)
+        torch.cuda.synchronize()
+    gq, gx = gq.cpu().numpy(), gx.cpu().numpy()
+    want_x = -(w[:, None] * rq["E"] + q[:, None] * rw["E"])
+    print("  dL/dq %.2e, dL/dx %.2e" % (rel_l2(gq, rw["phi"]), rel_l2(gx, want_x)))
+    assert rel_l2(gq, rw["phi"]) < TOL
+    assert rel_l2(gx, want_x) < TOL
+
+
+def test_adjoint_mixed_vs_fp64():
+    """The mixed form's gradient against the FP64 form's on the same tree,
+    with weights U[0,1) (no cancellation, so the 1e-6 budget applies as is)."""
+    pos, q = inputs.clustered(30_000, 95)
+    w = np.random.default_rng(96).random(len(q))
+    out = {}
+    for prec in ("fp64", "mixed"):
+        with fmm.Tree(dev(pos), p=8, leaf_max=32, precision=prec, adaptive=True) as t:
+            Q, W = dev(q), dev(w)
+            _, E = t.evaluate(Q)
+            gq, gx = t.backward(Q, W, E)
+            torch.cuda.synchronize()
+            out[prec] = (gq.cpu().numpy(), gx.cpu().numpy())
+    e_q = rel_l2(out["mixed"][0], out["fp64"][0])
+    e_x = rel_l2(out["mixed"][1], out["fp64"][1])
+    print("adaptive adjoint mixed vs FP64: dL/dq %.2e, dL/dx %.2e" % (e_q, e_x))
+    assert e_q < 1e-6 and e_x < 1e-6
+
+
+def test_adjoint_graph_replay_matches_eager():
+    pos, q = inputs.clustered(10_000, 97)
+    w = inputs.weights(len(q), 97)
+    with fmm.Tree(dev(pos), p=6, leaf_max=32, precision="fp64", adaptive=True) as eager, \
+            fmm.Tree(dev(pos), p=6, leaf_max=32, precision="fp64", adaptive=True, graph=True) as g:
+        Q, W = dev(q), dev(w)
+        _, E = eager.evaluate(Q)
+        gq_e, gx_e = eager.backward(Q, W, E)
+        gq = torch.empty_like(Q)
+        gx = torch.empty(len(q), 3, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            g.backward(Q, W, E, out_q=gq, out_pos=gx)
+            torch.cuda.synchronize()
+            assert torch.equal(gq, gq_e) and torch.equal(gx, gx_e)
