@@ -158,9 +158,7 @@ typedef struct {
                                   binary16 encoding described at m2l_fp16,
                                   with one operand scale per level).
                                   fmm_backward runs the transposed chain over
-                                  the same lists; overlap_near is ignored on
-                                  such a tree (the near field runs after the
-                                  far field); the build
+                                  the same lists; the build
                                   blocks once per tree level and once more at
                                   the end, until a few counts have reached the
                                   host. */

@@ -979,8 +979,31 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
     const uint32_t *ou = bp<uint32_t>(a->offs), *ow = ou + a->nbox + 1, *ox = ow + a->nbox + 1;
     CHK(rec(t, 0, st));
     HIPCHK(launch_gather_q(t->n, t->dtype, true, bp<uint32_t>(t->perm), charges, recs, st));
+    // the near field on the library's side stream beside the far field
+    // (cfg.overlap_near), as in the uniform chain: P2P reads only the records
+    // and writes its own buffer
+    const bool far = do_far && a->depth >= 2;
+    const bool side = do_near && far && t->cfg.overlap_near && !t->quiet;
+    t->p2p_side[t->cur] = side;
+    auto p2p = [&](hipStream_t s2) -> hipError_t {
+        return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
+                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, s2);
+    };
+    if (side) {
+        if (!t->side) {
+            HIPCHK(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(t->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
+        CHK(rec(t, kStages + 1, t->side));
+        HIPCHK(p2p(t->side));
+        CHK(rec(t, kStages + 2, t->side));
+        HIPCHK(hipEventRecord(t->ev_join, t->side));
+    }
     CHK(rec(t, 1, st));
-    if (do_far && a->depth >= 2) {
+    if (far) {
         if (!o || !w.farf || !w.M[0] || !w.Lc[0] || w.m2lpart_bytes < ad_m2l_partial_bytes(a->plan, P))
             return fail(FMM_EDEVICE, "internal: no far-field buffers");
         double *M = (double *)w.M[0], *Lc = (double *)w.Lc[0];
@@ -1020,9 +1043,10 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
         for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
     }
     CHK(rec(t, 7, st));
-    if (do_near)
-        HIPCHK(ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
-                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, st));
+    if (side)
+        HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
+    else if (do_near)
+        HIPCHK(p2p(st));
     else
         HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
     CHK(rec(t, 8, st));

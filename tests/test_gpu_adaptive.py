@@ -357,3 +357,34 @@ def test_adjoint_graph_replay_matches_eager():
             g.backward(Q, W, E, out_q=gq, out_pos=gx)
             torch.cuda.synchronize()
             assert torch.equal(gq, gq_e) and torch.equal(gx, gx_e)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_concurrent_near_field_is_identical(precision):
+    """The near field on the library's side stream (overlap_near) gives the
+    same bits as the serial chain, forward and adjoint, on repeated calls and
+    under graph replay."""
+    pos, q = inputs.clustered(15_000, 98)
+    w = inputs.weights(len(q), 98)
+    res = {}
+    for name, kw in (("serial", {}), ("side", {"overlap_near": True}),
+                     ("side_graph", {"overlap_near": True, "graph": True})):
+        with fmm.Tree(dev(pos), p=6, leaf_max=32, precision=precision, adaptive=True, **kw) as t:
+            Q, W = dev(q), dev(w)
+            phi = torch.empty_like(Q)
+            E = torch.empty(len(q), 3, dtype=torch.float64, device="cuda")
+            gq = torch.empty_like(Q)
+            gx = torch.empty_like(E)
+            outs = []
+            for _ in range(3):
+                t.evaluate(Q, phi=phi, out_vec=E)
+                t.backward(Q, W, E, out_q=gq, out_pos=gx)
+                torch.cuda.synchronize()
+                outs.append([x.cpu().numpy().copy() for x in (phi, E, gq, gx)])
+            for o in outs[1:]:
+                for a, b in zip(o, outs[0]):
+                    np.testing.assert_array_equal(a, b)
+            res[name] = outs[0]
+    for name in ("side", "side_graph"):
+        for a, b in zip(res[name], res["serial"]):
+            np.testing.assert_array_equal(a, b)
