@@ -1,5 +1,5 @@
 // adaptive.hip -- the adaptive octree on the GPU (the adaptive construction
-// that Sec. 5, future directions, names next to the uniform one), FP64 form.
+// that Sec. 5, future directions, names next to the uniform one).
 //
 // Tree.  Particles are counting-sorted by their Morton key at the finest
 // level Lf (stable, ties in input order), so every box of every level is one
@@ -8,22 +8,26 @@
 // appended to the next level in Morton order; the rest are leaves.  Box ids
 // are global (levels concatenated, breadth first), box 0 is the root.
 //
-// Lists, for box b (colleagues: the adjacent boxes of b's own level; two boxes
-// are adjacent when their closed cubes touch and neither contains the other):
+// Lists, for box b (colleagues: the boxes of b's own level at offsets -1..1;
+// two boxes are adjacent when their closed cubes touch and neither contains
+// the other):
 //   U(b), b a leaf: b and every leaf adjacent to b                    (P2P)
 //   V(b): the children of the colleagues of b's parent not adjacent to b
 //         (M2L; the 189 offsets of b's child class, absent sources empty)
 //   W(b), b a leaf: descendants of b's colleagues not adjacent to b whose
 //         parent is                                                   (M2P)
 //   X(b): the leaves c with b in W(c)                                 (P2L)
-// Each list is built by one thread per box walking the tree in a fixed
-// order, so the lists, and the sums over them, are the same on every run.
+// U, W and X are built by one thread per (box, colleague direction) walking
+// the tree in a fixed order, so the lists, and the sums over them, are the
+// same on every run.
 //
 // Coefficients live in box-id-indexed arrays [nbox + 1][S] (FP64); row nbox
 // is all zero (the source of an absent M2L slot).  Multipoles are in units of
 // their own box (mu = sum q rho(u)), locals ell with phi = (1/w) ell . rho(u),
 // as in the uniform tree, so the same translation tables serve.  Potentials
-// and fields leave the kernels in root units (phi * size, E * size^2).
+// and fields leave the kernels in root units (phi * size, E * size^2).  Every
+// kernel works in FP64 except the mixed form's M2L (binary16 parts on the
+// 16-bit matrix cores).
 #include <algorithm>
 
 #include "harmonics.hpp"

@@ -351,12 +351,12 @@ struct AdTree {
     AdM2LPlan plan{};
     uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
     Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
-        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, counts, ucnt, uoff, units, s27;
+        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, ucnt, uoff, units, s27;
     int64_t max_units = 0;  // bound of the P2P work units (their count stays on the device)
     std::vector<Buf *> bufs() {
         return {&code, &ps, &pe, &parent, &child, &leaf, &cmask, &nchild, &coff, &lev, &col, &vidx, &cnts,
                 &offs, &iu, &iw, &ix, &is_head, &head, &hoff, &lbox, &lstart, &llev, &tgt, &ccnt, &goffd,
-                &offd, &counts, &ucnt, &uoff, &units, &s27};
+                &offd, &ucnt, &uoff, &units, &s27};
     }
 };
 
