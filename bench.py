@@ -277,7 +277,7 @@ def adaptive_rooflines(p, res):
     return (m2l, p2p) if res["dom"] == "M2L" else (p2p, m2l)
 
 
-def adaptive_record(fmm, oracle, inputs, steps, warmup, sync, dev):
+def adaptive_record(fmm, oracle, inputs, steps, warmup, sync, dev, overlap=True):
     import torch
     a = ADAPTIVE
     n = a["n"]
@@ -305,9 +305,11 @@ def adaptive_record(fmm, oracle, inputs, steps, warmup, sync, dev):
     # the mixed form: the M2L in two binary16 parts (3 MFMA products), the rest FP64
     mix = measure(fmm, wl, P, Q, "mixed", steps, warmup, sync, adaptive=True, max_level=a["max_level"])
     log("adaptive tree: mixed form measured")
-    ov = measure(fmm, wl, P, Q, "mixed", steps, warmup, sync, adaptive=True, max_level=a["max_level"],
-                 overlap_near=True)
-    log("adaptive tree: mixed form with the concurrent near field measured")
+    ov = None
+    if overlap:
+        ov = measure(fmm, wl, P, Q, "mixed", steps, warmup, sync, adaptive=True, max_level=a["max_level"],
+                     overlap_near=True)
+        log("adaptive tree: mixed form with the concurrent near field measured")
     m2l_ms = mix["dom_ms"] if mix["dom"] == "M2L" else mix["stages_ms"]["M2L"]
     m2l_tf = 2.0 * a["p"] ** 4 * info["m2l_pairs"] / (m2l_ms * 1e-3) / 1e12
     out["mixed"] = {
@@ -316,7 +318,7 @@ def adaptive_record(fmm, oracle, inputs, steps, warmup, sync, dev):
         "roofline_m2l": {"kernel": "k_ad_m2l_h<%d>" % a["p"], "bound": "mfma", "achieved": m2l_tf,
                          "peak": PEAK_16BIT_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": m2l_tf / PEAK_16BIT_MFMA_TFLOPS,
                          "traffic": None, "ms": m2l_ms, "mfma_products_per_term": 3},
-        "overlap_ms_per_step": ov["sec"] * 1e3,
+        "overlap_ms_per_step": ov["sec"] * 1e3 if ov else None,
         "rel_l2_vs_direct": sampled_errors(mix, q_np, t_idx, phi_d, E_d),
         "rel_l2_vs_fp64_all": {
             "phi": float(np.linalg.norm((mix["phi"] - res["phi"]).cpu().numpy()) /
@@ -497,7 +499,8 @@ def main():
 
     adaptive = None
     if not args.no_adaptive:
-        adaptive = adaptive_record(fmm, oracle, inputs, max(5, args.steps // 2), 2, sync, dev)
+        adaptive = adaptive_record(fmm, oracle, inputs, max(5, args.steps // 2), 2, sync, dev,
+                                   overlap=not args.no_overlap)
         log("adaptive tree measured")
 
     cpu = None
