@@ -817,9 +817,9 @@ __device__ __forceinline__ void ad_pair(double xi, double yi, double zi, const d
 // P2P over U at the leaves (FP64), one wave per unit of up to 64 targets of
 // one leaf (a leaf of more than 64 particles gives several units, so that
 // the work of the fullest leaves spreads over several waves).  The unit's
-// targets take T = 2^LT lanes, two per lane (T the power of two >= half its
-// count), and the 64 / T lane groups split every source tile, their sums
-// joined by shuffles at the end.  The sources of U(g) are taken as one sequence, up to
+// targets take T lanes, two per lane (T = half the count, rounded up), and
+// the 64 / T lane groups split every source tile, their sums joined through
+// LDS in group order at the end.  The sources of U(g) are taken as one sequence, up to
 // 64 list entries at a time: each lane holds one entry's particle range and
 // its frame change (c_c - c_g)/w_g + u 2^(l_g - l_c) (exact scaling, one
 // rounding), a wave scan of the counts gives the entries' offsets, and the
@@ -835,17 +835,18 @@ struct AdP2PShared {
     uint32_t off[65];     // exclusive offsets of the entries, total last
 };
 
-template <int LT>
 __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, int lg, uint32_t cg, uint32_t t0,
                                             uint32_t nt, uint32_t u0, uint32_t u1, const int *__restrict__ iu,
                                             const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                             const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
                                             const double4 *__restrict__ rec, double4 *__restrict__ out) {
-    constexpr int T = 1 << LT, G = 64 >> LT;
-    const int slot = lane & (T - 1), grp = lane >> LT;
+    // T lanes hold the unit's targets, two per lane (slot and slot + T);
+    // G = 64 / T groups of them split every source tile; lanes past G T idle
+    const int T = (int)((nt + 1) / 2), G = 64 / T;
+    const int grp = lane / T, slot = lane - grp * T;
+    const bool act = grp < G;
     const double s1 = ldexp(1.0, lg), s2 = s1 * s1;
-    // two targets per lane, slot and slot + T: each source read feeds both
-    const bool live0 = (uint32_t)slot < nt, live1 = (uint32_t)(slot + T) < nt;
+    const bool live0 = act && (uint32_t)slot < nt, live1 = act && (uint32_t)(slot + T) < nt;
     const double4 r0 = live0 ? rec[t0 + slot] : make_double4(0.0, 0.0, 0.0, 0.0);
     const double4 r1 = live1 ? rec[t0 + slot + T] : make_double4(0.0, 0.0, 0.0, 0.0);
     double phi0 = 0.0, ex0 = 0.0, ey0 = 0.0, ez0 = 0.0, phi1 = 0.0, ex1 = 0.0, ey1 = 0.0, ez1 = 0.0;
@@ -889,28 +890,30 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
             wave_sync();  // the previous tile has been read
             sh.tile[lane] = src;
             wave_sync();
-#pragma unroll
-            for (int k = 0; k < 64; k += G) {
-                const double4 sk = sh.tile[k + grp];
-                ad_pair<true>(r0.x, r0.y, r0.z, sk, phi0, ex0, ey0, ez0);
-                ad_pair<true>(r1.x, r1.y, r1.z, sk, phi1, ex1, ey1, ez1);
+            if (act) {
+#pragma unroll 4
+                for (int k = grp; k < 64; k += G) {
+                    const double4 sk = sh.tile[k];
+                    ad_pair<true>(r0.x, r0.y, r0.z, sk, phi0, ex0, ey0, ez0);
+                    ad_pair<true>(r1.x, r1.y, r1.z, sk, phi1, ex1, ey1, ez1);
+                }
             }
         }
     }
-#pragma unroll
-    for (int d = 32; d >= T; d >>= 1) {
-        phi0 += __shfl_xor(phi0, d);
-        ex0 += __shfl_xor(ex0, d);
-        ey0 += __shfl_xor(ey0, d);
-        ez0 += __shfl_xor(ez0, d);
-        phi1 += __shfl_xor(phi1, d);
-        ex1 += __shfl_xor(ex1, d);
-        ey1 += __shfl_xor(ey1, d);
-        ez1 += __shfl_xor(ez1, d);
-    }
+    // the groups' sums in group order, through LDS (tile and frame are free)
+    wave_sync();
+    sh.tile[lane] = make_double4(phi0, ex0, ey0, ez0);
+    sh.frame[lane] = make_double4(phi1, ex1, ey1, ez1);
+    wave_sync();
     if (grp == 0) {
-        if (live0) out[t0 + slot] = make_double4(phi0 * s1, ex0 * s2, ey0 * s2, ez0 * s2);
-        if (live1) out[t0 + slot + T] = make_double4(phi1 * s1, ex1 * s2, ey1 * s2, ez1 * s2);
+        double4 a = sh.tile[slot], c = sh.frame[slot];
+        for (int k = 1; k < G; ++k) {
+            const double4 x = sh.tile[k * T + slot], y = sh.frame[k * T + slot];
+            a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
+            c.x += y.x; c.y += y.y; c.z += y.z; c.w += y.w;
+        }
+        if (live0) out[t0 + slot] = make_double4(a.x * s1, a.y * s2, a.z * s2, a.w * s2);
+        if (live1) out[t0 + slot + T] = make_double4(c.x * s1, c.y * s2, c.z * s2, c.w * s2);
     }
 }
 
@@ -927,17 +930,7 @@ __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
     const int j = un.x;
     const int g = lbox[j];
     const uint32_t t0 = lstart[j] + (uint32_t)un.y, nt = min(64u, lstart[j + 1] - t0);
-    int lt = 0;  // log2 T, T >= half the unit's targets
-    while (2u * (1u << lt) < nt && lt < 5) ++lt;
-#define AD_P2P_CASE(K)                                                                                       \
-    case K:                                                                                                  \
-        ad_p2p_unit<K>(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, \
-                       rec, out);                                                                            \
-        break;
-    switch (lt) {
-        AD_P2P_CASE(0) AD_P2P_CASE(1) AD_P2P_CASE(2) AD_P2P_CASE(3) AD_P2P_CASE(4) AD_P2P_CASE(5)
-    }
-#undef AD_P2P_CASE
+    ad_p2p_unit(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, rec, out);
 }
 
 // Gathered M2L (FP64 MFMA), added to the locals: the targets of each (level,
