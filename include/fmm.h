@@ -138,10 +138,12 @@ typedef struct {
                                   construction Sec. 5 names beside the uniform
                                   one.  A box is split while it holds more than
                                   leaf_max particles and its level is below
-                                  max_level, which is at most
-                                  FMM_ADAPTIVE_MAX_LEVEL (FMM_EINVAL above);
-                                  empty children are dropped, so leaves sit at
-                                  many levels.  The interactions follow the
+                                  max_level; empty children are dropped, so
+                                  leaves sit at many levels.  The build sorts
+                                  the particles into the 8^max_level boxes of
+                                  the finest level first: 8 bytes of workspace
+                                  per box (128 MiB at level 8, 8 GiB at level
+                                  10) and a pass over them per build.  The interactions follow the
                                   U/V/W/X lists of the adaptive FMM: U(b), b a
                                   leaf: b and the leaves touching it (P2P); V(b):
                                   the children of the colleagues of b's parent
@@ -165,8 +167,6 @@ typedef struct {
     int32_t reserved[1];       /* zero */
 } fmm_config;
 
-/* Deepest level of an adaptive tree (the finest Morton sort has 8^8 bins). */
-#define FMM_ADAPTIVE_MAX_LEVEL 8
 
 /* Fill `cfg` with defaults: p = 8, leaf_max = 64, max_level = 10, mixed
  * precision with the binary16 M2L encoding (m2l_fp16 = 1; bf16_splits = 3

@@ -23,6 +23,8 @@ FMM_F32, FMM_F64 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 VEC_NONE, VEC_FIELD, VEC_FORCE = 0, 1, 2
 PART_NEAR_ONLY, PART_FAR_ONLY = 4, 8
+# default depth cap of the adaptive tree (its build sorts into 8^max_level
+# finest-level boxes; deeper caps, up to 10, cost memory and time)
 ADAPTIVE_MAX_LEVEL = 8
 STAGES = ("gather", "P2M", "M2M", "pack", "M2L", "L2L", "L2P", "P2P", "combine")
 
@@ -168,8 +170,8 @@ def make_config(p=8, leaf_max=64, precision="mixed", max_level=None, bf16_splits
     m2l_fp16: None (the library's default), True (the mixed M2L in two
     binary16 parts) or False (bf16_splits bf16 parts).  m2l_rotation: the
     FP64 form's M2L by rotation (O(p^3) per pair).  adaptive: the adaptive
-    octree with U/V/W/X lists (FP64 form); max_level None selects 10 for
-    the uniform tree and ADAPTIVE_MAX_LEVEL for the adaptive one."""
+    octree with U/V/W/X lists; max_level None selects 10 for the uniform
+    tree and ADAPTIVE_MAX_LEVEL for the adaptive one."""
     c = Config()
     lib().fmm_config_default(ctypes.byref(c))
     c.p = int(p)

@@ -341,7 +341,7 @@ struct GraphSlot {
 // concatenated breadth first), the U/W/X lists in CSR form, the V lists as
 // 189 slots per box of level >= 2, the leaves in particle order, and host
 // copies of the level offsets and of the M2L target groups.
-constexpr int kAdHostWords = 64;
+constexpr int kAdHostWords = 128;  // 4 totals + 8 groups per level 2..10
 struct AdTree {
     int depth = 0;
     int64_t nbox = 0, nleaf = 0, nvbox = 0;  // nvbox: boxes of levels >= 2
@@ -524,8 +524,6 @@ fmm_status validate_cfg(const fmm_config *c) {
     if (c->m2l_rotation && c->precision != FMM_PREC_FP64)
         return fail(FMM_EINVAL, "the rotation-based M2L is an option of the FP64 form");
     if (c->m2l_rotation && c->p < 2) return fail(FMM_EINVAL, "the rotation-based M2L needs p >= 2");
-    if (c->adaptive && c->max_level > FMM_ADAPTIVE_MAX_LEVEL)
-        return fail(FMM_EINVAL, "an adaptive tree needs max_level <= 8");
     if (c->adaptive && c->precision == FMM_PREC_MIXED && !c->m2l_fp16)
         return fail(FMM_EUNSUPPORTED, "the adaptive tree's mixed form uses the binary16 M2L (m2l_fp16 = 1)");
     if (c->adaptive && c->m2l_rotation)

@@ -62,7 +62,7 @@ def test_build_rejects_bad_config(field, value):
 @pytest.mark.parametrize("changes,status", [
     (dict(precision=1, m2l_fp16=0), fmm.FMM_EUNSUPPORTED),  # the adaptive mixed form is binary16 only
     (dict(m2l_rotation=1), fmm.FMM_EUNSUPPORTED),       # and use the dense M2L
-    (dict(max_level=9), fmm.FMM_EINVAL),                # finest sort at level <= 8
+    (dict(max_level=11), fmm.FMM_EINVAL),               # keys have 30 bits
 ])
 def test_adaptive_config_checks(changes, status):
     cfg = fmm.make_config(precision="fp64", adaptive=True)

@@ -388,3 +388,27 @@ def test_concurrent_near_field_is_identical(precision):
     for name in ("side", "side_graph"):
         for a, b in zip(res[name], res["serial"]):
             np.testing.assert_array_equal(a, b)
+
+
+def test_deep_tree_to_level_10(oracle_mod):
+    """A blob narrower than a level-8 box: the tree refines to level 10 (the
+    finest sort has 8^10 bins); boxes, lists and the FMM against the oracle."""
+    pos, q = inputs.clustered(6_000, 99)
+    c = pos[:2_500].mean(axis=0)
+    pos[:2_500] = c + (pos[:2_500] - c) * 0.004  # a blob of width ~1e-4
+    q = q - 0.5
+    ref_t = oracle_mod.adaptive_tree(pos, 16, 10)
+    ref = oracle_mod.fmm_adaptive(pos, q, 6, 16, 10)
+    assert ref_t["depth"] == 10
+    out = {}
+    for prec in ("fp64", "mixed"):
+        with fmm.Tree(dev(pos), p=6, leaf_max=16, max_level=10, precision=prec, adaptive=True) as t:
+            if prec == "fp64":
+                got = t.export_adaptive()
+                np.testing.assert_array_equal(got["boxes"], ref_t["boxes"])
+                for name in "UVWX":
+                    for g, r in zip(_sets(got[name]), _sets(ref_t[name])):
+                        np.testing.assert_array_equal(g, r)
+            out[prec] = gpu_eval(t, q)
+    assert rel_l2(out["fp64"][0], ref["phi"]) < TOL and rel_l2(out["fp64"][1], ref["E"]) < TOL
+    assert rel_l2(out["mixed"][0], out["fp64"][0]) < 1e-6 and rel_l2(out["mixed"][1], out["fp64"][1]) < 1e-6
