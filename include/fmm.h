@@ -206,9 +206,9 @@ typedef struct {
  *          calls on the tree do not read `pos`.
  *   out    receives the tree.  If *out is a tree previously built by this
  *          library, it is rebuilt in place and its memory reused when large
- *          enough; its p, precision, bf16_splits (mixed form), dtype and
- *          allocator callbacks (alloc, free, alloc_ctx) must equal the ones it
- *          was created with, else the call returns FMM_EINVAL before any
+ *          enough; its p, precision, M2L encoding (bf16_splits, m2l_fp16;
+ *          mixed form), tree kind (adaptive), dtype and allocator callbacks
+ *          (alloc, free, alloc_ctx) must equal the ones it was created with, else the call returns FMM_EINVAL before any
  *          allocation or launch and leaves the tree as it was.  Otherwise *out
  *          must be NULL and a new tree is created.  The translation tables of
  *          p (made once per device and p, held until the process ends) are
@@ -217,7 +217,9 @@ typedef struct {
  * predicted level, level selection (one host wait; a finer level is tried
  * when the predicted one's fullest leaf exceeds leaf_max), exclusive scan of
  * leaf counts, stable counting sort (ties keep input order) and a gather of
- * leaf-relative coordinates.
+ * leaf-relative coordinates.  An adaptive tree (cfg.adaptive) sorts at
+ * max_level, then builds its boxes level by level and its lists; it waits
+ * for the host once per level and once more at the end.
  * Errors: FMM_EINVAL, FMM_EDOMAIN (detected at the synchronisation; a
  * coordinate equal to lo + size is clamped into the last box), FMM_ENOMEM
  * (the allocator callback returned NULL, or hipMallocAsync failed),
@@ -303,8 +305,8 @@ fmm_status fmm_backward(fmm_tree *tree, const void *q, const void *w, const void
                         void *grad_q, void *grad_pos, void *stream);
 
 /* Sizes and work counts of a built tree (host struct, filled synchronously;
- * pair counts are computed on the host from the leaf counts, which the
- * library copies back at the end of fmm_build_tree). */
+ * a small kernel counts the pairs, and on a uniform tree the M2L pairs are
+ * counted on the host). */
 fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
 
 /* Stage timings (milliseconds) on a tree built with cfg.profile != 0: HIP
@@ -315,8 +317,8 @@ fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
  * Stages, in order:
  *   0 gather   1 P2M   2 M2M   3 pack (M2L operand)   4 M2L   5 L2L
  *   6 L2P      7 P2P   8 combine
- * On an adaptive tree stage 3 is P2L (the X lists) and stage 6 holds L2P
- * and M2P (the W lists).
+ * On an adaptive tree stage 3 is P2L (the X lists, and in the mixed form
+ * the M2L operand pack) and stage 6 holds L2P and M2P (the W lists).
  * `ms` receives min(n_stages, 9) values; stages outside cfg.profile_stages
  * (when it is nonzero) receive NaN.  FMM_EINVAL if profiling is off or no
  * call was recorded. */
@@ -327,8 +329,9 @@ fmm_status fmm_stage_times(const fmm_tree *tree, double *ms, int32_t n_stages);
 fmm_status fmm_stage_times_reset(fmm_tree *tree);
 
 /* Copy the tree's sorting results to host memory (any pointer may be NULL):
- * perm[n] (sorted position -> input index, uint32), leaf_start[8^L + 1]
- * (uint32, Morton leaf order).  Synchronous. */
+ * perm[n] (sorted position -> input index, uint32), leaf_start[n_leaves + 1]
+ * (uint32; the uniform tree's 8^L leaves in Morton order, an adaptive tree's
+ * leaves in particle order).  Synchronous. */
 fmm_status fmm_tree_export(const fmm_tree *tree, uint32_t *perm, uint32_t *leaf_start);
 
 /* The boxes and interaction lists of an adaptive tree (cfg.adaptive), copied
