@@ -319,6 +319,9 @@ fmm_status fmm_tree_info(const fmm_tree *tree, fmm_tree_info_t *info);
  *   6 L2P      7 P2P   8 combine
  * On an adaptive tree stage 3 is P2L (the X lists, and in the mixed form
  * the M2L operand pack) and stage 6 holds L2P and M2P (the W lists).
+ * A uniform tree's forward evaluation ends its last kernel with the combine
+ * (P2P's, or L2P's with overlap_near), so its stage 8 is only the event
+ * markers; the adaptive tree and fmm_backward run a combine kernel there.
  * `ms` receives min(n_stages, 9) values; stages outside cfg.profile_stages
  * (when it is nonzero) receive NaN.  FMM_EINVAL if profiling is off or no
  * call was recorded. */

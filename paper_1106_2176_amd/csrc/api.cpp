@@ -378,6 +378,7 @@ struct fmm_tree {
     hipEvent_t ev_counters = nullptr;  // after the copy of the build counters
     Buf M[FMM_MAX_LEVEL + 1], Lc[FMM_MAX_LEVEL + 1], pack[FMM_MAX_LEVEL + 1];
     unsigned int *host_counters = nullptr;  // pinned [4]
+    unsigned int *host_counters_dev = nullptr;  // their address for kernels
     Ops *ops = nullptr;
     hipEvent_t ev[kTimeRing][kEvents] = {};
     bool p2p_side[kTimeRing] = {};  // the call's P2P ran on the side stream
@@ -640,8 +641,12 @@ fmm_status work_from_scratch(fmm_tree *t, bool far, Work &w) {
 }
 
 // The far + near chain shared by the forward evaluation and the adjoint.
+// fuse: the combine of a forward evaluation, taken over by the last kernel
+// (*fused is then set): P2P when it runs on the call's stream after the far
+// field; L2P, after the join, when the near field runs on the side stream
+// (forked beside M2L, it ends before the far field does)
 fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoint, bool do_far,
-                     bool do_near, hipStream_t st) {
+                     bool do_near, hipStream_t st, const Combine *fuse = nullptr, bool *fused = nullptr) {
     const int P = t->cfg.p, L = t->L;
     const bool f64 = is_f64_form(t);
     void *src = f64 ? t->xyz64.p : t->xyz32.p;
@@ -666,21 +671,25 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
         HIPCHK(launch_gather_q(t->n, t->dtype, f64, (const uint32_t *)t->perm.p, charges, src, st));
     // Near field concurrently with the far field: P2P needs only the sorted
     // particles and writes its own buffer, so it is forked onto the library's
-    // side stream after the gather and joined back before the combine.
+    // side stream and joined back before the combine.  The fork comes after
+    // the pack, when the M2L kernel is next on the call's stream: its blocks
+    // (two waves per SIMD) are placed with the P2P waves filling what they
+    // leave, where P2P forked earlier would hold every slot of the chip.
     t->p2p_side[t->cur] = side;
-    if (side) {
-        if (!t->side) {
-            HIPCHK(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
-        }
+    if (side && !t->side) {
+        HIPCHK(hipStreamCreateWithFlags(&t->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&t->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&t->ev_join, hipEventDisableTiming));
+    }
+    auto fork_near = [&]() -> fmm_status {
         HIPCHK(hipEventRecord(t->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
         CHK(rec(t, kStages + 1, t->side));
-        HIPCHK(launch_p2p(L, f64, src, start, w.nearf, t->side));
+        HIPCHK(launch_p2p(L, f64, src, start, w.nearf, nullptr, t->side));
         CHK(rec(t, kStages + 2, t->side));
         HIPCHK(hipEventRecord(t->ev_join, t->side));
-    }
+        return FMM_OK;
+    };
     if (L >= 2 && do_far) {
         if (!t->ops) return fail(FMM_EDEVICE, "internal: the tree has no translation tables");
         const Ops *o = t->ops;
@@ -714,6 +723,7 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
             HIPCHK(launch_pack(P, f64, pk, st));
         }
         CHK(rec(t, 4, st));
+        if (side) CHK(fork_near());
         // M2L at every level >= 2 in one launch (the levels are independent)
         {
             void *Bp[FMM_MAX_LEVEL + 1] = {}, *Lp[FMM_MAX_LEVEL + 1] = {};
@@ -746,14 +756,27 @@ fmm_status run_chain(fmm_tree *t, const Work &w, const void *charges, bool adjoi
         CHK(rec(t, 6, st));
         // L2P (adjoint: P2M^T with its position derivative)
         // leaf-level coefficients share the particle precision (level_f64)
-        HIPCHK(launch_l2p(P, L, f64, src, start, w.Lc[L], w.farf, st));
+        if (side && fuse) {
+            Combine cf = *fuse;
+            cf.farf = w.nearf;  // far + near in one pass, after the join
+            HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
+            HIPCHK(launch_l2p(P, L, f64, src, start, w.Lc[L], w.farf, &cf, st));
+            if (fused) *fused = true;
+        } else {
+            HIPCHK(launch_l2p(P, L, f64, src, start, w.Lc[L], w.farf, nullptr, st));
+        }
     } else {
         for (int s = 1; s <= 6; ++s) CHK(rec(t, s, st));
     }
     CHK(rec(t, 7, st));
-    if (side) HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
-    else if (do_near) HIPCHK(launch_p2p(L, f64, src, start, w.nearf, st));
-    else HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
+    if (side) {
+        HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
+    } else if (do_near) {
+        HIPCHK(launch_p2p(L, f64, src, start, w.nearf, fuse, st));
+        if (fused) *fused = fuse != nullptr;
+    } else {
+        HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
+    }
     CHK(rec(t, 8, st));
     return FMM_OK;
 }
@@ -815,7 +838,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     };
     HIPCHK(launch_keys(n, dtype, pos, c.box_lo, c.box_size, Lf, bp<uint32_t>(t->key10), bp<uint32_t>(t->cnt),
                        bp<uint32_t>(t->rank), dc, st));
-    HIPCHK(launch_scan_max(nf, bp<uint32_t>(t->cnt), fstart, scan, dc + 1, st));
+    HIPCHK(launch_scan_max(nf, bp<uint32_t>(t->cnt), fstart, scan, dc + 1, dc, nullptr, nullptr, st));
     HIPCHK(launch_sort(n, Lf, UINT32_MAX, bp<uint32_t>(t->key10), bp<uint32_t>(t->rank), fstart, bp<uint32_t>(t->tmp), dtype,
                        pos, c.box_lo, c.box_size, bp<uint32_t>(t->perm), nullptr, bp<double4>(t->xyz64), st));
     a->off[0] = 0;
@@ -1115,11 +1138,14 @@ fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int3
     const bool do_far = part != FMM_PART_NEAR_ONLY, do_near = part != FMM_PART_FAR_ONLY;
     Work w;
     CHK(noalloc ? work_from_scratch(t, do_far, w) : work_from_tree(t, do_far, st, w));
-    CHK(t->ad ? run_adaptive(t, w, q, false, do_far, do_near, st) : run_chain(t, w, q, false, do_far, do_near, st));
     // the adaptive kernels leave their results in units of the root box
     const double inv_w = (t->ad ? 1.0 : (double)((int64_t)1 << t->L)) / t->cfg.box_size;
-    HIPCHK(launch_combine(t->n, t->dtype, (const uint32_t *)t->perm.p, w.nearf,
-                          (t->L >= 2 && do_far) ? w.farf : nullptr, inv_w, q, phi, vec, kind, st));
+    const Combine c{(const uint32_t *)t->perm.p, (t->L >= 2 && do_far) ? w.farf : nullptr, inv_w, q, phi,
+                    vec, kind, t->dtype};
+    bool fused = false;
+    CHK(t->ad ? run_adaptive(t, w, q, false, do_far, do_near, st)
+              : run_chain(t, w, q, false, do_far, do_near, st, &c, &fused));
+    if (!fused) HIPCHK(launch_combine(t->n, w.nearf, c, st));
     CHK(rec(t, kStages, st));
     if (t->cfg.profile && !t->quiet) ++t->ncalls;
     return FMM_OK;
@@ -1244,8 +1270,11 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
         return bail(fail(FMM_EDEVICE, "cannot read the compute unit count"));
     if (!t->al.fa) ensure_pool(t->dev);
     if (!t->host_counters) {
-        if (hipHostMalloc((void **)&t->host_counters, 4 * sizeof(unsigned int)) != hipSuccess)
+        if (hipHostMalloc((void **)&t->host_counters, 4 * sizeof(unsigned int), hipHostMallocCoherent) !=
+            hipSuccess)
             return bail(fail(FMM_EDEVICE, "hipHostMalloc failed"));
+        if (hipHostGetDevicePointer((void **)&t->host_counters_dev, t->host_counters, 0) != hipSuccess)
+            return bail(fail(FMM_EDEVICE, "hipHostGetDevicePointer failed"));
     }
     fmm_status s;
     // S1: smallest level whose fullest leaf holds <= leaf_max; the coarsest
@@ -1283,12 +1312,15 @@ fmm_status fmm_build_tree(const fmm_config *cfg, int64_t n, int32_t dtype, const
         return ensure(t, t->scan, sizeof(uint32_t) * scan_scratch_words((int64_t)nb), st);
     };
     unsigned int *dc = (unsigned int *)t->counters.p;
-    // leaf starts (scan of the counts) and the fullest leaf, then the copy
-    // of the two build counters that the host reads
+    // leaf starts (scan of the counts) and the fullest leaf, and the two
+    // build counters in the pinned host words (stored by the scan when it is
+    // one kernel, else copied)
     auto read_counters = [&](int l) -> hipError_t {
+        bool direct = false;
         hipError_t r = launch_scan_max((int64_t)1 << (3 * l), (const uint32_t *)t->cnt.p,
-                                       (uint32_t *)t->start.p, (uint32_t *)t->scan.p, dc + 1, st);
-        if (r == hipSuccess)
+                                       (uint32_t *)t->start.p, (uint32_t *)t->scan.p, dc + 1, dc,
+                                       t->host_counters_dev, &direct, st);
+        if (r == hipSuccess && !direct)
             r = hipMemcpyAsync(t->host_counters, dc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, st);
         if (r == hipSuccess) r = hipEventRecord(t->ev_counters, st);
         return r;

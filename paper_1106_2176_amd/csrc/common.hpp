@@ -149,4 +149,33 @@ __device__ inline void unpack_rec(const double4 r, double &x, double &y, double 
     q = r.w;
 }
 
+// The last step of an evaluation for sorted particle i (Sec. 2.1, S11):
+// phi = (near + far) / w and E = (near + far) / w^2 in FP64 (near and far in
+// leaf units), the optional force q E, stored at the particle's place in the
+// caller's order and dtype.  Shared by the combine kernel and the P2P kernel
+// that ends with it.
+struct Combine {
+    const uint32_t *perm;
+    const double4 *farf;  // NULL: no far field
+    double inv_w;
+    const void *q;
+    void *phi, *vec;
+    int flags;            // FMM_VEC_*
+    int dtype;            // FMM_F32 / FMM_F64 of q, phi and vec
+};
+template <typename To>
+__device__ __forceinline__ void combine_one(const Combine &c, int64_t i, const double4 a) {
+    double4 b = make_double4(0, 0, 0, 0);
+    if (c.farf) b = c.farf[i];
+    const uint32_t o = c.perm[i];
+    ((To *)c.phi)[o] = (To)((a.x + b.x) * c.inv_w);
+    if (c.flags != FMM_VEC_NONE) {
+        const double s = c.inv_w * c.inv_w * (c.flags == FMM_VEC_FORCE ? (double)((const To *)c.q)[o] : 1.0);
+        To *const v = (To *)c.vec;
+        v[3 * (size_t)o] = (To)((a.y + b.y) * s);
+        v[3 * (size_t)o + 1] = (To)((a.z + b.z) * s);
+        v[3 * (size_t)o + 2] = (To)((a.w + b.w) * s);
+    }
+}
+
 }  // namespace fmm

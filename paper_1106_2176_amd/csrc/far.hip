@@ -192,10 +192,10 @@ __global__ __launch_bounds__(64) void k_p2m(int L, typename V4T<T>::type *__rest
 // Two Morton-consecutive leaves per 64-lane block, 32 lanes each (a leaf
 // holds a few tens of particles).  The harmonic loops are fully unrolled, so
 // that every recurrence coefficient is a compile-time constant.
-template <int P, typename T>
+template <int P, typename T, int FUSE>
 __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *__restrict__ src,
                                             const uint32_t *__restrict__ start,
-                                            const T *__restrict__ Lc, double4 *__restrict__ out) {
+                                            const T *__restrict__ Lc, double4 *__restrict__ out, const Combine c) {
     constexpr int P2 = P * P;
     constexpr int S = coef_stride(P);
     constexpr int HL = 32;  // lanes per leaf
@@ -225,6 +225,13 @@ __global__ __launch_bounds__(64) void k_l2p(int L, const typename V4T<T>::type *
         l2p_point<P, T, V>(coef, x, y, z, phi, gx, gy, gz);
         out[s0 + j0] = make_double4((double)phi, -(double)gx, -(double)gy, -(double)gz);
     }
+    // FUSE (1: FP32, 2: FP64 caller data): the combine of the lane's far
+    // values, just written, with the near field (c.farf holds the near
+    // partials here), in a loop of its own so that the harmonics loop keeps
+    // its registers
+    if constexpr (FUSE != 0)
+        for (uint32_t j0 = hl; j0 < cnt; j0 += HL)
+            combine_one<std::conditional_t<FUSE == 2, double, float>>(c, s0 + j0, out[s0 + j0]);
 }
 
 // ------------------------------------------------------- M2M / L2L transfers
@@ -567,23 +574,10 @@ __global__ void k_gather_q32(int64_t n, const uint32_t *__restrict__ perm, const
 // phi = (near + far) / w,  E = (near + far) / w^2 in FP64, scattered to the
 // caller's order; optional force q E.
 template <typename To>
-__global__ void k_combine(int64_t n, const uint32_t *__restrict__ perm,
-                          const double4 *__restrict__ nearf, const double4 *__restrict__ farf,
-                          double inv_w, const To *__restrict__ q, To *__restrict__ phi,
-                          To *__restrict__ vec, int flags) {
+__global__ void k_combine(int64_t n, const double4 *__restrict__ nearf, const Combine c) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double4 a = nearf[i];
-    double4 b = make_double4(0, 0, 0, 0);
-    if (farf) b = farf[i];
-    const uint32_t o = perm[i];
-    phi[o] = (To)((a.x + b.x) * inv_w);
-    if (flags != FMM_VEC_NONE) {
-        const double s = inv_w * inv_w * (flags == FMM_VEC_FORCE ? (double)q[o] : 1.0);
-        vec[3 * (size_t)o] = (To)((a.y + b.y) * s);
-        vec[3 * (size_t)o + 1] = (To)((a.z + b.z) * s);
-        vec[3 * (size_t)o + 2] = (To)((a.w + b.w) * s);
-    }
+    combine_one<To>(c, i, nearf[i]);
 }
 
 // Adjoint combine: grad_q = phi_w, grad_x = -(w E_q + q E_w) (E_q given in
@@ -639,12 +633,19 @@ hipError_t launch_p2m(int P, int L, bool f64, void *src, const uint32_t *start, 
 
 template <typename T>
 static hipError_t l2p_dispatch(int P, int L, const void *src, const uint32_t *start, const T *Lc,
-                               double4 *out, hipStream_t st) {
+                               double4 *out, const Combine &c, hipStream_t st) {
     const unsigned g = ((1u << (3 * L)) + 1) / 2;  // two leaves per block
     using V = typename V4T<T>::type;
     switch (P) {
-#define CASE(PP) \
-    case PP: k_l2p<PP, T><<<g, 64, 0, st>>>(L, (const V *)src, start, Lc, out); break;
+#define CASE(PP)                                                                            \
+    case PP:                                                                                \
+        if (!c.phi)                                                                         \
+            k_l2p<PP, T, 0><<<g, 64, 0, st>>>(L, (const V *)src, start, Lc, out, c);        \
+        else if (c.dtype == FMM_F64)                                                        \
+            k_l2p<PP, T, 2><<<g, 64, 0, st>>>(L, (const V *)src, start, Lc, out, c);        \
+        else                                                                                \
+            k_l2p<PP, T, 1><<<g, 64, 0, st>>>(L, (const V *)src, start, Lc, out, c);        \
+        break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
         CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16)
 #undef CASE
@@ -654,9 +655,10 @@ static hipError_t l2p_dispatch(int P, int L, const void *src, const uint32_t *st
 }
 
 hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *start,
-                      const void *Lc, double4 *out, hipStream_t st) {
-    return f64 ? l2p_dispatch<double>(P, L, src, start, (const double *)Lc, out, st)
-               : l2p_dispatch<float>(P, L, src, start, (const float *)Lc, out, st);
+                      const void *Lc, double4 *out, const Combine *fuse, hipStream_t st) {
+    const Combine c = fuse ? *fuse : Combine{};
+    return f64 ? l2p_dispatch<double>(P, L, src, start, (const double *)Lc, out, c, st)
+               : l2p_dispatch<float>(P, L, src, start, (const float *)Lc, out, c, st);
 }
 
 // in/out storage precisions: 0 = f32, 1 = f64 (the arithmetic is FP64)
@@ -748,17 +750,11 @@ hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm,
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
-                          const double4 *farf, double inv_w, const void *q, void *phi, void *vec,
-                          int flags, hipStream_t st) {
-    if (dtype == FMM_F64)
-        k_combine<double><<<nblk(n, 256), 256, 0, st>>>(n, perm, nearf, farf, inv_w,
-                                                         (const double *)q, (double *)phi,
-                                                         (double *)vec, flags);
+hipError_t launch_combine(int64_t n, const double4 *nearf, const Combine &c, hipStream_t st) {
+    if (c.dtype == FMM_F64)
+        k_combine<double><<<nblk(n, 256), 256, 0, st>>>(n, nearf, c);
     else
-        k_combine<float><<<nblk(n, 256), 256, 0, st>>>(n, perm, nearf, farf, inv_w,
-                                                        (const float *)q, (float *)phi,
-                                                        (float *)vec, flags);
+        k_combine<float><<<nblk(n, 256), 256, 0, st>>>(n, nearf, c);
     return hipGetLastError();
 }
 

@@ -20,11 +20,13 @@ int64_t scan_scratch_words(int64_t nb);
 hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
                        hipStream_t st);
 // exclusive scan (out[0..nb], total at out[nb]) and the maximum count into
-// *mx (one kernel up to 32768 counts; *mx must be zero before a larger scan)
+// *mx (one kernel up to 32768 counts; *mx must be zero before a larger scan).
+// With host (device-visible pinned words) the one-kernel form also stores
+// *nbad and the maximum there and sets *host_done; the caller copies them
+// otherwise.
 hipError_t launch_scan_max(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
-                           unsigned int *mx, hipStream_t st);
-// placement and in-leaf input order; leaves over `skip` particles are left
-// unordered and without records (a sort that the build repeats finer)
+                           unsigned int *mx, const unsigned int *nbad, unsigned int *host, bool *host_done,
+                           hipStream_t st);
 hipError_t launch_sort(int64_t n, int level, uint32_t skip, const uint32_t *key10, const uint32_t *rank,
                        const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,
@@ -33,7 +35,8 @@ hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long lon
                              hipStream_t st);
 
 // p2p.hip
-hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, double4 *out,
+// with fuse non-NULL the kernel ends with the combine (no near partials)
+hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, double4 *out, const Combine *fuse,
                       hipStream_t st);
 
 // far.hip
@@ -44,8 +47,9 @@ hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, d
 hipError_t launch_p2m(int P, int L, bool f64, void *src, const uint32_t *start, void *M,
                       double scale, const uint32_t *perm, const void *q, int q_dtype,
                       uint32_t *clear, hipStream_t st);
+// with fuse non-NULL (fuse->farf = the near partials) it ends with the combine
 hipError_t launch_l2p(int P, int L, bool f64, const void *src, const uint32_t *start,
-                      const void *Lc, double4 *out, hipStream_t st);
+                      const void *Lc, double4 *out, const Combine *fuse, hipStream_t st);
 hipError_t launch_transfer(bool up, int P, int lp, int in_f64, int out_f64, const void *in,
                            void *out, const void *tab32, const void *tab64, hipStream_t st);
 // M2L operand grids of levels 2..L in one launch; level i of the plan:
@@ -70,9 +74,7 @@ struct PackPlan {
 hipError_t launch_pack(int P, bool f64_out, const PackPlan &pl, hipStream_t st);
 hipError_t launch_gather_q(int64_t n, int dtype, bool f64, const uint32_t *perm, const void *q,
                            void *xyzq, hipStream_t st);
-hipError_t launch_combine(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
-                          const double4 *farf, double inv_w, const void *q, void *phi, void *vec,
-                          int flags, hipStream_t st);
+hipError_t launch_combine(int64_t n, const double4 *nearf, const Combine &c, hipStream_t st);
 hipError_t launch_combine_grad(int64_t n, int dtype, const uint32_t *perm, const double4 *nearf,
                                const double4 *farf, double inv_w, const void *q, const void *w,
                                const void *Eq, void *gq, void *gx, hipStream_t st);

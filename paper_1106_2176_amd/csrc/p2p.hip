@@ -27,6 +27,8 @@
 // mixed form, 1e-200 in FP64), which keeps a quantisation-induced r^2 == 0
 // finite and changes no pair farther apart than 1e-6 leaf widths by more
 // than 1e-6 relative.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace fmm {
@@ -110,7 +112,9 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // src: sorted particles (u_x, u_y, u_z, q) in leaf units; start: Morton leaf
-// ranges; out: (phi, E) per sorted particle in leaf units (phi * w, E * w^2).
+// ranges; out: (phi, E) per sorted particle in leaf units (phi * w, E * w^2),
+// or with FUSE (1: FP32, 2: FP64 caller data) the combine of each target
+// with its far field, stored in the caller's order (out unused).
 // NP = 1: one wave per target leaf.  NP = 3 (few leaves, too few waves to
 // hide the serial walk over 27 neighbours): a block of three waves per
 // target leaf, wave w taking the neighbour plane dz = w - 1; wave 0 adds the
@@ -121,12 +125,12 @@ __device__ __forceinline__ void wave_sync() {
 // data per pair and fits four (128 registers).
 template <typename T>
 constexpr int p2p_waves(int NP) { return NP == 1 ? (sizeof(T) == 4 ? 8 : 4) : 1; }
-template <typename T, int NP>
+template <typename T, int NP, int FUSE>
 __global__ __launch_bounds__(64 * NP)
 __attribute__((amdgpu_waves_per_eu(p2p_waves<T>(NP), NP == 1 ? p2p_waves<T>(NP) : 10))) void k_p2p(int L, uint32_t per_xcd,
                                                  const typename V4<T>::type *__restrict__ src,
                                                  const uint32_t *__restrict__ start,
-                                                 double4 *__restrict__ out) {
+                                                 double4 *__restrict__ out, const Combine c) {
     using V = typename V4<T>::type;
     __shared__ V tiles[NP][64];
     __shared__ double4 reds[NP][2][64];
@@ -140,6 +144,17 @@ __attribute__((amdgpu_waves_per_eu(p2p_waves<T>(NP), NP == 1 ? p2p_waves<T>(NP) 
             __syncthreads();
         else
             wave_sync();
+    };
+    // a target's sums in leaf units: stored, or combined with the far field
+    auto emit = [&](uint32_t i, double4 v) __attribute__((always_inline)) {
+        if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
+            const double s1 = kFixScale, s3 = kFixScale * kFixScale;
+            v = make_double4(v.x * s1, v.y * s3, v.z * s3, v.w * s3);
+        }
+        if constexpr (FUSE == 0)
+            out[i] = v;
+        else
+            combine_one<std::conditional_t<FUSE == 2, double, float>>(c, i, v);
     };
     // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
     // run of Morton leaves so its L2 holds the shared neighbour sources
@@ -231,21 +246,16 @@ __attribute__((amdgpu_waves_per_eu(p2p_waves<T>(NP), NP == 1 ? p2p_waves<T>(NP) 
         red[1][lane] = make_double4(b0, b1, b2, b3);
         sync();
         if constexpr (NP == 1) {
-            if (grp == 0) {
-                double4 sa = red[0][r], sb = red[1][r];
-                for (int g = 1; g < K; ++g) {
-                    const double4 xa = red[0][g * G + r], xb = red[1][g * G + r];
-                    sa.x += xa.x; sa.y += xa.y; sa.z += xa.z; sa.w += xa.w;
-                    sb.x += xb.x; sb.y += xb.y; sb.z += xb.z; sb.w += xb.w;
+            // the two targets one after the other (fewer live registers)
+            if (grp == 0)
+                for (int h = 0; h < (hasb ? 2 : 1); ++h) {
+                    double4 sh = red[h][r];
+                    for (int g = 1; g < K; ++g) {
+                        const double4 x = red[h][g * G + r];
+                        sh.x += x.x; sh.y += x.y; sh.z += x.z; sh.w += x.w;
+                    }
+                    emit(t0 + tc + r + h * G, sh);
                 }
-                if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
-                    const double s1 = kFixScale, s3 = kFixScale * kFixScale;
-                    sa = make_double4(sa.x * s1, sa.y * s3, sa.z * s3, sa.w * s3);
-                    sb = make_double4(sb.x * s1, sb.y * s3, sb.z * s3, sb.w * s3);
-                }
-                out[t0 + tc + r] = sa;
-                if (hasb) out[t0 + tc + r + G] = sb;
-            }
             continue;
         }
         double4 sa = make_double4(0, 0, 0, 0), sb = sa;
@@ -276,18 +286,26 @@ __attribute__((amdgpu_waves_per_eu(p2p_waves<T>(NP), NP == 1 ? p2p_waves<T>(NP) 
                 }
         }
         if (grp == 0) {
-            if constexpr (sizeof(T) == 4) {  // raw fixed-point units -> leaf units
-                const double s1 = kFixScale, s3 = kFixScale * kFixScale;
-                sa = make_double4(sa.x * s1, sa.y * s3, sa.z * s3, sa.w * s3);
-                sb = make_double4(sb.x * s1, sb.y * s3, sb.z * s3, sb.w * s3);
-            }
-            out[t0 + tc + r] = sa;
-            if (hasb) out[t0 + tc + r + G] = sb;
+            emit(t0 + tc + r, sa);
+            if (hasb) emit(t0 + tc + r + G, sb);
         }
     }
 }
 
-hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, double4 *out,
+template <typename T, int NP>
+static void p2p_go(unsigned grid, int L, uint32_t per, const void *src, const uint32_t *start, double4 *out,
+                   const Combine *fuse, hipStream_t st) {
+    using V = typename V4<T>::type;
+    const Combine c = fuse ? *fuse : Combine{};
+    if (!fuse)
+        k_p2p<T, NP, 0><<<grid, 64 * NP, 0, st>>>(L, per, (const V *)src, start, out, c);
+    else if (fuse->dtype == FMM_F64)
+        k_p2p<T, NP, 2><<<grid, 64 * NP, 0, st>>>(L, per, (const V *)src, start, out, c);
+    else
+        k_p2p<T, NP, 1><<<grid, 64 * NP, 0, st>>>(L, per, (const V *)src, start, out, c);
+}
+
+hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, double4 *out, const Combine *fuse,
                       hipStream_t st) {
     const uint32_t nleaf = 1u << (3 * L);
     const uint32_t per = (nleaf + 7) / 8;
@@ -295,14 +313,14 @@ hipError_t launch_p2p(int L, bool f64, const void *src, const uint32_t *start, d
     // below 4 waves per SIMD with one wave per leaf, split the neighbours
     if (nleaf <= 4096) {
         if (f64)
-            k_p2p<double, 3><<<grid, 192, 0, st>>>(L, per, (const double4 *)src, start, out);
+            p2p_go<double, 3>(grid, L, per, src, start, out, fuse, st);
         else
-            k_p2p<float, 3><<<grid, 192, 0, st>>>(L, per, (const int4 *)src, start, out);
+            p2p_go<float, 3>(grid, L, per, src, start, out, fuse, st);
     } else {
         if (f64)
-            k_p2p<double, 1><<<grid, 64, 0, st>>>(L, per, (const double4 *)src, start, out);
+            p2p_go<double, 1>(grid, L, per, src, start, out, fuse, st);
         else
-            k_p2p<float, 1><<<grid, 64, 0, st>>>(L, per, (const int4 *)src, start, out);
+            p2p_go<float, 1>(grid, L, per, src, start, out, fuse, st);
     }
     return hipGetLastError();
 }

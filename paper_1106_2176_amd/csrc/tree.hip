@@ -119,7 +119,9 @@ __device__ __forceinline__ int scan1_slot(int i) { return i + (i >> 5); }
 
 __global__ __launch_bounds__(1024) void k_scan_max1(int64_t nb, const uint32_t *__restrict__ in,
                                                     uint32_t *__restrict__ out,
-                                                    unsigned int *__restrict__ mx) {
+                                                    unsigned int *__restrict__ mx,
+                                                    const unsigned int *__restrict__ nbad,
+                                                    unsigned int *host) {
     __shared__ uint32_t buf[kScan1 + kScan1 / 32];
     __shared__ uint32_t ws[16], wm[16];
     const int n = (int)nb, tid = threadIdx.x;
@@ -156,7 +158,17 @@ __global__ __launch_bounds__(1024) void k_scan_max1(int64_t nb, const uint32_t *
             mm = max(mm, (uint32_t)__shfl_xor(mm, d, 16));
         }
         ws[tid] = s;
-        if (tid == 0) *mx = mm;
+        if (tid == 0) {
+            *mx = mm;
+            // the two build counters straight into the caller's pinned host
+            // words (no copy on the stream): positions out of the domain
+            // (final since the key pass ended) and the fullest leaf
+            if (host) {
+                host[0] = *nbad;
+                host[1] = mm;
+                __threadfence_system();
+            }
+        }
     }
     __syncthreads();
     uint32_t excl = x - t + (wave > 0 ? ws[wave - 1] : 0u);
@@ -350,9 +362,12 @@ hipError_t launch_scan(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *
 }
 
 hipError_t launch_scan_max(int64_t nb, const uint32_t *in, uint32_t *out, uint32_t *scratch,
-                           unsigned int *mx, hipStream_t st) {
+                           unsigned int *mx, const unsigned int *nbad, unsigned int *host, bool *host_done,
+                           hipStream_t st) {
+    if (host_done) *host_done = false;
     if (nb <= kScan1) {
-        k_scan_max1<<<1, 1024, 0, st>>>(nb, in, out, mx);
+        k_scan_max1<<<1, 1024, 0, st>>>(nb, in, out, mx, nbad, host);
+        if (host_done) *host_done = host != nullptr;
         return hipGetLastError();
     }
     // larger trees: the maximum (into *mx, zeroed by the key or histogram
