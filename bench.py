@@ -440,6 +440,12 @@ def main():
                         ("roofline_p2p" if m3["dom"] == "M2L" else "roofline_m2l"): o3,
                         "tree_pass": tree_pass(w3, m3, "mixed")},
               "rel_l2": {"mixed_vs_direct": errs(m3, p3, q3, t3, pd3, Ed3)}}
+        if not args.no_overlap:
+            ov3 = measure(fmm, w3, P3, Q3, "mixed", max(5, args.steps // 2), 2, sync, overlap_near=True, **enc_kw)
+            c3["overlap"] = {"ms_per_step": ov3["sec"] * 1e3, "particles_per_s": w3.n / ov3["sec"],
+                             "p2p_ms_side_stream": ov3["stages_ms"]["P2P"], "m2l_ms": ov3["stages_ms"]["M2L"]}
+            del ov3
+            log("C3 overlapped near field measured")
         if not args.no_fp64:
             f3 = measure(fmm, w3, P3, Q3, "fp64", 3, 1, sync)
             log("C3 FP64 form measured")

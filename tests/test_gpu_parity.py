@@ -287,6 +287,42 @@ def test_concurrent_near_field_is_identical():
         np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_combine_in_p2p_and_in_l2p(oracle_mod, dtype, precision):
+    """The forward chain ends its last kernel with the combine: P2P's in the
+    serial order, L2P's after the join when P2P runs on the side stream.  Both
+    give the same bits for every output kind and caller dtype, the force is
+    q E, and the near-only and far-only parts (the latter through the combine
+    kernel) add up to the whole."""
+    pos, q = inputs.particles(30_000, 52, dtype=dtype)
+    ref = oracle_mod.fmm(pos.astype(np.float64), q.astype(np.float64), 6, 32)
+    out = {}
+    for ov in (False, True):
+        with fmm.Tree(dev(pos), p=6, leaf_max=32, precision=precision, overlap_near=ov) as t:
+            for vec in ("field", "force", None):
+                phi, v = t.evaluate(dev(q), vec=vec)
+                out[ov, vec] = (phi.cpu().numpy(), None if v is None else v.cpu().numpy())
+            near, En = t.evaluate(dev(q), part="near")
+            far, Ef = t.evaluate(dev(q), part="far")
+            torch.cuda.synchronize()
+            parts = [x.cpu().numpy().astype(np.float64) for x in (near, En, far, Ef)]
+    for vec in ("field", "force", None):
+        for a, b in zip(out[False, vec], out[True, vec]):
+            if a is not None:
+                np.testing.assert_array_equal(a, b)
+    phi, E = (x.astype(np.float64) for x in out[False, "field"])
+    F = out[False, "force"][1].astype(np.float64)
+    np.testing.assert_array_equal(out[False, None][0], out[False, "field"][0])
+    eps = 1e-6 if dtype == "f32" else 1e-14
+    np.testing.assert_allclose(F, q.astype(np.float64)[:, None] * E, rtol=eps, atol=eps * np.abs(F).max())
+    assert rel_l2(parts[0] + parts[2], phi) < 10 * eps
+    assert rel_l2(parts[1] + parts[3], E) < 10 * eps
+    tol_phi, tol_e = (1e-10, 1e-10) if precision == "fp64" and dtype == "f64" else (2e-6, 2e-5)
+    assert rel_l2(phi, ref["phi"]) < tol_phi
+    assert rel_l2(E, ref["E"]) < tol_e
+
+
 def test_domain_errors():
     pos, q = inputs.particles(1000, 34)
     for bad in (np.nan, 1.5, -0.25, np.inf):
