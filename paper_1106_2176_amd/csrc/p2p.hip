@@ -27,6 +27,7 @@
 // mixed form, 1e-200 in FP64), which keeps a quantisation-induced r^2 == 0
 // finite and changes no pair farther apart than 1e-6 leaf widths by more
 // than 1e-6 relative.
+#include <climits>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -111,6 +112,43 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Chunks of a target leaf.  A chunk of c targets uses G = ceil(c/2) lanes
+// (two targets each) times K = 64/G source groups, so one tile of 64 sources
+// costs about ceil(64/K) steps of the pair loop (37 instructions for its two
+// pairs) plus ~45 for staging the tile and merging the partial sums.  When
+// G K falls well short of 64 (34 targets: G = 17, K = 3, 51 lanes busy) a
+// leaf costs less as two chunks that fill the lanes (32 + 2), although each
+// walks the neighbours again.  The next chunk is the size that minimises the
+// cost of it and one more chunk for the rest, among the remainder itself
+// and the sizes that fill the lanes; this matches the best split into any
+// number of chunks for leaves of up to ~100 targets.  The per-tile overhead
+// of 200 is measured rather than counted: with 45 (the instructions alone),
+// C2 split most leaves of 25-40 targets and its P2P slowed by 5%.
+// Splitting is used only for trees of at least 8^7 leaves (split): there it
+// took the C4 P2P from 58.9 to 55.1 ms, while at C2 (8^5 leaves, four waves
+// per wave slot) the split leaves' longer waves set the kernel's tail and
+// it ran 2% slower.
+__device__ __forceinline__ int p2p_tile_cost(int c) {
+    const int g = (c + 1) >> 1, k = max(1, 64 / g);
+    return ((64 + k - 1) / k) * 37 + 200;
+}
+__device__ __forceinline__ int p2p_next_chunk(int n, bool split) {
+    if (!split) return min(n, 128);
+    constexpr int kFill[7] = {128, 64, 42, 32, 24, 20, 16};
+    int best = n <= 128 ? n : 128, bestv = n <= 128 ? p2p_tile_cost(n) : INT_MAX;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int c = kFill[i];
+        if (c >= n || n - c > 128) continue;
+        const int v = p2p_tile_cost(c) + p2p_tile_cost(n - c);
+        if (v < bestv) {
+            bestv = v;
+            best = c;
+        }
+    }
+    return best;
+}
+
 // src: sorted particles (u_x, u_y, u_z, q) in leaf units; start: Morton leaf
 // ranges; out: (phi, E) per sorted particle in leaf units (phi * w, E * w^2),
 // or with FUSE (1: FP32, 2: FP64 caller data) the combine of each target
@@ -166,8 +204,9 @@ __attribute__((amdgpu_waves_per_eu(p2p_waves<T>(NP), NP == 1 ? p2p_waves<T>(NP) 
     const int side = 1 << L;
     const int ix = (int)compact3(leaf), iy = (int)compact3(leaf >> 1), iz = (int)compact3(leaf >> 2);
 
-    for (uint32_t tc = 0; tc < nt; tc += 128) {
-        const int ntc = (int)min(128u, nt - tc);
+    for (uint32_t tc = 0, step = 0; tc < nt; tc += step) {
+        const int ntc = p2p_next_chunk((int)(nt - tc), L >= 7);
+        step = (uint32_t)ntc;
         const int G = (ntc + 1) >> 1;
         const int K = 64 / G;
         const int grp = lane / G, r = lane - grp * G;

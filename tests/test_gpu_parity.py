@@ -323,6 +323,26 @@ def test_combine_in_p2p_and_in_l2p(oracle_mod, dtype, precision):
     assert rel_l2(E, ref["E"]) < tol_e
 
 
+def test_leaves_split_into_chunks_at_level_7(oracle_mod):
+    """Trees of 8^7 leaves and more run a target leaf as several chunks when
+    that fills more lanes (here 73 particles a leaf on average, 84% of the
+    leaves over 64): FP64 against the oracle at sampled targets, and the
+    mixed form against FP64 within its budget."""
+    rng = np.random.default_rng(5)
+    n = 300_000
+    pos = rng.random((n, 3)) * 0.125  # one corner: level 6 would hold ~590 a leaf
+    q = rng.random(n)
+    tg = rng.choice(n, 2000, replace=False)
+    ref = oracle_mod.fmm(pos, q, 4, 128, targets=tg)
+    phi64, E64, info = gpu_eval(pos, q, 4, 128, "fp64")
+    assert info["levels"] == 7 == ref["level"]
+    assert rel_l2(phi64[tg], ref["phi"]) < 1e-10
+    assert rel_l2(E64[tg], ref["E"]) < 1e-10
+    phim, Em, _ = gpu_eval(pos, q, 4, 128, "mixed")
+    assert rel_l2(phim, phi64) < 1e-6
+    assert rel_l2(Em, E64) < 1e-6
+
+
 def test_domain_errors():
     pos, q = inputs.particles(1000, 34)
     for bad in (np.nan, 1.5, -0.25, np.inf):
