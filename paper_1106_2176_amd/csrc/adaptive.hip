@@ -31,6 +31,8 @@
 #include <algorithm>
 
 #include "harmonics.hpp"
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace fmm {
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(256) void k_ad_leafmax(int64_t nleaf, const uint32_
         if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(mx, red[0]);
+    if (threadIdx.x == 0) atomic_max_shared(mx, red[0]);
 }
 
 // P2P work units: ceil(count / 64) per leaf (pass 0), then each unit's
@@ -835,11 +837,15 @@ struct AdP2PShared {
     uint32_t off[65];     // exclusive offsets of the entries, total last
 };
 
+// FUSE (1: FP32, 2: FP64 caller data): each target's sums go through the
+// combine with its far field (c) into the caller's order instead of out.
+template <int FUSE>
 __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, int lg, uint32_t cg, uint32_t t0,
                                             uint32_t nt, uint32_t u0, uint32_t u1, const int *__restrict__ iu,
                                             const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                             const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
-                                            const double4 *__restrict__ rec, double4 *__restrict__ out) {
+                                            const double4 *__restrict__ rec, double4 *__restrict__ out,
+                                            const Combine &c) {
     // T lanes hold the unit's targets, two per lane (slot and slot + T);
     // G = 64 / T groups of them split every source tile; lanes past G T idle
     const int T = (int)((nt + 1) / 2), G = 64 / T;
@@ -906,22 +912,31 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
     sh.frame[lane] = make_double4(phi1, ex1, ey1, ez1);
     wave_sync();
     if (grp == 0) {
-        double4 a = sh.tile[slot], c = sh.frame[slot];
+        double4 a = sh.tile[slot], cc = sh.frame[slot];
         for (int k = 1; k < G; ++k) {
             const double4 x = sh.tile[k * T + slot], y = sh.frame[k * T + slot];
             a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
-            c.x += y.x; c.y += y.y; c.z += y.z; c.w += y.w;
+            cc.x += y.x; cc.y += y.y; cc.z += y.z; cc.w += y.w;
         }
-        if (live0) out[t0 + slot] = make_double4(a.x * s1, a.y * s2, a.z * s2, a.w * s2);
-        if (live1) out[t0 + slot + T] = make_double4(c.x * s1, c.y * s2, c.z * s2, c.w * s2);
+        const double4 v0 = make_double4(a.x * s1, a.y * s2, a.z * s2, a.w * s2);
+        const double4 v1 = make_double4(cc.x * s1, cc.y * s2, cc.z * s2, cc.w * s2);
+        if constexpr (FUSE == 0) {
+            if (live0) out[t0 + slot] = v0;
+            if (live1) out[t0 + slot + T] = v1;
+        } else {
+            using To = std::conditional_t<FUSE == 2, double, float>;
+            if (live0) combine_one<To>(c, t0 + slot, v0);
+            if (live1) combine_one<To>(c, t0 + slot + T, v1);
+        }
     }
 }
 
+template <int FUSE>
 __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
     const uint32_t *__restrict__ nunits, const int2 *__restrict__ units, const int *__restrict__ lbox,
     const uint32_t *__restrict__ lstart, const uint32_t *__restrict__ ou, const int *__restrict__ iu,
     const int *__restrict__ lev, const uint32_t *__restrict__ code, const uint32_t *__restrict__ ps,
-    const uint32_t *__restrict__ pe, const double4 *__restrict__ rec, double4 *__restrict__ out) {
+    const uint32_t *__restrict__ pe, const double4 *__restrict__ rec, double4 *__restrict__ out, const Combine c) {
     __shared__ AdP2PShared shm[kAdP2PWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * kAdP2PWaves + wave;
@@ -930,7 +945,8 @@ __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
     const int j = un.x;
     const int g = lbox[j];
     const uint32_t t0 = lstart[j] + (uint32_t)un.y, nt = min(64u, lstart[j + 1] - t0);
-    ad_p2p_unit(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, rec, out);
+    ad_p2p_unit<FUSE>(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, rec,
+                      out, c);
 }
 
 // Gathered M2L (FP64 MFMA), added to the locals: the targets of each (level,
@@ -1161,7 +1177,7 @@ __global__ __launch_bounds__(256) void k_ad_level_max(int P, int64_t box2, int64
         if (v > 0.0f) atomicMax(&lm[lev[g]], __float_as_uint(v));
     }
     __syncthreads();
-    if (threadIdx.x < kLevelSlots && lm[threadIdx.x]) atomicMax(lmax + threadIdx.x, lm[threadIdx.x]);
+    if (threadIdx.x < kLevelSlots && lm[threadIdx.x]) atomic_max_shared(lmax + threadIdx.x, lm[threadIdx.x]);
 }
 
 // One thread per 8-coefficient piece of rows box2 .. nbox (the last the zero
@@ -1635,9 +1651,19 @@ hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint
 
 hipError_t ad_launch_p2p(int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
                          const uint32_t *lstart, const uint32_t *ou, const int *iu, const int *lev, const uint32_t *code,
-                         const uint32_t *ps, const uint32_t *pe, const double4 *rec, double4 *out, hipStream_t st) {
-    k_ad_p2p<<<ad_blocks(max_units, kAdP2PWaves), 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu,
-                                                                            lev, code, ps, pe, rec, out);
+                         const uint32_t *ps, const uint32_t *pe, const double4 *rec, double4 *out, const Combine *fuse,
+                         hipStream_t st) {
+    const Combine c = fuse ? *fuse : Combine{};
+    const unsigned grid = ad_blocks(max_units, kAdP2PWaves);
+    if (!fuse)
+        k_ad_p2p<0><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, rec,
+                                                      out, c);
+    else if (fuse->dtype == FMM_F64)
+        k_ad_p2p<2><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, rec,
+                                                      out, c);
+    else
+        k_ad_p2p<1><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, rec,
+                                                      out, c);
     return hipGetLastError();
 }
 

@@ -986,7 +986,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
 // L2P and M2P as P2M^T and P2L^T with their position derivatives (X and W
 // are each other's transposes), and P2P on the weights (U is symmetric).
 fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool adjoint, bool do_far, bool do_near,
-                        hipStream_t st) {
+                        hipStream_t st, const Combine *fuse = nullptr, bool *fused = nullptr) {
     const AdTree *a = t->ad;
     const int P = t->cfg.p, S = coef_stride(P);
     const Ops *o = t->ops;
@@ -1006,9 +1006,9 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
     const bool far = do_far && a->depth >= 2;
     const bool side = do_near && far && t->cfg.overlap_near && !t->quiet;
     t->p2p_side[t->cur] = side;
-    auto p2p = [&](hipStream_t s2) -> hipError_t {
+    auto p2p = [&](hipStream_t s2, const Combine *cf) -> hipError_t {
         return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
-                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, s2);
+                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf, s2);
     };
     if (side) {
         if (!t->side) {
@@ -1019,7 +1019,7 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
         HIPCHK(hipEventRecord(t->ev_fork, st));
         HIPCHK(hipStreamWaitEvent(t->side, t->ev_fork, 0));
         CHK(rec(t, kStages + 1, t->side));
-        HIPCHK(p2p(t->side));
+        HIPCHK(p2p(t->side, nullptr));
         CHK(rec(t, kStages + 2, t->side));
         HIPCHK(hipEventRecord(t->ev_join, t->side));
     }
@@ -1064,12 +1064,14 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
         for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
     }
     CHK(rec(t, 7, st));
-    if (side)
+    if (side) {
         HIPCHK(hipStreamWaitEvent(st, t->ev_join, 0));
-    else if (do_near)
-        HIPCHK(p2p(st));
-    else
+    } else if (do_near) {  // last on the call's stream: it takes over the combine
+        HIPCHK(p2p(st, fuse));
+        if (fused) *fused = fuse != nullptr;
+    } else {
         HIPCHK(launch_zero((uint32_t *)w.nearf, 8 * t->n, st));
+    }
     CHK(rec(t, 8, st));
     return FMM_OK;
 }
@@ -1143,7 +1145,7 @@ fmm_status evaluate_chain(fmm_tree *t, const void *q, void *phi, void *vec, int3
     const Combine c{(const uint32_t *)t->perm.p, (t->L >= 2 && do_far) ? w.farf : nullptr, inv_w, q, phi,
                     vec, kind, t->dtype};
     bool fused = false;
-    CHK(t->ad ? run_adaptive(t, w, q, false, do_far, do_near, st)
+    CHK(t->ad ? run_adaptive(t, w, q, false, do_far, do_near, st, &c, &fused)
               : run_chain(t, w, q, false, do_far, do_near, st, &c, &fused));
     if (!fused) HIPCHK(launch_combine(t->n, w.nearf, c, st));
     CHK(rec(t, kStages, st));

@@ -149,6 +149,14 @@ __device__ inline void unpack_rec(const double4 r, double &x, double &y, double 
     q = r.w;
 }
 
+// atomicMax on a word that many blocks share.  Atomics on one word run one
+// after another where memory performs them, so a block whose value does not
+// exceed the word's current one (a coherent read; the word only grows, so a
+// stale read only lets an atomic through) skips its atomic.
+__device__ __forceinline__ void atomic_max_shared(unsigned int *p, unsigned int v) {
+    if (v > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(p, v);
+}
+
 // The last step of an evaluation for sorted particle i (Sec. 2.1, S11):
 // phi = (near + far) / w and E = (near + far) / w^2 in FP64 (near and far in
 // leaf units), the optional force q E, stored at the particle's place in the

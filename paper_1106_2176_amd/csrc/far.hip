@@ -528,19 +528,50 @@ __global__ __launch_bounds__(256) void k_level_max(int P, PackPlan pl) {
     const int64_t g0 = (b - b0) * (kLevelMaxChunk / 4), g1 = min(ng, g0 + kLevelMaxChunk / 4);
     int cg = (int)((g0 + threadIdx.x) % S4);  // group's position in its box
     const int step = 256 % S4;
-    float mx = 0.0f;
-    for (int64_t gi = g0 + threadIdx.x; gi < g1; gi += 256) {
-        float v[4];
-        if (in_f64) {
-            const double2 d0 = ((const double2 *)in)[2 * gi], d1 = ((const double2 *)in)[2 * gi + 1];
-            v[0] = (float)d0.x; v[1] = (float)d0.y; v[2] = (float)d1.x; v[3] = (float)d1.y;
-        } else {
-            const float4 f = ((const float4 *)in)[gi];
-            v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    // eight steps of four elements per thread, every load issued before the
+    // first use (the steps past the level's end read nothing and add zeros)
+    constexpr int STEPS = kLevelMaxChunk / 4 / 256;
+    float v[STEPS][4];
+    // (a step past the end reads the chunk's first group, in bounds, and is
+    // zeroed afterwards: no branch between the loads)
+    if (in_f64) {
+        double2 d[STEPS][2];
+#pragma unroll
+        for (int t = 0; t < STEPS; ++t) {
+            const int64_t gi = g0 + threadIdx.x + 256 * t, gs = gi < g1 ? gi : g0;
+            d[t][0] = ((const double2 *)in)[2 * gs];
+            d[t][1] = ((const double2 *)in)[2 * gs + 1];
         }
 #pragma unroll
+        for (int t = 0; t < STEPS; ++t) {
+            const bool in_range = g0 + threadIdx.x + 256 * t < g1;
+            v[t][0] = in_range ? (float)d[t][0].x : 0.0f;
+            v[t][1] = in_range ? (float)d[t][0].y : 0.0f;
+            v[t][2] = in_range ? (float)d[t][1].x : 0.0f;
+            v[t][3] = in_range ? (float)d[t][1].y : 0.0f;
+        }
+    } else {
+        float4 f[STEPS];
+#pragma unroll
+        for (int t = 0; t < STEPS; ++t) {
+            const int64_t gi = g0 + threadIdx.x + 256 * t;
+            f[t] = ((const float4 *)in)[gi < g1 ? gi : g0];
+        }
+#pragma unroll
+        for (int t = 0; t < STEPS; ++t) {
+            const bool in_range = g0 + threadIdx.x + 256 * t < g1;
+            v[t][0] = in_range ? f[t].x : 0.0f;
+            v[t][1] = in_range ? f[t].y : 0.0f;
+            v[t][2] = in_range ? f[t].z : 0.0f;
+            v[t][3] = in_range ? f[t].w : 0.0f;
+        }
+    }
+    float mx = 0.0f;
+#pragma unroll
+    for (int t = 0; t < STEPS; ++t) {
+#pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (4 * cg + k < P2) mx = fmaxf(mx, fabsf(v[k]) * rinv[4 * cg + k]);
+            if (4 * cg + k < P2) mx = fmaxf(mx, fabsf(v[t][k]) * rinv[4 * cg + k]);
         cg += step;
         if (cg >= S4) cg -= S4;
     }
@@ -551,7 +582,7 @@ __global__ __launch_bounds__(256) void k_level_max(int P, PackPlan pl) {
     __syncthreads();
     if (threadIdx.x == 0) {
         mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
-        atomicMax(pl.lmax + l, __float_as_uint(mx));
+        atomic_max_shared(pl.lmax + l, __float_as_uint(mx));  // hundreds of blocks a level
     }
 }
 

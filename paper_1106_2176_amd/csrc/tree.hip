@@ -69,7 +69,7 @@ __global__ void k_max(int64_t nb, const uint32_t *__restrict__ cnt, unsigned int
         if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(mx, red[0]);
+    if (threadIdx.x == 0) atomic_max_shared(mx, red[0]);
 }
 
 // Exclusive scan in blocks of 4096 (1024 threads x 4); block totals to sums.
