@@ -140,10 +140,12 @@ typedef struct {
                                   leaf_max particles and its level is below
                                   max_level; empty children are dropped, so
                                   leaves sit at many levels.  The build sorts
-                                  the particles into the 8^max_level boxes of
-                                  the finest level first: 8 bytes of workspace
-                                  per box (128 MiB at level 8, 8 GiB at level
-                                  10) and a pass over them per build.  The interactions follow the
+                                  the particles by their key at max_level (a
+                                  radix sort of the keys, no bin per finest
+                                  box) and finds box ranges in the sorted keys
+                                  through a table of 8^min(max_level, 7) + 1
+                                  words (8 MiB at most), so a deeper cap costs
+                                  little.  The interactions follow the
                                   U/V/W/X lists of the adaptive FMM: U(b), b a
                                   leaf: b and the leaves touching it (P2P); V(b):
                                   the children of the colleagues of b's parent

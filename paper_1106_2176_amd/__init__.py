@@ -23,8 +23,9 @@ FMM_F32, FMM_F64 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 VEC_NONE, VEC_FIELD, VEC_FORCE = 0, 1, 2
 PART_NEAR_ONLY, PART_FAR_ONLY = 4, 8
-# default depth cap of the adaptive tree (its build sorts into 8^max_level
-# finest-level boxes; deeper caps, up to 10, cost memory and time)
+# default depth cap of the adaptive tree (up to 10; on 10^6 particles in
+# Gaussian blobs caps of 9 and 10 halve the P2P pairs but add boxes, M2L and
+# build time, for about the same total)
 ADAPTIVE_MAX_LEVEL = 8
 STAGES = ("gather", "P2M", "M2M", "pack", "M2L", "L2L", "L2P", "P2P", "combine")
 

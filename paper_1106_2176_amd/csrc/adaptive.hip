@@ -77,11 +77,29 @@ __global__ void k_ad_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe
     parent[0] = -1;
 }
 
+// The first sorted position whose key at the finest level Lf is >= x (x in
+// [0, 8^Lf]): the table entry when x is a key of level cl, else a binary
+// search of the sorted keys between the entries of x's level-cl key.
+__device__ __forceinline__ uint32_t key_start(const KeyIndex &ki, uint64_t x) {
+    const int sh = 3 * (ki.Lf - ki.cl);
+    const uint64_t xc = x >> sh;
+    uint32_t lo = ki.cstart[xc];
+    if ((x & ((1ull << sh) - 1)) == 0) return lo;
+    uint32_t hi = ki.cstart[xc + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)ki.skey[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // Split decision and the non-empty children of the level's boxes [b0, b0+nb).
 __global__ void k_ad_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, const uint32_t *__restrict__ code,
-                           const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
-                           const uint32_t *__restrict__ fstart, uint8_t *__restrict__ leaf,
-                           uint32_t *__restrict__ nchild, uint8_t *__restrict__ cmask) {
+                           const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe, const KeyIndex ki,
+                           uint8_t *__restrict__ leaf, uint32_t *__restrict__ nchild, uint8_t *__restrict__ cmask) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     const int64_t g = b0 + i;
@@ -89,12 +107,15 @@ __global__ void k_ad_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, 
     uint32_t k = 0, mask = 0;
     if (split) {
         const int sh = 3 * (Lf - l - 1);
+        const uint64_t m0 = (uint64_t)code[g] << 3;
+        uint32_t s = key_start(ki, m0 << sh);
         for (uint32_t c = 0; c < 8; ++c) {
-            const uint64_t m = ((uint64_t)code[g] << 3) | c;
-            if (fstart[(m + 1) << sh] > fstart[m << sh]) {
+            const uint32_t e = key_start(ki, (m0 + c + 1) << sh);
+            if (e > s) {
                 mask |= 1u << c;
                 ++k;
             }
+            s = e;
         }
     }
     leaf[g] = split ? 0 : 1;
@@ -103,8 +124,8 @@ __global__ void k_ad_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, 
 }
 
 // Append the children of level l's boxes at global ids next0 + coff[i] ...
-__global__ void k_ad_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0,
-                              const uint32_t *__restrict__ fstart, const uint32_t *__restrict__ coff,
+__global__ void k_ad_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const KeyIndex ki,
+                              const uint32_t *__restrict__ coff,
                               const uint8_t *__restrict__ cmask, uint32_t *__restrict__ code,
                               uint32_t *__restrict__ ps, uint32_t *__restrict__ pe, int *__restrict__ parent,
                               int *__restrict__ child) {
@@ -121,8 +142,8 @@ __global__ void k_ad_children(int64_t b0, int64_t nb, int l, int Lf, int64_t nex
         }
         const uint64_t m = ((uint64_t)code[g] << 3) | c;
         code[j] = (uint32_t)m;
-        ps[j] = fstart[m << sh];
-        pe[j] = fstart[(m + 1) << sh];
+        ps[j] = key_start(ki, m << sh);
+        pe[j] = key_start(ki, (m + 1) << sh);
         parent[j] = (int)g;
         child[8 * g + c] = (int)j;
         ++j;
@@ -1428,17 +1449,17 @@ hipError_t ad_launch_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe
 }
 
 hipError_t ad_launch_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, const uint32_t *code,
-                           const uint32_t *ps, const uint32_t *pe, const uint32_t *fstart, uint8_t *leaf,
+                           const uint32_t *ps, const uint32_t *pe, const KeyIndex &ki, uint8_t *leaf,
                            uint32_t *nchild, uint8_t *cmask, hipStream_t st) {
-    k_ad_count<<<ad_blocks(nb, 256), 256, 0, st>>>(b0, nb, l, Lf, leaf_max, code, ps, pe, fstart, leaf, nchild, cmask);
+    k_ad_count<<<ad_blocks(nb, 256), 256, 0, st>>>(b0, nb, l, Lf, leaf_max, code, ps, pe, ki, leaf, nchild, cmask);
     return hipGetLastError();
 }
 
-hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const uint32_t *fstart,
+hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const KeyIndex &ki,
                               const uint32_t *coff, const uint8_t *cmask, uint32_t *code, uint32_t *ps,
                               uint32_t *pe, int *parent, int *child, hipStream_t st) {
-    k_ad_children<<<ad_blocks(nb, 256), 256, 0, st>>>(b0, nb, l, Lf, next0, fstart, coff, cmask, code, ps, pe,
-                                                       parent, child);
+    k_ad_children<<<ad_blocks(nb, 256), 256, 0, st>>>(b0, nb, l, Lf, next0, ki, coff, cmask, code, ps, pe, parent,
+                                                       child);
     return hipGetLastError();
 }
 

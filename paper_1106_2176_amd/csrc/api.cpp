@@ -352,11 +352,12 @@ struct AdTree {
     uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
     Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
         is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, ucnt, uoff, units, s27;
+    Buf skey, cstart, ks_a, ks_b, ks_v, ks_h;  // the key sort: sorted keys, coarse starts, scratch
     int64_t max_units = 0;  // bound of the P2P work units (their count stays on the device)
     std::vector<Buf *> bufs() {
         return {&code, &ps, &pe, &parent, &child, &leaf, &cmask, &nchild, &coff, &lev, &col, &vidx, &cnts,
                 &offs, &iu, &iw, &ix, &is_head, &head, &hoff, &lbox, &lstart, &llev, &tgt, &ccnt, &goffd,
-                &offd, &ucnt, &uoff, &units, &s27};
+                &offd, &ucnt, &uoff, &units, &s27, &skey, &cstart, &ks_a, &ks_b, &ks_v, &ks_h};
     }
 };
 
@@ -798,7 +799,11 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     if (!t->ad && !(t->ad = new (std::nothrow) AdTree())) return fail(FMM_ENOMEM, "host allocation failed");
     AdTree *a = t->ad;
     if (!a->hbuf) HIPCHK(hipHostMalloc((void **)&a->hbuf, kAdHostWords * sizeof(uint32_t)));
-    const int64_t nf = (int64_t)1 << (3 * Lf);
+    // the finest keys are sorted themselves (no bin per key of level Lf, so
+    // that the cost does not grow with 8^Lf); box ranges come from the
+    // sorted keys through the first position of each key of level cl
+    const int cl = std::min(Lf, 7);
+    const int64_t nc = (int64_t)1 << (3 * cl), hw = key_sort_hist_words(n);
     // the boxes of a level l >= 1 are non-empty children of split boxes of
     // level l - 1, which are disjoint and hold more than leaf_max each
     int64_t bound = 0;
@@ -809,14 +814,16 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     }
     const size_t u4 = sizeof(uint32_t);
     CHK(ensure(t, t->key10, u4 * n, st));
-    CHK(ensure(t, t->rank, u4 * n, st));
     CHK(ensure(t, t->counters, 4 * u4, st));
-    CHK(ensure(t, t->tmp, u4 * n, st));
     CHK(ensure(t, t->perm, u4 * n, st));
     CHK(ensure(t, t->xyz64, sizeof(double4) * n, st));
-    CHK(ensure(t, t->cnt, u4 * nf, st));
-    CHK(ensure(t, t->start, u4 * (nf + 1), st));
-    CHK(ensure(t, t->scan, u4 * scan_scratch_words(std::max(std::max(nf, n), bound) + 1), st));
+    CHK(ensure(t, t->scan, u4 * scan_scratch_words(bound + 1), st));
+    CHK(ensure(t, a->skey, u4 * n, st));
+    CHK(ensure(t, a->cstart, u4 * (nc + 1), st));
+    CHK(ensure(t, a->ks_a, u4 * n, st));
+    CHK(ensure(t, a->ks_b, u4 * n, st));
+    CHK(ensure(t, a->ks_v, u4 * n, st));
+    CHK(ensure(t, a->ks_h, u4 * (2 * hw + 1 + scan_scratch_words(hw)), st));
     CHK(ensure(t, a->code, u4 * bound, st));
     CHK(ensure(t, a->ps, u4 * bound, st));
     CHK(ensure(t, a->pe, u4 * bound, st));
@@ -830,27 +837,35 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     uint32_t *code = bp<uint32_t>(a->code), *ps = bp<uint32_t>(a->ps), *pe = bp<uint32_t>(a->pe);
     int *parent = bp<int>(a->parent), *child = bp<int>(a->child);
     uint8_t *leaf = bp<uint8_t>(a->leaf);
-    uint32_t *fstart = bp<uint32_t>(t->start), *scan = bp<uint32_t>(t->scan);
+    uint32_t *scan = bp<uint32_t>(t->scan);
+    KeySortWork ksw;
+    ksw.keys_a = bp<uint32_t>(a->ks_a);
+    ksw.keys_b = bp<uint32_t>(a->ks_b);
+    ksw.vals = bp<uint32_t>(a->ks_v);
+    ksw.hist = bp<uint32_t>(a->ks_h);
+    ksw.off = ksw.hist + hw;
+    ksw.scan = ksw.off + hw + 1;
+    const KeyIndex ki{bp<uint32_t>(a->cstart), bp<uint32_t>(a->skey), Lf, cl};
     auto host_read = [&]() -> fmm_status {
         HIPCHK(hipEventRecord(t->ev_counters, st));
         HIPCHK(hipEventSynchronize(t->ev_counters));
         return FMM_OK;
     };
-    HIPCHK(launch_keys(n, dtype, pos, c.box_lo, c.box_size, Lf, bp<uint32_t>(t->key10), bp<uint32_t>(t->cnt),
-                       bp<uint32_t>(t->rank), dc, st));
-    HIPCHK(launch_scan_max(nf, bp<uint32_t>(t->cnt), fstart, scan, dc + 1, dc, nullptr, nullptr, st));
-    HIPCHK(launch_sort(n, Lf, UINT32_MAX, bp<uint32_t>(t->key10), bp<uint32_t>(t->rank), fstart, bp<uint32_t>(t->tmp), dtype,
-                       pos, c.box_lo, c.box_size, bp<uint32_t>(t->perm), nullptr, bp<double4>(t->xyz64), st));
+    HIPCHK(launch_keys(n, dtype, pos, c.box_lo, c.box_size, Lf, bp<uint32_t>(t->key10), nullptr, nullptr, dc, st));
+    HIPCHK(launch_key_sort(n, Lf, bp<uint32_t>(t->key10), ksw, bp<uint32_t>(t->perm), bp<uint32_t>(a->skey), st));
+    HIPCHK(launch_records(n, Lf, bp<uint32_t>(t->perm), bp<uint32_t>(t->key10), dtype, pos, c.box_lo, c.box_size,
+                          bp<double4>(t->xyz64), st));
+    HIPCHK(launch_key_starts(n, Lf, cl, bp<uint32_t>(a->skey), bp<uint32_t>(a->cstart), st));
     a->off[0] = 0;
     a->off[1] = 1;
     HIPCHK(ad_launch_root((uint32_t)n, code, ps, pe, parent, st));
     int l = 0;
     for (;; ++l) {
         const int64_t b0 = a->off[l], nb = a->off[l + 1] - a->off[l];
-        HIPCHK(ad_launch_count(b0, nb, l, Lf, c.leaf_max, code, ps, pe, fstart, leaf, bp<uint32_t>(a->nchild),
+        HIPCHK(ad_launch_count(b0, nb, l, Lf, c.leaf_max, code, ps, pe, ki, leaf, bp<uint32_t>(a->nchild),
                                bp<uint8_t>(a->cmask), st));
         HIPCHK(launch_scan(nb, bp<uint32_t>(a->nchild), bp<uint32_t>(a->coff), scan, st));
-        HIPCHK(ad_launch_children(b0, nb, l, Lf, a->off[l + 1], fstart, bp<uint32_t>(a->coff),
+        HIPCHK(ad_launch_children(b0, nb, l, Lf, a->off[l + 1], ki, bp<uint32_t>(a->coff),
                                   bp<uint8_t>(a->cmask), code, ps, pe, parent, child, st));
         HIPCHK(hipMemcpyAsync(a->hbuf, bp<uint32_t>(a->coff) + nb, u4, hipMemcpyDeviceToHost, st));
         if (l == 0) HIPCHK(hipMemcpyAsync(a->hbuf + 1, dc, u4, hipMemcpyDeviceToHost, st));

@@ -7,7 +7,8 @@
 namespace fmm {
 
 // tree.hip
-// keys + leaf counts + ranks at `level` (zeroes cnt and counters[0..1] first)
+// keys + leaf counts + ranks at `level` (zeroes cnt and counters[0..1] first);
+// with cnt NULL the keys alone
 hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3], double size,
                        int level, uint32_t *key10, uint32_t *cnt, uint32_t *rank,
                        unsigned int *counters, hipStream_t st);
@@ -31,6 +32,23 @@ hipError_t launch_sort(int64_t n, int level, uint32_t skip, const uint32_t *key1
                        const uint32_t *start, uint32_t *tmp, int dtype, const void *pos,
                        const double lo[3], double size, uint32_t *perm, int4 *xyz32,
                        double4 *xyz64, hipStream_t st);
+// Key sort of an adaptive build (no bin per key of the finest level):
+// stable radix sort by the key at `level`, perm (sorted position -> input
+// index) and the sorted keys skey.  Scratch: keys_a, keys_b and vals of n
+// words, hist of key_sort_hist_words(n), off of one more, scan of
+// scan_scratch_words(key_sort_hist_words(n)).
+struct KeySortWork {
+    uint32_t *keys_a, *keys_b, *vals, *hist, *off, *scan;
+};
+int64_t key_sort_hist_words(int64_t n);
+hipError_t launch_key_sort(int64_t n, int level, const uint32_t *key10, const KeySortWork &w, uint32_t *perm,
+                           uint32_t *skey, hipStream_t st);
+// FP64 leaf-relative records at `level` in sorted order
+hipError_t launch_records(int64_t n, int level, const uint32_t *perm, const uint32_t *key10, int dtype,
+                          const void *pos, const double lo[3], double size, double4 *xyz64, hipStream_t st);
+// cstart[x], x in [0, 8^cl]: the first sorted position whose key at level
+// cl is >= x, from the keys at `level` >= cl sorted (skey)
+hipError_t launch_key_starts(int64_t n, int level, int cl, const uint32_t *skey, uint32_t *cstart, hipStream_t st);
 hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long long *out,
                              hipStream_t st);
 
@@ -99,10 +117,16 @@ hipError_t launch_m2l_rot(int P, int L, void *const *B, void *const *Lc, const d
 // adaptive.hip: the adaptive octree (FP64 form); see the file's header for
 // the layout.  Build steps (per level, host-driven) and list construction:
 hipError_t ad_launch_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe, int *parent, hipStream_t st);
+// the sorted keys of the finest level Lf and the first position of each
+// key of level cl <= Lf (cstart[8^cl + 1]), for the box ranges
+struct KeyIndex {
+    const uint32_t *cstart, *skey;
+    int Lf, cl;
+};
 hipError_t ad_launch_count(int64_t b0, int64_t nb, int l, int Lf, int leaf_max, const uint32_t *code,
-                           const uint32_t *ps, const uint32_t *pe, const uint32_t *fstart, uint8_t *leaf,
+                           const uint32_t *ps, const uint32_t *pe, const KeyIndex &ki, uint8_t *leaf,
                            uint32_t *nchild, uint8_t *cmask, hipStream_t st);
-hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const uint32_t *fstart,
+hipError_t ad_launch_children(int64_t b0, int64_t nb, int l, int Lf, int64_t next0, const KeyIndex &ki,
                               const uint32_t *coff, const uint8_t *cmask, uint32_t *code, uint32_t *ps,
                               uint32_t *pe, int *parent, int *child, hipStream_t st);
 hipError_t ad_launch_structure(int64_t nbox, int nlev, const int64_t *off_host, const int64_t *off_dev,

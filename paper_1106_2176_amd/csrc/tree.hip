@@ -46,7 +46,7 @@ __global__ void k_keys(int64_t n, const T *__restrict__ pos, double lo0, double 
     else
         atomicAdd(nbad, 1u);
     key10[i] = k;
-    rank[i] = atomicAdd(&cnt[k >> shift], 1u);
+    if (cnt) rank[i] = atomicAdd(&cnt[k >> shift], 1u);
 }
 
 // Leaf counts and ranks at another level, from the keys.
@@ -277,6 +277,133 @@ __global__ __launch_bounds__(256) void k_fixup(int L, uint32_t skip, const uint3
     }
 }
 
+// ----------------------------------------------------- key sort (adaptive)
+// Stable LSD radix sort of the particles by their key at a level (the 3L
+// high bits of the level-10 key), 8 bits a pass, for trees whose finest
+// level is too deep for a bin per key (8^L bins): the first pass takes the
+// input order as the values, so ties keep input order and the last pass's
+// values are the permutation (sorted position -> input index); the last
+// pass also writes the sorted keys.  A block takes 4096 elements, element
+// j * 256 + t of its range in thread t's step j (so the steps in order visit
+// the block's elements in index order).  Per pass one kernel writes each
+// block's digit histogram, digit-major (a scan then gives every (digit,
+// block) its output offset), and one places each element at its offset plus
+// its rank among the block's earlier elements of the same digit: within a
+// wave from ballots on the digit's bits, across waves and steps from LDS
+// counts.
+constexpr int kKsSteps = 16, kKsBlock = 256 * kKsSteps;
+
+__device__ __forceinline__ uint32_t ks_key(bool first, int64_t e, const uint32_t *__restrict__ key10, int shift,
+                                           const uint32_t *__restrict__ kin) {
+    return first ? key10[e] >> shift : kin[e];
+}
+
+__global__ __launch_bounds__(256) void k_ks_hist(int64_t n, int64_t nblocks, int first,
+                                                 const uint32_t *__restrict__ key10, int shift,
+                                                 const uint32_t *__restrict__ kin, int bit, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kKsBlock;
+    for (int j = 0; j < kKsSteps; ++j) {
+        const int64_t e = base + j * 256 + threadIdx.x;
+        if (e < n) atomicAdd(&h[(ks_key(first, e, key10, shift, kin) >> bit) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_ks_scatter(int64_t n, int64_t nblocks, int first,
+                                                    const uint32_t *__restrict__ key10, int shift,
+                                                    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                    int bit, const uint32_t *__restrict__ off,
+                                                    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    __shared__ uint32_t wcnt[2][4][256];  // per step parity and wave: the step's count of each digit
+    __shared__ uint32_t run[256];         // the block's elements of each digit in earlier steps
+    __shared__ uint32_t goff[256];        // the block's output offset of each digit
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    goff[tid] = off[(int64_t)tid * nblocks + blockIdx.x];
+    run[tid] = 0;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * kKsBlock;
+    for (int j = 0; j < kKsSteps; ++j) {
+        const int64_t e = base + j * 256 + tid;
+        const bool valid = e < n;
+        const uint32_t key = valid ? ks_key(first, e, key10, shift, kin) : 0u;
+        const uint32_t d = (key >> bit) & 255u;
+        // this wave's row of counts of this step's parity, cleared: it was
+        // last read two steps back, before the previous step's first barrier
+        uint32_t(*const cnt)[256] = wcnt[j & 1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cnt[wave][lane + 64 * i] = 0u;
+        // the lanes of the wave holding the same digit
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint64_t bk = __ballot(valid && ((d >> k) & 1u));
+            m &= ((d >> k) & 1u) ? bk : ~bk;
+        }
+        __syncthreads();  // the rows are cleared
+        if (valid && (m & below) == 0) cnt[wave][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t r = run[d] + (uint32_t)__popcll(m & below);
+            for (int w = 0; w < wave; ++w) r += cnt[w][d];
+            const uint32_t dst = goff[d] + r;
+            kout[dst] = key;
+            vout[dst] = first ? (uint32_t)e : vin[e];
+        }
+        __syncthreads();  // every read of run of this step is done
+        run[tid] += cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
+    }
+}
+
+__global__ void k_iota(int64_t n, uint32_t *__restrict__ v, uint32_t *__restrict__ zero) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        v[i] = (uint32_t)i;
+        zero[i] = 0u;
+    }
+}
+
+// Sorted records: for sorted position d the particle perm[d] relative to its
+// leaf centre in units of the leaf width, u = s 2^L - (i + 1/2), computed in
+// FP64 as the fix-up does.
+template <typename T>
+__global__ void k_records(int64_t n, int L, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ key10,
+                          const T *__restrict__ pos, double lo0, double lo1, double lo2, double size,
+                          double4 *__restrict__ xyz64) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    const uint32_t me = perm[d];
+    const uint32_t leaf = key10[me] >> (3 * (10 - L));
+    const double scale = (double)(1u << L);
+    const double bx = (double)compact3(leaf) + 0.5, by = (double)compact3(leaf >> 1) + 0.5,
+                 bz = (double)compact3(leaf >> 2) + 0.5;
+    const double ux = ((double)pos[3 * (size_t)me] - lo0) / size * scale - bx;
+    const double uy = ((double)pos[3 * (size_t)me + 1] - lo1) / size * scale - by;
+    const double uz = ((double)pos[3 * (size_t)me + 2] - lo2) / size * scale - bz;
+    xyz64[d] = make_double4(ux, uy, uz, 0.0);
+}
+
+// First sorted position of every key at level cl (cstart[x], x in
+// [0, 8^cl]) from the keys at level L >= cl sorted: a binary search per x
+// (an empty stretch of keys costs no thread more than another).
+__global__ void k_key_starts(int64_t n, int sh, const uint32_t *__restrict__ skey, int64_t nc,
+                             uint32_t *__restrict__ cstart) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > nc) return;
+    int64_t lo = 0, hi = n;  // first d with skey[d] >> sh >= x
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)(skey[mid] >> sh) < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    cstart[x] = (uint32_t)lo;
+}
+
 // Per leaf: n_t * (sum of counts over the near leaves) ; summed in int64.
 __global__ void k_pair_count(int L, const uint32_t *__restrict__ start,
                              unsigned long long *__restrict__ out) {
@@ -308,7 +435,8 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 hipError_t launch_keys(int64_t n, int dtype, const void *pos, const double lo[3], double size,
                        int level, uint32_t *key10, uint32_t *cnt, uint32_t *rank,
                        unsigned int *counters, hipStream_t st) {
-    const int64_t nb = (int64_t)1 << (3 * level);
+    // without cnt, the keys alone (for the key sort)
+    const int64_t nb = cnt ? (int64_t)1 << (3 * level) : 0;
     // counters: [0] positions out of the domain, [1] largest leaf count
     k_zero<<<nblk(std::max<int64_t>(nb, 2), 256), 256, 0, st>>>(nb, cnt, counters, 2);
     const int shift = 3 * (10 - level);
@@ -401,6 +529,51 @@ hipError_t launch_pair_count(int level, const uint32_t *start, unsigned long lon
     hipError_t e = hipMemsetAsync(out, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     k_pair_count<<<nblk(nb, 256), 256, 0, st>>>(level, start, out);
+    return hipGetLastError();
+}
+
+int64_t key_sort_hist_words(int64_t n) { return 256 * ((n + kKsBlock - 1) / kKsBlock); }
+
+hipError_t launch_key_sort(int64_t n, int level, const uint32_t *key10, const KeySortWork &w, uint32_t *perm,
+                           uint32_t *skey, hipStream_t st) {
+    const int passes = (3 * level + 7) / 8, shift = 3 * (10 - level);
+    const int64_t nblocks = (n + kKsBlock - 1) / kKsBlock;
+    if (passes == 0) {
+        k_iota<<<nblk(n, 256), 256, 0, st>>>(n, perm, skey);
+        return hipGetLastError();
+    }
+    // values alternate between perm and w.vals so that the last pass writes
+    // perm; keys between two buffers, the last pass writing skey
+    const uint32_t *kin = nullptr, *vin = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        const int back = passes - 1 - p;  // passes after this one
+        uint32_t *kout = back == 0 ? skey : ((p & 1) ? w.keys_b : w.keys_a);
+        uint32_t *vout = (back & 1) ? w.vals : perm;
+        k_ks_hist<<<(unsigned)nblocks, 256, 0, st>>>(n, nblocks, p == 0, key10, shift, kin, 8 * p, w.hist);
+        hipError_t e = launch_scan(256 * nblocks, w.hist, w.off, w.scan, st);
+        if (e != hipSuccess) return e;
+        k_ks_scatter<<<(unsigned)nblocks, 256, 0, st>>>(n, nblocks, p == 0, key10, shift, kin, vin, 8 * p, w.off,
+                                                        kout, vout);
+        kin = kout;
+        vin = vout;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_records(int64_t n, int level, const uint32_t *perm, const uint32_t *key10, int dtype,
+                          const void *pos, const double lo[3], double size, double4 *xyz64, hipStream_t st) {
+    if (dtype == FMM_F64)
+        k_records<double><<<nblk(n, 256), 256, 0, st>>>(n, level, perm, key10, (const double *)pos, lo[0], lo[1],
+                                                        lo[2], size, xyz64);
+    else
+        k_records<float><<<nblk(n, 256), 256, 0, st>>>(n, level, perm, key10, (const float *)pos, lo[0], lo[1],
+                                                       lo[2], size, xyz64);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_starts(int64_t n, int level, int cl, const uint32_t *skey, uint32_t *cstart, hipStream_t st) {
+    const int64_t nc = (int64_t)1 << (3 * cl);
+    k_key_starts<<<nblk(nc + 1, 256), 256, 0, st>>>(n, 3 * (level - cl), skey, nc, cstart);
     return hipGetLastError();
 }
 
