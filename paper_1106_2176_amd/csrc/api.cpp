@@ -801,8 +801,10 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     if (!a->hbuf) HIPCHK(hipHostMalloc((void **)&a->hbuf, kAdHostWords * sizeof(uint32_t)));
     // the finest keys are sorted themselves (no bin per key of level Lf, so
     // that the cost does not grow with 8^Lf); box ranges come from the
-    // sorted keys through the first position of each key of level cl
-    const int cl = std::min(Lf, 7);
+    // sorted keys through the first position of each key of level cl, the
+    // first level with about as many keys as particles (at most 7)
+    int cl = 0;
+    while (cl < std::min(Lf, 7) && ((int64_t)1 << (3 * cl)) < n) ++cl;
     const int64_t nc = (int64_t)1 << (3 * cl), hw = key_sort_hist_words(n);
     // the boxes of a level l >= 1 are non-empty children of split boxes of
     // level l - 1, which are disjoint and hold more than leaf_max each
