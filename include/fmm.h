@@ -160,7 +160,9 @@ typedef struct {
                                   neither contains the other.  Every step is
                                   FP64 except, in the mixed form, the M2L (the
                                   binary16 encoding described at m2l_fp16,
-                                  with one operand scale per level).
+                                  with one operand scale per level) and the
+                                  P2P pairs (FP32 on FP64 differences, FP64
+                                  merges).
                                   fmm_backward runs the transposed chain over
                                   the same lists; the build
                                   blocks once per tree level and once more at

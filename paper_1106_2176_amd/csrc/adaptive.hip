@@ -27,7 +27,7 @@
 // as in the uniform tree, so the same translation tables serve.  Potentials
 // and fields leave the kernels in root units (phi * size, E * size^2).  Every
 // kernel works in FP64 except the mixed form's M2L (binary16 parts on the
-// 16-bit matrix cores).
+// 16-bit matrix cores) and its P2P pairs (FP32 on FP64 differences).
 #include <algorithm>
 
 #include "harmonics.hpp"
@@ -837,6 +837,27 @@ __device__ __forceinline__ void ad_pair(double xi, double yi, double zi, const d
     ez = __builtin_fma(qr3, dz, ez);
 }
 
+// The mixed form's pair: the FP64 difference rounded once to FP32 (both
+// points in the target leaf's frame, so it carries no cancellation against
+// absolute positions), then the FP32 arithmetic of the uniform tree's mixed
+// P2P with the hardware reciprocal square root.
+template <bool SELF>
+__device__ __forceinline__ void ad_pair32(double xi, double yi, double zi, const double4 s, float &phi, float &ex,
+                                          float &ey, float &ez) {
+    const float dx = (float)(xi - s.x), dy = (float)(yi - s.y), dz = (float)(zi - s.z);
+    float r2 = dx * dx;
+    r2 = __builtin_fmaf(dy, dy, r2);
+    r2 = __builtin_fmaf(dz, dz, r2);
+    float y = __builtin_amdgcn_rsqf(r2);
+    if (SELF) y = r2 > 0.0f ? y : 0.0f;
+    const float qr = (float)s.w * y;
+    phi += qr;
+    const float qr3 = qr * (y * y);
+    ex = __builtin_fmaf(qr3, dx, ex);
+    ey = __builtin_fmaf(qr3, dy, ey);
+    ez = __builtin_fmaf(qr3, dz, ez);
+}
+
 // P2P over U at the leaves (FP64), one wave per unit of up to 64 targets of
 // one leaf (a leaf of more than 64 particles gives several units, so that
 // the work of the fullest leaves spreads over several waves).  The unit's
@@ -860,7 +881,9 @@ struct AdP2PShared {
 
 // FUSE (1: FP32, 2: FP64 caller data): each target's sums go through the
 // combine with its far field (c) into the caller's order instead of out.
-template <int FUSE>
+// F32 (the mixed form): the pairs in FP32 (ad_pair32), each tile's partial
+// sums merged into the FP64 sums.
+template <int FUSE, bool F32>
 __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, int lg, uint32_t cg, uint32_t t0,
                                             uint32_t nt, uint32_t u0, uint32_t u1, const int *__restrict__ iu,
                                             const int *__restrict__ lev, const uint32_t *__restrict__ code,
@@ -918,11 +941,23 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
             sh.tile[lane] = src;
             wave_sync();
             if (act) {
+                if constexpr (F32) {
+                    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f;
 #pragma unroll 4
-                for (int k = grp; k < 64; k += G) {
-                    const double4 sk = sh.tile[k];
-                    ad_pair<true>(r0.x, r0.y, r0.z, sk, phi0, ex0, ey0, ez0);
-                    ad_pair<true>(r1.x, r1.y, r1.z, sk, phi1, ex1, ey1, ez1);
+                    for (int k = grp; k < 64; k += G) {
+                        const double4 sk = sh.tile[k];
+                        ad_pair32<true>(r0.x, r0.y, r0.z, sk, a0, a1, a2, a3);
+                        ad_pair32<true>(r1.x, r1.y, r1.z, sk, b0, b1, b2, b3);
+                    }
+                    phi0 += (double)a0; ex0 += (double)a1; ey0 += (double)a2; ez0 += (double)a3;
+                    phi1 += (double)b0; ex1 += (double)b1; ey1 += (double)b2; ez1 += (double)b3;
+                } else {
+#pragma unroll 4
+                    for (int k = grp; k < 64; k += G) {
+                        const double4 sk = sh.tile[k];
+                        ad_pair<true>(r0.x, r0.y, r0.z, sk, phi0, ex0, ey0, ez0);
+                        ad_pair<true>(r1.x, r1.y, r1.z, sk, phi1, ex1, ey1, ez1);
+                    }
                 }
             }
         }
@@ -952,7 +987,7 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
     }
 }
 
-template <int FUSE>
+template <int FUSE, bool F32>
 __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
     const uint32_t *__restrict__ nunits, const int2 *__restrict__ units, const int *__restrict__ lbox,
     const uint32_t *__restrict__ lstart, const uint32_t *__restrict__ ou, const int *__restrict__ iu,
@@ -966,8 +1001,8 @@ __global__ __launch_bounds__(64 * kAdP2PWaves) void k_ad_p2p(
     const int j = un.x;
     const int g = lbox[j];
     const uint32_t t0 = lstart[j] + (uint32_t)un.y, nt = min(64u, lstart[j + 1] - t0);
-    ad_p2p_unit<FUSE>(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe, rec,
-                      out, c);
+    ad_p2p_unit<FUSE, F32>(shm[wave], lane, g, lev[g], code[g], t0, nt, ou[g], ou[g + 1], iu, lev, code, ps, pe,
+                           rec, out, c);
 }
 
 // Gathered M2L (FP64 MFMA), added to the locals: the targets of each (level,
@@ -1673,18 +1708,23 @@ hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint
 hipError_t ad_launch_p2p(int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
                          const uint32_t *lstart, const uint32_t *ou, const int *iu, const int *lev, const uint32_t *code,
                          const uint32_t *ps, const uint32_t *pe, const double4 *rec, double4 *out, const Combine *fuse,
-                         hipStream_t st) {
+                         bool f32, hipStream_t st) {
     const Combine c = fuse ? *fuse : Combine{};
     const unsigned grid = ad_blocks(max_units, kAdP2PWaves);
-    if (!fuse)
-        k_ad_p2p<0><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, rec,
-                                                      out, c);
-    else if (fuse->dtype == FMM_F64)
-        k_ad_p2p<2><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, rec,
-                                                      out, c);
-    else
-        k_ad_p2p<1><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, rec,
-                                                      out, c);
+#define AD_P2P(FU, F)                                                                                          \
+    k_ad_p2p<FU, F><<<grid, 64 * kAdP2PWaves, 0, st>>>(nunits, units, lbox, lstart, ou, iu, lev, code, ps, pe, \
+                                                        rec, out, c)
+    const int fu = !fuse ? 0 : fuse->dtype == FMM_F64 ? 2 : 1;
+    if (f32) {
+        if (fu == 0) AD_P2P(0, true);
+        else if (fu == 2) AD_P2P(2, true);
+        else AD_P2P(1, true);
+    } else {
+        if (fu == 0) AD_P2P(0, false);
+        else if (fu == 2) AD_P2P(2, false);
+        else AD_P2P(1, false);
+    }
+#undef AD_P2P
     return hipGetLastError();
 }
 

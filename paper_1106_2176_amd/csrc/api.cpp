@@ -1025,7 +1025,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
     t->p2p_side[t->cur] = side;
     auto p2p = [&](hipStream_t s2, const Combine *cf) -> hipError_t {
         return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
-                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf, s2);
+                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf,
+                             t->cfg.precision == FMM_PREC_MIXED, s2);
     };
     if (side) {
         if (!t->side) {

@@ -216,11 +216,12 @@ hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const
 hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint32_t *cnt, const uint32_t *uoff,
                            int2 *units, hipStream_t st);
 // one wave per unit; max_units bounds *nunits (the grid's size)
-// with fuse non-NULL the kernel ends with the combine (no near partials)
+// with fuse non-NULL the kernel ends with the combine (no near partials);
+// f32: the pair arithmetic in FP32 (the mixed form)
 hipError_t ad_launch_p2p(int64_t max_units, const uint32_t *nunits, const int2 *units, const int *lbox,
                          const uint32_t *lstart, const uint32_t *ou, const int *iu, const int *lev, const uint32_t *code,
                          const uint32_t *ps, const uint32_t *pe, const double4 *rec, double4 *out, const Combine *fuse,
-                         hipStream_t st);
+                         bool f32, hipStream_t st);
 
 // scratch.hip: device address of the current device's static scratch array
 // (FMM_NOALLOC_SCRATCH_BYTES), looked up on the first call per device
