@@ -940,11 +940,13 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
             wave_sync();  // the previous tile has been read
             sh.tile[lane] = src;
             wave_sync();
+            // the tile's sources (the last tile of a batch is partly filled)
+            const int ns = (int)min(64u, total - f0);
             if (act) {
                 if constexpr (F32) {
                     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f, b3 = 0.0f;
 #pragma unroll 4
-                    for (int k = grp; k < 64; k += G) {
+                    for (int k = grp; k < ns; k += G) {
                         const double4 sk = sh.tile[k];
                         ad_pair32<true>(r0.x, r0.y, r0.z, sk, a0, a1, a2, a3);
                         ad_pair32<true>(r1.x, r1.y, r1.z, sk, b0, b1, b2, b3);
@@ -953,7 +955,7 @@ __device__ __forceinline__ void ad_p2p_unit(AdP2PShared &sh, int lane, int g, in
                     phi1 += (double)b0; ex1 += (double)b1; ey1 += (double)b2; ez1 += (double)b3;
                 } else {
 #pragma unroll 4
-                    for (int k = grp; k < 64; k += G) {
+                    for (int k = grp; k < ns; k += G) {
                         const double4 sk = sh.tile[k];
                         ad_pair<true>(r0.x, r0.y, r0.z, sk, phi0, ex0, ey0, ez0);
                         ad_pair<true>(r1.x, r1.y, r1.z, sk, phi1, ex1, ey1, ez1);
