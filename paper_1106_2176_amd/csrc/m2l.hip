@@ -242,10 +242,15 @@ struct MixCfg {
     static constexpr int UNROLL = NA == 6 ? 12 : 8;
     static constexpr int MERGE = NA == 6 ? 6 : 8;
     static constexpr int NBL = NB * 2;               // multipole loads per K-step
+    // A fragments read one step ahead (step) while the two steps' fragments
+    // and the accumulators fit two waves per SIMD without spilling (up to
+    // p = 12 with two parts, 11 with three), else during their own step,
+    // one split part at a time (step8)
+    static constexpr bool PIPE = NW != 8 || 8 * NSPLIT * RT + 12 * RT <= 288;
     // loads this wave issues after the operator chunks it waits for at the
-    // top of step kc (those of step kc + 1 with four waves, of step kc with
-    // eight, issued NA - 1 steps earlier either way): the multipole loads of
-    // that step and everything of the NA - 2 steps between
+    // top of step kc (those of step kc + 1 with PIPE, else of step kc, issued
+    // NA - 1 steps earlier either way): the multipole loads of that step and
+    // everything of the NA - 2 steps between
     static constexpr int VMW = NBL + (NA - 2) * (CPW + NBL);
     static constexpr int NPC = kOffsetsPerClass * PPO;  // K pieces of a class
     static constexpr int NCH = ((NPC + 3) / 4 + UNROLL - 1) / UNROLL * UNROLL;  // K-steps, padded
@@ -395,11 +400,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     };
     float4 bv[D][NB][2];
     bf16x8 af[RT][NSPLIT], bf[NB][NSPLIT];
-    // NW = 8 reads each step's A fragments from its own stage during the step
-    // (one split part at a time, to fit two waves per SIMD), so its ring is
-    // one step shorter: step kc copies step kc + NA - 1 into the stage of
-    // step kc - 1, which every wave has finished reading by step kc's barrier
-    constexpr int PRE = NW == 8 ? NA - 1 : NA;
+    // Without PIPE each step's A fragments are read from its own stage
+    // during the step, so the ring is one step shorter: step kc copies step
+    // kc + NA - 1 into the stage of step kc - 1, which every wave has finished
+    // reading by step kc's barrier.  Reading them a step ahead (PIPE) lets the
+    // matrix products start right after the barrier: 2.3% faster at C2 and
+    // C3 (p = 10), where waiting at every step for all of the step's
+    // fragments had held them back.
+    constexpr bool PIPE = C::PIPE;
+    constexpr int PRE = PIPE ? NA : NA - 1;
     static_for<0, PRE>([&](auto ic) __attribute__((always_inline)) {
         issue_a(kbeg + decltype(ic)::value, stage(ic));
     });
@@ -410,7 +419,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     // and waits for every load in flight at each pass through the header.
     wait_vm<0>();
     lds_barrier();
-    if constexpr (NW != 8) read_a(stage(std::integral_constant<int, 0>{}), af);
+    if constexpr (PIPE) read_a(stage(std::integral_constant<int, 0>{}), af);
 #pragma unroll
     for (int b = 0; b < NB; ++b) b_parts<NSPLIT, H>(bv[0][b][0], bv[0][b][1], bf[b]);
 
@@ -496,10 +505,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
     for (int kc = kbeg; kc < kend; kc += UNROLL) {
         static_for<0, UNROLL>([&](auto ic) __attribute__((always_inline)) {
             constexpr int i = decltype(ic)::value;
-            if constexpr (NW == 8)
-                step8(kc + i, ic);
-            else
+            if constexpr (PIPE)
                 step(kc + i, ic);
+            else
+                step8(kc + i, ic);
             if constexpr ((i + 1) % MERGE == 0) merge();  // every MERGE * 32 <= 256 K terms
         });
     }
