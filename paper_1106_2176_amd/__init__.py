@@ -23,10 +23,10 @@ FMM_F32, FMM_F64 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 VEC_NONE, VEC_FIELD, VEC_FORCE = 0, 1, 2
 PART_NEAR_ONLY, PART_FAR_ONLY = 4, 8
-# default depth cap of the adaptive tree (up to 10; on 10^6 particles in
-# Gaussian blobs caps of 9 and 10 halve the P2P pairs but add boxes, M2L and
-# build time, for about the same total)
-ADAPTIVE_MAX_LEVEL = 8
+# default depth cap of the adaptive tree: the deepest, 10 (the build sorts
+# the keys, so a deep cap costs little; on 10^7 particles in Gaussian blobs a
+# cap of 8 leaves leaves far over leaf_max and takes 3x as long)
+ADAPTIVE_MAX_LEVEL = 10
 STAGES = ("gather", "P2M", "M2M", "pack", "M2L", "L2L", "L2P", "P2P", "combine")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -163,7 +163,7 @@ def test_rebuild_and_graph_replay(oracle_mod):
     recaptures); replays equal eager calls."""
     pos1, q1 = inputs.clustered(12_000, 51)
     pos2, q2 = inputs.clustered(9_000, 52, blobs=3)
-    ref2 = oracle_mod.fmm_adaptive(pos2, q2, 6, 32, 8)
+    ref2 = oracle_mod.fmm_adaptive(pos2, q2, 6, 32, fmm.ADAPTIVE_MAX_LEVEL)
     with fmm.Tree(dev(pos1), p=6, leaf_max=32, precision="fp64", adaptive=True) as eager, \
             fmm.Tree(dev(pos1), p=6, leaf_max=32, precision="fp64", adaptive=True, graph=True) as g:
         Q1 = dev(q1)
