@@ -160,9 +160,10 @@ typedef struct {
                                   neither contains the other.  Every step is
                                   FP64 except, in the mixed form, the M2L (the
                                   binary16 encoding described at m2l_fp16,
-                                  with one operand scale per level) and the
+                                  with one operand scale per level), the
                                   P2P pairs (FP32 on FP64 differences, FP64
-                                  merges).
+                                  merges) and the P2L and M2P terms (FP32 per
+                                  particle and box, summed in FP64).
                                   fmm_backward runs the transposed chain over
                                   the same lists; the build
                                   blocks once per tree level and once more at

@@ -26,8 +26,9 @@
 // their own box (mu = sum q rho(u)), locals ell with phi = (1/w) ell . rho(u),
 // as in the uniform tree, so the same translation tables serve.  Potentials
 // and fields leave the kernels in root units (phi * size, E * size^2).  Every
-// kernel works in FP64 except the mixed form's M2L (binary16 parts on the
-// 16-bit matrix cores) and its P2P pairs (FP32 on FP64 differences).
+// kernel works in FP64 except, in the mixed form, the M2L (binary16 parts on
+// the 16-bit matrix cores), the P2P pairs (FP32 on FP64 differences) and the
+// P2L and M2P terms (FP32, summed in FP64).
 #include <algorithm>
 
 #include "harmonics.hpp"
@@ -561,28 +562,28 @@ __global__ __launch_bounds__(64) void k_ad_l2p(const int *__restrict__ lbox, con
 // the translation operators: I_0^0 = 1/r, I_m^m = -(2m-1) (x+iy)/r^2
 // I_{m-1}^{m-1}, I_{m+1}^m = (2m+1) z/r^2 I_m^m, r^2 I_n^m = (2n-1) z
 // I_{n-1}^m - (n-m-1)(n+m-1) I_{n-2}^m), visited column by column: f(n, m,
-// re, im) for every pair.
-template <int N, typename F>
-__device__ __forceinline__ void irregular_each(double x, double y, double z, F &&f) {
-    const double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
-    double dr = sqrt(ir2), di = 0.0;  // I_m^m
+// re, im) for every pair, in the arithmetic type R of the position.
+template <int N, typename R, typename F>
+__device__ __forceinline__ void irregular_each(R x, R y, R z, F &&f) {
+    const R r2 = x * x + y * y + z * z, ir2 = R(1) / r2;
+    R dr = sqrt(ir2), di = R(0);  // I_m^m
 #pragma unroll
     for (int m = 0; m <= N; ++m) {
         if (m > 0) {
-            const double k = -(2.0 * m - 1.0) * ir2;
-            const double nr = k * (x * dr - y * di), ni = k * (x * di + y * dr);
+            const R k = -R(2 * m - 1) * ir2;
+            const R nr = k * (x * dr - y * di), ni = k * (x * di + y * dr);
             dr = nr;
             di = ni;
         }
-        double ar = dr, ai = di, br = 0.0, bi = 0.0;
+        R ar = dr, ai = di, br = R(0), bi = R(0);
 #pragma unroll
         for (int n = m; n <= N; ++n) {
-            double cr = ar, ci = ai;
+            R cr = ar, ci = ai;
             if (n == m + 1) {
-                cr = (2.0 * m + 1.0) * z * ir2 * ar;
-                ci = (2.0 * m + 1.0) * z * ir2 * ai;
+                cr = R(2 * m + 1) * z * ir2 * ar;
+                ci = R(2 * m + 1) * z * ir2 * ai;
             } else if (n > m + 1) {
-                const double a = (2.0 * n - 1.0) * z, b = (double)((n - m - 1) * (n + m - 1));
+                const R a = R(2 * n - 1) * z, b = R((n - m - 1) * (n + m - 1));
                 cr = (a * ar - b * br) * ir2;
                 ci = (a * ai - b * bi) * ir2;
             }
@@ -605,15 +606,18 @@ __device__ __forceinline__ void irregular_each(double x, double y, double z, F &
 // particles of X(g) are taken as one sequence (up to 64 list entries at a
 // time, offsets by a wave scan, each lane finding its entry by bisection),
 // B of them at a time each expanded by one lane into an LDS row, and the
-// rows summed coefficient by coefficient.
-template <int P>
+// rows summed coefficient by coefficient.  R is the arithmetic of the
+// expansion (FP32 in the mixed form, the offset formed in FP64 and rounded
+// once); the rows are summed in FP64.
+template <int P, typename R>
 __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, const int *__restrict__ ix,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                                const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
                                                int adj, const double4 *__restrict__ rec, double *__restrict__ Lc) {
     constexpr int P2 = P * P, S = coef_stride(P), NC = (P2 + 63) / 64;
-    constexpr int B = P <= 8 ? 32 : (P <= 11 ? 16 : 8);  // rows of at most ~17 KB (2 waves per SIMD)
-    __shared__ double rows[B][P2 + 1];
+    // rows of at most ~17 KB (2 waves per SIMD)
+    constexpr int B = (P <= 8 ? 32 : (P <= 11 ? 16 : 8)) * (int)(sizeof(double) / sizeof(R));
+    __shared__ R rows[B][P2 + 1];
     __shared__ double4 frame[64];
     __shared__ uint32_t first[64], off[65];
     const int g = blockIdx.x, t = threadIdx.x;
@@ -649,7 +653,7 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
         for (uint32_t f0 = 0; f0 < total; f0 += B) {
             __syncthreads();  // the previous rows have been summed
             if (t < B) {
-                double *row = rows[t];
+                R *row = rows[t];
                 const uint32_t f = f0 + t;
                 if (f < total) {
                     int lo = 0, hi = nb - 1;
@@ -660,18 +664,18 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
                     }
                     const double4 fr = frame[lo];
                     const double4 v = rec[first[lo] + (f - off[lo])];
-                    const double q = v.w;
-                    irregular_each<P - 1>(fr.x + fr.w * v.x, fr.y + fr.w * v.y, fr.z + fr.w * v.z,
-                                          [&](int n, int m, double re, double im) {
+                    const R q = (R)v.w;
+                    irregular_each<P - 1>((R)(fr.x + fr.w * v.x), (R)(fr.y + fr.w * v.y), (R)(fr.z + fr.w * v.z),
+                                          [&](int n, int m, R re, R im) {
                                               if (m == 0) {
                                                   row[n * n] = q * re;
                                               } else {
-                                                  row[n * n + 2 * m - 1] = 2.0 * q * re;
-                                                  row[n * n + 2 * m] = -2.0 * q * im;
+                                                  row[n * n + 2 * m - 1] = R(2) * q * re;
+                                                  row[n * n + 2 * m] = -R(2) * q * im;
                                               }
                                           });
                 } else {
-                    for (int k = 0; k < P2; ++k) row[k] = 0.0;
+                    for (int k = 0; k < P2; ++k) row[k] = R(0);
                 }
             }
             __syncthreads();
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
             for (int a = 0; a < NC; ++a) {
                 const int k = t + 64 * a;
                 if (k < P2)
-                    for (int r = 0; r < B; ++r) acc[a] += rows[r][k];
+                    for (int r = 0; r < B; ++r) acc[a] += (double)rows[r][k];
             }
         }
     }
@@ -701,9 +705,11 @@ __global__ __launch_bounds__(64) void k_ad_p2l(const uint32_t *__restrict__ ox, 
 // transpose of P2L and its position derivative: phi, E * 2^l_w).  One wave per unit
 // of up to 64 targets (the P2P units): the targets take T = 2^LT lanes, and
 // the 64 / T lane groups take the boxes of W(g) in turn, each staging its
-// box's multipole in LDS; the groups' sums are joined by shuffles.
-template <int P, int LT>
-__device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int adj, int g, int lg, uint32_t cg,
+// box's multipole in LDS; the groups' sums are joined by shuffles.  R is
+// the arithmetic of one box's terms (FP32 in the mixed form: multipole and
+// offset rounded once); the boxes' sums are added in FP64.
+template <int P, int LT, typename R>
+__device__ __forceinline__ void ad_m2p_unit(R (*mus)[P * P], int lane, int adj, int g, int lg, uint32_t cg,
                                             uint32_t t0, uint32_t nt, uint32_t w0, uint32_t w1,
                                             const int *__restrict__ iw,
                                             const int *__restrict__ lev, const uint32_t *__restrict__ code,
@@ -714,25 +720,25 @@ __device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int 
     const bool live = (uint32_t)slot < nt;
     const double4 r = live ? rec[t0 + slot] : make_double4(0.0, 0.0, 0.0, 0.0);
     double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-    double *const mu = mus[grp];
+    R *const mu = mus[grp];
     for (uint32_t e0 = w0; e0 < w1; e0 += G) {
         const uint32_t e = e0 + grp;
         const bool has = e < w1;
         const int w = has ? iw[e] : 0;
         wave_sync();  // the previous round's multipoles have been read
         if (has)
-            for (int c = slot; c < P2; c += T) mu[c] = M[(size_t)w * S + c];
+            for (int c = slot; c < P2; c += T) mu[c] = (R)M[(size_t)w * S + c];
         wave_sync();
         if (!has) continue;
         const int lw = lev[w];
         double cx, cy, cz;
         ad_centre_diff(lg, cg, lw, code[w], lw, cx, cy, cz);
         const double sc = ldexp(1.0, lw - lg);
-        double l00 = 0.0, l10 = 0.0, l11r = 0.0, l11i = 0.0;
-        irregular_each<P>(cx + sc * r.x, cy + sc * r.y, cz + sc * r.z, [&](int n, int m, double ir, double ii) {
+        R l00 = R(0), l10 = R(0), l11r = R(0), l11i = R(0);
+        irregular_each<P>((R)(cx + sc * r.x), (R)(cy + sc * r.y), (R)(cz + sc * r.z), [&](int n, int m, R ir, R ii) {
             // M_{n'}^{m'} of the multipole (0 outside n' < P, 0 <= m' <= n')
-            auto Mc = [&](int nn, int mm, double &mr, double &mi) {
-                mr = mi = 0.0;
+            auto Mc = [&](int nn, int mm, R &mr, R &mi) {
+                mr = mi = R(0);
                 if (nn < 0 || nn >= P || mm > nn || mm < 0) return;
                 if (mm == 0) {
                     mr = mu[nn * nn];
@@ -741,17 +747,17 @@ __device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int 
                     mi = mu[nn * nn + 2 * mm];
                 }
             };
-            double mr, mi;
+            R mr, mi;
             if (n < P) {  // L_0^0: M_n^m I_n^m and its conjugate partner
                 Mc(n, m, mr, mi);
                 const double re = mr * ir - mi * ii;
-                l00 += m == 0 ? re : 2.0 * re;
+                l00 += m == 0 ? re : R(2) * re;
             }
             if (n >= 1) {
                 // L_1^0: -M_{n-1}^m I_n^m, with the partner -m
                 Mc(n - 1, m, mr, mi);
                 const double re = mr * ir - mi * ii;
-                l10 -= m == 0 ? re : 2.0 * re;
+                l10 -= m == 0 ? re : R(2) * re;
                 // L_1^1: -M_{n-1}^{m-1} I_n^m (m >= 1) and
                 //        +conj(M_{n-1}^{m+1} I_n^m) (the terms of order -(m+1))
                 if (m >= 1) {
@@ -765,10 +771,10 @@ __device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int 
             }
         });
         const double s1 = ldexp(1.0, (1 - adj) * lw), s2 = ldexp(1.0, (2 - adj) * lw);
-        phi += l00 * s1;
-        ex += l11r * s2;
-        ey += l11i * s2;
-        ez -= l10 * s2;
+        phi += (double)l00 * s1;
+        ex += (double)l11r * s2;
+        ey += (double)l11i * s2;
+        ez -= (double)l10 * s2;
     }
 #pragma unroll
     for (int d = 32; d >= T; d >>= 1) {
@@ -789,14 +795,14 @@ __device__ __forceinline__ void ad_m2p_unit(double (*mus)[P * P], int lane, int 
 
 // at most 16 lane groups (4 lanes per unit target at least), so that the
 // staged multipoles stay within 32 KB at p = 16
-template <int P>
+template <int P, typename R>
 __global__ __launch_bounds__(64) void k_ad_m2p(const uint32_t *__restrict__ nunits, const int2 *__restrict__ units,
                                                int adj, const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
                                                const uint32_t *__restrict__ ow, const int *__restrict__ iw,
                                                const int *__restrict__ lev, const uint32_t *__restrict__ code,
                                                const double4 *__restrict__ rec, const double *__restrict__ M,
                                                double4 *__restrict__ out) {
-    __shared__ double mus[16][P * P];
+    __shared__ R mus[16][P * P];
     if (blockIdx.x >= *nunits) return;
     const int2 un = units[blockIdx.x];
     const int j = un.x;
@@ -809,7 +815,7 @@ __global__ __launch_bounds__(64) void k_ad_m2p(const uint32_t *__restrict__ nuni
     while ((1u << lt) < nt && lt < 6) ++lt;
 #define AD_M2P_CASE(K)                                                                                          \
     case K:                                                                                                     \
-        ad_m2p_unit<P, K>(mus, lane, adj, g, lev[g], code[g], t0, nt, w0, w1, iw, lev, code, rec, M, out);     \
+        ad_m2p_unit<P, K, R>(mus, lane, adj, g, lev[g], code[g], t0, nt, w0, w1, iw, lev, code, rec, M, out);     \
         break;
     switch (lt) { AD_M2P_CASE(2) AD_M2P_CASE(3) AD_M2P_CASE(4) AD_M2P_CASE(5) AD_M2P_CASE(6) }
 #undef AD_M2P_CASE
@@ -1664,9 +1670,13 @@ hipError_t ad_launch_class(int64_t box2, int64_t nb, const int *lev, const uint3
 
 hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
                          const uint32_t *code, const uint32_t *ps, const uint32_t *pe, int adj, const double4 *rec,
-                         double *Lc, hipStream_t st) {
+                         double *Lc, bool f32, hipStream_t st) {
     switch (P) {
-#define X(PP) case PP: k_ad_p2l<PP><<<(unsigned)nbox, 64, 0, st>>>(ox, ix, lev, code, ps, pe, adj, rec, Lc); break;
+#define X(PP)                                                                                                   \
+    case PP:                                                                                                    \
+        if (f32) k_ad_p2l<PP, float><<<(unsigned)nbox, 64, 0, st>>>(ox, ix, lev, code, ps, pe, adj, rec, Lc);  \
+        else k_ad_p2l<PP, double><<<(unsigned)nbox, 64, 0, st>>>(ox, ix, lev, code, ps, pe, adj, rec, Lc);     \
+        break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -1687,12 +1697,17 @@ hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *
 
 hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, int adj,
                          const int *lbox, const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
-                         const uint32_t *code, const double4 *rec, const double *M, double4 *out, hipStream_t st) {
+                         const uint32_t *code, const double4 *rec, const double *M, double4 *out, bool f32,
+                         hipStream_t st) {
     switch (P) {
 #define X(PP)                                                                                                   \
     case PP:                                                                                                    \
-        k_ad_m2p<PP><<<(unsigned)max_units, 64, 0, st>>>(nunits, units, adj, lbox, lstart, ow, iw, lev, code, rec, \
-                                                         M, out);                                               \
+        if (f32)                                                                                                \
+            k_ad_m2p<PP, float><<<(unsigned)max_units, 64, 0, st>>>(nunits, units, adj, lbox, lstart, ow, iw,   \
+                                                                    lev, code, rec, M, out);                    \
+        else                                                                                                    \
+            k_ad_m2p<PP, double><<<(unsigned)max_units, 64, 0, st>>>(nunits, units, adj, lbox, lstart, ow, iw,  \
+                                                                     lev, code, rec, M, out);                   \
         break;
         AD_CASES(X)
 #undef X

@@ -1023,10 +1023,11 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
     const bool far = do_far && a->depth >= 2;
     const bool side = do_near && far && t->cfg.overlap_near && !t->quiet;
     t->p2p_side[t->cur] = side;
+    // the mixed form: FP32 pair arithmetic in P2P, and FP32 terms in P2L and M2P
+    const bool f32 = t->cfg.precision == FMM_PREC_MIXED;
     auto p2p = [&](hipStream_t s2, const Combine *cf) -> hipError_t {
         return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
-                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf,
-                             t->cfg.precision == FMM_PREC_MIXED, s2);
+                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf, f32, s2);
     };
     if (side) {
         if (!t->side) {
@@ -1057,7 +1058,7 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
             HIPCHK(ad_launch_m2m(P, a->off[l], a->off[l + 1] - a->off[l], bp<uint8_t>(a->leaf), bp<int>(a->child),
                                  adjoint ? o->aup64 : o->up64, M, st));
         CHK(rec(t, 3, st));
-        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, adj, recs, Lc, st));
+        HIPCHK(ad_launch_p2l(P, a->nbox, ox, bp<int>(a->ix), lev, code, ps, pe, adj, recs, Lc, f32, st));
         if (half) {  // the mixed form's operands: level maxima, scaled binary16 parts
             HIPCHK(launch_zero(w.lmax, kLevelSlots, st));
             HIPCHK(ad_launch_pack_h(P, a->off[2], a->nbox, lev, M, o->rho_inv, w.lmax, w.pack[0], st));
@@ -1077,7 +1078,7 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
         CHK(rec(t, 6, st));
         HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, llev, adj, recs, Lc, w.farf, st));
         HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), adj, lbox,
-                             lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, st));
+                             lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, f32, st));
     } else {
         for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
     }

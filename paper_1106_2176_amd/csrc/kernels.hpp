@@ -202,7 +202,7 @@ hipError_t ad_launch_m2l(int P, const AdM2LPlan &pl, const double *A, const int2
                          hipStream_t st);
 hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix, const int *lev,
                          const uint32_t *code, const uint32_t *ps, const uint32_t *pe, int adj, const double4 *rec,
-                         double *Lc, hipStream_t st);
+                         double *Lc, bool f32, hipStream_t st);
 hipError_t ad_launch_l2l(int P, int64_t b0, int64_t nb, const uint32_t *code, const int *parent, const double *tab,
                          double *Lc, hipStream_t st);
 hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
@@ -210,7 +210,8 @@ hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *
 // one wave per P2P work unit (see ad_launch_units)
 hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, int adj,
                          const int *lbox, const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
-                         const uint32_t *code, const double4 *rec, const double *M, double4 *out, hipStream_t st);
+                         const uint32_t *code, const double4 *rec, const double *M, double4 *out, bool f32,
+                         hipStream_t st);
 // P2P work units of up to 64 targets: pass 0 counts per leaf into cnt,
 // pass 1 fills units (leaf, first target) from uoff, the scan of the counts
 hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint32_t *cnt, const uint32_t *uoff,
