@@ -1222,6 +1222,9 @@ __global__ __launch_bounds__(256) void k_ad_class(int64_t box2, int64_t nb, cons
 
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+// operator fragments as a native vector: a HIP uint4 is a struct, whose
+// copies become memcpy calls that kept the prefetched fragments in scratch
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 // Per-level maxima of |M_c rho_inv[c]|: one thread per (box, coefficient),
 // an LDS maximum per level in the block, one global atomic per level and
@@ -1299,7 +1302,7 @@ __global__ __launch_bounds__(256) void k_ad_m2l_h(AdM2LPlan pl, const uint16_t *
     constexpr int NFR = 2 * RT;                  // operator fragments per step
     constexpr int EPT = (NFR * 64 + 255) / 256;  // of them per thread
     constexpr int D = 3;                         // multipole steps in flight
-    __shared__ uint4 As[2][NFR * 64];
+    __shared__ u32x4_t As[2][NFR * 64];
     __shared__ int sA[kOffsetsPerClass + 1];
     const int64_t part = blockIdx.x / pl.units, b = blockIdx.x - part * pl.units;
     const int kbeg = (int)(part * NCH / pl.nsplit), kend = (int)((part + 1) * NCH / pl.nsplit);
@@ -1322,7 +1325,7 @@ __global__ __launch_bounds__(256) void k_ad_m2l_h(AdM2LPlan pl, const uint16_t *
         vrow[bb] = tbox[bb] >= 0 ? vidx + (tbox[bb] - box2) * kOffsetsPerClass : nullptr;
     }
     __syncthreads();
-    auto load_a = [&](int kc, uint4 (&dst)[EPT]) __attribute__((always_inline)) {
+    auto load_a = [&](int kc, u32x4_t (&dst)[EPT]) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + 256 * i;
@@ -1330,11 +1333,11 @@ __global__ __launch_bounds__(256) void k_ad_m2l_h(AdM2LPlan pl, const uint16_t *
                 const int fr = e >> 6, L = e & 63, sp = fr / RT, r = fr - sp * RT;
                 const int g = 4 * kc + (L >> 4);
                 const int slot = g < NPC ? g / PPO : kOffsetsPerClass, pc = g < NPC ? g - (g / PPO) * PPO : 0;
-                dst[i] = *(const uint4 *)(Ah + sp * astride + sA[slot] + (r * PPO + pc) * 128 + (L & 15) * 8);
+                dst[i] = *(const u32x4_t *)(Ah + sp * astride + sA[slot] + (r * PPO + pc) * 128 + (L & 15) * 8);
             }
         }
     };
-    auto store_a = [&](int buf, const uint4 (&src)[EPT]) __attribute__((always_inline)) {
+    auto store_a = [&](int buf, const u32x4_t (&src)[EPT]) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + 256 * i;
@@ -1388,7 +1391,8 @@ __global__ __launch_bounds__(256) void k_ad_m2l_h(AdM2LPlan pl, const uint16_t *
             acc[r][bb] = f32x4_t{0, 0, 0, 0};
             acc64[r][bb] = f64x4{0, 0, 0, 0};
         }
-    uint4 ar[EPT], bhi[D][NB], blo[D][NB];
+    u32x4_t ar[EPT];
+    uint4 bhi[D][NB], blo[D][NB];
     load_a(kbeg, ar);
     store_a(0, ar);
 #pragma unroll
@@ -1397,7 +1401,7 @@ __global__ __launch_bounds__(256) void k_ad_m2l_h(AdM2LPlan pl, const uint16_t *
     __syncthreads();
     auto step = [&](int kc, auto dc) __attribute__((always_inline)) {
         constexpr int d = decltype(dc)::value % D, ph = decltype(dc)::value & 1;
-        const uint4 *as = As[ph];
+        const u32x4_t *as = As[ph];
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
             const f16x8_t ah = __builtin_bit_cast(f16x8_t, as[r * 64 + lane]);
