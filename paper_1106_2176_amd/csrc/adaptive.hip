@@ -209,28 +209,47 @@ __global__ void k_ad_vslots(int64_t b0, int64_t nb, const uint32_t *__restrict__
     vidx[i] = r;
 }
 
-// The part of U and W of leaf g that comes through colleague direction o
-// (count only when the item pointers are NULL).  o = 13 (the box itself):
-// g.  Otherwise: the colleague o of each proper ancestor (from the parent
-// up) when it is a leaf touching g; then g's own colleague o: a leaf goes to
-// U, a split one is opened depth first (touching leaves to U, touching split
-// boxes opened, the rest to W).
-__device__ void ad_uw(int g, int o, const int *lev, const uint32_t *code, const int *parent, const int *col,
-                      const int *child, const uint8_t *leaf, int *u, int &nu, int *w, int &nw) {
-    nu = nw = 0;
+// The parts of U and W (leaf g only) and of X (any box g) that come
+// through colleague direction o (counts only when the item pointers are
+// NULL).  o = 13 (the box itself): U = {g}.  Otherwise one walk over the
+// colleagues o of g's proper ancestors (from the parent up) that are
+// leaves: one touching g goes to U, one touching g's parent but not g to X.
+// Then g's own colleague o: a leaf goes to U, a split one is opened depth
+// first (touching leaves to U, touching split boxes opened, the rest to W).
+__device__ void ad_uwx(int g, int o, bool lg_leaf, const int *lev, const uint32_t *code, const int *parent,
+                       const int *col, const int *child, const uint8_t *leaf, int *u, int &nu, int *w, int &nw,
+                       int *x, int &nx) {
+    nu = nw = nx = 0;
     if (o == 13) {
-        if (u) u[0] = g;
-        nu = 1;
+        if (lg_leaf) {
+            if (u) u[0] = g;
+            nu = 1;
+        }
         return;
     }
     const int lg = lev[g];
     const uint32_t cg = code[g];
-    for (int a = parent[g]; a >= 0; a = parent[a]) {
-        const int c = col[27 * (int64_t)a + o];
-        if (c < 0 || !leaf[c] || !ad_adjacent(lg, cg, lev[c], code[c])) continue;
-        if (u) u[nu] = c;
-        ++nu;
+    const int p = parent[g];
+    if (p >= 0) {
+        const int lp = lev[p];
+        const uint32_t cp = code[p];
+        for (int a = p; a >= 0; a = parent[a]) {
+            const int c = col[27 * (int64_t)a + o];
+            if (c < 0 || !leaf[c]) continue;
+            const int lc = lev[c];
+            const uint32_t cc = code[c];
+            if (ad_adjacent(lg, cg, lc, cc)) {
+                if (lg_leaf) {
+                    if (u) u[nu] = c;
+                    ++nu;
+                }
+            } else if (ad_adjacent(lp, cp, lc, cc)) {
+                if (x) x[nx] = c;
+                ++nx;
+            }
+        }
     }
+    if (!lg_leaf) return;
     const int c = col[27 * (int64_t)g + o];
     if (c < 0) return;
     if (leaf[c]) {
@@ -257,25 +276,6 @@ __device__ void ad_uw(int g, int o, const int *lev, const uint32_t *code, const 
     }
 }
 
-// The part of X of box g through direction o: the colleague o of each
-// proper ancestor (from the parent up) when it is a leaf that touches g's
-// parent but not g.
-__device__ int ad_x(int g, int o, const int *lev, const uint32_t *code, const int *parent, const int *col,
-                    const uint8_t *leaf, int *x) {
-    int nx = 0;
-    const int p = parent[g];
-    if (p < 0 || o == 13) return 0;
-    for (int a = p; a >= 0; a = parent[a]) {
-        const int c = col[27 * (int64_t)a + o];
-        if (c < 0 || !leaf[c]) continue;
-        if (ad_adjacent(lev[p], code[p], lev[c], code[c]) && !ad_adjacent(lev[g], code[g], lev[c], code[c])) {
-            if (x) x[nx] = c;
-            ++nx;
-        }
-    }
-    return nx;
-}
-
 // One thread per (box, direction), i = 27 g + o.  pass 0: counts of U, W
 // (leaves) and X (all boxes); pass 1: the items, at the scanned offsets.
 __global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, const uint32_t *__restrict__ code,
@@ -288,15 +288,15 @@ __global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 27 * nbox) return;
     const int g = (int)(i / 27), o = (int)(i % 27);
-    int a = 0, b = 0;
+    int a, b, c;
     if (pass == 0) {
-        if (leaf[g]) ad_uw(g, o, lev, code, parent, col, child, leaf, nullptr, a, nullptr, b);
+        ad_uwx(g, o, leaf[g] != 0, lev, code, parent, col, child, leaf, nullptr, a, nullptr, b, nullptr, c);
         nu[i] = a;
         nw[i] = b;
-        nx[i] = ad_x(g, o, lev, code, parent, col, leaf, nullptr);
+        nx[i] = c;
     } else {
-        if (leaf[g]) ad_uw(g, o, lev, code, parent, col, child, leaf, iu + ou[i], a, iw + ow[i], b);
-        (void)ad_x(g, o, lev, code, parent, col, leaf, ix + ox[i]);
+        ad_uwx(g, o, leaf[g] != 0, lev, code, parent, col, child, leaf, iu + ou[i], a, iw + ow[i], b, ix + ox[i],
+               c);
     }
 }
 
