@@ -563,9 +563,12 @@ __global__ __launch_bounds__(64) void k_ad_l2p(const int *__restrict__ lbox, con
 // I_{m-1}^{m-1}, I_{m+1}^m = (2m+1) z/r^2 I_m^m, r^2 I_n^m = (2n-1) z
 // I_{n-1}^m - (n-m-1)(n+m-1) I_{n-2}^m), visited column by column: f(n, m,
 // re, im) for every pair, in the arithmetic type R of the position.
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <int N, typename R, typename F>
 __device__ __forceinline__ void irregular_each(R x, R y, R z, F &&f) {
-    const R r2 = x * x + y * y + z * z, ir2 = R(1) / r2;
+    const R r2 = x * x + y * y + z * z, ir2 = R(1) / r2, zr = z * ir2;
     R dr = sqrt(ir2), di = R(0);  // I_m^m
 #pragma unroll
     for (int m = 0; m <= N; ++m) {
@@ -575,17 +578,19 @@ __device__ __forceinline__ void irregular_each(R x, R y, R z, F &&f) {
             dr = nr;
             di = ni;
         }
+        // column m; the imaginary parts of column 0 are zero and not formed
         R ar = dr, ai = di, br = R(0), bi = R(0);
 #pragma unroll
         for (int n = m; n <= N; ++n) {
             R cr = ar, ci = ai;
             if (n == m + 1) {
-                cr = R(2 * m + 1) * z * ir2 * ar;
-                ci = R(2 * m + 1) * z * ir2 * ai;
+                const R h = R(2 * m + 1) * zr;
+                cr = h * ar;
+                if (m > 0) ci = h * ai;
             } else if (n > m + 1) {
-                const R a = R(2 * n - 1) * z, b = R((n - m - 1) * (n + m - 1));
-                cr = (a * ar - b * br) * ir2;
-                ci = (a * ai - b * bi) * ir2;
+                const R h = R(2 * n - 1) * zr, c = R((n - m - 1) * (n + m - 1)) * ir2;
+                cr = h * ar - c * br;
+                if (m > 0) ci = h * ai - c * bi;
             }
             if (n > m) {
                 br = ar;
@@ -593,7 +598,7 @@ __device__ __forceinline__ void irregular_each(R x, R y, R z, F &&f) {
                 ar = cr;
                 ai = ci;
             }
-            f(n, m, cr, ci);
+            f(n, m, cr, m > 0 ? ci : R(0));
         }
     }
 }
@@ -734,42 +739,46 @@ __device__ __forceinline__ void ad_m2p_unit(R (*mus)[P * P], int lane, int adj, 
         double cx, cy, cz;
         ad_centre_diff(lg, cg, lw, code[w], lw, cx, cy, cz);
         const double sc = ldexp(1.0, lw - lg);
-        R l00 = R(0), l10 = R(0), l11r = R(0), l11i = R(0);
+        // l00: L_0^0 = sum over n < P of M_n^m I_n^m with its conjugate
+        // partner (m > 0 terms twice), l10: -L_1^0, the same over M_{n-1}^m,
+        // l11: L_1^1 = -sum M_{n-1}^{m-1} I_n^m (m >= 1) + conj(M_{n-1}^{m+1}
+        // I_n^m) (the terms of order -(m+1)).  Coefficients outside
+        // 0 <= m' <= n' < P are zero and skipped at compile time; the m = 0
+        // and m > 0 parts of l00 and l10 are kept apart, so that the factor 2
+        // is applied once.
+        R l00 = R(0), l00m = R(0), l10 = R(0), l10m = R(0), l11r = R(0), l11i = R(0);
         irregular_each<P>((R)(cx + sc * r.x), (R)(cy + sc * r.y), (R)(cz + sc * r.z), [&](int n, int m, R ir, R ii) {
-            // M_{n'}^{m'} of the multipole (0 outside n' < P, 0 <= m' <= n')
-            auto Mc = [&](int nn, int mm, R &mr, R &mi) {
-                mr = mi = R(0);
-                if (nn < 0 || nn >= P || mm > nn || mm < 0) return;
-                if (mm == 0) {
-                    mr = mu[nn * nn];
-                } else {
-                    mr = mu[nn * nn + 2 * mm - 1];
-                    mi = mu[nn * nn + 2 * mm];
-                }
+            auto re_of = [&](int nn, int mm) { return mu[mm == 0 ? nn * nn : nn * nn + 2 * mm - 1]; };
+            auto im_of = [&](int nn, int mm) { return mu[nn * nn + 2 * mm]; };
+            // acc += Re(M_nn^mm I_n^m)
+            auto add_re = [&](R &acc, int nn, int mm) {
+                acc = fma_r(re_of(nn, mm), ir, acc);
+                if (mm > 0) acc = fma_r(-im_of(nn, mm), ii, acc);
             };
-            R mr, mi;
-            if (n < P) {  // L_0^0: M_n^m I_n^m and its conjugate partner
-                Mc(n, m, mr, mi);
-                const double re = mr * ir - mi * ii;
-                l00 += m == 0 ? re : R(2) * re;
-            }
-            if (n >= 1) {
-                // L_1^0: -M_{n-1}^m I_n^m, with the partner -m
-                Mc(n - 1, m, mr, mi);
-                const double re = mr * ir - mi * ii;
-                l10 -= m == 0 ? re : R(2) * re;
-                // L_1^1: -M_{n-1}^{m-1} I_n^m (m >= 1) and
-                //        +conj(M_{n-1}^{m+1} I_n^m) (the terms of order -(m+1))
-                if (m >= 1) {
-                    Mc(n - 1, m - 1, mr, mi);
-                    l11r -= mr * ir - mi * ii;
-                    l11i -= mr * ii + mi * ir;
+            if (n < P) add_re(m == 0 ? l00 : l00m, n, m);
+            if (n >= 1 && m <= n - 1) add_re(m == 0 ? l10 : l10m, n - 1, m);
+            if (n >= 1 && m >= 1) {  // l11 -= M_{n-1}^{m-1} I
+                const R mr = re_of(n - 1, m - 1);
+                l11r = fma_r(-mr, ir, l11r);
+                l11i = fma_r(-mr, ii, l11i);
+                if (m - 1 > 0) {
+                    const R mi = im_of(n - 1, m - 1);
+                    l11r = fma_r(mi, ii, l11r);
+                    l11i = fma_r(-mi, ir, l11i);
                 }
-                Mc(n - 1, m + 1, mr, mi);
-                l11r += mr * ir - mi * ii;
-                l11i -= mr * ii + mi * ir;
+            }
+            if (n >= 1 && m + 1 <= n - 1) {  // l11 += conj(M_{n-1}^{m+1} I)
+                const R mr = re_of(n - 1, m + 1), mi = im_of(n - 1, m + 1);
+                l11r = fma_r(mr, ir, l11r);
+                l11i = fma_r(-mi, ir, l11i);
+                if (m > 0) {  // I_n^0 is real
+                    l11r = fma_r(-mi, ii, l11r);
+                    l11i = fma_r(-mr, ii, l11i);
+                }
             }
         });
+        l00 += R(2) * l00m;
+        l10 = -(l10 + R(2) * l10m);
         const double s1 = ldexp(1.0, (1 - adj) * lw), s2 = ldexp(1.0, (2 - adj) * lw);
         phi += (double)l00 * s1;
         ex += (double)l11r * s2;
