@@ -162,8 +162,9 @@ typedef struct {
                                   binary16 encoding described at m2l_fp16,
                                   with one operand scale per level), the
                                   P2P pairs (FP32 on FP64 differences, FP64
-                                  merges) and the P2L and M2P terms (FP32 per
-                                  particle and box, summed in FP64).
+                                  merges) and the P2M, L2P, P2L and M2P
+                                  terms (FP32 per particle and box, summed
+                                  in FP64).
                                   fmm_backward runs the transposed chain over
                                   the same lists; the build
                                   blocks once per tree level and once more at

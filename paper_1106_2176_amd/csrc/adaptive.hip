@@ -28,7 +28,7 @@
 // and fields leave the kernels in root units (phi * size, E * size^2).  Every
 // kernel works in FP64 except, in the mixed form, the M2L (binary16 parts on
 // the 16-bit matrix cores), the P2P pairs (FP32 on FP64 differences) and the
-// P2L and M2P terms (FP32, summed in FP64).
+// P2M, L2P, P2L and M2P terms (FP32, summed in FP64).
 #include <algorithm>
 
 #include "harmonics.hpp"
@@ -438,16 +438,60 @@ __device__ inline void ad_centre_diff(int l1, uint32_t c1, int l2, uint32_t c2, 
     dz = ((double)a[2] + 0.5) * s1 - ((double)b[2] + 0.5) * s2;
 }
 
+// Regular solid harmonics times a seed, s R_n^m(x) for 0 <= m <= n < N, by
+// the recurrences of regular_rho (R_m^m = -(x - iy)/(2m) R_{m-1}^{m-1},
+// R_{m+1}^m = z R_m^m, (n-m)(n+m) R_n^m = (2n-1) z R_{n-1}^m - r^2
+// R_{n-2}^m, linear in the seed), unrolled at compile time and visited
+// column by column: f(n, m, re, im), im = 0 for m = 0.
+template <int N, typename R, typename F>
+__device__ __forceinline__ void regular_each(R x, R y, R z, R seed, F &&f) {
+    const R r2 = x * x + y * y + z * z;
+    R dr = seed, di = R(0);  // s R_m^m
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        if (m > 0) {
+            const R inv = R(-1) / R(2 * m);
+            const R nr = (dr * x + di * y) * inv, ni = (di * x - dr * y) * inv;
+            dr = nr;
+            di = ni;
+        }
+        R ar = dr, ai = di, br = R(0), bi = R(0);
+#pragma unroll
+        for (int n = m; n < N; ++n) {
+            R cr = ar, ci = ai;
+            if (n == m + 1) {
+                cr = z * ar;
+                if (m > 0) ci = z * ai;
+            } else if (n > m + 1) {
+                const R inv = R(1) / R((n - m) * (n + m)), h = R(2 * n - 1) * inv * z, c = inv * r2;
+                cr = h * ar - c * br;
+                if (m > 0) ci = h * ai - c * bi;
+            }
+            if (n > m) {
+                br = ar;
+                bi = ai;
+                ar = cr;
+                ai = ci;
+            }
+            f(n, m, cr, m > 0 ? ci : R(0));
+        }
+    }
+}
+
 // P2M at the leaves: mu(g) = sum_j q_j rho(u_j), leaf units; one block of 64
-// per leaf, 16 particles' harmonics at a time in LDS.  Rows are written whole
-// (zero past p^2).  adj = 1: the transpose of L2P (the weights' sum times
-// 2^l, the leaf's root-unit factor).
-template <int P>
+// per leaf, B particles' harmonics (times their charges) at a time as LDS
+// rows, summed in FP64 coefficient by coefficient over the rows filled.  R:
+// the arithmetic of the harmonics (FP32 in the mixed form, the leaf-relative
+// position rounded once).  adj = 1: the
+// transpose of L2P (the weights' sum times 2^l, the leaf's root-unit factor).
+template <int P, typename R>
 __global__ __launch_bounds__(64) void k_ad_p2m(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
                                                const uint8_t *__restrict__ llev, int adj,
                                                const double4 *__restrict__ rec, double *__restrict__ M) {
-    constexpr int P2 = P * P, S = coef_stride(P), B = 16, NC = (S + 63) / 64;
-    __shared__ double rows[B][P2 + 1];
+    constexpr int P2 = P * P, S = coef_stride(P), NC = (S + 63) / 64;
+    // rows of at most ~17 KB
+    constexpr int B0 = P <= 5 ? 64 : P <= 8 ? 32 : P <= 11 ? 16 : 8, B = sizeof(R) == 4 && B0 < 64 ? 2 * B0 : B0;
+    __shared__ R rows[B][P2 + 1];
     const int j = blockIdx.x, t = threadIdx.x;
     const uint32_t s0 = lstart[j], s1 = lstart[j + 1];
     double acc[NC];
@@ -455,21 +499,25 @@ __global__ __launch_bounds__(64) void k_ad_p2m(const int *__restrict__ lbox, con
     for (int a = 0; a < NC; ++a) acc[a] = 0.0;
     for (uint32_t b0 = s0; b0 < s1; b0 += B) {
         __syncthreads();
-        if (t < B) {
-            if (b0 + t < s1) {
-                const double4 r = rec[b0 + t];
-                regular_rho<double>(P, r.x, r.y, r.z, rows[t]);
-                for (int c = 0; c < P2; ++c) rows[t][c] *= r.w;
-            } else {
-                for (int c = 0; c < P2; ++c) rows[t][c] = 0.0;
-            }
+        if (t < B && b0 + t < s1) {
+            R *row = rows[t];
+            const double4 r = rec[b0 + t];
+            regular_each<P>((R)r.x, (R)r.y, (R)r.z, (R)r.w, [&](int n, int m, R re, R im) {
+                if (m == 0) {
+                    row[n * n] = re;
+                } else {
+                    row[n * n + 2 * m - 1] = re;
+                    row[n * n + 2 * m] = im;
+                }
+            });
         }
         __syncthreads();
+        const int nr = (int)min((uint32_t)B, s1 - b0);
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
             const int c = t + 64 * a;
             if (c < P2)
-                for (int k = 0; k < B; ++k) acc[a] += rows[k][c];
+                for (int k = 0; k < nr; ++k) acc[a] += (double)rows[k][c];
         }
     }
     const int g = lbox[j];
@@ -533,28 +581,31 @@ __global__ __launch_bounds__(256) void k_ad_l2l(int64_t b0, const uint32_t *__re
 }
 
 // L2P at the leaves, outputs in root units (phi * 2^l, E * 4^l).  adj = 1:
-// the transpose of P2M and its position derivative (phi, E * 2^l).
-template <int P>
+// the transpose of P2M and its position derivative (phi, E * 2^l).  R: the
+// arithmetic of the evaluation (FP32 in the mixed form: the local
+// expansion and the leaf-relative position rounded once).
+template <int P, typename R>
 __global__ __launch_bounds__(64) void k_ad_l2p(const int *__restrict__ lbox, const uint32_t *__restrict__ lstart,
                                                const uint8_t *__restrict__ llev, int adj,
                                                const double4 *__restrict__ rec, const double *__restrict__ Lc,
                                                double4 *__restrict__ out) {
+    using V = typename std::conditional<sizeof(R) == 4, float4, double4>::type;
     constexpr int P2 = P * P, S = coef_stride(P);
-    __shared__ double ell[P2];
-    __shared__ double4 coef[P2];
+    __shared__ R ell[P2];
+    __shared__ V coef[P2];
     const int j = blockIdx.x;
     const int g = lbox[j];
-    for (int c = threadIdx.x; c < P2; c += 64) ell[c] = Lc[(size_t)g * S + c];
+    for (int c = threadIdx.x; c < P2; c += 64) ell[c] = (R)Lc[(size_t)g * S + c];
     __syncthreads();
-    for (int c = threadIdx.x; c < P2; c += 64) coef[c] = l2p_coef<double, double4>(ell, P, c);
+    for (int c = threadIdx.x; c < P2; c += 64) coef[c] = l2p_coef<R, V>(ell, P, c);
     __syncthreads();
     const double s1 = ldexp(1.0, (1 - adj) * (int)llev[j]), s2 = ldexp(1.0, (2 - adj) * (int)llev[j]);
     for (uint32_t i = lstart[j] + threadIdx.x; i < lstart[j + 1]; i += 64) {
         __asm__ volatile("" ::: "memory");
         const double4 r = rec[i];
-        double phi, gx, gy, gz;
-        l2p_point<P, double, double4>(coef, r.x, r.y, r.z, phi, gx, gy, gz);
-        out[i] = make_double4(phi * s1, -gx * s2, -gy * s2, -gz * s2);
+        R phi, gx, gy, gz;
+        l2p_point<P, R, V>(coef, (R)r.x, (R)r.y, (R)r.z, phi, gx, gy, gz);
+        out[i] = make_double4((double)phi * s1, -(double)gx * s2, -(double)gy * s2, -(double)gz * s2);
     }
 }
 
@@ -1588,10 +1639,14 @@ hipError_t ad_launch_records(int64_t n, int dtype, const uint32_t *hoff, const i
 #define AD_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev, int adj,
-                         const double4 *rec, double *M, hipStream_t st) {
+                         const double4 *rec, double *M, bool f32, hipStream_t st) {
     if (nleaf == 0) return hipSuccess;
     switch (P) {
-#define X(PP) case PP: k_ad_p2m<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, M); break;
+#define X(PP)                                                                                                   \
+    case PP:                                                                                                    \
+        if (f32) k_ad_p2m<PP, float><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, M);         \
+        else k_ad_p2m<PP, double><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, M);            \
+        break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
@@ -1698,9 +1753,13 @@ hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix,
 }
 
 hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
-                         int adj, const double4 *rec, const double *Lc, double4 *out, hipStream_t st) {
+                         int adj, const double4 *rec, const double *Lc, double4 *out, bool f32, hipStream_t st) {
     switch (P) {
-#define X(PP) case PP: k_ad_l2p<PP><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, Lc, out); break;
+#define X(PP)                                                                                                   \
+    case PP:                                                                                                    \
+        if (f32) k_ad_l2p<PP, float><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, Lc, out);   \
+        else k_ad_l2p<PP, double><<<(unsigned)nleaf, 64, 0, st>>>(lbox, lstart, llev, adj, rec, Lc, out);      \
+        break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;

@@ -1023,7 +1023,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
     const bool far = do_far && a->depth >= 2;
     const bool side = do_near && far && t->cfg.overlap_near && !t->quiet;
     t->p2p_side[t->cur] = side;
-    // the mixed form: FP32 pair arithmetic in P2P, and FP32 terms in P2L and M2P
+    // the mixed form: FP32 pair arithmetic in P2P, FP32 terms in P2M, P2L,
+    // L2P and M2P
     const bool f32 = t->cfg.precision == FMM_PREC_MIXED;
     auto p2p = [&](hipStream_t s2, const Combine *cf) -> hipError_t {
         return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
@@ -1052,7 +1053,7 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
         HIPCHK(launch_zero((uint32_t *)(M + (size_t)a->nbox * S), 2 * S, st));  // the zero row
         const int adj = adjoint ? 1 : 0;
         const uint8_t *llev = bp<uint8_t>(a->llev);
-        HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, llev, adj, recs, M, st));
+        HIPCHK(ad_launch_p2m(P, a->nleaf, lbox, lstart, llev, adj, recs, M, f32, st));
         CHK(rec(t, 2, st));
         for (int l = a->depth - 1; l >= 2; --l)
             HIPCHK(ad_launch_m2m(P, a->off[l], a->off[l + 1] - a->off[l], bp<uint8_t>(a->leaf), bp<int>(a->child),
@@ -1076,7 +1077,7 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
             HIPCHK(ad_launch_l2l(P, a->off[l], a->off[l + 1] - a->off[l], code, bp<int>(a->parent),
                                  adjoint ? o->adown64 : o->down64, Lc, st));
         CHK(rec(t, 6, st));
-        HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, llev, adj, recs, Lc, w.farf, st));
+        HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, llev, adj, recs, Lc, w.farf, f32, st));
         HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), adj, lbox,
                              lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, f32, st));
     } else {

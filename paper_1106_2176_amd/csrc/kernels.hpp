@@ -181,7 +181,7 @@ inline size_t ad_m2l_partial_bytes(const AdM2LPlan &pl, int P) {
 // P2L as that of M2P (times 2^l of the box), L2P and M2P as those of P2M
 // and P2L with their position derivatives (outputs times 2^-l)
 hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev, int adj,
-                         const double4 *rec, double *M, hipStream_t st);
+                         const double4 *rec, double *M, bool f32, hipStream_t st);
 hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
                          double *M, hipStream_t st);
 // mixed form: the per-level maxima of |M_c rho_inv[c]| over the boxes of
@@ -206,7 +206,7 @@ hipError_t ad_launch_p2l(int P, int64_t nbox, const uint32_t *ox, const int *ix,
 hipError_t ad_launch_l2l(int P, int64_t b0, int64_t nb, const uint32_t *code, const int *parent, const double *tab,
                          double *Lc, hipStream_t st);
 hipError_t ad_launch_l2p(int P, int64_t nleaf, const int *lbox, const uint32_t *lstart, const uint8_t *llev,
-                         int adj, const double4 *rec, const double *Lc, double4 *out, hipStream_t st);
+                         int adj, const double4 *rec, const double *Lc, double4 *out, bool f32, hipStream_t st);
 // one wave per P2P work unit (see ad_launch_units)
 hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const int2 *units, int adj,
                          const int *lbox, const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,

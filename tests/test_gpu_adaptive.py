@@ -213,7 +213,7 @@ def test_noalloc_matches_evaluate():
     ("clustered", 8_000, 20, 8, 1, 86),
 ])
 def test_mixed_form_vs_fp64_and_oracle(oracle_mod, kind, n, leaf, ml, p, seed):
-    """The mixed form (binary16 M2L, FP32 P2P pairs, the rest FP64) against the FP64 form on
+    """The mixed form (binary16 M2L; FP32 P2P pairs and P2M, L2P, P2L, M2P terms; the rest FP64) against the FP64 form on
     the same tree, all N, within the mixed form's 1e-6 budget, and against
     the oracle."""
     pos, q = _input(kind, n, seed)
