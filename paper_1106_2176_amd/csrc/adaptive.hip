@@ -364,18 +364,37 @@ __global__ __launch_bounds__(256) void k_ad_leafmax(int64_t nleaf, const uint32_
 }
 
 // P2P work units: ceil(count / 64) per leaf (pass 0), then each unit's
-// (leaf, first target) from the scanned counts (pass 1).
+// (leaf, first target) from the scanned counts (pass 1).  The counts are
+// laid out as kAdUnitClasses runs of nleaf, by the pairs of a full unit of
+// the leaf (its targets times the sources of U): at least 2^19, 2^18, ...,
+// 2^13, then the rest, so that the scan orders the units heaviest class
+// first (about a longest-first schedule, which a sort would refine by ~1%).
+// The heaviest waves then start with the grid instead of wherever the leaf
+// order puts them, and the kernels that take the units (P2P, M2P) do not
+// end on a late heavy wave.
 __global__ void k_ad_units(int64_t nleaf, int pass, const uint32_t *__restrict__ lstart,
-                           uint32_t *__restrict__ cnt, const uint32_t *__restrict__ uoff,
-                           int2 *__restrict__ units) {
+                           const int *__restrict__ lbox, const uint32_t *__restrict__ ou,
+                           const int *__restrict__ iu, const uint32_t *__restrict__ ps,
+                           const uint32_t *__restrict__ pe, uint32_t *__restrict__ cnt,
+                           const uint32_t *__restrict__ uoff, int2 *__restrict__ units) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nleaf) return;
-    const uint32_t m = (lstart[j + 1] - lstart[j] + 63) / 64;
+    const uint32_t np = lstart[j + 1] - lstart[j], m = (np + 63) / 64;
+    const int g = lbox[j];
+    uint64_t src = 0;
+    for (uint32_t e = ou[g]; e < ou[g + 1]; ++e) {
+        const int c = iu[e];
+        src += pe[c] - ps[c];
+    }
+    const uint64_t pairs = (uint64_t)min(np, 64u) * src;
+    int cls = 0;
+    while (cls < kAdUnitClasses - 1 && pairs < (1ull << (19 - cls))) ++cls;
     if (pass == 0) {
-        cnt[j] = m;
+        for (int k = 0; k < kAdUnitClasses; ++k) cnt[k * nleaf + j] = k == cls ? m : 0;
         return;
     }
-    for (uint32_t k = 0; k < m; ++k) units[uoff[j] + k] = make_int2((int)j, (int)(64 * k));
+    const uint32_t base = uoff[cls * nleaf + j];
+    for (uint32_t k = 0; k < m; ++k) units[base + k] = make_int2((int)j, (int)(64 * k));
 }
 
 // Work counts: [0] ordered P2P pairs (self pairs included), [1] V entries,
@@ -1788,9 +1807,10 @@ hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const
     return hipGetLastError();
 }
 
-hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, uint32_t *cnt, const uint32_t *uoff,
+hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, const int *lbox, const uint32_t *ou,
+                           const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt, const uint32_t *uoff,
                            int2 *units, hipStream_t st) {
-    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, lstart, cnt, uoff, units);
+    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, lstart, lbox, ou, iu, ps, pe, cnt, uoff, units);
     return hipGetLastError();
 }
 

@@ -944,13 +944,15 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
                              pos, c.box_lo, c.box_size, bp<double4>(t->xyz64), st));
     // P2P work units: at most one per leaf plus one per 64 particles
     a->max_units = a->nleaf + n / 64;
-    CHK(ensure(t, a->ucnt, u4 * a->nleaf, st));
-    CHK(ensure(t, a->uoff, u4 * (a->nleaf + 1), st));
+    // (heaviest units first: one run of nleaf counts per weight class, one scan)
+    CHK(ensure(t, a->ucnt, u4 * kAdUnitClasses * a->nleaf, st));
+    CHK(ensure(t, a->uoff, u4 * (kAdUnitClasses * a->nleaf + 1), st));
     CHK(ensure(t, a->units, sizeof(int2) * a->max_units, st));
-    HIPCHK(ad_launch_units(a->nleaf, 0, bp<uint32_t>(a->lstart), bp<uint32_t>(a->ucnt), nullptr, nullptr, st));
-    HIPCHK(launch_scan(a->nleaf, bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), scan, st));
-    HIPCHK(ad_launch_units(a->nleaf, 1, bp<uint32_t>(a->lstart), nullptr, bp<uint32_t>(a->uoff), bp<int2>(a->units),
-                           st));
+    HIPCHK(ad_launch_units(a->nleaf, 0, bp<uint32_t>(a->lstart), bp<int>(a->lbox), ou, bp<int>(a->iu), ps, pe,
+                           bp<uint32_t>(a->ucnt), nullptr, nullptr, st));
+    HIPCHK(launch_scan(kAdUnitClasses * a->nleaf, bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), scan, st));
+    HIPCHK(ad_launch_units(a->nleaf, 1, bp<uint32_t>(a->lstart), bp<int>(a->lbox), ou, bp<int>(a->iu), ps, pe,
+                           nullptr, bp<uint32_t>(a->uoff), bp<int2>(a->units), st));
     // M2L targets grouped by (level, class), tiles of 128 targets per block
     a->plan = AdM2LPlan{};
     int64_t at = 0;
@@ -1027,8 +1029,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
     // L2P and M2P
     const bool f32 = t->cfg.precision == FMM_PREC_MIXED;
     auto p2p = [&](hipStream_t s2, const Combine *cf) -> hipError_t {
-        return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), lbox, lstart, ou,
-                             bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf, f32, s2);
+        return ad_launch_p2p(a->max_units, bp<uint32_t>(a->uoff) + kAdUnitClasses * a->nleaf, bp<int2>(a->units),
+                             lbox, lstart, ou, bp<int>(a->iu), lev, code, ps, pe, recs, w.nearf, cf, f32, s2);
     };
     if (side) {
         if (!t->side) {
@@ -1078,8 +1080,8 @@ fmm_status run_adaptive(fmm_tree *t, const Work &w, const void *charges, bool ad
                                  adjoint ? o->adown64 : o->down64, Lc, st));
         CHK(rec(t, 6, st));
         HIPCHK(ad_launch_l2p(P, a->nleaf, lbox, lstart, llev, adj, recs, Lc, w.farf, f32, st));
-        HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + a->nleaf, bp<int2>(a->units), adj, lbox,
-                             lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, f32, st));
+        HIPCHK(ad_launch_m2p(P, a->max_units, bp<uint32_t>(a->uoff) + kAdUnitClasses * a->nleaf, bp<int2>(a->units),
+                             adj, lbox, lstart, ow, bp<int>(a->iw), lev, code, recs, M, w.farf, f32, st));
     } else {
         for (int s = 2; s <= 6; ++s) CHK(rec(t, s, st));
     }
