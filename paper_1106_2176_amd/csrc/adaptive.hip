@@ -549,32 +549,66 @@ __global__ __launch_bounds__(64) void k_ad_p2m(const int *__restrict__ lbox, con
 }
 
 // M2M for the split boxes of one level: mu(g) = sum_c A_c mu(child c)
-// (tab [8][p^2][p^2] input-major, [c][in][out])
+// (tab [8][p^2][p^2] input-major, [c][in][out]).  A block takes BX
+// consecutive boxes of the level, so that each table entry read from L2
+// serves BX boxes (one box a block read the whole 8 p^4 table per box); its
+// threads are (output o, K part kg), KG parts of the p^2 inputs per output,
+// whose partial sums are joined through LDS in kg order.
 template <int P>
-__global__ __launch_bounds__(256) void k_ad_m2m(int64_t b0, const uint8_t *__restrict__ leaf,
+__global__ __launch_bounds__(256) void k_ad_m2m(int64_t b0, int64_t nb, const uint8_t *__restrict__ leaf,
                                                 const int *__restrict__ child, const double *__restrict__ tab,
                                                 double *__restrict__ M) {
     constexpr int P2 = P * P, S = coef_stride(P);
-    __shared__ double in[8][P2];
-    __shared__ int has[8];
-    const int64_t g = b0 + blockIdx.x;
-    if (leaf[g]) return;
-    for (int i = threadIdx.x; i < 8 * P2; i += 256) {
-        const int c = i / P2, k = i - c * P2;
-        const int ch = child[8 * g + c];
-        in[c][k] = ch >= 0 ? M[(size_t)ch * S + k] : 0.0;
+    constexpr int KG = P2 > 128 ? 1 : (P2 > 64 ? 2 : 4);
+    constexpr int BX0 = 4096 / (8 * P2), BX = BX0 < 1 ? 1 : (BX0 > 8 ? 8 : BX0);
+    constexpr int KL = (P2 + KG - 1) / KG;  // inputs per part
+    __shared__ double in[BX][8][P2];
+    __shared__ double part[KG][BX][P2];
+    __shared__ int has[BX][8];
+    const int64_t g0 = b0 + (int64_t)blockIdx.x * BX;
+    const int nbx = (int)min((int64_t)BX, b0 + nb - g0);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < BX * 8 * P2; i += 256) {
+        const int bx = i / (8 * P2), r = i - bx * 8 * P2, c = r / P2, k = r - c * P2;
+        int ch = -1;
+        if (bx < nbx && !leaf[g0 + bx]) ch = child[8 * (g0 + bx) + c];
+        in[bx][c][k] = ch >= 0 ? M[(size_t)ch * S + k] : 0.0;
     }
-    if (threadIdx.x < 8) has[threadIdx.x] = child[8 * g + threadIdx.x] >= 0;
+    for (int i = tid; i < BX * 8; i += 256) {
+        const int bx = i >> 3, c = i & 7;
+        has[bx][c] = bx < nbx && !leaf[g0 + bx] && child[8 * (g0 + bx) + c] >= 0;
+    }
     __syncthreads();
-    for (int o = threadIdx.x; o < S; o += 256) {
-        double v = 0.0;
-        if (o < P2)
-            for (int c = 0; c < 8; ++c) {
-                if (!has[c]) continue;
-                const double *tc = tab + (size_t)c * P2 * P2 + o;
-                for (int k = 0; k < P2; ++k) v += tc[(size_t)k * P2] * in[c][k];
+    const int o = tid % P2, kg = tid / P2;
+    if (kg < KG) {
+        double v[BX];
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) v[bx] = 0.0;
+        const int k0 = kg * KL, k1 = min(P2, k0 + KL);
+        for (int c = 0; c < 8; ++c) {
+            bool any = false;
+#pragma unroll
+            for (int bx = 0; bx < BX; ++bx) any |= has[bx][c] != 0;
+            if (!any) continue;
+            const double *tc = tab + (size_t)c * P2 * P2 + o;
+            for (int k = k0; k < k1; ++k) {
+                const double a = tc[(size_t)k * P2];
+#pragma unroll
+                for (int bx = 0; bx < BX; ++bx) v[bx] = __builtin_fma(a, in[bx][c][k], v[bx]);
             }
-        M[(size_t)g * S + o] = v;
+        }
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) part[kg][bx][o] = v[bx];
+    }
+    __syncthreads();
+    for (int i = tid; i < BX * S; i += 256) {
+        const int bx = i / S, oo = i - bx * S;
+        if (bx >= nbx || leaf[g0 + bx]) continue;
+        double v = 0.0;
+        if (oo < P2)
+#pragma unroll
+            for (int q = 0; q < KG; ++q) v += part[q][bx][oo];
+        M[(size_t)(g0 + bx) * S + oo] = v;
     }
 }
 
@@ -1673,11 +1707,20 @@ hipError_t ad_launch_p2m(int P, int64_t nleaf, const int *lbox, const uint32_t *
     return hipGetLastError();
 }
 
+// boxes per block of k_ad_m2m (its BX)
+static constexpr int m2m_boxes(int P) {
+    return 4096 / (8 * P * P) < 1 ? 1 : (4096 / (8 * P * P) > 8 ? 8 : 4096 / (8 * P * P));
+}
+
 hipError_t ad_launch_m2m(int P, int64_t b0, int64_t nb, const uint8_t *leaf, const int *child, const double *tab,
                          double *M, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     switch (P) {
-#define X(PP) case PP: k_ad_m2m<PP><<<(unsigned)nb, 256, 0, st>>>(b0, leaf, child, tab, M); break;
+#define X(PP)                                                                                                   \
+    case PP:                                                                                                    \
+        k_ad_m2m<PP><<<(unsigned)((nb + m2m_boxes(PP) - 1) / m2m_boxes(PP)), 256, 0, st>>>(b0, nb, leaf, child,  \
+                                                                                         tab, M);                \
+        break;
         AD_CASES(X)
 #undef X
         default: return hipErrorInvalidValue;
