@@ -380,19 +380,21 @@ __global__ void k_ad_units(int64_t nleaf, int pass, const uint32_t *__restrict__
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nleaf) return;
     const uint32_t np = lstart[j + 1] - lstart[j], m = (np + 63) / 64;
-    const int g = lbox[j];
-    uint64_t src = 0;
-    for (uint32_t e = ou[g]; e < ou[g + 1]; ++e) {
-        const int c = iu[e];
-        src += pe[c] - ps[c];
-    }
-    const uint64_t pairs = (uint64_t)min(np, 64u) * src;
     int cls = 0;
-    while (cls < kAdUnitClasses - 1 && pairs < (1ull << (19 - cls))) ++cls;
     if (pass == 0) {
+        const int g = lbox[j];
+        uint64_t src = 0;
+        for (uint32_t e = ou[g]; e < ou[g + 1]; ++e) {
+            const int c = iu[e];
+            src += pe[c] - ps[c];
+        }
+        const uint64_t pairs = (uint64_t)min(np, 64u) * src;
+        while (cls < kAdUnitClasses - 1 && pairs < (1ull << (19 - cls))) ++cls;
         for (int k = 0; k < kAdUnitClasses; ++k) cnt[k * nleaf + j] = k == cls ? m : 0;
         return;
     }
+    // pass 1: the class is the run whose count is set (a leaf has m >= 1)
+    while (cls < kAdUnitClasses - 1 && cnt[cls * nleaf + j] == 0) ++cls;
     const uint32_t base = uoff[cls * nleaf + j];
     for (uint32_t k = 0; k < m; ++k) units[base + k] = make_int2((int)j, (int)(64 * k));
 }

@@ -952,7 +952,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
                            bp<uint32_t>(a->ucnt), nullptr, nullptr, st));
     HIPCHK(launch_scan(kAdUnitClasses * a->nleaf, bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), scan, st));
     HIPCHK(ad_launch_units(a->nleaf, 1, bp<uint32_t>(a->lstart), bp<int>(a->lbox), ou, bp<int>(a->iu), ps, pe,
-                           nullptr, bp<uint32_t>(a->uoff), bp<int2>(a->units), st));
+                           bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), bp<int2>(a->units), st));
     // M2L targets grouped by (level, class), tiles of 128 targets per block
     a->plan = AdM2LPlan{};
     int64_t at = 0;

@@ -215,7 +215,8 @@ hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const
 // P2P work units of up to 64 targets: pass 0 counts per leaf into cnt
 // (kAdUnitClasses nleaf words: one run of leaves per class of unit weight,
 // heaviest first), pass 1 fills units (leaf, first target) from uoff, the
-// scan of those counts (the total at uoff[kAdUnitClasses nleaf])
+// scan of those counts (the total at uoff[kAdUnitClasses nleaf]), reading
+// each leaf's class back from cnt
 constexpr int kAdUnitClasses = 8;
 hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, const int *lbox, const uint32_t *ou,
                            const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt, const uint32_t *uoff,
