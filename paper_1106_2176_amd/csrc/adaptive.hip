@@ -363,17 +363,19 @@ __global__ __launch_bounds__(256) void k_ad_leafmax(int64_t nleaf, const uint32_
     if (threadIdx.x == 0) atomic_max_shared(mx, red[0]);
 }
 
-// P2P work units: ceil(count / 64) per leaf (pass 0), then each unit's
-// (leaf, first target) from the scanned counts (pass 1).  The counts are
-// laid out as kAdUnitClasses runs of nleaf, by the pairs of a full unit of
-// the leaf (its targets times the sources of U): at least 2^19, 2^18, ...,
-// 2^13, then the rest, so that the scan orders the units heaviest class
-// first (about a longest-first schedule, which a sort would refine by ~1%).
-// The heaviest waves then start with the grid instead of wherever the leaf
-// order puts them, and the kernels that take the units (P2P, M2P) do not
-// end on a late heavy wave.
-__global__ void k_ad_units(int64_t nleaf, int pass, const uint32_t *__restrict__ lstart,
-                           const int *__restrict__ lbox, const uint32_t *__restrict__ ou,
+// Work units: ceil(count / 64) per leaf (pass 0), then each unit's (leaf,
+// first target) from the scanned counts (pass 1).  The counts are laid out
+// as kAdUnitClasses runs of nleaf, by the weight of a full unit of the leaf,
+// so that the scan orders the units heaviest class first (about a
+// longest-first schedule, which a sort would refine by ~1%): the heaviest
+// waves then start with the grid instead of wherever the leaf order puts
+// them, and the kernel does not end on a late heavy wave.  kind 0 (P2P):
+// the weight is the unit's pairs, its targets times the sources of U (off =
+// the U offsets); kind 1 (M2P): its rounds of W boxes, |W| over the lane
+// groups of the unit, times 2^12 (off = the W offsets).  Classes: weight at
+// least 2^19, 2^18, ..., 2^13, then the rest.
+__global__ void k_ad_units(int64_t nleaf, int pass, int kind, const uint32_t *__restrict__ lstart,
+                           const int *__restrict__ lbox, const uint32_t *__restrict__ off,
                            const int *__restrict__ iu, const uint32_t *__restrict__ ps,
                            const uint32_t *__restrict__ pe, uint32_t *__restrict__ cnt,
                            const uint32_t *__restrict__ uoff, int2 *__restrict__ units) {
@@ -383,13 +385,22 @@ __global__ void k_ad_units(int64_t nleaf, int pass, const uint32_t *__restrict__
     int cls = 0;
     if (pass == 0) {
         const int g = lbox[j];
-        uint64_t src = 0;
-        for (uint32_t e = ou[g]; e < ou[g + 1]; ++e) {
-            const int c = iu[e];
-            src += pe[c] - ps[c];
+        const uint32_t nt = min(np, 64u);
+        uint64_t weight = 0;
+        if (kind == 0) {
+            uint64_t src = 0;
+            for (uint32_t e = off[g]; e < off[g + 1]; ++e) {
+                const int c = iu[e];
+                src += pe[c] - ps[c];
+            }
+            weight = (uint64_t)nt * src;
+        } else {  // the lane groups of k_ad_m2p: 64 / T, T = max(4, nt rounded up to a power of 2)
+            uint32_t t = 4;
+            while (t < nt && t < 64) t <<= 1;
+            const uint32_t groups = 64 / t;
+            weight = (uint64_t)((off[g + 1] - off[g] + groups - 1) / groups) << 12;
         }
-        const uint64_t pairs = (uint64_t)min(np, 64u) * src;
-        while (cls < kAdUnitClasses - 1 && pairs < (1ull << (19 - cls))) ++cls;
+        while (cls < kAdUnitClasses - 1 && weight < (1ull << (19 - cls))) ++cls;
         for (int k = 0; k < kAdUnitClasses; ++k) cnt[k * nleaf + j] = k == cls ? m : 0;
         return;
     }
@@ -1852,10 +1863,11 @@ hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const
     return hipGetLastError();
 }
 
-hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, const int *lbox, const uint32_t *ou,
-                           const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt, const uint32_t *uoff,
-                           int2 *units, hipStream_t st) {
-    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, lstart, lbox, ou, iu, ps, pe, cnt, uoff, units);
+hipError_t ad_launch_units(int64_t nleaf, int pass, int kind, const uint32_t *lstart, const int *lbox,
+                           const uint32_t *off, const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt,
+                           const uint32_t *uoff, int2 *units, hipStream_t st) {
+    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, kind, lstart, lbox, off, iu, ps, pe, cnt, uoff,
+                                                      units);
     return hipGetLastError();
 }
 
