@@ -277,7 +277,8 @@ __device__ void ad_uwx(int g, int o, bool lg_leaf, const int *lev, const uint32_
 }
 
 // One thread per (box, direction), i = 27 g + o.  pass 0: counts of U, W
-// (leaves) and X (all boxes); pass 1: the items, at the scanned offsets.
+// (leaves) and X (all boxes); pass 1: the items, at the scanned offsets
+// (ou, ow, ox: the three runs of one scan, each taken from its first entry).
 __global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, const uint32_t *__restrict__ code,
                            const int *__restrict__ parent, const int *__restrict__ col,
                            const int *__restrict__ child, const uint8_t *__restrict__ leaf,
@@ -295,8 +296,8 @@ __global__ void k_ad_lists(int64_t nbox, int pass, const int *__restrict__ lev, 
         nw[i] = b;
         nx[i] = c;
     } else {
-        ad_uwx(g, o, leaf[g] != 0, lev, code, parent, col, child, leaf, iu + ou[i], a, iw + ow[i], b, ix + ox[i],
-               c);
+        ad_uwx(g, o, leaf[g] != 0, lev, code, parent, col, child, leaf, iu + (ou[i] - ou[0]), a,
+               iw + (ow[i] - ow[0]), b, ix + (ox[i] - ox[0]), c);
     }
 }
 
@@ -306,10 +307,10 @@ __global__ void k_ad_box_offsets(int64_t nbox, const uint32_t *__restrict__ s27,
                                  uint32_t *__restrict__ ow, uint32_t *__restrict__ ox) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g > nbox) return;
-    const int64_t m = 27 * nbox + 1;
+    const int64_t m = 27 * nbox;  // one scan of the U, W and X counts: run k starts at s27[k m]
     ou[g] = s27[27 * g];
-    ow[g] = s27[m + 27 * g];
-    ox[g] = s27[2 * m + 27 * g];
+    ow[g] = s27[m + 27 * g] - s27[m];
+    ox[g] = s27[2 * m + 27 * g] - s27[2 * m];
 }
 
 // level of every box from the level offsets

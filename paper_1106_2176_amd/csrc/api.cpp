@@ -895,7 +895,7 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     CHK(ensure(t, a->cnts, 3 * u4 * n27, st));
     CHK(ensure(t, a->s27, 3 * u4 * (n27 + 1), st));
     CHK(ensure(t, a->offs, 3 * u4 * (nbox + 1), st));
-    CHK(ensure(t, t->scan, u4 * scan_scratch_words(std::max(n27, n) + 1), st));
+    CHK(ensure(t, t->scan, u4 * scan_scratch_words(std::max(3 * n27, n) + 1), st));
     scan = bp<uint32_t>(t->scan);
     CHK(ensure(t, a->is_head, u4 * n, st));
     CHK(ensure(t, a->head, u4 * n, st));
@@ -904,16 +904,15 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
     CHK(ensure(t, a->ccnt, u4 * std::max(ngrp, 1), st));
     int *lev = bp<int>(a->lev), *col = bp<int>(a->col), *vidx = bp<int>(a->vidx);
     uint32_t *nu = bp<uint32_t>(a->cnts), *nw = nu + n27, *nx = nw + n27;
-    uint32_t *su = bp<uint32_t>(a->s27), *sw = su + n27 + 1, *sx = sw + n27 + 1;
+    // the U, W and X counts (contiguous) in one scan: run k starts at k n27
+    uint32_t *su = bp<uint32_t>(a->s27), *sw = su + n27, *sx = sw + n27;
     uint32_t *ou = bp<uint32_t>(a->offs), *ow = ou + nbox + 1, *ox = ow + nbox + 1;
     HIPCHK(hipMemcpyAsync(a->offd.p, a->off, sizeof(int64_t) * (nlev + 1), hipMemcpyHostToDevice, st));
     HIPCHK(ad_launch_structure(nbox, nlev, a->off, bp<int64_t>(a->offd), code, parent, child, lev, col,
                                t->ops->cls, vidx, st));
     HIPCHK(ad_launch_lists(nbox, 0, lev, code, parent, col, child, leaf, nu, nw, nx, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, st));
-    HIPCHK(launch_scan(n27, nu, su, scan, st));
-    HIPCHK(launch_scan(n27, nw, sw, scan, st));
-    HIPCHK(launch_scan(n27, nx, sx, scan, st));
+    HIPCHK(launch_scan(3 * n27, nu, su, scan, st));
     HIPCHK(ad_launch_box_offsets(nbox, su, ou, ow, ox, st));
     HIPCHK(launch_zero(bp<uint32_t>(a->is_head), n, st));
     HIPCHK(ad_launch_heads(nbox, leaf, ps, pe, bp<uint32_t>(a->is_head), bp<int>(a->head), st));
