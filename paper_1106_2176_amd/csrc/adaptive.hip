@@ -71,6 +71,31 @@ __device__ inline bool ad_adjacent(int la, uint32_t ca, int lb, uint32_t cb) {
     return !inside;
 }
 
+// a box as its level and coordinates at that level (each below 2^10), for
+// the list walks, which test one box against many: decoded once, compared
+// in 32-bit arithmetic
+struct AdBox {
+    int l, x, y, z;
+};
+__device__ __forceinline__ AdBox ad_box(int l, uint32_t code) {
+    return AdBox{l, (int)compact3(code), (int)compact3(code >> 1), (int)compact3(code >> 2)};
+}
+// ad_adjacent on decoded boxes
+__device__ __forceinline__ bool ad_touch(const AdBox a, const AdBox b) {
+    const bool af = a.l >= b.l;  // a is the finer (or equal)
+    const int k = af ? a.l - b.l : b.l - a.l;
+    const int f[3] = {af ? a.x : b.x, af ? a.y : b.y, af ? a.z : b.z};
+    const int c[3] = {af ? b.x : a.x, af ? b.y : a.y, af ? b.z : a.z};
+    bool inside = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int lo = c[ax] << k, hi = ((c[ax] + 1) << k) - 1;
+        if (f[ax] < lo - 1 || f[ax] > hi + 1) return false;
+        if (f[ax] < lo || f[ax] > hi) inside = false;
+    }
+    return !inside;
+}
+
 __global__ void k_ad_root(uint32_t n, uint32_t *code, uint32_t *ps, uint32_t *pe, int *parent) {
     code[0] = 0;
     ps[0] = 0;
@@ -227,23 +252,20 @@ __device__ void ad_uwx(int g, int o, bool lg_leaf, const int *lev, const uint32_
         }
         return;
     }
-    const int lg = lev[g];
-    const uint32_t cg = code[g];
+    const AdBox bg = ad_box(lev[g], code[g]);
     const int p = parent[g];
     if (p >= 0) {
-        const int lp = lev[p];
-        const uint32_t cp = code[p];
+        const AdBox bp = ad_box(lev[p], code[p]);
         for (int a = p; a >= 0; a = parent[a]) {
             const int c = col[27 * (int64_t)a + o];
             if (c < 0 || !leaf[c]) continue;
-            const int lc = lev[c];
-            const uint32_t cc = code[c];
-            if (ad_adjacent(lg, cg, lc, cc)) {
+            const AdBox bc = ad_box(lev[c], code[c]);
+            if (ad_touch(bg, bc)) {
                 if (lg_leaf) {
                     if (u) u[nu] = c;
                     ++nu;
                 }
-            } else if (ad_adjacent(lp, cp, lc, cc)) {
+            } else if (ad_touch(bp, bc)) {
                 if (x) x[nx] = c;
                 ++nx;
             }
@@ -263,7 +285,7 @@ __device__ void ad_uwx(int g, int o, bool lg_leaf, const int *lev, const uint32_
         if (child[8 * (int64_t)c + ch] >= 0) stack[sp++] = child[8 * (int64_t)c + ch];
     while (sp > 0) {
         const int d = stack[--sp];
-        if (!ad_adjacent(lg, cg, lev[d], code[d])) {
+        if (!ad_touch(bg, ad_box(lev[d], code[d]))) {
             if (w) w[nw] = d;
             ++nw;
         } else if (leaf[d]) {
