@@ -387,50 +387,55 @@ __global__ __launch_bounds__(256) void k_ad_leafmax(int64_t nleaf, const uint32_
 }
 
 // Work units: ceil(count / 64) per leaf (pass 0), then each unit's (leaf,
-// first target) from the scanned counts (pass 1).  The counts are laid out
-// as kAdUnitClasses runs of nleaf, by the weight of a full unit of the leaf,
-// so that the scan orders the units heaviest class first (about a
-// longest-first schedule, which a sort would refine by ~1%): the heaviest
-// waves then start with the grid instead of wherever the leaf order puts
-// them, and the kernel does not end on a late heavy wave.  kind 0 (P2P):
-// the weight is the unit's pairs, its targets times the sources of U (off =
-// the U offsets); kind 1 (M2P): its rounds of W boxes, |W| over the lane
-// groups of the unit, times 2^12 (off = the W offsets).  Classes: weight at
-// least 2^19, 2^18, ..., 2^13, then the rest.
-__global__ void k_ad_units(int64_t nleaf, int pass, int kind, const uint32_t *__restrict__ lstart,
-                           const int *__restrict__ lbox, const uint32_t *__restrict__ off,
-                           const int *__restrict__ iu, const uint32_t *__restrict__ ps,
-                           const uint32_t *__restrict__ pe, uint32_t *__restrict__ cnt,
-                           const uint32_t *__restrict__ uoff, int2 *__restrict__ units) {
+// first target) from the scanned counts (pass 1), in two orders: units for
+// P2P and units_m for M2P.  The counts are laid out as 2 kAdUnitClasses runs
+// of nleaf (the P2P classes, then the M2P classes), by the weight of a full
+// unit of the leaf, so that one scan orders each copy heaviest class first
+// (about a longest-first schedule, which a sort would refine by ~1%): the
+// heaviest waves then start with the grid instead of wherever the leaf order
+// puts them, and the kernel does not end on a late heavy wave.  P2P weight:
+// the unit's pairs, its targets times the sources of U; M2P weight: its
+// rounds of W boxes, |W| over the lane groups of the unit, times 2^12.
+// Classes: weight at least 2^19, 2^18, ..., 2^13, then the rest.
+__global__ void k_ad_units(int64_t nleaf, int pass, const uint32_t *__restrict__ lstart,
+                           const int *__restrict__ lbox, const uint32_t *__restrict__ ou,
+                           const uint32_t *__restrict__ ow, const int *__restrict__ iu,
+                           const uint32_t *__restrict__ ps, const uint32_t *__restrict__ pe,
+                           uint32_t *__restrict__ cnt, const uint32_t *__restrict__ uoff,
+                           int2 *__restrict__ units, int2 *__restrict__ units_m) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nleaf) return;
     const uint32_t np = lstart[j + 1] - lstart[j], m = (np + 63) / 64;
-    int cls = 0;
+    const int64_t half = (int64_t)kAdUnitClasses * nleaf;
     if (pass == 0) {
         const int g = lbox[j];
         const uint32_t nt = min(np, 64u);
-        uint64_t weight = 0;
-        if (kind == 0) {
-            uint64_t src = 0;
-            for (uint32_t e = off[g]; e < off[g + 1]; ++e) {
-                const int c = iu[e];
-                src += pe[c] - ps[c];
-            }
-            weight = (uint64_t)nt * src;
-        } else {  // the lane groups of k_ad_m2p: 64 / T, T = max(4, nt rounded up to a power of 2)
-            uint32_t t = 4;
-            while (t < nt && t < 64) t <<= 1;
-            const uint32_t groups = 64 / t;
-            weight = (uint64_t)((off[g + 1] - off[g] + groups - 1) / groups) << 12;
+        uint64_t src = 0;
+        for (uint32_t e = ou[g]; e < ou[g + 1]; ++e) {
+            const int c = iu[e];
+            src += pe[c] - ps[c];
         }
-        while (cls < kAdUnitClasses - 1 && weight < (1ull << (19 - cls))) ++cls;
-        for (int k = 0; k < kAdUnitClasses; ++k) cnt[k * nleaf + j] = k == cls ? m : 0;
+        uint32_t t = 4;  // the lane groups of k_ad_m2p: 64 / T, T = max(4, nt rounded up to a power of 2)
+        while (t < nt && t < 64) t <<= 1;
+        const uint32_t groups = 64 / t;
+        const uint64_t weight[2] = {(uint64_t)nt * src, (uint64_t)((ow[g + 1] - ow[g] + groups - 1) / groups) << 12};
+#pragma unroll
+        for (int kind = 0; kind < 2; ++kind) {
+            int cls = 0;
+            while (cls < kAdUnitClasses - 1 && weight[kind] < (1ull << (19 - cls))) ++cls;
+            for (int k = 0; k < kAdUnitClasses; ++k) cnt[kind * half + k * nleaf + j] = k == cls ? m : 0;
+        }
         return;
     }
-    // pass 1: the class is the run whose count is set (a leaf has m >= 1)
-    while (cls < kAdUnitClasses - 1 && cnt[cls * nleaf + j] == 0) ++cls;
-    const uint32_t base = uoff[cls * nleaf + j];
-    for (uint32_t k = 0; k < m; ++k) units[base + k] = make_int2((int)j, (int)(64 * k));
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+        // the class is the run whose count is set (a leaf has m >= 1)
+        int cls = 0;
+        while (cls < kAdUnitClasses - 1 && cnt[kind * half + cls * nleaf + j] == 0) ++cls;
+        const uint32_t base = uoff[kind * half + cls * nleaf + j] - (kind ? uoff[half] : 0u);
+        int2 *dst = kind ? units_m : units;
+        for (uint32_t k = 0; k < m; ++k) dst[base + k] = make_int2((int)j, (int)(64 * k));
+    }
 }
 
 // Work counts: [0] ordered P2P pairs (self pairs included), [1] V entries,
@@ -1886,11 +1891,11 @@ hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const
     return hipGetLastError();
 }
 
-hipError_t ad_launch_units(int64_t nleaf, int pass, int kind, const uint32_t *lstart, const int *lbox,
-                           const uint32_t *off, const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt,
-                           const uint32_t *uoff, int2 *units, hipStream_t st) {
-    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, kind, lstart, lbox, off, iu, ps, pe, cnt, uoff,
-                                                      units);
+hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, const int *lbox, const uint32_t *ou,
+                           const uint32_t *ow, const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt,
+                           const uint32_t *uoff, int2 *units, int2 *units_m, hipStream_t st) {
+    k_ad_units<<<ad_blocks(nleaf, 256), 256, 0, st>>>(nleaf, pass, lstart, lbox, ou, ow, iu, ps, pe, cnt, uoff, units,
+                                                      units_m);
     return hipGetLastError();
 }
 

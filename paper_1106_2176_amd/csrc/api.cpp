@@ -351,15 +351,13 @@ struct AdTree {
     AdM2LPlan plan{};
     uint32_t *hbuf = nullptr;                 // pinned host words for the build's counts
     Buf code, ps, pe, parent, child, leaf, cmask, nchild, coff, lev, col, vidx, cnts, offs, iu, iw, ix,
-        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, ucnt, uoff, units, s27, uoff_m,
-        units_m;
+        is_head, head, hoff, lbox, lstart, llev, tgt, ccnt, goffd, offd, ucnt, uoff, units, s27, units_m;
     Buf skey, cstart, ks_a, ks_b, ks_v, ks_h;  // the key sort: sorted keys, coarse starts, scratch
     int64_t max_units = 0;  // bound of the P2P work units (their count stays on the device)
     std::vector<Buf *> bufs() {
         return {&code, &ps, &pe, &parent, &child, &leaf, &cmask, &nchild, &coff, &lev, &col, &vidx, &cnts,
                 &offs, &iu, &iw, &ix, &is_head, &head, &hoff, &lbox, &lstart, &llev, &tgt, &ccnt, &goffd,
-                &offd, &ucnt, &uoff, &units, &s27, &skey, &cstart, &ks_a, &ks_b, &ks_v, &ks_h, &uoff_m,
-                &units_m};
+                &offd, &ucnt, &uoff, &units, &s27, &skey, &cstart, &ks_a, &ks_b, &ks_v, &ks_h, &units_m};
     }
 };
 
@@ -945,23 +943,18 @@ fmm_status build_adaptive(fmm_tree *t, int64_t n, int32_t dtype, const void *pos
                              pos, c.box_lo, c.box_size, bp<double4>(t->xyz64), st));
     // P2P work units: at most one per leaf plus one per 64 particles
     a->max_units = a->nleaf + n / 64;
-    // (heaviest units first: one run of nleaf counts per weight class, one
-    // scan), once weighed for P2P and once, into units_m, for M2P
-    CHK(ensure(t, a->ucnt, u4 * kAdUnitClasses * a->nleaf, st));
-    CHK(ensure(t, a->uoff, u4 * (kAdUnitClasses * a->nleaf + 1), st));
-    CHK(ensure(t, a->uoff_m, u4 * (kAdUnitClasses * a->nleaf + 1), st));
+    // (heaviest units first: one run of nleaf counts per weight class and
+    // order, P2P over U and M2P over W, and one scan)
+    CHK(ensure(t, a->ucnt, u4 * 2 * kAdUnitClasses * a->nleaf, st));
+    CHK(ensure(t, a->uoff, u4 * (2 * kAdUnitClasses * a->nleaf + 1), st));
     CHK(ensure(t, a->units, sizeof(int2) * a->max_units, st));
     CHK(ensure(t, a->units_m, sizeof(int2) * a->max_units, st));
-    for (int kind = 0; kind < 2; ++kind) {
-        uint32_t *uo = bp<uint32_t>(kind ? a->uoff_m : a->uoff);
-        int2 *un = bp<int2>(kind ? a->units_m : a->units);
-        const uint32_t *lo = kind ? ow : ou;
-        HIPCHK(ad_launch_units(a->nleaf, 0, kind, bp<uint32_t>(a->lstart), bp<int>(a->lbox), lo, bp<int>(a->iu), ps,
-                               pe, bp<uint32_t>(a->ucnt), nullptr, nullptr, st));
-        HIPCHK(launch_scan(kAdUnitClasses * a->nleaf, bp<uint32_t>(a->ucnt), uo, scan, st));
-        HIPCHK(ad_launch_units(a->nleaf, 1, kind, bp<uint32_t>(a->lstart), bp<int>(a->lbox), lo, bp<int>(a->iu), ps,
-                               pe, bp<uint32_t>(a->ucnt), uo, un, st));
-    }
+    HIPCHK(ad_launch_units(a->nleaf, 0, bp<uint32_t>(a->lstart), bp<int>(a->lbox), ou, ow, bp<int>(a->iu), ps, pe,
+                           bp<uint32_t>(a->ucnt), nullptr, nullptr, nullptr, st));
+    HIPCHK(launch_scan(2 * kAdUnitClasses * a->nleaf, bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), scan, st));
+    HIPCHK(ad_launch_units(a->nleaf, 1, bp<uint32_t>(a->lstart), bp<int>(a->lbox), ou, ow, bp<int>(a->iu), ps, pe,
+                           bp<uint32_t>(a->ucnt), bp<uint32_t>(a->uoff), bp<int2>(a->units), bp<int2>(a->units_m),
+                           st));
     // M2L targets grouped by (level, class), tiles of 128 targets per block
     a->plan = AdM2LPlan{};
     int64_t at = 0;

@@ -212,16 +212,17 @@ hipError_t ad_launch_m2p(int P, int64_t max_units, const uint32_t *nunits, const
                          const int *lbox, const uint32_t *lstart, const uint32_t *ow, const int *iw, const int *lev,
                          const uint32_t *code, const double4 *rec, const double *M, double4 *out, bool f32,
                          hipStream_t st);
-// Work units of up to 64 targets: pass 0 counts per leaf into cnt
-// (kAdUnitClasses nleaf words: one run of leaves per class of unit weight,
-// heaviest first; kind 0 weighs P2P over U with off the U offsets, kind 1
-// M2P over W with off the W offsets), pass 1 fills units (leaf, first
-// target) from uoff, the scan of those counts (the total at
-// uoff[kAdUnitClasses nleaf]), reading each leaf's class back from cnt
+// Work units of up to 64 targets, in two orders (units for P2P over U, with
+// ou the U offsets; units_m for M2P over W, with ow the W offsets): pass 0
+// counts per leaf into cnt (2 kAdUnitClasses nleaf words: per order, one
+// run of leaves per class of unit weight, heaviest first), pass 1 fills both
+// copies (leaf, first target) from uoff, the scan of those counts (the
+// number of units at uoff[kAdUnitClasses nleaf]), reading each leaf's
+// classes back from cnt
 constexpr int kAdUnitClasses = 8;
-hipError_t ad_launch_units(int64_t nleaf, int pass, int kind, const uint32_t *lstart, const int *lbox,
-                           const uint32_t *off, const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt,
-                           const uint32_t *uoff, int2 *units, hipStream_t st);
+hipError_t ad_launch_units(int64_t nleaf, int pass, const uint32_t *lstart, const int *lbox, const uint32_t *ou,
+                           const uint32_t *ow, const int *iu, const uint32_t *ps, const uint32_t *pe, uint32_t *cnt,
+                           const uint32_t *uoff, int2 *units, int2 *units_m, hipStream_t st);
 // one wave per unit; max_units bounds *nunits (the grid's size)
 // with fuse non-NULL the kernel ends with the combine (no near partials);
 // f32: the pair arithmetic in FP32 (the mixed form)
